@@ -1,0 +1,139 @@
+"""Seeded synthetic inputs for the ADR-amplitude solve: media, travel times, absorbing
+layers, sources.  Shared by the tests, the benchmark and the smoke check.
+
+This module holds none of the solver's arithmetic: it only builds the inputs that the
+solver takes (kappa^2, tau, gamma, the source node and the point-source right-hand side).
+The paper's own performance media (a figure-only linear model, Marmousi2, Overthrust)
+are not available, so these synthetic media stand in for them with the paper's kind of
+setting (Sec. 4.2): smooth velocity, about 10 points per wavelength, a point source in
+the interior of a unit square / cube.
+
+Arrays are C-ordered with the last axis = x (fastest); axis 0 is depth (y in 2D, z in
+3D).  Source indices are NumPy index tuples in the same order.
+"""
+from dataclasses import dataclass, field
+from typing import Optional, Tuple
+
+import numpy as np
+
+
+@dataclass
+class Workload:
+    name: str
+    shape: Tuple[int, ...]
+    h: float
+    omega: float
+    src: Tuple[int, ...]
+    kappa2: np.ndarray
+    tau: np.ndarray
+    gamma: Optional[np.ndarray]
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def ndim(self):
+        return len(self.shape)
+
+    @property
+    def nodes(self):
+        return int(np.prod(self.shape))
+
+    def rhs(self):
+        """Point source q = e_src / h^d (Sec. 4.1 discretizes delta as 1/h^d)."""
+        q = np.zeros(self.shape, dtype=np.complex128)
+        q[self.src] = 1.0 / self.h ** self.ndim
+        return q
+
+
+def node_coordinates(shape, h):
+    return np.meshgrid(*[np.arange(n, dtype=np.float64) * h for n in shape], indexing="ij")
+
+
+def distance(shape, h, src):
+    xs = node_coordinates(shape, h)
+    return np.sqrt(sum((x - s * h) ** 2 for x, s in zip(xs, src)))
+
+
+def omega_for_ppw(v_min, h, ppw=10.0):
+    """Angular frequency giving ``ppw`` nodes per minimum wavelength v_min / f."""
+    return 2.0 * np.pi * v_min / (ppw * h)
+
+
+def absorbing_layer(shape, h, omega, thickness, faces=None):
+    """gamma rising quadratically from 0 to omega over ``thickness`` towards the listed
+    faces (Sec. 1); in several dimensions the largest per-axis value.  ``faces`` is a
+    list of (axis, side) with side 0 = low, 1 = high; default: every face."""
+    d = len(shape)
+    if faces is None:
+        faces = [(a, s) for a in range(d) for s in (0, 1)]
+    xs = node_coordinates(shape, h)
+    gam = np.zeros(shape)
+    for a, side in faces:
+        extent = (shape[a] - 1) * h
+        depth = xs[a] if side == 0 else extent - xs[a]
+        pen = np.clip((thickness - depth) / thickness, 0.0, 1.0)
+        gam = np.maximum(gam, omega * pen ** 2)
+    return gam
+
+
+def linear_velocity_traveltime(shape, h, src, v0, grad):
+    """First-arrival time for v = v0 + grad * depth (depth = axis 0) from node ``src``:
+    tau = (1/g) arccosh(1 + g^2 |x - x0|^2 / (2 v(x) v(x0)))."""
+    xs = node_coordinates(shape, h)
+    depth = xs[0]
+    v = v0 + grad * depth
+    v_src = v0 + grad * src[0] * h
+    r2 = sum((x - s * h) ** 2 for x, s in zip(xs, src))
+    if grad == 0.0:
+        return np.sqrt(r2) / v0
+    return np.arccosh(1.0 + grad * grad * r2 / (2.0 * v * v_src)) / grad
+
+
+def constant_medium(n, ndim=2, ppw=10.0, absorb=True, src=None, name="const"):
+    """kappa = 1 on the unit square/cube, tau = r, source at the centre node."""
+    shape = (n,) * ndim
+    h = 1.0 / (n - 1)
+    omega = omega_for_ppw(1.0, h, ppw)
+    src = tuple(s for s in (src if src is not None else (n // 2,) * ndim))
+    kappa2 = np.ones(shape)
+    tau = distance(shape, h, src)
+    gamma = absorbing_layer(shape, h, omega, 10 * h) if absorb else None
+    return Workload(name, shape, h, omega, src, kappa2, tau, gamma)
+
+
+def linear_gradient(n, ndim=3, v0=1.5, grad=0.8, ppw=10.0, src_frac=None, absorb=True,
+                    name="linear_gradient"):
+    """v = v0 + grad*depth over the unit square/cube, analytic tau, source at
+    (0.5, 0.5, 0.1) (depth fraction last in ``src_frac`` order x, y, depth) snapped to
+    the nearest node."""
+    shape = (n,) * ndim
+    h = 1.0 / (n - 1)
+    if src_frac is None:
+        src_frac = (0.5,) * (ndim - 1) + (0.1,)
+    # src_frac is (x, y, ..., depth); NumPy order is (depth, ..., y, x).
+    src = tuple(int(round(f / h)) for f in reversed(src_frac))
+    v = v0 + grad * node_coordinates(shape, h)[0]
+    kappa2 = 1.0 / v ** 2
+    tau = linear_velocity_traveltime(shape, h, src, v0, grad)
+    omega = omega_for_ppw(v0, h, ppw)
+    gamma = absorbing_layer(shape, h, omega, 10 * h) if absorb else None
+    return Workload(name, shape, h, omega, src, kappa2, tau, gamma)
+
+
+def config_2d_129():
+    """2D 129^2 unit square, kappa = 1, 10 points per wavelength, source (0.5, 0.5)."""
+    return constant_medium(129, ndim=2, name="2d_129_const")
+
+
+def config_3d_129():
+    """3D 129^3 unit cube (1 km), v = 1.5 + 0.8 z km/s, analytic tau, source
+    (0.5, 0.5, 0.1) km snapped to node (x, y, z) = (64, 64, 13), 10 points per
+    wavelength at v_min = 1.5 km/s."""
+    return linear_gradient(129, ndim=3, name="3d_129_linear_gradient")
+
+
+def random_vector(shape, seed, dtype=np.complex128):
+    """Seeded complex Gaussian test vector."""
+    rng = np.random.default_rng(seed)
+    if np.dtype(dtype).kind == "c":
+        return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(dtype)
+    return rng.standard_normal(shape).astype(dtype)
