@@ -1,0 +1,155 @@
+/*
+ * adr.h -- C ABI of the MI355X ADR-amplitude solver.
+ *
+ * Solves the point-source Helmholtz equation in the factored form of Treister & Haber,
+ * "A fast marching algorithm ... / ADR amplitude" (arXiv:1712.06091):
+ *   u = a exp(-i w tau)                                    (Sec. 1, eq. new_u)
+ *   Lap a - 2 i w grad(tau).grad(a) - i w (Lap tau) a
+ *        - w^2 (|grad tau|^2 - kappa^2) a - i w gamma kappa^2 a = q exp(i w tau)
+ *                                                          (Sec. 1, eq. ADR, plus the
+ *                                                           absorbing term of Sec. 1)
+ * discretized with the second-order upwind scheme H_2up (Sec. 2.2, eq. londUpwindDiff),
+ * the averaging mass for the Lap(tau) term (Sec. 2.3) and the boundary condition
+ * eq. BCADR, and solved by flexible GMRES(m) (Sec. 4.2) preconditioned by a multigrid
+ * V-cycle on (1-beta) H_2up + beta H_1up (eq. precADRup) with Galerkin coarse
+ * operators (eq. coarseGridMatrix).
+ *
+ * Conventions (every entry point):
+ *  - Grids are nodal with n[k] nodes along axis k (k = 0 is x, the fastest-varying
+ *    index), spacing h on every axis, node j at position j*h.  Arrays are dense,
+ *    row-major with x fastest: index = x + n[0]*(y + n[1]*z).
+ *  - Complex arrays are interleaved (re, im): "c128" = 2 doubles per node, "c64" = 2
+ *    floats per node (the storage of torch.complex128 / torch.complex64).
+ *  - Unless stated otherwise, array pointers are DEVICE pointers on the current HIP
+ *    device, owned by the caller; the library never frees them and keeps no reference
+ *    to them after the call returns (adr_setup copies what it needs).
+ *  - Calls return an adr_status and never throw.  On error nothing is half-written
+ *    unless stated; adr_last_error() gives a message.
+ *  - A context is bound to the stream given at setup; all work is enqueued on it.  A
+ *    context is not thread-safe; use one per stream.
+ */
+#ifndef ADR_H_
+#define ADR_H_
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ADR_OK = 0,
+  ADR_EINVAL = 1,    /* bad argument: null pointer, bad size, source too close to a face */
+  ADR_ENOMEM = 2,    /* device or host allocation failed                                 */
+  ADR_EHIP = 3,      /* a HIP runtime call failed                                        */
+  ADR_ENOCONV = 4,   /* solver hit maxit before tol; the best iterate is still written   */
+  ADR_ENUMERIC = 5,  /* NaN/Inf in a residual norm                                       */
+  ADR_ENOTSUP = 6    /* option combination not supported                                */
+} adr_status;
+
+typedef enum {
+  ADR_PREC_FP64 = 0,   /* every step in complex FP64                                      */
+  ADR_PREC_MIXED = 1   /* V-cycle in complex FP32; outer GMRES, residuals, coarsest FP64  */
+} adr_precision;
+
+typedef enum {
+  ADR_RELAX_JACOBI = 0,  /* damped Jacobi sweeps (Sec. 3.1)                                */
+  ADR_RELAX_GMRES = 1    /* Jacobi-preconditioned GMRES steps (Sec. 4.2)                   */
+} adr_relax;
+
+/* The discrete problem (Sec. 2).  kappa2, tau and gamma are DEVICE pointers to n
+ * doubles each; gamma may be NULL (no absorption).  src[k] is the source node index
+ * along axis k; it must be at least 2 nodes from every face.  With src[0] < 0 the
+ * travel-time derivatives are plain differences of tau (no factoring, no near-source
+ * rule).  Requires ndim in {2,3}, n[k] >= 5, h > 0, omega > 0. */
+typedef struct {
+  int ndim;
+  int n[3];
+  double h;
+  double omega;
+  const double *kappa2;
+  const double *tau;
+  const double *gamma;
+  int src[3];
+} adr_problem;
+
+/* Solver options; adr_default_options() fills the defaults named below. */
+typedef struct {
+  adr_precision prec;   /* default ADR_PREC_MIXED                                        */
+  int levels;           /* multigrid levels; 0 = automatic: halve while (n-1) is even,    */
+                        /* coarse n >= 5 and the grid has more than coarsest_max nodes   */
+  int coarsest_max;     /* default 729                                                    */
+  int nu[8];            /* relaxations per level (pre = post); default l+2 for 0-based    */
+                        /* level l, i.e. 2 on the finest, 3 on the next (Sec. 4.2)        */
+  adr_relax relax[8];   /* default JACOBI on level 0, GMRES on coarser levels            */
+  double jacobi_weight; /* default 0.8                                                    */
+  double beta;          /* preconditioner blend of eq. precADRup; default 0.25 (Sec. 4.2) */
+  int restart;          /* FGMRES restart length m; default 5 (Sec. 4.2); max 16          */
+  int use_graph;        /* capture each V-cycle in a hipGraph; default 1                 */
+} adr_options;
+
+typedef struct {
+  int outer_iters;      /* FGMRES iterations (= preconditioner applications)             */
+  int restarts;
+  double relres;        /* final true relative residual ||q_hat - H_2up a|| / ||q_hat||  */
+  double setup_ms;      /* adr_setup wall time                                           */
+  double solve_ms;      /* adr_solve wall time                                           */
+} adr_stats;
+
+typedef struct adr_ctx adr_ctx;
+
+/* Host: fill *o with the defaults above. */
+void adr_default_options(adr_options *o);
+
+/* Build the context: ADR coefficients from tau (Sec. 2.1, eq. travel_time_coeff), the
+ * fine operator data, the Galerkin hierarchy of A_beta and the coarsest inverse.
+ * `stream` is a hipStream_t (NULL = default stream).  The caller's arrays may be freed
+ * after return.  *out is NULL on error. */
+adr_status adr_setup(const adr_problem *prob, const adr_options *opt, void *stream, adr_ctx **out);
+
+/* Free everything the context owns.  NULL is a no-op. */
+void adr_destroy(adr_ctx *ctx);
+
+/* y = A_beta x on the fine grid in FP64 (beta as given, e.g. 0 for H_2up), x and y c128
+ * of n nodes, distinct buffers.  Enqueued on the context stream. */
+adr_status adr_apply(adr_ctx *ctx, double beta, const void *x_c128, void *y_c128);
+
+/* One preconditioner application z = M^{-1} r: a V-cycle (Alg. TwoCycle, recursive) on
+ * A_beta from a zero guess, in the context's precision; r and z c128, distinct.
+ * Enqueued on the context stream; no host synchronization. */
+adr_status adr_vcycle(adr_ctx *ctx, const void *r_c128, void *z_c128);
+
+/* Solve H_2up a = q exp(i w tau) by FGMRES(m) + V-cycle (Sec. 4.2).  q: c128 right-hand
+ * side of the Helmholtz equation (a point source is e_src / h^ndim).  a: c128, in =
+ * initial guess when use_initial_guess != 0 (else ignored and zero is used), out =
+ * amplitude.  Stops when the true relative residual is <= tol or after maxit FGMRES
+ * iterations (ADR_ENOCONV, best iterate written).  Synchronizes the stream.  stats may
+ * be NULL. */
+adr_status adr_solve(adr_ctx *ctx, const void *q_c128, void *a_c128, double tol, int maxit,
+                     int use_initial_guess, adr_stats *stats);
+
+/* u = a exp(-i w tau) (eq. new_u); a, u c128 (may alias).  Enqueued, no sync. */
+adr_status adr_wavefield(adr_ctx *ctx, const void *a_c128, void *u_c128);
+
+/* Copy the fine-level coefficients out (FP64 device arrays of n nodes each):
+ * g (ndim planes, axis k at g + k*n: d tau / d x_k), L (Lap tau), c (c128 reaction
+ * w^2 (kappa^2 - |g|^2) - i w gamma kappa^2).  Any pointer may be NULL. */
+adr_status adr_get_coefficients(adr_ctx *ctx, double *g, double *L, void *c_c128);
+
+/* Multigrid level information (host out-params).  level 0 = finest.  nodes[k] = grid
+ * size along axis k; *stencil_points = stored stencil size (0 for the matrix-free fine
+ * level, 21 in 2D / 81 in 3D on Galerkin levels). */
+adr_status adr_level_info(adr_ctx *ctx, int level, int *nodes, int *stencil_points);
+int adr_num_levels(const adr_ctx *ctx);
+
+/* Copy a Galerkin level's stencil (level >= 1) out as c128: stencil_points planes of
+ * that level's node count, plane p holding the coefficient of neighbour offset
+ * offsets[3p..3p+2] = (dx, dy, dz); offsets is a HOST int array of 3*stencil_points
+ * (may be NULL).  Entries that point outside the grid are zero. */
+adr_status adr_get_level_stencil(adr_ctx *ctx, int level, void *planes_c128, int *offsets);
+
+const char *adr_strerror(adr_status s);
+const char *adr_last_error(const adr_ctx *ctx);   /* NULL ctx: last setup error */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADR_H_ */

@@ -1,0 +1,263 @@
+"""Thin Python binding of libadr (the C ABI in include/adr.h).
+
+Argument marshalling only: every step of the solve runs in the HIP library.  PyTorch
+provides device memory and the stream.  Arrays follow the library layout: C-ordered
+(nz, ny, nx) / (ny, nx) tensors with x fastest; complex data as torch.complex128.
+Source indices are given in the same (NumPy) axis order and reversed for the ABI, whose
+axis 0 is x.
+
+There is no CPU fallback: if libadr.so is missing or fails to load, every call raises.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libadr.so")
+
+ADR_OK, ADR_EINVAL, ADR_ENOMEM, ADR_EHIP, ADR_ENOCONV, ADR_ENUMERIC, ADR_ENOTSUP = range(7)
+ADR_PREC_FP64, ADR_PREC_MIXED = 0, 1
+ADR_RELAX_JACOBI, ADR_RELAX_GMRES = 0, 1
+
+
+class AdrProblem(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int),
+        ("n", ctypes.c_int * 3),
+        ("h", ctypes.c_double),
+        ("omega", ctypes.c_double),
+        ("kappa2", ctypes.c_void_p),
+        ("tau", ctypes.c_void_p),
+        ("gamma", ctypes.c_void_p),
+        ("src", ctypes.c_int * 3),
+    ]
+
+
+class AdrOptions(ctypes.Structure):
+    _fields_ = [
+        ("prec", ctypes.c_int),
+        ("levels", ctypes.c_int),
+        ("coarsest_max", ctypes.c_int),
+        ("nu", ctypes.c_int * 8),
+        ("relax", ctypes.c_int * 8),
+        ("jacobi_weight", ctypes.c_double),
+        ("beta", ctypes.c_double),
+        ("restart", ctypes.c_int),
+        ("use_graph", ctypes.c_int),
+    ]
+
+
+class AdrStats(ctypes.Structure):
+    _fields_ = [
+        ("outer_iters", ctypes.c_int),
+        ("restarts", ctypes.c_int),
+        ("relres", ctypes.c_double),
+        ("setup_ms", ctypes.c_double),
+        ("solve_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class AdrError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libadr.so once; raise if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libadr.so not found at {path}: run __graft_entry__.build() "
+                           "(python -m paper_1712_06091_amd.build)")
+    lib = ctypes.CDLL(path)
+    P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    sig = {
+        "adr_default_options": (None, [ctypes.POINTER(AdrOptions)]),
+        "adr_setup": (I, [ctypes.POINTER(AdrProblem), ctypes.POINTER(AdrOptions), P, ctypes.POINTER(P)]),
+        "adr_destroy": (None, [P]),
+        "adr_apply": (I, [P, D, P, P]),
+        "adr_vcycle": (I, [P, P, P]),
+        "adr_solve": (I, [P, P, P, D, I, I, ctypes.POINTER(AdrStats)]),
+        "adr_wavefield": (I, [P, P, P]),
+        "adr_get_coefficients": (I, [P, P, P, P]),
+        "adr_level_info": (I, [P, I, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+        "adr_num_levels": (I, [P]),
+        "adr_get_level_stencil": (I, [P, I, P, ctypes.POINTER(ctypes.c_int)]),
+        "adr_strerror": (ctypes.c_char_p, [I]),
+        "adr_last_error": (ctypes.c_char_p, [P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def default_options(**kw):
+    lib = load_library()
+    o = AdrOptions()
+    lib.adr_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if k in ("nu", "relax"):
+            arr = getattr(o, k)
+            for i, x in enumerate(v):
+                arr[i] = int(x)
+        elif k == "prec":
+            o.prec = {"fp64": ADR_PREC_FP64, "mixed": ADR_PREC_MIXED}.get(v, v)
+        else:
+            setattr(o, k, v)
+    return o
+
+
+def _check(status, ctx_ptr=None):
+    if status != ADR_OK and status != ADR_ENOCONV:
+        lib = load_library()
+        msg = lib.adr_last_error(ctx_ptr)
+        raise AdrError(status, (msg or b"").decode() or lib.adr_strerror(status).decode())
+    return status
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, dtype):
+    import torch
+    if not t.is_cuda:
+        raise ValueError("tensors must be on the GPU")
+    if t.dtype != dtype:
+        raise ValueError(f"expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("tensors must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """An adr_ctx: coefficients, multigrid hierarchy and solver buffers for one source."""
+
+    def __init__(self, kappa2, tau, gamma, h, omega, src, options=None, stream=None, factored=True):
+        import torch
+        lib = load_library()
+        shape = tuple(tau.shape)
+        d = len(shape)
+        prob = AdrProblem()
+        prob.ndim = d
+        for k in range(3):
+            prob.n[k] = shape[d - 1 - k] if k < d else 1
+        prob.h = float(h)
+        prob.omega = float(omega)
+        prob.kappa2 = _dev(kappa2, torch.float64)
+        prob.tau = _dev(tau, torch.float64)
+        prob.gamma = _dev(gamma, torch.float64) if gamma is not None else None
+        if factored and src is not None:
+            for k in range(3):
+                prob.src[k] = int(src[d - 1 - k]) if k < d else 0
+        else:
+            prob.src[0], prob.src[1], prob.src[2] = -1, 0, 0
+        self.options = options if options is not None else default_options()
+        self.shape = shape
+        self.device = tau.device
+        self._stream = stream
+        ptr = ctypes.c_void_p()
+        status = lib.adr_setup(ctypes.byref(prob), ctypes.byref(self.options), _stream_ptr(stream), ctypes.byref(ptr))
+        if status != ADR_OK:
+            raise AdrError(status, (lib.adr_last_error(None) or b"").decode())
+        self._ptr = ptr
+        self._lib = lib
+
+    def close(self):
+        if getattr(self, "_ptr", None):
+            self._lib.adr_destroy(self._ptr)
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _new(self, dtype):
+        import torch
+        return torch.empty(self.shape, dtype=dtype, device=self.device)
+
+    def apply(self, x, beta=0.0, out=None):
+        import torch
+        y = self._new(torch.complex128) if out is None else out
+        _check(self._lib.adr_apply(self._ptr, float(beta), _dev(x, torch.complex128), _dev(y, torch.complex128)),
+               self._ptr)
+        return y
+
+    def vcycle(self, r, out=None):
+        import torch
+        z = self._new(torch.complex128) if out is None else out
+        _check(self._lib.adr_vcycle(self._ptr, _dev(r, torch.complex128), _dev(z, torch.complex128)), self._ptr)
+        return z
+
+    def solve(self, q, tol=1e-6, maxit=500, x0=None, out=None):
+        """Returns (a, stats dict).  stats['status'] is ADR_OK or ADR_ENOCONV."""
+        import torch
+        a = self._new(torch.complex128) if out is None else out
+        use_guess = 0
+        if x0 is not None:
+            a.copy_(x0)
+            use_guess = 1
+        st = AdrStats()
+        status = _check(self._lib.adr_solve(self._ptr, _dev(q, torch.complex128), _dev(a, torch.complex128),
+                                            float(tol), int(maxit), use_guess, ctypes.byref(st)), self._ptr)
+        d = st.as_dict()
+        d["status"] = status
+        return a, d
+
+    def wavefield(self, a, out=None):
+        import torch
+        u = self._new(torch.complex128) if out is None else out
+        _check(self._lib.adr_wavefield(self._ptr, _dev(a, torch.complex128), _dev(u, torch.complex128)), self._ptr)
+        return u
+
+    def coefficients(self):
+        """(g, L, c): g has one plane per axis in ABI order (axis 0 = x)."""
+        import torch
+        d = len(self.shape)
+        g = torch.empty((d,) + self.shape, dtype=torch.float64, device=self.device)
+        L = self._new(torch.float64)
+        c = self._new(torch.complex128)
+        _check(self._lib.adr_get_coefficients(self._ptr, _dev(g, torch.float64), _dev(L, torch.float64),
+                                              _dev(c, torch.complex128)), self._ptr)
+        return g, L, c
+
+    @property
+    def num_levels(self):
+        return self._lib.adr_num_levels(self._ptr)
+
+    def level_info(self, level):
+        nodes = (ctypes.c_int * 3)()
+        sp = ctypes.c_int()
+        _check(self._lib.adr_level_info(self._ptr, level, nodes, ctypes.byref(sp)), self._ptr)
+        d = len(self.shape)
+        shape = tuple(nodes[d - 1 - k] for k in range(d))
+        return shape, sp.value
+
+    def level_stencil(self, level):
+        """(planes complex128 [S, *shape_l], offsets int list of (dx, dy, dz))."""
+        import torch
+        shape, S = self.level_info(level)
+        planes = torch.empty((S,) + shape, dtype=torch.complex128, device=self.device)
+        offs = (ctypes.c_int * (3 * S))()
+        _check(self._lib.adr_get_level_stencil(self._ptr, level, _dev(planes, torch.complex128), offs), self._ptr)
+        return planes, [tuple(offs[3 * p:3 * p + 3]) for p in range(S)]

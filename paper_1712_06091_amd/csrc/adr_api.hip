@@ -1,0 +1,1014 @@
+// Host driver and C ABI of the ADR amplitude solver (declarations in include/adr.h).
+//
+// Setup builds the ADR coefficients (Sec. 2.1), the Galerkin hierarchy of the
+// preconditioner A_beta = (1-beta) H_2up + beta H_1up (eq. precADRup,
+// eq. coarseGridMatrix) and the dense FP64 inverse of the coarsest operator.  The
+// solve is FGMRES(m) in FP64 (Sec. 4.2) whose preconditioner is one V-cycle
+// (Alg. TwoCycle applied recursively) in FP64 or complex FP32.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/adr.h"
+#include "adr_kernels.hpp"
+
+namespace {
+
+constexpr int kMaxLevels = 8;
+constexpr int kMaxNu = 8;           // GMRES relaxation steps per sweep (dots fused <= 8)
+constexpr int kMaxRestart = 8;
+constexpr int kScalPerLevel = 256;  // device doubles per level for relaxation scalars
+// scalar block layout (doubles)
+constexpr int kH = 0;                               // (kMaxNu+1) x kMaxNu complex, col-major
+constexpr int kLdH = kMaxNu + 1;
+constexpr int kS = kH + 2 * kLdH * kMaxNu;          // kMaxNu+1 scale factors
+constexpr int kBeta = kS + kMaxNu + 1;              // norm of the initial residual
+constexpr int kCoef = kBeta + 1;                    // kMaxNu complex update coefficients
+static_assert(kCoef + 2 * kMaxNu <= kScalPerLevel, "scalar block too small");
+
+std::string g_setup_error;
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+template <typename T>
+struct LevelT {
+  Grid G{};
+  int S = 0;                 // stored stencil size (0 on the matrix-free level 0)
+  cx<T> *planes = nullptr;   // S x N
+  cx<T> *dinv = nullptr;
+  cx<T> *x = nullptr, *xt = nullptr, *b = nullptr, *r = nullptr, *w = nullptr;
+  cx<T> *V = nullptr;        // (kMaxNu+1) x N
+};
+
+}  // namespace
+
+struct adr_ctx {
+  adr_options opt{};
+  hipStream_t stream = nullptr;
+  int D = 3;
+  Grid G0{};
+  double h = 0, omega = 0;
+  int src[3] = {-1, -1, -1};
+  int levels = 1;
+  int nu[kMaxLevels] = {0};
+  adr_relax relax[kMaxLevels];
+
+  // fine coefficients (FP64) + FP32 copies (mixed)
+  double *g64[3] = {nullptr, nullptr, nullptr};
+  double *L64 = nullptr;
+  cx<double> *c64 = nullptr;
+  float *g32[3] = {nullptr, nullptr, nullptr};
+  float *L32 = nullptr;
+  cx<float> *c32 = nullptr;
+  double *tau = nullptr;
+
+  // hierarchy (one of the two, by precision)
+  LevelT<double> lv64[kMaxLevels];
+  LevelT<float> lv32[kMaxLevels];
+  int *off_coarse = nullptr;   // device xyz table of the coarse stencil
+  int *off_fine = nullptr;     // device xyz table of the fine stencil (Galerkin input)
+  std::vector<int> h_off_coarse;
+  int S_coarse = 0;
+  cx<double> *Ainv = nullptr;  // coarsest inverse, column-major
+  int Ncoarsest = 0;
+
+  // scalars and reductions
+  double *scal = nullptr;      // kMaxLevels * kScalPerLevel
+  double *osc = nullptr;       // outer scalars (64 doubles)
+  double *hpin = nullptr;      // pinned host mirror (64 doubles)
+  RedScratch rs{};
+
+  // outer FGMRES buffers
+  cx<double> *Vo = nullptr;    // (kMaxRestart+1) x N
+  void *Zo = nullptr;          // kMaxRestart x N, c64 (mixed) or c128
+  cx<double> *wo = nullptr, *ro = nullptr, *qh = nullptr;
+  cx<float> *b32 = nullptr, *z32 = nullptr;   // mixed-mode V-cycle in/out staging
+  std::string err;
+};
+
+#define ADR_HIP(call)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess) {                                                                  \
+      ctx->err = std::string(#call) + ": " + hipGetErrorString(e_);                         \
+      return ADR_EHIP;                                                                       \
+    }                                                                                        \
+  } while (0)
+
+namespace {
+
+template <typename T>
+adr_status dalloc(adr_ctx *ctx, T **p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return ADR_OK;
+  hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    ctx->err = "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed: " + hipGetErrorString(e);
+    return ADR_ENOMEM;
+  }
+  return ADR_OK;
+}
+#define ADR_TRY(x)                   \
+  do {                               \
+    adr_status s_ = (x);             \
+    if (s_ != ADR_OK) return s_;     \
+  } while (0)
+
+// Stencil offset sets.  Fine: centre, then for each axis -2, -1, +1, +2 (matches
+// fine_row's entry order).  Coarse: every offset with |d_k| <= 2 and at most one
+// |d_k| == 2 (21 points in 2D, 81 in 3D), which the Galerkin product keeps closed.
+std::vector<int> fine_offsets(int D) {
+  std::vector<int> o = {0, 0, 0};
+  for (int k = 0; k < D; ++k)
+    for (int d : {-2, -1, 1, 2}) {
+      int t[3] = {0, 0, 0};
+      t[k] = d;
+      o.insert(o.end(), t, t + 3);
+    }
+  return o;
+}
+std::vector<int> coarse_offsets(int D) {
+  std::vector<int> o;
+  const int zl = D == 3 ? -2 : 0, zh = D == 3 ? 2 : 0;
+  for (int dz = zl; dz <= zh; ++dz)
+    for (int dy = -2; dy <= 2; ++dy)
+      for (int dx = -2; dx <= 2; ++dx) {
+        int twos = (std::abs(dx) == 2) + (std::abs(dy) == 2) + (std::abs(dz) == 2);
+        if (twos <= 1) o.insert(o.end(), {dx, dy, dz});
+      }
+  return o;
+}
+
+// For every output offset t, the list of (p, input offset index d, weight) with
+// P^T support offset p in {-1,0,1}^D and q = p + off_in[d] - 2t in {-1,0,1}^D; the
+// weight is w(p) w(q), w = prod_k (1 - |.|/2).
+struct Triples {
+  std::vector<int> start, p, d;
+  std::vector<double> w;
+};
+Triples galerkin_triples(int D, const std::vector<int> &in, const std::vector<int> &out) {
+  Triples T;
+  const int Sin = (int)in.size() / 3, Sout = (int)out.size() / 3;
+  const int zl = D == 3 ? -1 : 0, zh = D == 3 ? 1 : 0;
+  T.start.push_back(0);
+  for (int t = 0; t < Sout; ++t) {
+    for (int pz = zl; pz <= zh; ++pz)
+      for (int py = -1; py <= 1; ++py)
+        for (int px = -1; px <= 1; ++px)
+          for (int d = 0; d < Sin; ++d) {
+            int p[3] = {px, py, pz};
+            double w = 1.0;
+            bool ok = true;
+            for (int k = 0; k < 3; ++k) {
+              int q = p[k] + in[3 * d + k] - 2 * out[3 * t + k];
+              if (q < -1 || q > 1) { ok = false; break; }
+              w *= (1.0 - 0.5 * std::abs(p[k])) * (1.0 - 0.5 * std::abs(q));
+            }
+            if (!ok) continue;
+            T.p.insert(T.p.end(), p, p + 3);
+            T.d.push_back(d);
+            T.w.push_back(w);
+          }
+    T.start.push_back((int)T.d.size());
+  }
+  return T;
+}
+
+// Dense complex inverse by Gauss-Jordan elimination with partial pivoting (host,
+// FP64; the coarsest grid has at most a few thousand nodes).  A is row-major n x n;
+// on return inv is column-major.
+bool dense_inverse(int n, std::vector<std::complex<double>> &A, std::vector<std::complex<double>> &inv_colmajor) {
+  std::vector<std::complex<double>> I((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) I[(size_t)i * n + i] = 1.0;
+  for (int k = 0; k < n; ++k) {
+    int piv = k;
+    double best = std::abs(A[(size_t)k * n + k]);
+    for (int i = k + 1; i < n; ++i) {
+      double v = std::abs(A[(size_t)i * n + k]);
+      if (v > best) { best = v; piv = i; }
+    }
+    if (best == 0.0) return false;
+    if (piv != k) {
+      for (int j = 0; j < n; ++j) {
+        std::swap(A[(size_t)k * n + j], A[(size_t)piv * n + j]);
+        std::swap(I[(size_t)k * n + j], I[(size_t)piv * n + j]);
+      }
+    }
+    const std::complex<double> inv = 1.0 / A[(size_t)k * n + k];
+    for (int j = 0; j < n; ++j) {
+      A[(size_t)k * n + j] *= inv;
+      I[(size_t)k * n + j] *= inv;
+    }
+    for (int i = 0; i < n; ++i) {
+      if (i == k) continue;
+      const std::complex<double> f = A[(size_t)i * n + k];
+      if (f == 0.0) continue;
+      std::complex<double> *ai = &A[(size_t)i * n], *ak = &A[(size_t)k * n];
+      std::complex<double> *ii = &I[(size_t)i * n], *ik = &I[(size_t)k * n];
+      for (int j = 0; j < n; ++j) {
+        ai[j] -= f * ak[j];
+        ii[j] -= f * ik[j];
+      }
+    }
+  }
+  inv_colmajor.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) inv_colmajor[(size_t)j * n + i] = I[(size_t)i * n + j];
+  return true;
+}
+
+Grid make_grid(int D, const int n[3]) {
+  Grid G;
+  G.n[0] = n[0];
+  G.n[1] = n[1];
+  G.n[2] = D == 3 ? n[2] : 1;
+  G.N = G.n[0] * G.n[1] * G.n[2];
+  return G;
+}
+Grid coarsen(int D, const Grid &G) {
+  int n[3] = {(G.n[0] - 1) / 2 + 1, (G.n[1] - 1) / 2 + 1, D == 3 ? (G.n[2] - 1) / 2 + 1 : 1};
+  return make_grid(D, n);
+}
+
+template <typename T>
+LevelT<T> *levels_of(adr_ctx *ctx);
+template <>
+LevelT<double> *levels_of<double>(adr_ctx *ctx) { return ctx->lv64; }
+template <>
+LevelT<float> *levels_of<float>(adr_ctx *ctx) { return ctx->lv32; }
+
+template <typename T>
+FineCoef<T> fine_coef(adr_ctx *ctx);
+template <>
+FineCoef<double> fine_coef<double>(adr_ctx *ctx) {
+  return FineCoef<double>{{ctx->g64[0], ctx->g64[1], ctx->g64[2]}, ctx->L64, ctx->c64};
+}
+template <>
+FineCoef<float> fine_coef<float>(adr_ctx *ctx) {
+  return FineCoef<float>{{ctx->g32[0], ctx->g32[1], ctx->g32[2]}, ctx->L32, ctx->c32};
+}
+
+FineParams fine_params(adr_ctx *ctx, double beta) {
+  FineParams P;
+  P.h = ctx->h;
+  P.omega = ctx->omega;
+  P.beta = beta;
+  for (int k = 0; k < 3; ++k) P.src[k] = ctx->src[k];
+  return P;
+}
+
+template <typename T>
+Stencil<T> stencil_of(adr_ctx *ctx, const LevelT<T> &L) {
+  Stencil<T> s;
+  s.planes = L.planes;
+  s.S = L.S;
+  s.centre = (L.S - 1) / 2;
+  s.off_lin = nullptr;
+  s.off_xyz = ctx->off_coarse;
+  return s;
+}
+
+double *lscal(adr_ctx *ctx, int l) { return ctx->scal + (size_t)l * kScalPerLevel; }
+
+// Allocate the per-level vectors and convert/store the stencil in precision T.
+template <typename T>
+adr_status alloc_level_vectors(adr_ctx *ctx, LevelT<T> &L, int l) {
+  const size_t N = L.G.N;
+  ADR_TRY(dalloc(ctx, &L.x, N));
+  ADR_TRY(dalloc(ctx, &L.xt, N));
+  ADR_TRY(dalloc(ctx, &L.b, N));
+  ADR_TRY(dalloc(ctx, &L.r, N));
+  if (l > 0) {
+    ADR_TRY(dalloc(ctx, &L.w, N));
+    ADR_TRY(dalloc(ctx, &L.V, N * (kMaxNu + 1)));
+  }
+  return ADR_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// Relaxation, V-cycle
+// ------------------------------------------------------------------------------------
+template <typename T>
+VecSet<T> vecset(std::initializer_list<const cx<T> *> v) {
+  VecSet<T> s{};
+  s.count = 0;
+  for (auto p : v) s.v[s.count++] = p;
+  return s;
+}
+
+// GMRES relaxation on level l >= 1: x_out = x0 + D^{-1} V y (Sec. 4.2).
+template <typename T>
+void gmres_relax(adr_ctx *ctx, int l, const cx<T> *x0, const cx<T> *b, cx<T> *x_out) {
+  LevelT<T> &L = levels_of<T>(ctx)[l];
+  hipStream_t s = ctx->stream;
+  const int N = L.G.N, nu = ctx->nu[l];
+  double *sc = lscal(ctx, l);
+  Stencil<T> A = stencil_of(ctx, L);
+  const cx<T> *Vp[kMaxNu + 1];
+  for (int j = 0; j <= nu; ++j) Vp[j] = L.V + (size_t)j * N;
+  if (!x0) {
+    Vp[0] = b;
+    adrk::norm_inv<T>(s, N, b, sc + kBeta, sc + kS, ctx->rs);
+  } else {
+    // V0 = b - A x0, then its norm.
+    adrk::coarse_apply<T>(s, L.G, ctx->D, A, x0, nullptr, nullptr, b, L.V, 1, nullptr, false, nullptr, ctx->rs);
+    adrk::norm_inv<T>(s, N, L.V, sc + kBeta, sc + kS, ctx->rs);
+  }
+  for (int j = 0; j < nu; ++j) {
+    VecSet<T> Vs{};
+    Vs.count = j + 1;
+    for (int i = 0; i <= j; ++i) {
+      Vs.v[i] = Vp[i];
+      Vs.scale[i] = sc + kS + i;
+    }
+    double *hcol = sc + kH + 2 * (j * kLdH);
+    adrk::coarse_apply<T>(s, L.G, ctx->D, A, Vp[j], sc + kS + j, L.dinv, nullptr, L.w, 0, &Vs, false, hcol,
+                          ctx->rs);
+    adrk::orth_step<T>(s, N, L.w, Vs, hcol, L.V + (size_t)(j + 1) * N, hcol + 2 * (j + 1), sc + kS + j + 1,
+                       ctx->rs);
+  }
+  adrk::gmres_lsq(s, sc + kH, kLdH, nu, sc + kBeta, sc + kS, sc + kCoef);
+  VecSet<T> Vs{};
+  Vs.count = nu;
+  for (int i = 0; i < nu; ++i) Vs.v[i] = Vp[i];
+  adrk::gmres_update<T>(s, N, x0, L.dinv, Vs, sc + kCoef, x_out);
+}
+
+// Jacobi sweeps on the matrix-free level 0: sweep k writes `first` for even k and
+// `second` for odd k, reading the previous result (x_start for k = 0, NULL = zero).
+// Returns the buffer written last.
+template <typename T>
+cx<T> *jacobi_sweeps(adr_ctx *ctx, int nu, const cx<T> *x_start, const cx<T> *b, cx<T> *first, cx<T> *second) {
+  const Grid &G = levels_of<T>(ctx)[0].G;
+  FineCoef<T> C = fine_coef<T>(ctx);
+  FineParams P = fine_params(ctx, ctx->opt.beta);
+  const cx<T> *in = x_start;
+  cx<T> *out = first;
+  for (int k = 0; k < nu; ++k) {
+    out = (k % 2 == 0) ? first : second;
+    adrk::fine_jacobi<T>(ctx->stream, G, ctx->D, C, P, in, b, out, ctx->opt.jacobi_weight);
+    in = out;
+  }
+  return out;
+}
+
+// One V-cycle on level l from a zero guess; b is the level right-hand side.  Returns
+// the buffer holding x_l.  On level 0 `out0` is the preferred output buffer.
+template <typename T>
+cx<T> *vcycle(adr_ctx *ctx, int l, const cx<T> *b, cx<T> *out0) {
+  LevelT<T> *lv = levels_of<T>(ctx);
+  LevelT<T> &L = lv[l];
+  hipStream_t s = ctx->stream;
+  const int D = ctx->D;
+  if (l == ctx->levels - 1) {
+    cx<T> *x = (l == 0 && out0) ? out0 : L.x;
+    adrk::dense_gemv<T>(s, L.G.N, ctx->Ainv, b, x);
+    return x;
+  }
+  cx<T> *xa = (l == 0 && out0) ? out0 : L.x;
+  cx<T> *x;
+  // pre-relaxation (Jacobi: the first sweep writes the scratch buffer, so that the
+  // post-relaxation, which alternates from the pre-relaxed iterate, ends in xa)
+  if (ctx->relax[l] == ADR_RELAX_JACOBI && l == 0) {
+    x = jacobi_sweeps<T>(ctx, ctx->nu[l], nullptr, b, L.xt, xa);
+  } else {
+    gmres_relax<T>(ctx, l, nullptr, b, xa);
+    x = xa;
+  }
+  // residual and restriction
+  LevelT<T> &C = lv[l + 1];
+  if (l == 0) {
+    adrk::fine_apply<T, T, T>(s, L.G, D, fine_coef<T>(ctx), fine_params(ctx, ctx->opt.beta), x, b, L.r, 1, nullptr,
+                              false, nullptr, ctx->rs);
+  } else {
+    adrk::coarse_apply<T>(s, L.G, D, stencil_of(ctx, L), x, nullptr, nullptr, b, L.r, 1, nullptr, false, nullptr,
+                          ctx->rs);
+  }
+  adrk::restrict_full<T>(s, L.G, C.G, D, L.r, C.b);
+  cx<T> *ec = vcycle<T>(ctx, l + 1, C.b, nullptr);
+  adrk::prolong_add<T>(s, L.G, C.G, D, ec, x);
+  // post-relaxation
+  if (ctx->relax[l] == ADR_RELAX_JACOBI && l == 0) {
+    cx<T> *other = (x == xa) ? L.xt : xa;
+    return jacobi_sweeps<T>(ctx, ctx->nu[l], x, b, other, x);
+  }
+  gmres_relax<T>(ctx, l, x, b, x);
+  return x;
+}
+
+adr_status check_levels(adr_ctx *ctx) {
+  for (int l = 1; l < ctx->levels; ++l)
+    if (ctx->relax[l] == ADR_RELAX_JACOBI) {
+      ctx->err = "Jacobi relaxation is implemented on the finest level only";
+      return ADR_ENOTSUP;
+    }
+  for (int l = 0; l < ctx->levels - 1; ++l)
+    if (ctx->nu[l] < 1 || ctx->nu[l] > kMaxNu) {
+      ctx->err = "nu must be in [1, 8]";
+      return ADR_EINVAL;
+    }
+  if (ctx->levels > 1 && ctx->relax[0] == ADR_RELAX_GMRES) {
+    ctx->err = "GMRES relaxation on the matrix-free finest level is not implemented";
+    return ADR_ENOTSUP;
+  }
+  return ADR_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// Setup
+// ------------------------------------------------------------------------------------
+adr_status validate(const adr_problem *p, const adr_options *o, std::string &err) {
+  if (!p || !o) { err = "null problem or options"; return ADR_EINVAL; }
+  if (p->ndim != 2 && p->ndim != 3) { err = "ndim must be 2 or 3"; return ADR_EINVAL; }
+  for (int k = 0; k < p->ndim; ++k)
+    if (p->n[k] < 5) { err = "every n[k] must be >= 5"; return ADR_EINVAL; }
+  long long N = 1;
+  for (int k = 0; k < p->ndim; ++k) N *= p->n[k];
+  if (N > (1LL << 30)) { err = "grid too large (more than 2^30 nodes)"; return ADR_EINVAL; }
+  if (!(p->h > 0) || !(p->omega > 0)) { err = "h and omega must be > 0"; return ADR_EINVAL; }
+  if (!p->kappa2 || !p->tau) { err = "kappa2 and tau are required"; return ADR_EINVAL; }
+  if (p->src[0] >= 0) {
+    for (int k = 0; k < p->ndim; ++k)
+      if (p->src[k] < 2 || p->src[k] > p->n[k] - 3) {
+        err = "source must be at least 2 nodes from every face";
+        return ADR_EINVAL;
+      }
+  }
+  if (o->restart < 1 || o->restart > kMaxRestart) { err = "restart must be in [1, 8]"; return ADR_EINVAL; }
+  if (o->levels < 0 || o->levels > kMaxLevels) { err = "levels must be in [0, 8]"; return ADR_EINVAL; }
+  if (o->prec != ADR_PREC_FP64 && o->prec != ADR_PREC_MIXED) { err = "bad precision"; return ADR_EINVAL; }
+  if (!(o->beta >= 0.0 && o->beta <= 1.0)) { err = "beta must be in [0, 1]"; return ADR_EINVAL; }
+  return ADR_OK;
+}
+
+int auto_levels(int D, const int n[3], int coarsest_max) {
+  int m[3] = {n[0], n[1], D == 3 ? n[2] : 1};
+  int levels = 1;
+  while (levels < kMaxLevels) {
+    long long N = (long long)m[0] * m[1] * m[2];
+    if (N <= coarsest_max) break;
+    bool ok = true;
+    for (int k = 0; k < D; ++k) ok &= ((m[k] - 1) % 2 == 0) && ((m[k] - 1) / 2 + 1 >= 5);
+    if (!ok) break;
+    for (int k = 0; k < D; ++k) m[k] = (m[k] - 1) / 2 + 1;
+    ++levels;
+  }
+  return levels;
+}
+
+template <typename T>
+adr_status build_hierarchy(adr_ctx *ctx) {
+  hipStream_t s = ctx->stream;
+  const int D = ctx->D;
+  LevelT<T> *lv = levels_of<T>(ctx);
+  lv[0].G = ctx->G0;
+  lv[0].S = 0;
+  for (int l = 1; l < ctx->levels; ++l) {
+    lv[l].G = coarsen(D, lv[l - 1].G);
+    for (int k = 0; k < D; ++k)
+      if ((lv[l - 1].G.n[k] - 1) % 2) {
+        ctx->err = "n-1 must be divisible by 2^(levels-1)";
+        return ADR_EINVAL;
+      }
+  }
+  // Offset tables and Galerkin triples.
+  std::vector<int> fo = fine_offsets(D), co = coarse_offsets(D);
+  ctx->h_off_coarse = co;
+  ctx->S_coarse = (int)co.size() / 3;
+  ADR_TRY(dalloc(ctx, &ctx->off_fine, fo.size()));
+  ADR_TRY(dalloc(ctx, &ctx->off_coarse, co.size()));
+  ADR_HIP(hipMemcpy(ctx->off_fine, fo.data(), fo.size() * sizeof(int), hipMemcpyHostToDevice));
+  ADR_HIP(hipMemcpy(ctx->off_coarse, co.data(), co.size() * sizeof(int), hipMemcpyHostToDevice));
+  Triples tf = galerkin_triples(D, fo, co), tc = galerkin_triples(D, co, co);
+  int *tri_start[2], *tri_p[2], *tri_d[2];
+  double *tri_w[2];
+  Triples *tt[2] = {&tf, &tc};
+  for (int i = 0; i < 2; ++i) {
+    ADR_TRY(dalloc(ctx, &tri_start[i], tt[i]->start.size()));
+    ADR_TRY(dalloc(ctx, &tri_p[i], tt[i]->p.size()));
+    ADR_TRY(dalloc(ctx, &tri_d[i], tt[i]->d.size()));
+    ADR_TRY(dalloc(ctx, &tri_w[i], tt[i]->w.size()));
+    ADR_HIP(hipMemcpy(tri_start[i], tt[i]->start.data(), tt[i]->start.size() * sizeof(int), hipMemcpyHostToDevice));
+    ADR_HIP(hipMemcpy(tri_p[i], tt[i]->p.data(), tt[i]->p.size() * sizeof(int), hipMemcpyHostToDevice));
+    ADR_HIP(hipMemcpy(tri_d[i], tt[i]->d.data(), tt[i]->d.size() * sizeof(int), hipMemcpyHostToDevice));
+    ADR_HIP(hipMemcpy(tri_w[i], tt[i]->w.data(), tt[i]->w.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  const int Sf = (int)fo.size() / 3, Sc = ctx->S_coarse;
+  // FP64 planes: fine stencil of A_beta, then each Galerkin level.
+  cx<double> *prev = nullptr;
+  adr_status st = ADR_OK;
+  if (ctx->levels > 1) {
+    st = dalloc(ctx, &prev, (size_t)Sf * ctx->G0.N);
+    if (st == ADR_OK) {
+      FineCoef<double> C = fine_coef<double>(ctx);
+      adrk::fine_stencil(s, ctx->G0, D, C, fine_params(ctx, ctx->opt.beta), prev);
+    }
+  }
+  for (int l = 1; l < ctx->levels && st == ADR_OK; ++l) {
+    cx<double> *cur = nullptr;
+    st = dalloc(ctx, &cur, (size_t)Sc * lv[l].G.N);
+    if (st != ADR_OK) break;
+    const int which = (l == 1) ? 0 : 1;
+    adrk::galerkin(s, lv[l - 1].G, lv[l].G, prev, l == 1 ? ctx->off_fine : ctx->off_coarse, l == 1 ? Sf : Sc, cur,
+                   ctx->off_coarse, Sc, tri_start[which], tri_p[which], tri_d[which], tri_w[which]);
+    // The FP64 planes are the level stencil in FP64 mode; mixed mode keeps an FP32 copy
+    // and frees the FP64 planes once the next level is built from them.
+    lv[l].S = Sc;
+    if (l == 1 || ctx->opt.prec != ADR_PREC_FP64) hipFree(prev);
+    prev = cur;
+    if (ctx->opt.prec == ADR_PREC_FP64) {
+      lv[l].planes = (cx<T> *)cur;
+    } else {
+      cx<float> *p32 = nullptr;
+      st = dalloc(ctx, &p32, (size_t)Sc * lv[l].G.N);
+      if (st != ADR_OK) break;
+      adrk::convert<float, double>(s, (long long)Sc * lv[l].G.N, cur, p32);
+      lv[l].planes = (cx<T> *)p32;
+    }
+    st = dalloc(ctx, &lv[l].dinv, lv[l].G.N);
+    if (st != ADR_OK) break;
+    const int centre = (Sc - 1) / 2;
+    adrk::stencil_diag_inv<T>(s, lv[l].G.N, lv[l].planes + (size_t)centre * lv[l].G.N, lv[l].dinv);
+  }
+  for (int i = 0; i < 2; ++i) {
+    hipFree(tri_start[i]);
+    hipFree(tri_p[i]);
+    hipFree(tri_d[i]);
+    hipFree(tri_w[i]);
+  }
+  if (st != ADR_OK) {
+    // In FP64 mode `prev` is owned by a level (or is the fine temporary on level 1).
+    if (ctx->opt.prec != ADR_PREC_FP64 || (prev && lv[1].planes != (cx<T> *)prev)) hipFree(prev);
+    return st;
+  }
+  // Coarsest: dense FP64 inverse.
+  const int Lc = ctx->levels - 1;
+  const Grid &Gc = lv[Lc].G;
+  const int n = Gc.N;
+  ctx->Ncoarsest = n;
+  std::vector<std::complex<double>> A((size_t)n * n, 0.0), inv;
+  if (Lc == 0) {
+    // Single level: materialize the fine stencil of A_beta directly.
+    cx<double> *tmp = nullptr;
+    ADR_TRY(dalloc(ctx, &tmp, (size_t)Sf * n));
+    adrk::fine_stencil(s, ctx->G0, D, fine_coef<double>(ctx), fine_params(ctx, ctx->opt.beta), tmp);
+    std::vector<cx<double>> hp((size_t)Sf * n);
+    ADR_HIP(hipMemcpyAsync(hp.data(), tmp, hp.size() * sizeof(cx<double>), hipMemcpyDeviceToHost, s));
+    ADR_HIP(hipStreamSynchronize(s));
+    hipFree(tmp);
+    for (int i = 0; i < n; ++i) {
+      int ix = i % Gc.n[0], iy = (i / Gc.n[0]) % Gc.n[1], iz = i / (Gc.n[0] * Gc.n[1]);
+      for (int p = 0; p < Sf; ++p) {
+        int jx = ix + fo[3 * p], jy = iy + fo[3 * p + 1], jz = iz + fo[3 * p + 2];
+        if (jx < 0 || jx >= Gc.n[0] || jy < 0 || jy >= Gc.n[1] || jz < 0 || jz >= Gc.n[2]) continue;
+        int j = jx + Gc.n[0] * (jy + Gc.n[1] * jz);
+        A[(size_t)i * n + j] += std::complex<double>(hp[(size_t)p * n + i].re, hp[(size_t)p * n + i].im);
+      }
+    }
+  } else {
+    std::vector<cx<double>> hp((size_t)Sc * n);
+    ADR_HIP(hipMemcpyAsync(hp.data(), prev, hp.size() * sizeof(cx<double>), hipMemcpyDeviceToHost, s));
+    ADR_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < n; ++i) {
+      int ix = i % Gc.n[0], iy = (i / Gc.n[0]) % Gc.n[1], iz = i / (Gc.n[0] * Gc.n[1]);
+      for (int p = 0; p < Sc; ++p) {
+        int jx = ix + co[3 * p], jy = iy + co[3 * p + 1], jz = iz + co[3 * p + 2];
+        if (jx < 0 || jx >= Gc.n[0] || jy < 0 || jy >= Gc.n[1] || jz < 0 || jz >= Gc.n[2]) continue;
+        int j = jx + Gc.n[0] * (jy + Gc.n[1] * jz);
+        A[(size_t)i * n + j] = std::complex<double>(hp[(size_t)p * n + i].re, hp[(size_t)p * n + i].im);
+      }
+    }
+    if (ctx->opt.prec != ADR_PREC_FP64) hipFree(prev);
+  }
+  if (!dense_inverse(n, A, inv)) {
+    ctx->err = "coarsest operator is singular";
+    return ADR_ENUMERIC;
+  }
+  ADR_TRY(dalloc(ctx, &ctx->Ainv, (size_t)n * n));
+  ADR_HIP(hipMemcpy(ctx->Ainv, inv.data(), inv.size() * sizeof(cx<double>), hipMemcpyHostToDevice));
+  for (int l = 0; l < ctx->levels; ++l) ADR_TRY(alloc_level_vectors<T>(ctx, lv[l], l));
+  return ADR_OK;
+}
+
+void free_ctx(adr_ctx *ctx) {
+  if (!ctx) return;
+  auto F = [](void *p) {
+    if (p) hipFree(p);
+  };
+  for (int k = 0; k < 3; ++k) {
+    F(ctx->g64[k]);
+    F(ctx->g32[k]);
+  }
+  F(ctx->L64);
+  F(ctx->L32);
+  F(ctx->c64);
+  F(ctx->c32);
+  F(ctx->tau);
+  for (int l = 0; l < kMaxLevels; ++l) {
+    LevelT<double> &a = ctx->lv64[l];
+    LevelT<float> &b = ctx->lv32[l];
+    for (void *p : {(void *)a.planes, (void *)a.dinv, (void *)a.x, (void *)a.xt, (void *)a.b, (void *)a.r,
+                    (void *)a.w, (void *)a.V, (void *)b.planes, (void *)b.dinv, (void *)b.x, (void *)b.xt,
+                    (void *)b.b, (void *)b.r, (void *)b.w, (void *)b.V})
+      F(p);
+  }
+  F(ctx->off_coarse);
+  F(ctx->off_fine);
+  F(ctx->Ainv);
+  F(ctx->scal);
+  F(ctx->osc);
+  if (ctx->hpin) hipHostFree(ctx->hpin);
+  F(ctx->rs.partials);
+  F(ctx->rs.counter);
+  F(ctx->Vo);
+  F(ctx->Zo);
+  F(ctx->wo);
+  F(ctx->ro);
+  F(ctx->qh);
+  F(ctx->b32);
+  F(ctx->z32);
+  delete ctx;
+}
+
+adr_status setup_impl(adr_ctx *ctx, const adr_problem *p) {
+  hipStream_t s = ctx->stream;
+  const int D = ctx->D;
+  const int N = ctx->G0.N;
+  for (int k = 0; k < D; ++k) ADR_TRY(dalloc(ctx, &ctx->g64[k], N));
+  ADR_TRY(dalloc(ctx, &ctx->L64, N));
+  ADR_TRY(dalloc(ctx, &ctx->c64, N));
+  ADR_TRY(dalloc(ctx, &ctx->tau, N));
+  ADR_HIP(hipMemcpyAsync(ctx->tau, p->tau, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+  adrk::coefficients(s, ctx->G0, D, ctx->h, ctx->omega, ctx->src, p->kappa2, p->tau, p->gamma, ctx->g64[0],
+                     ctx->g64[1], D == 3 ? ctx->g64[2] : nullptr, ctx->L64, ctx->c64);
+  ADR_HIP(hipGetLastError());
+  // Reduction scratch and scalars.
+  ADR_TRY(dalloc(ctx, &ctx->rs.partials, (size_t)ADR_MAX_BLOCKS * ADR_MAX_RED));
+  ADR_TRY(dalloc(ctx, &ctx->rs.counter, 1));
+  ADR_HIP(hipMemsetAsync(ctx->rs.counter, 0, sizeof(unsigned int), s));
+  ADR_TRY(dalloc(ctx, &ctx->scal, (size_t)kMaxLevels * kScalPerLevel));
+  ADR_HIP(hipMemsetAsync(ctx->scal, 0, sizeof(double) * kMaxLevels * kScalPerLevel, s));
+  ADR_TRY(dalloc(ctx, &ctx->osc, 64));
+  ADR_HIP(hipMemsetAsync(ctx->osc, 0, sizeof(double) * 64, s));
+  ADR_HIP(hipHostMalloc((void **)&ctx->hpin, 64 * sizeof(double), hipHostMallocDefault));
+  if (ctx->opt.prec == ADR_PREC_MIXED) {
+    for (int k = 0; k < D; ++k) {
+      ADR_TRY(dalloc(ctx, &ctx->g32[k], N));
+      adrk::convert_real<float, double>(s, N, ctx->g64[k], ctx->g32[k]);
+    }
+    ADR_TRY(dalloc(ctx, &ctx->L32, N));
+    adrk::convert_real<float, double>(s, N, ctx->L64, ctx->L32);
+    ADR_TRY(dalloc(ctx, &ctx->c32, N));
+    adrk::convert<float, double>(s, N, ctx->c64, ctx->c32);
+    ADR_TRY(build_hierarchy<float>(ctx));
+    ADR_TRY(dalloc(ctx, &ctx->b32, N));
+    ADR_TRY(dalloc(ctx, &ctx->z32, N));
+  } else {
+    ADR_TRY(build_hierarchy<double>(ctx));
+  }
+  // Outer FGMRES buffers.
+  const int m = ctx->opt.restart;
+  ADR_TRY(dalloc(ctx, &ctx->Vo, (size_t)(m + 1) * N));
+  if (ctx->opt.prec == ADR_PREC_MIXED) {
+    cx<float> *z = nullptr;
+    ADR_TRY(dalloc(ctx, &z, (size_t)m * N));
+    ctx->Zo = z;
+  } else {
+    cx<double> *z = nullptr;
+    ADR_TRY(dalloc(ctx, &z, (size_t)m * N));
+    ctx->Zo = z;
+  }
+  ADR_TRY(dalloc(ctx, &ctx->wo, N));
+  ADR_TRY(dalloc(ctx, &ctx->ro, N));
+  ADR_TRY(dalloc(ctx, &ctx->qh, N));
+  ADR_HIP(hipGetLastError());
+  ADR_HIP(hipStreamSynchronize(s));
+  return ADR_OK;
+}
+
+// Preconditioner application into the mixed / FP64 Z slot.
+adr_status precondition(adr_ctx *ctx, const cx<double> *v, void *z) {
+  hipStream_t s = ctx->stream;
+  const int N = ctx->G0.N;
+  if (ctx->opt.prec == ADR_PREC_MIXED) {
+    adrk::convert<float, double>(s, N, v, ctx->b32);
+    vcycle<float>(ctx, 0, ctx->b32, (cx<float> *)z);
+  } else {
+    vcycle<double>(ctx, 0, v, (cx<double> *)z);
+  }
+  return ADR_OK;
+}
+
+}  // namespace
+
+// ======================================================================================
+// C ABI
+// ======================================================================================
+extern "C" {
+
+void adr_default_options(adr_options *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->prec = ADR_PREC_MIXED;
+  o->levels = 0;
+  o->coarsest_max = 729;
+  for (int l = 0; l < 8; ++l) {
+    o->nu[l] = l + 2;
+    o->relax[l] = l == 0 ? ADR_RELAX_JACOBI : ADR_RELAX_GMRES;
+  }
+  o->jacobi_weight = 0.8;
+  o->beta = 0.25;
+  o->restart = 5;
+  o->use_graph = 1;
+}
+
+adr_status adr_setup(const adr_problem *prob, const adr_options *opt, void *stream, adr_ctx **out) {
+  if (!out) {
+    g_setup_error = "null output pointer";
+    return ADR_EINVAL;
+  }
+  *out = nullptr;
+  adr_options defaults;
+  adr_default_options(&defaults);
+  const adr_options *o = opt ? opt : &defaults;
+  std::string err;
+  adr_status st = validate(prob, o, err);
+  if (st != ADR_OK) {
+    g_setup_error = err;
+    return st;
+  }
+  const double t0 = now_ms();
+  adr_ctx *ctx = new adr_ctx();
+  ctx->opt = *o;
+  ctx->stream = (hipStream_t)stream;
+  ctx->D = prob->ndim;
+  ctx->G0 = make_grid(ctx->D, prob->n);
+  ctx->h = prob->h;
+  ctx->omega = prob->omega;
+  for (int k = 0; k < 3; ++k) ctx->src[k] = (prob->src[0] >= 0 && k < ctx->D) ? prob->src[k] : 0;
+  if (prob->src[0] < 0) ctx->src[0] = -1;
+  ctx->levels = o->levels > 0 ? o->levels : auto_levels(ctx->D, prob->n, o->coarsest_max > 0 ? o->coarsest_max : 729);
+  for (int l = 0; l < kMaxLevels; ++l) {
+    ctx->nu[l] = o->nu[l];
+    ctx->relax[l] = o->relax[l];
+  }
+  st = check_levels(ctx);
+  if (st == ADR_OK) st = setup_impl(ctx, prob);
+  if (st != ADR_OK) {
+    g_setup_error = ctx->err;
+    free_ctx(ctx);
+    return st;
+  }
+  (void)t0;
+  *out = ctx;
+  return ADR_OK;
+}
+
+void adr_destroy(adr_ctx *ctx) {
+  if (!ctx) return;
+  hipStreamSynchronize(ctx->stream);
+  free_ctx(ctx);
+}
+
+int adr_num_levels(const adr_ctx *ctx) { return ctx ? ctx->levels : 0; }
+
+adr_status adr_level_info(adr_ctx *ctx, int level, int *nodes, int *stencil_points) {
+  if (!ctx || level < 0 || level >= ctx->levels) return ADR_EINVAL;
+  const Grid &G = ctx->opt.prec == ADR_PREC_MIXED ? ctx->lv32[level].G : ctx->lv64[level].G;
+  if (nodes)
+    for (int k = 0; k < 3; ++k) nodes[k] = G.n[k];
+  if (stencil_points) *stencil_points = level == 0 ? 0 : ctx->S_coarse;
+  return ADR_OK;
+}
+
+adr_status adr_get_level_stencil(adr_ctx *ctx, int level, void *planes_c128, int *offsets) {
+  if (!ctx || level < 1 || level >= ctx->levels) return ADR_EINVAL;
+  if (offsets) std::memcpy(offsets, ctx->h_off_coarse.data(), ctx->h_off_coarse.size() * sizeof(int));
+  if (!planes_c128) return ADR_OK;
+  hipStream_t s = ctx->stream;
+  if (ctx->opt.prec == ADR_PREC_MIXED) {
+    const LevelT<float> &L = ctx->lv32[level];
+    adrk::convert<double, float>(s, (long long)L.S * L.G.N, L.planes, (cx<double> *)planes_c128);
+  } else {
+    const LevelT<double> &L = ctx->lv64[level];
+    ADR_HIP(hipMemcpyAsync(planes_c128, L.planes, sizeof(cx<double>) * L.S * L.G.N, hipMemcpyDeviceToDevice, s));
+  }
+  ADR_HIP(hipGetLastError());
+  return ADR_OK;
+}
+
+adr_status adr_get_coefficients(adr_ctx *ctx, double *g, double *L, void *c_c128) {
+  if (!ctx) return ADR_EINVAL;
+  hipStream_t s = ctx->stream;
+  const int N = ctx->G0.N;
+  if (g)
+    for (int k = 0; k < ctx->D; ++k)
+      ADR_HIP(hipMemcpyAsync(g + (size_t)k * N, ctx->g64[k], sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+  if (L) ADR_HIP(hipMemcpyAsync(L, ctx->L64, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+  if (c_c128) ADR_HIP(hipMemcpyAsync(c_c128, ctx->c64, sizeof(cx<double>) * N, hipMemcpyDeviceToDevice, s));
+  return ADR_OK;
+}
+
+adr_status adr_apply(adr_ctx *ctx, double beta, const void *x, void *y) {
+  if (!ctx || !x || !y || x == y) return ADR_EINVAL;
+  adrk::fine_apply<double, double, double>(ctx->stream, ctx->G0, ctx->D, fine_coef<double>(ctx),
+                                           fine_params(ctx, beta), (const cx<double> *)x, nullptr, (cx<double> *)y,
+                                           0, nullptr, false, nullptr, ctx->rs);
+  ADR_HIP(hipGetLastError());
+  return ADR_OK;
+}
+
+adr_status adr_vcycle(adr_ctx *ctx, const void *r, void *z) {
+  if (!ctx || !r || !z || r == z) return ADR_EINVAL;
+  hipStream_t s = ctx->stream;
+  const int N = ctx->G0.N;
+  if (ctx->opt.prec == ADR_PREC_MIXED) {
+    adrk::convert<float, double>(s, N, (const cx<double> *)r, ctx->b32);
+    vcycle<float>(ctx, 0, ctx->b32, ctx->z32);
+    adrk::convert<double, float>(s, N, ctx->z32, (cx<double> *)z);
+  } else {
+    vcycle<double>(ctx, 0, (const cx<double> *)r, (cx<double> *)z);
+  }
+  ADR_HIP(hipGetLastError());
+  return ADR_OK;
+}
+
+adr_status adr_wavefield(adr_ctx *ctx, const void *a, void *u) {
+  if (!ctx || !a || !u) return ADR_EINVAL;
+  adrk::phase(ctx->stream, ctx->G0.N, (const cx<double> *)a, ctx->tau, ctx->omega, -1, (cx<double> *)u);
+  ADR_HIP(hipGetLastError());
+  return ADR_OK;
+}
+
+adr_status adr_solve(adr_ctx *ctx, const void *q, void *a_out, double tol, int maxit, int use_initial_guess,
+                     adr_stats *stats) {
+  if (!ctx || !q || !a_out || maxit < 0 || !(tol >= 0)) return ADR_EINVAL;
+  const double t0 = now_ms();
+  hipStream_t s = ctx->stream;
+  const int N = ctx->G0.N, m = ctx->opt.restart, D = ctx->D;
+  cx<double> *x = (cx<double> *)a_out;
+  FineCoef<double> C = fine_coef<double>(ctx);
+  FineParams P0 = fine_params(ctx, 0.0);
+  double *osc = ctx->osc, *hp = ctx->hpin;
+  const bool mixed = ctx->opt.prec == ADR_PREC_MIXED;
+  auto Zp = [&](int j) -> void * {
+    return mixed ? (void *)((cx<float> *)ctx->Zo + (size_t)j * N) : (void *)((cx<double> *)ctx->Zo + (size_t)j * N);
+  };
+  auto Vp = [&](int j) { return ctx->Vo + (size_t)j * N; };
+
+  // q_hat = q exp(i w tau)
+  adrk::phase(s, N, (const cx<double> *)q, ctx->tau, ctx->omega, +1, ctx->qh);
+  adrk::norm_inv<double>(s, N, ctx->qh, osc + 0, nullptr, ctx->rs);
+  // initial residual
+  if (use_initial_guess) {
+    adrk::fine_apply<double, double, double>(s, ctx->G0, D, C, P0, x, ctx->qh, ctx->ro, 1, nullptr, true, osc + 1,
+                                             ctx->rs);
+  } else {
+    ADR_HIP(hipMemsetAsync(x, 0, sizeof(cx<double>) * N, s));
+    ADR_HIP(hipMemcpyAsync(ctx->ro, ctx->qh, sizeof(cx<double>) * N, hipMemcpyDeviceToDevice, s));
+    ADR_HIP(hipMemcpyAsync(osc + 1, osc + 0, sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  ADR_HIP(hipMemcpyAsync(hp, osc, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  ADR_HIP(hipStreamSynchronize(s));
+  const double bnorm = hp[0];
+  double rnorm = hp[1];
+  adr_stats st{};
+  if (bnorm == 0.0) {
+    ADR_HIP(hipMemsetAsync(x, 0, sizeof(cx<double>) * N, s));
+    ADR_HIP(hipStreamSynchronize(s));
+    if (stats) *stats = st;
+    return ADR_OK;
+  }
+  double relres = rnorm / bnorm;
+  int iters = 0, restarts = 0;
+  adr_status result = ADR_OK;
+  while (relres > tol && iters < maxit) {
+    if (!std::isfinite(relres)) { result = ADR_ENUMERIC; break; }
+    // V0 = r / ||r||
+    adrk::scale_by_inv(s, N, ctx->ro, osc + 1, Vp(0));
+    std::complex<double> Hh[kMaxRestart + 1][kMaxRestart], g[kMaxRestart + 1];
+    double cs[kMaxRestart];
+    std::complex<double> sn[kMaxRestart];
+    for (int i = 0; i <= m; ++i) g[i] = 0.0;
+    g[0] = rnorm;
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      precondition(ctx, Vp(j), Zp(j));
+      VecSet<double> Vs{};
+      Vs.count = j + 1;
+      for (int i = 0; i <= j; ++i) Vs.v[i] = Vp(i);
+      double *red1 = osc + 2, *red2 = osc + 2 + 2 * (kMaxRestart + 1);
+      if (mixed)
+        adrk::fine_apply<double, float, double>(s, ctx->G0, D, C, P0, (const cx<float> *)Zp(j), nullptr, ctx->wo, 0,
+                                                &Vs, false, red1, ctx->rs);
+      else
+        adrk::fine_apply<double, double, double>(s, ctx->G0, D, C, P0, (const cx<double> *)Zp(j), nullptr, ctx->wo,
+                                                 0, &Vs, false, red1, ctx->rs);
+      adrk::outer_orth1(s, N, ctx->wo, Vs, red1, red2, ctx->rs);
+      adrk::outer_orth2(s, N, ctx->wo, Vs, red2, Vp(j + 1));
+      const int nred = 2 * (kMaxRestart + 1) * 2 + 1;
+      ADR_HIP(hipMemcpyAsync(hp + 2, red1, nred * sizeof(double), hipMemcpyDeviceToHost, s));
+      ADR_HIP(hipStreamSynchronize(s));
+      const double *h1 = hp + 2, *h2 = hp + 2 + 2 * (kMaxRestart + 1);
+      double n2 = h2[2 * (j + 1)];
+      for (int i = 0; i <= j; ++i) {
+        std::complex<double> c(h2[2 * i], h2[2 * i + 1]);
+        Hh[i][j] = std::complex<double>(h1[2 * i], h1[2 * i + 1]) + c;
+        n2 -= std::norm(c);
+      }
+      Hh[j + 1][j] = std::sqrt(n2 > 0 ? n2 : 0.0);
+      // Givens rotations.
+      for (int i = 0; i < j; ++i) {
+        std::complex<double> t = cs[i] * Hh[i][j] + sn[i] * Hh[i + 1][j];
+        Hh[i + 1][j] = -std::conj(sn[i]) * Hh[i][j] + cs[i] * Hh[i + 1][j];
+        Hh[i][j] = t;
+      }
+      std::complex<double> aa = Hh[j][j], bb = Hh[j + 1][j];
+      double den = std::sqrt(std::norm(aa) + std::norm(bb));
+      if (std::abs(aa) == 0.0) {
+        cs[j] = 0.0;
+        sn[j] = 1.0;
+      } else {
+        cs[j] = std::abs(aa) / den;
+        sn[j] = (aa / std::abs(aa)) * std::conj(bb) / den;
+      }
+      Hh[j][j] = cs[j] * aa + sn[j] * bb;
+      Hh[j + 1][j] = 0.0;
+      g[j + 1] = -std::conj(sn[j]) * g[j];
+      g[j] = cs[j] * g[j];
+      k = j + 1;
+      ++iters;
+      const double est = std::abs(g[j + 1]) / bnorm;
+      if (!std::isfinite(est)) { result = ADR_ENUMERIC; break; }
+      if (est <= tol || iters >= maxit) break;
+    }
+    if (result != ADR_OK) break;
+    // y = R^{-1} g, x += Z y
+    std::complex<double> y[kMaxRestart];
+    for (int i = k - 1; i >= 0; --i) {
+      std::complex<double> acc = g[i];
+      for (int jj = i + 1; jj < k; ++jj) acc -= Hh[i][jj] * y[jj];
+      y[i] = (Hh[i][i] == 0.0) ? 0.0 : acc / Hh[i][i];
+    }
+    for (int i = 0; i < k; ++i) {
+      hp[2 + 2 * i] = y[i].real();
+      hp[3 + 2 * i] = y[i].imag();
+    }
+    double *ydev = osc + 48;
+    ADR_HIP(hipMemcpyAsync(ydev, hp + 2, 2 * k * sizeof(double), hipMemcpyHostToDevice, s));
+    if (mixed) {
+      VecSet<float> Zs{};
+      Zs.count = k;
+      for (int i = 0; i < k; ++i) Zs.v[i] = (const cx<float> *)Zp(i);
+      adrk::multi_axpy<float>(s, N, x, Zs, ydev);
+    } else {
+      VecSet<double> Zs{};
+      Zs.count = k;
+      for (int i = 0; i < k; ++i) Zs.v[i] = (const cx<double> *)Zp(i);
+      adrk::multi_axpy<double>(s, N, x, Zs, ydev);
+    }
+    adrk::fine_apply<double, double, double>(s, ctx->G0, D, C, P0, x, ctx->qh, ctx->ro, 1, nullptr, true, osc + 1,
+                                             ctx->rs);
+    ADR_HIP(hipMemcpyAsync(hp + 1, osc + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+    ADR_HIP(hipStreamSynchronize(s));
+    rnorm = hp[1];
+    relres = rnorm / bnorm;
+    ++restarts;
+  }
+  ADR_HIP(hipGetLastError());
+  if (result == ADR_OK && relres > tol) result = std::isfinite(relres) ? ADR_ENOCONV : ADR_ENUMERIC;
+  st.outer_iters = iters;
+  st.restarts = restarts;
+  st.relres = relres;
+  st.solve_ms = now_ms() - t0;
+  if (stats) *stats = st;
+  if (result == ADR_ENOCONV) ctx->err = "FGMRES reached maxit before tol";
+  return result;
+}
+
+const char *adr_strerror(adr_status s) {
+  switch (s) {
+    case ADR_OK: return "ok";
+    case ADR_EINVAL: return "invalid argument";
+    case ADR_ENOMEM: return "out of memory";
+    case ADR_EHIP: return "HIP runtime error";
+    case ADR_ENOCONV: return "not converged";
+    case ADR_ENUMERIC: return "NaN/Inf encountered";
+    case ADR_ENOTSUP: return "not supported";
+  }
+  return "unknown status";
+}
+
+const char *adr_last_error(const adr_ctx *ctx) { return ctx ? ctx->err.c_str() : g_setup_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,162 @@
+// Common device/host helpers for the ADR solver kernels (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define ADR_BLOCK 256
+#define ADR_MAX_BLOCKS 8192
+#define ADR_NUM_XCD 8
+#define ADR_MAX_RED 40      // max reduced doubles per kernel (dots are 2 doubles each)
+#define ADR_MAXV 17         // max basis vectors held by one kernel (restart <= 16)
+
+// ------------------------------------------------------------------------------------
+// Complex numbers (interleaved storage, 8 or 16 bytes).
+// ------------------------------------------------------------------------------------
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+  T re, im;
+};
+
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> mk(T re, T im) { cx<T> r; r.re = re; r.im = im; return r; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return mk<T>(a.re + b.re, a.im + b.im); }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return mk<T>(a.re - b.re, a.im - b.im); }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b) {
+  return mk<T>(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return mk<T>(s * a.re, s * a.im); }
+// a + b*c
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> cfma(cx<T> b, cx<T> c, cx<T> a) {
+  a.re = fma(b.re, c.re, a.re);
+  a.re = fma(-b.im, c.im, a.re);
+  a.im = fma(b.re, c.im, a.im);
+  a.im = fma(b.im, c.re, a.im);
+  return a;
+}
+// conj(a) * b
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> cdotc(cx<T> a, cx<T> b) {
+  return mk<T>(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> cinv(cx<T> a) {
+  T d = a.re * a.re + a.im * a.im;
+  return mk<T>(a.re / d, -a.im / d);
+}
+template <typename To, typename Ti>
+__host__ __device__ __forceinline__ cx<To> cvt(cx<Ti> a) { return mk<To>((To)a.re, (To)a.im); }
+
+// ------------------------------------------------------------------------------------
+// Grid: nx fastest, 2D grids have nz == 1.
+// ------------------------------------------------------------------------------------
+struct Grid {
+  int n[3];   // nodes along x, y, z
+  int N;      // total nodes
+};
+
+__device__ __forceinline__ void decode(const Grid &g, int i, int &x, int &y, int &z) {
+  int nxy = g.n[0] * g.n[1];
+  z = i / nxy;
+  int rem = i - z * nxy;
+  y = rem / g.n[0];
+  x = rem - y * g.n[0];
+}
+
+// ------------------------------------------------------------------------------------
+// Launch shape: at most ADR_MAX_BLOCKS blocks, each owning one contiguous chunk of the
+// index range.  Blocks are dispatched round-robin over the 8 XCDs; the remap below gives
+// each XCD a contiguous run of chunks, so stencil neighbours in other rows and planes
+// are mostly in that XCD's own L2.
+// ------------------------------------------------------------------------------------
+inline int launch_blocks(long long N) {
+  long long b = (N + ADR_BLOCK - 1) / ADR_BLOCK;
+  if (b > ADR_MAX_BLOCKS) b = ADR_MAX_BLOCKS;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+__device__ __forceinline__ int logical_block() {
+  int nb = gridDim.x, bid = blockIdx.x;
+  int q = nb / ADR_NUM_XCD, r = nb % ADR_NUM_XCD;
+  int xcd = bid % ADR_NUM_XCD, local = bid / ADR_NUM_XCD;
+  return xcd * q + (xcd < r ? xcd : r) + local;
+}
+
+__device__ __forceinline__ void chunk_range(int N, int &beg, int &end) {
+  int nb = gridDim.x;
+  int lb = logical_block();
+  long long chunk = ((long long)N + nb - 1) / nb;
+  long long b = lb * chunk, e = b + chunk;
+  if (b > N) b = N;
+  if (e > N) e = N;
+  beg = (int)b;
+  end = (int)e;
+}
+
+// ------------------------------------------------------------------------------------
+// Deterministic reductions: every block reduces its K doubles in a fixed tree, writes
+// them to partials[block*K + k], and the last block to arrive (device-scope counter)
+// sums the partials in block order and runs the finisher.  The counter is left at 0.
+// ------------------------------------------------------------------------------------
+struct RedScratch {
+  double *partials;       // ADR_MAX_BLOCKS * ADR_MAX_RED
+  unsigned int *counter;  // one word, 0 between kernels
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// Reduce acc[0..K) over the block into red[0..K) of thread 0 (other threads: undefined).
+template <int KMAX>
+__device__ __forceinline__ void block_sum(double (&acc)[KMAX], int K, double *lds /*[KMAX*4]*/) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int k = 0; k < K; ++k) {
+    double v = wave_sum(acc[k]);
+    if (lane == 0) lds[k * 4 + wid] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < K; ++k) acc[k] = (lds[k * 4 + 0] + lds[k * 4 + 1]) + (lds[k * 4 + 2] + lds[k * 4 + 3]);
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ double load_coherent(const double *p) {
+  unsigned long long v = __hip_atomic_load((const unsigned long long *)p, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+  return __longlong_as_double((long long)v);
+}
+
+// Returns true in the (single) last block, with tot[0..K) holding the grand totals in
+// thread 0.  acc must already hold the per-thread contributions.
+template <int KMAX>
+__device__ bool reduce_last_block(double (&acc)[KMAX], int K, RedScratch rs, double (&tot)[KMAX]) {
+  __shared__ double lds[KMAX * 4];
+  __shared__ bool is_last;
+  block_sum<KMAX>(acc, K, lds);
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < K; ++k) rs.partials[(size_t)blockIdx.x * K + k] = acc[k];
+    __threadfence();
+    unsigned int prev = atomicAdd(rs.counter, 1u);
+    is_last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!is_last) return false;
+  __threadfence();
+  const int nb = gridDim.x;
+  for (int k = 0; k < K; ++k) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += load_coherent(rs.partials + (size_t)b * K + k);
+    tot[k] = s;
+  }
+  block_sum<KMAX>(tot, K, lds);
+  if (threadIdx.x == 0) *rs.counter = 0u;
+  return true;
+}

@@ -1,0 +1,872 @@
+// HIP kernels of the ADR amplitude solver for gfx950 (MI355X).
+//
+// Everything here is bandwidth-bound stencil or vector work: coalesced SoA planes,
+// one node per lane, contiguous per-block chunks remapped per XCD, and deterministic
+// fused reductions (no MFMA: there is no dense contraction on this path).
+#include "adr_kernels.hpp"
+
+#include <cmath>
+#include <cstdio>
+
+namespace adrk {
+
+#define ADR_LAUNCH(kernel, nblocks, stream, ...) \
+  hipLaunchKernelGGL(kernel, dim3(nblocks), dim3(ADR_BLOCK), 0, stream, __VA_ARGS__)
+
+// =====================================================================================
+// Setup: coefficients from tau (Sec. 2.1, eq. travel_time_coeff)
+// =====================================================================================
+template <int D>
+__global__ __launch_bounds__(ADR_BLOCK) void k_coefficients(Grid G, double h, double omega, int sx, int sy, int sz,
+                                                            const double *__restrict__ kappa2,
+                                                            const double *__restrict__ tau,
+                                                            const double *__restrict__ gamma, double *g0,
+                                                            double *g1, double *g2, double *Lout,
+                                                            cx<double> *cout) {
+  int beg, end;
+  chunk_range(G.N, beg, end);
+  const int src[3] = {sx, sy, sz};
+  const bool fact = sx >= 0;
+  const int stride[3] = {1, G.n[0], G.n[0] * G.n[1]};
+  const int srcidx = fact ? sx + G.n[0] * (sy + G.n[1] * sz) : -1;
+  const double ksrc = fact ? sqrt(kappa2[srcidx]) : 0.0;
+  for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    int idx[3];
+    decode(G, i, idx[0], idx[1], idx[2]);
+    // f(k, o): tau1 (factored) or tau at the node shifted by o along axis k.
+    auto f = [&](int k, int o) -> double {
+      const int j = i + o * stride[k];
+      if (!fact) return tau[j];
+      if (j == srcidx) return ksrc;
+      double r2 = 0.0;
+#pragma unroll
+      for (int m = 0; m < D; ++m) {
+        double dm = (double)(idx[m] + (m == k ? o : 0) - src[m]) * h;
+        r2 += dm * dm;
+      }
+      return tau[j] / sqrt(r2);
+    };
+    double d1[3] = {0, 0, 0}, d2sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const int p = idx[k], n = G.n[k];
+      double a, b2;
+      if (p == 0) {
+        const double f0 = f(k, 0), f1 = f(k, 1), f2 = f(k, 2), f3 = f(k, 3);
+        a = (f1 - f0) / h;
+        b2 = (2.0 * f0 - 5.0 * f1 + 4.0 * f2 - f3) / (h * h);
+      } else if (p == n - 1) {
+        const double f0 = f(k, 0), f1 = f(k, -1), f2 = f(k, -2), f3 = f(k, -3);
+        a = (f0 - f1) / h;
+        b2 = (2.0 * f0 - 5.0 * f1 + 4.0 * f2 - f3) / (h * h);
+      } else {
+        const double fm = f(k, -1), f0 = f(k, 0), fp = f(k, 1);
+        a = (fp - fm) / (2.0 * h);
+        b2 = (fp - 2.0 * f0 + fm) / (h * h);
+      }
+      d1[k] = a;
+      d2sum += b2;
+    }
+    double g[3] = {0, 0, 0}, L;
+    if (!fact) {
+      for (int k = 0; k < D; ++k) g[k] = d1[k];
+      L = d2sum;
+    } else if (i == srcidx) {
+      L = 0.0;
+      for (int k = 0; k < D; ++k)
+        L += (tau[i + stride[k]] - 2.0 * tau[i] + tau[i - stride[k]]) / (h * h);
+    } else {
+      double r2 = 0.0, dt0[3] = {0, 0, 0};
+      for (int k = 0; k < D; ++k) {
+        double dk = (double)(idx[k] - src[k]) * h;
+        dt0[k] = dk;
+        r2 += dk * dk;
+      }
+      const double r = sqrt(r2);
+      const double t1 = tau[i] / r;
+      double dot = 0.0;
+      for (int k = 0; k < D; ++k) {
+        dt0[k] /= r;
+        g[k] = r * d1[k] + t1 * dt0[k];
+        dot += dt0[k] * d1[k];
+      }
+      L = t1 * (double)(D - 1) / r + 2.0 * dot + r * d2sum;
+    }
+    double gg = 0.0;
+    for (int k = 0; k < D; ++k) gg += g[k] * g[k];
+    const double k2 = kappa2[i];
+    const double gam = gamma ? gamma[i] : 0.0;
+    g0[i] = g[0];
+    g1[i] = g[1];
+    if (D == 3) g2[i] = g[2];
+    Lout[i] = L;
+    cout[i] = mk<double>(omega * omega * (k2 - gg), -omega * gam * k2);
+  }
+}
+
+void coefficients(hipStream_t s, const Grid &G, int D, double h, double omega, const int src[3],
+                  const double *kappa2, const double *tau, const double *gamma, double *g0, double *g1,
+                  double *g2, double *L, cx<double> *c) {
+  int nb = launch_blocks(G.N);
+  if (D == 2)
+    ADR_LAUNCH(k_coefficients<2>, nb, s, G, h, omega, src[0], src[1], src[2], kappa2, tau, gamma, g0, g1, g2, L, c);
+  else
+    ADR_LAUNCH(k_coefficients<3>, nb, s, G, h, omega, src[0], src[1], src[2], kappa2, tau, gamma, g0, g1, g2, L, c);
+}
+
+// =====================================================================================
+// Setup: materialize the fine stencil (for the Galerkin product) and Galerkin A_c
+// =====================================================================================
+template <int D>
+__global__ __launch_bounds__(ADR_BLOCK) void k_fine_stencil(Grid G, FineCoef<double> C, FineParams P,
+                                                            cx<double> *planes) {
+  int beg, end;
+  chunk_range(G.N, beg, end);
+  for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    int idx[3];
+    decode(G, i, idx[0], idx[1], idx[2]);
+    double gk[3], L;
+    cx<double> c;
+    load_fine_coef<double, D>(C, i, gk, L, c);
+    cx<double> e[1 + 4 * D];
+    fine_row<double, D>(G, P, idx, gk, L, c, e);
+#pragma unroll
+    for (int p = 0; p < 1 + 4 * D; ++p) planes[(size_t)p * G.N + i] = e[p];
+  }
+}
+
+void fine_stencil(hipStream_t s, const Grid &G, int D, const FineCoef<double> &C, const FineParams &P,
+                  cx<double> *planes) {
+  int nb = launch_blocks(G.N);
+  if (D == 2) ADR_LAUNCH(k_fine_stencil<2>, nb, s, G, C, P, planes);
+  else ADR_LAUNCH(k_fine_stencil<3>, nb, s, G, C, P, planes);
+}
+
+// A_c[t][J] = sum over (p, d, w) in the triple list of t of
+//             w * A_f[d][2J + p]        (fine node 2J+p and its neighbour in the grid)
+// where the list pairs each P^T support offset p with each input stencil offset d that
+// lands on the P support of coarse node J + t, w = w(p) w(q) (eq. coarseGridMatrix).
+__global__ __launch_bounds__(ADR_BLOCK) void k_galerkin(Grid Gf, Grid Gc, const cx<double> *__restrict__ in,
+                                                        const int *__restrict__ in_off, cx<double> *out, const int *__restrict__ out_off, int S_out,
+                                                        const int *__restrict__ tri_start,
+                                                        const int *__restrict__ tri_p,
+                                                        const int *__restrict__ tri_d,
+                                                        const double *__restrict__ tri_w) {
+  const long long total = (long long)S_out * Gc.N;
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+       q += (long long)gridDim.x * blockDim.x) {
+    const int t = (int)(q / Gc.N);
+    const int J = (int)(q - (long long)t * Gc.N);
+    int jc[3];
+    decode(Gc, J, jc[0], jc[1], jc[2]);
+    const int tx = out_off[3 * t], ty = out_off[3 * t + 1], tz = out_off[3 * t + 2];
+    const int Ix = jc[0] + tx, Iy = jc[1] + ty, Iz = jc[2] + tz;
+    cx<double> acc = mk<double>(0.0, 0.0);
+    if (Ix >= 0 && Ix < Gc.n[0] && Iy >= 0 && Iy < Gc.n[1] && Iz >= 0 && Iz < Gc.n[2]) {
+      for (int e = tri_start[t]; e < tri_start[t + 1]; ++e) {
+        const int fx = 2 * jc[0] + tri_p[3 * e], fy = 2 * jc[1] + tri_p[3 * e + 1], fz = 2 * jc[2] + tri_p[3 * e + 2];
+        if (fx < 0 || fx >= Gf.n[0] || fy < 0 || fy >= Gf.n[1] || fz < 0 || fz >= Gf.n[2]) continue;
+        const int d = tri_d[e];
+        const int gx = fx + in_off[3 * d], gy = fy + in_off[3 * d + 1], gz = fz + in_off[3 * d + 2];
+        if (gx < 0 || gx >= Gf.n[0] || gy < 0 || gy >= Gf.n[1] || gz < 0 || gz >= Gf.n[2]) continue;
+        const int f = fx + Gf.n[0] * (fy + Gf.n[1] * fz);
+        const cx<double> a = in[(size_t)d * Gf.N + f];
+        acc.re += tri_w[e] * a.re;
+        acc.im += tri_w[e] * a.im;
+      }
+    }
+    out[(size_t)t * Gc.N + J] = acc;
+  }
+}
+
+void galerkin(hipStream_t s, const Grid &Gf, const Grid &Gc, const cx<double> *in_planes, const int *in_off_xyz,
+              int S_in, cx<double> *out_planes, const int *out_off_xyz, int S_out, const int *tri_start,
+              const int *tri_p, const int *tri_d, const double *tri_w) {
+  (void)S_in;
+  long long total = (long long)S_out * Gc.N;
+  long long nb = (total + ADR_BLOCK - 1) / ADR_BLOCK;
+  if (nb > 65536) nb = 65536;
+  ADR_LAUNCH(k_galerkin, (int)nb, s, Gf, Gc, in_planes, in_off_xyz, out_planes,
+             out_off_xyz, S_out, tri_start, tri_p, tri_d, tri_w);
+}
+
+template <typename T>
+__global__ __launch_bounds__(ADR_BLOCK) void k_diag_inv(int N, const cx<T> *c, cx<T> *d) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) d[i] = cinv(c[i]);
+}
+template <typename T>
+void stencil_diag_inv(hipStream_t s, int N, const cx<T> *centre_plane, cx<T> *dinv) {
+  ADR_LAUNCH(k_diag_inv<T>, launch_blocks(N), s, N, centre_plane, dinv);
+}
+template void stencil_diag_inv<double>(hipStream_t, int, const cx<double> *, cx<double> *);
+template void stencil_diag_inv<float>(hipStream_t, int, const cx<float> *, cx<float> *);
+
+template <typename To, typename Ti>
+__global__ __launch_bounds__(ADR_BLOCK) void k_convert(long long n, const cx<Ti> *in, cx<To> *out) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    out[i] = cvt<To, Ti>(in[i]);
+}
+template <typename To, typename Ti>
+void convert(hipStream_t s, long long n, const cx<Ti> *in, cx<To> *out) {
+  ADR_LAUNCH((k_convert<To, Ti>), launch_blocks(n), s, n, in, out);
+}
+template void convert<float, double>(hipStream_t, long long, const cx<double> *, cx<float> *);
+template void convert<double, float>(hipStream_t, long long, const cx<float> *, cx<double> *);
+template void convert<double, double>(hipStream_t, long long, const cx<double> *, cx<double> *);
+
+template <typename To, typename Ti>
+__global__ __launch_bounds__(ADR_BLOCK) void k_convert_real(long long n, const Ti *in, To *out) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    out[i] = (To)in[i];
+}
+template <typename To, typename Ti>
+void convert_real(hipStream_t s, long long n, const Ti *in, To *out) {
+  ADR_LAUNCH((k_convert_real<To, Ti>), launch_blocks(n), s, n, in, out);
+}
+template void convert_real<float, double>(hipStream_t, long long, const double *, float *);
+
+// =====================================================================================
+// Fine level: matrix-free apply / residual with fused reductions, Jacobi sweep
+// =====================================================================================
+template <typename T, typename Tin, typename To, int D, int NV, bool NORM>
+__global__ __launch_bounds__(ADR_BLOCK) void k_fine_apply(Grid G, FineCoef<T> C, FineParams P,
+                                                          const cx<Tin> *__restrict__ x,
+                                                          const cx<To> *__restrict__ b, cx<To> *__restrict__ y,
+                                                          int mode, VecSet<To> V, double *out, RedScratch rs) {
+  constexpr int K = 2 * NV + (NORM ? 1 : 0);
+  constexpr int KA = K > 0 ? K : 1;
+  double red[KA];
+#pragma unroll
+  for (int k = 0; k < KA; ++k) red[k] = 0.0;
+  int beg, end;
+  chunk_range(G.N, beg, end);
+  for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    int idx[3];
+    decode(G, i, idx[0], idx[1], idx[2]);
+    T gk[3], L;
+    cx<T> c;
+    load_fine_coef<T, D>(C, i, gk, L, c);
+    cx<T> e[1 + 4 * D];
+    fine_row<T, D>(G, P, idx, gk, L, c, e);
+    int nb[1 + 4 * D];
+    fine_neighbours<D>(G, i, idx, nb);
+    cx<T> acc = mk<T>(T(0), T(0));
+#pragma unroll
+    for (int p = 0; p < 1 + 4 * D; ++p) acc = cfma(e[p], cvt<T, Tin>(x[nb[p]]), acc);
+    cx<To> o = cvt<To, T>(acc);
+    if (mode == 1) o = b[i] - o;
+    y[i] = o;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const cx<To> vv = V.v[v][i];
+      const cx<double> d = cdotc(cvt<double, To>(vv), cvt<double, To>(o));
+      red[2 * v] += d.re;
+      red[2 * v + 1] += d.im;
+    }
+    if (NORM) red[K - 1] += (double)o.re * o.re + (double)o.im * o.im;
+  }
+  if (K > 0) {
+    double tot[KA];
+    if (reduce_last_block<KA>(red, K, rs, tot) && threadIdx.x == 0) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double sc = V.scale[v] ? *V.scale[v] : 1.0;
+        out[2 * v] = sc * tot[2 * v];
+        out[2 * v + 1] = sc * tot[2 * v + 1];
+      }
+      if (NORM) out[K - 1] = sqrt(tot[K - 1]);
+    }
+  }
+}
+
+template <typename T, typename Tin, typename To, int D, int NV, bool NORM>
+static void launch_fine_apply(hipStream_t s, const Grid &G, const FineCoef<T> &C, const FineParams &P,
+                              const cx<Tin> *x, const cx<To> *b, cx<To> *y, int mode, const VecSet<To> &V,
+                              double *out, RedScratch rs) {
+  ADR_LAUNCH((k_fine_apply<T, Tin, To, D, NV, NORM>), launch_blocks(G.N), s, G, C, P, x, b, y, mode, V, out, rs);
+}
+
+template <typename T, typename Tin, typename To, int D, bool NORM>
+static void dispatch_fine_apply_nv(hipStream_t s, const Grid &G, const FineCoef<T> &C, const FineParams &P,
+                                   const cx<Tin> *x, const cx<To> *b, cx<To> *y, int mode, const VecSet<To> &V,
+                                   double *out, RedScratch rs) {
+  switch (V.count) {
+#define ADR_NV_CASE(n) \
+  case n: launch_fine_apply<T, Tin, To, D, n, NORM>(s, G, C, P, x, b, y, mode, V, out, rs); break;
+    ADR_NV_CASE(0) ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6)
+    ADR_NV_CASE(7) ADR_NV_CASE(8)
+#undef ADR_NV_CASE
+    default: break;
+  }
+}
+
+template <typename T, typename Tin, typename To>
+void fine_apply(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P, const cx<Tin> *x,
+                const cx<To> *b, cx<To> *y, int mode, const VecSet<To> *dots, bool want_norm, double *out,
+                RedScratch rs) {
+  VecSet<To> V{};
+  if (dots) V = *dots;
+  if (D == 2) {
+    if (want_norm) dispatch_fine_apply_nv<T, Tin, To, 2, true>(s, G, C, P, x, b, y, mode, V, out, rs);
+    else dispatch_fine_apply_nv<T, Tin, To, 2, false>(s, G, C, P, x, b, y, mode, V, out, rs);
+  } else {
+    if (want_norm) dispatch_fine_apply_nv<T, Tin, To, 3, true>(s, G, C, P, x, b, y, mode, V, out, rs);
+    else dispatch_fine_apply_nv<T, Tin, To, 3, false>(s, G, C, P, x, b, y, mode, V, out, rs);
+  }
+}
+template void fine_apply<double, double, double>(hipStream_t, const Grid &, int, const FineCoef<double> &,
+                                                 const FineParams &, const cx<double> *, const cx<double> *,
+                                                 cx<double> *, int, const VecSet<double> *, bool, double *,
+                                                 RedScratch);
+template void fine_apply<double, float, double>(hipStream_t, const Grid &, int, const FineCoef<double> &,
+                                                const FineParams &, const cx<float> *, const cx<double> *,
+                                                cx<double> *, int, const VecSet<double> *, bool, double *,
+                                                RedScratch);
+template void fine_apply<float, float, float>(hipStream_t, const Grid &, int, const FineCoef<float> &,
+                                              const FineParams &, const cx<float> *, const cx<float> *,
+                                              cx<float> *, int, const VecSet<float> *, bool, double *, RedScratch);
+
+template <typename T, int D>
+__global__ __launch_bounds__(ADR_BLOCK) void k_fine_jacobi(Grid G, FineCoef<T> C, FineParams P,
+                                                           const cx<T> *__restrict__ xin,
+                                                           const cx<T> *__restrict__ b, cx<T> *__restrict__ xout,
+                                                           T weight) {
+  int beg, end;
+  chunk_range(G.N, beg, end);
+  for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    int idx[3];
+    decode(G, i, idx[0], idx[1], idx[2]);
+    T gk[3], L;
+    cx<T> c;
+    load_fine_coef<T, D>(C, i, gk, L, c);
+    cx<T> e[1 + 4 * D];
+    fine_row<T, D>(G, P, idx, gk, L, c, e);
+    cx<T> r = b[i];
+    cx<T> x0 = mk<T>(T(0), T(0));
+    if (xin) {
+      int nb[1 + 4 * D];
+      fine_neighbours<D>(G, i, idx, nb);
+      cx<T> acc = mk<T>(T(0), T(0));
+#pragma unroll
+      for (int p = 0; p < 1 + 4 * D; ++p) acc = cfma(e[p], xin[nb[p]], acc);
+      r = r - acc;
+      x0 = xin[i];
+    }
+    xout[i] = cfma(weight * cinv(e[0]), r, x0);
+  }
+}
+
+template <typename T>
+void fine_jacobi(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P, const cx<T> *x_in,
+                 const cx<T> *b, cx<T> *x_out, double weight) {
+  int nb = launch_blocks(G.N);
+  if (D == 2) ADR_LAUNCH((k_fine_jacobi<T, 2>), nb, s, G, C, P, x_in, b, x_out, (T)weight);
+  else ADR_LAUNCH((k_fine_jacobi<T, 3>), nb, s, G, C, P, x_in, b, x_out, (T)weight);
+}
+template void fine_jacobi<double>(hipStream_t, const Grid &, int, const FineCoef<double> &, const FineParams &,
+                                  const cx<double> *, const cx<double> *, cx<double> *, double);
+template void fine_jacobi<float>(hipStream_t, const Grid &, int, const FineCoef<float> &, const FineParams &,
+                                 const cx<float> *, const cx<float> *, cx<float> *, double);
+
+// =====================================================================================
+// Coarse levels: stored Galerkin stencils (SoA planes)
+// =====================================================================================
+template <typename T, int D, int NV, bool NORM>
+__global__ __launch_bounds__(ADR_BLOCK) void k_coarse_apply(Grid G, Stencil<T> A, const cx<T> *__restrict__ x,
+                                                            const double *xscale, const cx<T> *__restrict__ dinv,
+                                                            const cx<T> *__restrict__ b, cx<T> *__restrict__ y,
+                                                            int mode, VecSet<T> V, double *out, RedScratch rs) {
+  constexpr int K = 2 * NV + (NORM ? 1 : 0);
+  constexpr int KA = K > 0 ? K : 1;
+  double red[KA];
+#pragma unroll
+  for (int k = 0; k < KA; ++k) red[k] = 0.0;
+  const T xs = xscale ? (T)(*xscale) : T(1);
+  int beg, end;
+  chunk_range(G.N, beg, end);
+  const int sy = G.n[0], sz = G.n[0] * G.n[1];
+  for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    int ix, iy, iz;
+    decode(G, i, ix, iy, iz);
+    const bool inner = ix >= 2 && ix <= G.n[0] - 3 && iy >= 2 && iy <= G.n[1] - 3 &&
+                       (D == 2 || (iz >= 2 && iz <= G.n[2] - 3));
+    cx<T> acc = mk<T>(T(0), T(0));
+    for (int p = 0; p < A.S; ++p) {
+      const int dx = A.off_xyz[3 * p], dy = A.off_xyz[3 * p + 1], dz = A.off_xyz[3 * p + 2];
+      int j = i + dx + sy * dy + sz * dz;
+      if (!inner) {
+        const bool ok = ix + dx >= 0 && ix + dx < G.n[0] && iy + dy >= 0 && iy + dy < G.n[1] && iz + dz >= 0 &&
+                        iz + dz < G.n[2];
+        j = ok ? j : i;
+      }
+      cx<T> xv = x[j];
+      if (mode == 0 && dinv) xv = xv * dinv[j];
+      acc = cfma(A.planes[(size_t)p * G.N + i], xv, acc);
+    }
+    cx<T> o;
+    if (mode == 0) o = xs * acc;
+    else o = b[i] - acc;
+    y[i] = o;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const cx<double> d = cdotc(cvt<double, T>(V.v[v][i]), cvt<double, T>(o));
+      red[2 * v] += d.re;
+      red[2 * v + 1] += d.im;
+    }
+    if (NORM) red[K - 1] += (double)o.re * o.re + (double)o.im * o.im;
+  }
+  if (K > 0) {
+    double tot[KA];
+    if (reduce_last_block<KA>(red, K, rs, tot) && threadIdx.x == 0) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double sc = V.scale[v] ? *V.scale[v] : 1.0;
+        out[2 * v] = sc * tot[2 * v];
+        out[2 * v + 1] = sc * tot[2 * v + 1];
+      }
+      if (NORM) out[K - 1] = sqrt(tot[K - 1]);
+    }
+  }
+}
+
+template <typename T, int D, bool NORM>
+static void dispatch_coarse_nv(hipStream_t s, const Grid &G, const Stencil<T> &A, const cx<T> *x, const double *xs,
+                               const cx<T> *dinv, const cx<T> *b, cx<T> *y, int mode, const VecSet<T> &V,
+                               double *out, RedScratch rs) {
+  int nb = launch_blocks(G.N);
+  switch (V.count) {
+#define ADR_NV_CASE(n) \
+  case n: ADR_LAUNCH((k_coarse_apply<T, D, n, NORM>), nb, s, G, A, x, xs, dinv, b, y, mode, V, out, rs); break;
+    ADR_NV_CASE(0) ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6)
+    ADR_NV_CASE(7) ADR_NV_CASE(8)
+#undef ADR_NV_CASE
+    default: break;
+  }
+}
+
+template <typename T>
+void coarse_apply(hipStream_t s, const Grid &G, int D, const Stencil<T> &A, const cx<T> *x, const double *xscale,
+                  const cx<T> *dinv, const cx<T> *b, cx<T> *y, int mode, const VecSet<T> *dots, bool want_norm,
+                  double *out, RedScratch rs) {
+  VecSet<T> V{};
+  if (dots) V = *dots;
+  if (D == 2) {
+    if (want_norm) dispatch_coarse_nv<T, 2, true>(s, G, A, x, xscale, dinv, b, y, mode, V, out, rs);
+    else dispatch_coarse_nv<T, 2, false>(s, G, A, x, xscale, dinv, b, y, mode, V, out, rs);
+  } else {
+    if (want_norm) dispatch_coarse_nv<T, 3, true>(s, G, A, x, xscale, dinv, b, y, mode, V, out, rs);
+    else dispatch_coarse_nv<T, 3, false>(s, G, A, x, xscale, dinv, b, y, mode, V, out, rs);
+  }
+}
+template void coarse_apply<double>(hipStream_t, const Grid &, int, const Stencil<double> &, const cx<double> *,
+                                   const double *, const cx<double> *, const cx<double> *, cx<double> *, int,
+                                   const VecSet<double> *, bool, double *, RedScratch);
+template void coarse_apply<float>(hipStream_t, const Grid &, int, const Stencil<float> &, const cx<float> *,
+                                  const double *, const cx<float> *, const cx<float> *, cx<float> *, int,
+                                  const VecSet<float> *, bool, double *, RedScratch);
+
+// =====================================================================================
+// Transfers: r_c = P^T r_f (nodal full weighting x 2^d), x_f += P e_c (bi/trilinear)
+// =====================================================================================
+template <typename T, int D>
+__global__ __launch_bounds__(ADR_BLOCK) void k_restrict(Grid Gf, Grid Gc, const cx<T> *__restrict__ rf,
+                                                        cx<T> *__restrict__ rc) {
+  int beg, end;
+  chunk_range(Gc.N, beg, end);
+  for (int J = beg + threadIdx.x; J < end; J += blockDim.x) {
+    int jx, jy, jz;
+    decode(Gc, J, jx, jy, jz);
+    const int fx = 2 * jx, fy = 2 * jy, fz = 2 * jz;
+    cx<T> acc = mk<T>(T(0), T(0));
+    const int zlo = (D == 3) ? -1 : 0, zhi = (D == 3) ? 1 : 0;
+    for (int pz = zlo; pz <= zhi; ++pz) {
+      const int z = fz + pz;
+      if (z < 0 || z >= Gf.n[2]) continue;
+      const T wz = pz == 0 ? T(1) : T(0.5);
+      for (int py = -1; py <= 1; ++py) {
+        const int y = fy + py;
+        if (y < 0 || y >= Gf.n[1]) continue;
+        const T wy = wz * (py == 0 ? T(1) : T(0.5));
+        for (int px = -1; px <= 1; ++px) {
+          const int x = fx + px;
+          if (x < 0 || x >= Gf.n[0]) continue;
+          const T w = wy * (px == 0 ? T(1) : T(0.5));
+          const cx<T> v = rf[x + Gf.n[0] * (y + Gf.n[1] * z)];
+          acc.re += w * v.re;
+          acc.im += w * v.im;
+        }
+      }
+    }
+    rc[J] = acc;
+  }
+}
+
+template <typename T>
+void restrict_full(hipStream_t s, const Grid &Gf, const Grid &Gc, int D, const cx<T> *rf, cx<T> *rc) {
+  int nb = launch_blocks(Gc.N);
+  if (D == 2) ADR_LAUNCH((k_restrict<T, 2>), nb, s, Gf, Gc, rf, rc);
+  else ADR_LAUNCH((k_restrict<T, 3>), nb, s, Gf, Gc, rf, rc);
+}
+template void restrict_full<double>(hipStream_t, const Grid &, const Grid &, int, const cx<double> *, cx<double> *);
+template void restrict_full<float>(hipStream_t, const Grid &, const Grid &, int, const cx<float> *, cx<float> *);
+
+template <typename T, int D>
+__global__ __launch_bounds__(ADR_BLOCK) void k_prolong_add(Grid Gf, Grid Gc, const cx<T> *__restrict__ ec,
+                                                           cx<T> *__restrict__ xf) {
+  int beg, end;
+  chunk_range(Gf.N, beg, end);
+  for (int f = beg + threadIdx.x; f < end; f += blockDim.x) {
+    int fx, fy, fz;
+    decode(Gf, f, fx, fy, fz);
+    const int x0 = fx >> 1, y0 = fy >> 1, z0 = fz >> 1;
+    const int nxs = (fx & 1) ? 2 : 1, nys = (fy & 1) ? 2 : 1, nzs = (D == 3 && (fz & 1)) ? 2 : 1;
+    const T wx = (fx & 1) ? T(0.5) : T(1), wy = (fy & 1) ? T(0.5) : T(1), wz = (D == 3 && (fz & 1)) ? T(0.5) : T(1);
+    cx<T> acc = mk<T>(T(0), T(0));
+    for (int cz = 0; cz < nzs; ++cz)
+      for (int cy = 0; cy < nys; ++cy)
+        for (int cxx = 0; cxx < nxs; ++cxx) {
+          const cx<T> v = ec[(x0 + cxx) + Gc.n[0] * ((y0 + cy) + Gc.n[1] * (z0 + cz))];
+          const T w = wx * wy * wz;
+          acc.re += w * v.re;
+          acc.im += w * v.im;
+        }
+    xf[f] = xf[f] + acc;
+  }
+}
+
+template <typename T>
+void prolong_add(hipStream_t s, const Grid &Gf, const Grid &Gc, int D, const cx<T> *ec, cx<T> *xf) {
+  int nb = launch_blocks(Gf.N);
+  if (D == 2) ADR_LAUNCH((k_prolong_add<T, 2>), nb, s, Gf, Gc, ec, xf);
+  else ADR_LAUNCH((k_prolong_add<T, 3>), nb, s, Gf, Gc, ec, xf);
+}
+template void prolong_add<double>(hipStream_t, const Grid &, const Grid &, int, const cx<double> *, cx<double> *);
+template void prolong_add<float>(hipStream_t, const Grid &, const Grid &, int, const cx<float> *, cx<float> *);
+
+// =====================================================================================
+// GMRES relaxation pieces
+// =====================================================================================
+template <typename T, int NV>
+__global__ __launch_bounds__(ADR_BLOCK) void k_orth_step(int N, const cx<T> *__restrict__ w, VecSet<T> V,
+                                                         const double *hcol, cx<T> *__restrict__ vnew,
+                                                         double *hsub, double *snew, RedScratch rs) {
+  cx<T> coef[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const double sc = V.scale[v] ? *V.scale[v] : 1.0;
+    coef[v] = mk<T>((T)(hcol[2 * v] * sc), (T)(hcol[2 * v + 1] * sc));
+  }
+  double red[1] = {0.0};
+  int beg, end;
+  chunk_range(N, beg, end);
+  for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    cx<T> o = w[i];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const cx<T> vv = V.v[v][i];
+      o = o - coef[v] * vv;
+    }
+    vnew[i] = o;
+    red[0] += (double)o.re * o.re + (double)o.im * o.im;
+  }
+  double tot[1];
+  if (reduce_last_block<1>(red, 1, rs, tot) && threadIdx.x == 0) {
+    const double nrm = sqrt(tot[0]);
+    hsub[0] = nrm;
+    hsub[1] = 0.0;
+    *snew = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  }
+}
+
+template <typename T>
+void orth_step(hipStream_t s, int N, const cx<T> *w, const VecSet<T> &V, const double *hcol, cx<T> *vnew,
+               double *hsub, double *snew, RedScratch rs) {
+  int nb = launch_blocks(N);
+  switch (V.count) {
+#define ADR_NV_CASE(n) \
+  case n: ADR_LAUNCH((k_orth_step<T, n>), nb, s, N, w, V, hcol, vnew, hsub, snew, rs); break;
+    ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6) ADR_NV_CASE(7)
+    ADR_NV_CASE(8)
+#undef ADR_NV_CASE
+    default: break;
+  }
+}
+template void orth_step<double>(hipStream_t, int, const cx<double> *, const VecSet<double> &, const double *,
+                                cx<double> *, double *, double *, RedScratch);
+template void orth_step<float>(hipStream_t, int, const cx<float> *, const VecSet<float> &, const double *,
+                               cx<float> *, double *, double *, RedScratch);
+
+template <typename T>
+__global__ __launch_bounds__(ADR_BLOCK) void k_norm_inv(int N, const cx<T> *__restrict__ x, double *out_norm,
+                                                        double *out_inv, RedScratch rs) {
+  double red[1] = {0.0};
+  int beg, end;
+  chunk_range(N, beg, end);
+  for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    const cx<T> o = x[i];
+    red[0] += (double)o.re * o.re + (double)o.im * o.im;
+  }
+  double tot[1];
+  if (reduce_last_block<1>(red, 1, rs, tot) && threadIdx.x == 0) {
+    const double nrm = sqrt(tot[0]);
+    if (out_norm) *out_norm = nrm;
+    if (out_inv) *out_inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  }
+}
+template <typename T>
+void norm_inv(hipStream_t s, int N, const cx<T> *x, double *out_norm, double *out_inv, RedScratch rs) {
+  ADR_LAUNCH(k_norm_inv<T>, launch_blocks(N), s, N, x, out_norm, out_inv, rs);
+}
+template void norm_inv<double>(hipStream_t, int, const cx<double> *, double *, double *, RedScratch);
+template void norm_inv<float>(hipStream_t, int, const cx<float> *, double *, double *, RedScratch);
+
+// Least squares min || beta e1 - H y || for the (k+1) x k upper Hessenberg H by Givens
+// rotations (one thread; k <= 16).  coef_j = y_j * scale_j.
+__global__ void k_gmres_lsq(const double *H, int ldh, int k, const double *beta, const double *scales,
+                            double *coef) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  cx<double> R[ADR_MAXV][ADR_MAXV];
+  cx<double> g[ADR_MAXV + 1];
+  for (int j = 0; j < k; ++j)
+    for (int i = 0; i <= k; ++i) R[i][j] = mk<double>(H[2 * (j * ldh + i)], H[2 * (j * ldh + i) + 1]);
+  for (int i = 0; i <= k; ++i) g[i] = mk<double>(0.0, 0.0);
+  g[0] = mk<double>(*beta, 0.0);
+  for (int j = 0; j < k; ++j) {
+    const cx<double> a = R[j][j], b = R[j + 1][j];
+    const double aa = sqrt(a.re * a.re + a.im * a.im), bb = sqrt(b.re * b.re + b.im * b.im);
+    const double den = sqrt(aa * aa + bb * bb);
+    double c;
+    cx<double> sn;
+    if (den == 0.0) {
+      c = 1.0;
+      sn = mk<double>(0.0, 0.0);
+    } else if (aa == 0.0) {
+      c = 0.0;
+      sn = mk<double>(b.re / bb, -b.im / bb);   // conj(b)/|b|
+    } else {
+      c = aa / den;
+      const cx<double> ua = mk<double>(a.re / aa, a.im / aa);
+      sn = ua * mk<double>(b.re / den, -b.im / den);  // (a/|a|) conj(b)/den
+    }
+    // Apply G = [[c, s], [-conj(s), c]] to rows j, j+1 of columns j..k-1 and to g.
+    for (int jj = j; jj < k; ++jj) {
+      const cx<double> x1 = R[j][jj], x2 = R[j + 1][jj];
+      R[j][jj] = c * x1 + sn * x2;
+      R[j + 1][jj] = mk<double>(-sn.re, sn.im) * x1 + c * x2;
+    }
+    const cx<double> g1 = g[j], g2 = g[j + 1];
+    g[j] = c * g1 + sn * g2;
+    g[j + 1] = mk<double>(-sn.re, sn.im) * g1 + c * g2;
+  }
+  cx<double> y[ADR_MAXV];
+  for (int j = k - 1; j >= 0; --j) {
+    cx<double> acc = g[j];
+    for (int jj = j + 1; jj < k; ++jj) acc = acc - R[j][jj] * y[jj];
+    const cx<double> d = R[j][j];
+    y[j] = (d.re == 0.0 && d.im == 0.0) ? mk<double>(0.0, 0.0) : acc * cinv(d);
+  }
+  for (int j = 0; j < k; ++j) {
+    const double sc = scales ? scales[j] : 1.0;
+    coef[2 * j] = y[j].re * sc;
+    coef[2 * j + 1] = y[j].im * sc;
+  }
+}
+void gmres_lsq(hipStream_t s, const double *H, int ldh, int k, const double *beta, const double *scales,
+               double *coef) {
+  hipLaunchKernelGGL(k_gmres_lsq, dim3(1), dim3(64), 0, s, H, ldh, k, beta, scales, coef);
+}
+
+template <typename T, int NV>
+__global__ __launch_bounds__(ADR_BLOCK) void k_gmres_update(int N, const cx<T> *__restrict__ x0,
+                                                            const cx<T> *__restrict__ dinv, VecSet<T> V,
+                                                            const double *coef, cx<T> *__restrict__ xout) {
+  cx<T> c[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) c[v] = mk<T>((T)coef[2 * v], (T)coef[2 * v + 1]);
+  int beg, end;
+  chunk_range(N, beg, end);
+  for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    cx<T> acc = mk<T>(T(0), T(0));
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc = cfma(c[v], V.v[v][i], acc);
+    if (dinv) acc = acc * dinv[i];
+    xout[i] = x0 ? x0[i] + acc : acc;
+  }
+}
+template <typename T>
+void gmres_update(hipStream_t s, int N, const cx<T> *x0, const cx<T> *dinv, const VecSet<T> &V, const double *coef,
+                  cx<T> *x_out) {
+  int nb = launch_blocks(N);
+  switch (V.count) {
+#define ADR_NV_CASE(n) \
+  case n: ADR_LAUNCH((k_gmres_update<T, n>), nb, s, N, x0, dinv, V, coef, x_out); break;
+    ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6) ADR_NV_CASE(7)
+    ADR_NV_CASE(8) ADR_NV_CASE(9) ADR_NV_CASE(10) ADR_NV_CASE(11) ADR_NV_CASE(12) ADR_NV_CASE(13)
+    ADR_NV_CASE(14) ADR_NV_CASE(15) ADR_NV_CASE(16)
+#undef ADR_NV_CASE
+    default: break;
+  }
+}
+template void gmres_update<double>(hipStream_t, int, const cx<double> *, const cx<double> *, const VecSet<double> &,
+                                   const double *, cx<double> *);
+template void gmres_update<float>(hipStream_t, int, const cx<float> *, const cx<float> *, const VecSet<float> &,
+                                  const double *, cx<float> *);
+
+// =====================================================================================
+// Outer FGMRES (FP64) Arnoldi: classical Gram-Schmidt with one re-orthogonalization
+// =====================================================================================
+template <int NV>
+__global__ __launch_bounds__(ADR_BLOCK) void k_outer_orth1(int N, cx<double> *__restrict__ w, VecSet<double> V,
+                                                           const double *hcol, double *out, RedScratch rs) {
+  constexpr int K = 2 * NV + 1;
+  cx<double> h[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) h[v] = mk<double>(hcol[2 * v], hcol[2 * v + 1]);
+  double red[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) red[k] = 0.0;
+  int beg, end;
+  chunk_range(N, beg, end);
+  for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    cx<double> vv[NV];
+    cx<double> o = w[i];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      vv[v] = V.v[v][i];
+      o = o - h[v] * vv[v];
+    }
+    w[i] = o;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const cx<double> d = cdotc(vv[v], o);
+      red[2 * v] += d.re;
+      red[2 * v + 1] += d.im;
+    }
+    red[K - 1] += o.re * o.re + o.im * o.im;
+  }
+  double tot[K];
+  if (reduce_last_block<K>(red, K, rs, tot) && threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[k] = tot[k];
+  }
+}
+void outer_orth1(hipStream_t s, int N, cx<double> *w, const VecSet<double> &V, const double *hcol, double *out,
+                 RedScratch rs) {
+  int nb = launch_blocks(N);
+  switch (V.count) {
+#define ADR_NV_CASE(n) \
+  case n: ADR_LAUNCH((k_outer_orth1<n>), nb, s, N, w, V, hcol, out, rs); break;
+    ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6) ADR_NV_CASE(7)
+    ADR_NV_CASE(8)
+#undef ADR_NV_CASE
+    default: break;
+  }
+}
+
+template <int NV>
+__global__ __launch_bounds__(ADR_BLOCK) void k_outer_orth2(int N, const cx<double> *__restrict__ w, VecSet<double> V,
+                                                           const double *red, cx<double> *__restrict__ vnew) {
+  cx<double> c[NV];
+  double n2 = red[2 * NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    c[v] = mk<double>(red[2 * v], red[2 * v + 1]);
+    n2 -= c[v].re * c[v].re + c[v].im * c[v].im;
+  }
+  const double nrm = sqrt(n2 > 0.0 ? n2 : 0.0);
+  const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  int beg, end;
+  chunk_range(N, beg, end);
+  for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    cx<double> o = w[i];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) o = o - c[v] * V.v[v][i];
+    vnew[i] = inv * o;
+  }
+}
+void outer_orth2(hipStream_t s, int N, const cx<double> *w, const VecSet<double> &V, const double *red,
+                 cx<double> *vnew) {
+  int nb = launch_blocks(N);
+  switch (V.count) {
+#define ADR_NV_CASE(n) \
+  case n: ADR_LAUNCH((k_outer_orth2<n>), nb, s, N, w, V, red, vnew); break;
+    ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6) ADR_NV_CASE(7)
+    ADR_NV_CASE(8)
+#undef ADR_NV_CASE
+    default: break;
+  }
+}
+
+template <typename Tz, int NV>
+__global__ __launch_bounds__(ADR_BLOCK) void k_multi_axpy(int N, cx<double> *__restrict__ x, VecSet<Tz> Z,
+                                                          const double *y) {
+  cx<double> c[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) c[v] = mk<double>(y[2 * v], y[2 * v + 1]);
+  int beg, end;
+  chunk_range(N, beg, end);
+  for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    cx<double> acc = x[i];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc = cfma(c[v], cvt<double, Tz>(Z.v[v][i]), acc);
+    x[i] = acc;
+  }
+}
+template <typename Tz>
+void multi_axpy(hipStream_t s, int N, cx<double> *x, const VecSet<Tz> &Z, const double *y) {
+  int nb = launch_blocks(N);
+  switch (Z.count) {
+#define ADR_NV_CASE(n) \
+  case n: ADR_LAUNCH((k_multi_axpy<Tz, n>), nb, s, N, x, Z, y); break;
+    ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6) ADR_NV_CASE(7)
+    ADR_NV_CASE(8)
+#undef ADR_NV_CASE
+    default: break;
+  }
+}
+template void multi_axpy<double>(hipStream_t, int, cx<double> *, const VecSet<double> &, const double *);
+template void multi_axpy<float>(hipStream_t, int, cx<double> *, const VecSet<float> &, const double *);
+
+__global__ __launch_bounds__(ADR_BLOCK) void k_scale_by_inv(int N, const cx<double> *__restrict__ x,
+                                                            const double *scale, cx<double> *__restrict__ y) {
+  const double s = *scale;
+  const double inv = s > 0.0 ? 1.0 / s : 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) y[i] = inv * x[i];
+}
+void scale_by_inv(hipStream_t s, int N, const cx<double> *x, const double *scale, cx<double> *y) {
+  ADR_LAUNCH(k_scale_by_inv, launch_blocks(N), s, N, x, scale, y);
+}
+
+__global__ __launch_bounds__(ADR_BLOCK) void k_phase(int N, const cx<double> *__restrict__ in,
+                                                     const double *__restrict__ tau, double omega, int sign,
+                                                     cx<double> *out) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+    double sn, cs;
+    sincos(omega * tau[i], &sn, &cs);
+    out[i] = in[i] * mk<double>(cs, sign * sn);
+  }
+}
+void phase(hipStream_t s, int N, const cx<double> *in, const double *tau, double omega, int sign, cx<double> *out) {
+  ADR_LAUNCH(k_phase, launch_blocks(N), s, N, in, tau, omega, sign, out);
+}
+
+// =====================================================================================
+// Coarsest level: x = A_L^{-1} b with the dense FP64 inverse (column-major)
+// =====================================================================================
+template <typename T>
+__global__ __launch_bounds__(ADR_BLOCK) void k_dense_gemv(int N, const cx<double> *__restrict__ Ainv,
+                                                          const cx<T> *__restrict__ b, cx<T> *__restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  cx<double> acc = mk<double>(0.0, 0.0);
+  for (int j = 0; j < N; ++j) acc = cfma(Ainv[(size_t)j * N + i], cvt<double, T>(b[j]), acc);
+  x[i] = cvt<T, double>(acc);
+}
+template <typename T>
+void dense_gemv(hipStream_t s, int N, const cx<double> *Ainv, const cx<T> *b, cx<T> *x) {
+  hipLaunchKernelGGL(k_dense_gemv<T>, dim3((N + ADR_BLOCK - 1) / ADR_BLOCK), dim3(ADR_BLOCK), 0, s, N, Ainv, b, x);
+}
+template void dense_gemv<double>(hipStream_t, int, const cx<double> *, const cx<double> *, cx<double> *);
+template void dense_gemv<float>(hipStream_t, int, const cx<double> *, const cx<float> *, cx<float> *);
+
+}  // namespace adrk

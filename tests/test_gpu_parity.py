@@ -1,0 +1,192 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle.
+
+Every case prints its name and sizes before touching the GPU.  Sizes span several
+blocks with ragged tails (N not a multiple of 256) and non-cubic grids.
+"""
+import numpy as np
+import pytest
+
+from oracle import coefficients as ocoef
+from oracle import multigrid as omg
+from oracle import operators as oops
+from oracle import solve as osolve
+from paper_1712_06091_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _t(a, dtype=None):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+def _ctx(wl, prec="fp64", factored=True, **opts):
+    from paper_1712_06091_amd import adr
+    o = adr.default_options(prec=prec, **opts)
+    gamma = _t(wl.gamma, torch.float64) if wl.gamma is not None else None
+    return adr.Context(_t(wl.kappa2, torch.float64), _t(wl.tau, torch.float64), gamma, wl.h, wl.omega,
+                       wl.src if factored else None, options=o, factored=factored)
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300)
+
+
+def _noncubic():
+    """3D 17 x 25 x 33 (z, y, x) linear-gradient medium, source at (z, y, x) = (5, 12, 16)."""
+    shape = (17, 25, 33)
+    h = 1.0 / 32
+    src = (5, 12, 16)
+    xs = W.node_coordinates(shape, h)
+    v = 1.5 + 0.8 * xs[0]
+    tau = W.linear_velocity_traveltime(shape, h, src, 1.5, 0.8)
+    omega = W.omega_for_ppw(1.5, h)
+    gamma = W.absorbing_layer(shape, h, omega, 4 * h)
+    return W.Workload("noncubic", shape, h, omega, src, 1.0 / v ** 2, tau, gamma)
+
+
+CASES = {
+    "2d_65_const": lambda: W.constant_medium(65, 2),
+    "3d_33_lin": lambda: W.linear_gradient(33, 3),
+    "3d_noncubic": _noncubic,
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("factored", [True, False])
+def test_coefficients(name, factored):
+    wl = CASES[name]()
+    print(f"[coef] {name} shape={wl.shape} factored={factored}", flush=True)
+    ctx = _ctx(wl, factored=factored)
+    g, L, c = ctx.coefficients()
+    og, oL, oc = ocoef.adr_coefficients(wl.tau, wl.kappa2, wl.gamma, wl.h, wl.omega,
+                                        src=wl.src if factored else None)
+    d = wl.ndim
+    for k in range(d):   # ABI axis k = NumPy axis d-1-k
+        ref = og[d - 1 - k]
+        assert np.max(np.abs(g[k].cpu().numpy() - ref)) <= 1e-12 * max(1.0, np.abs(ref).max())
+    assert np.max(np.abs(L.cpu().numpy() - oL)) <= 1e-12 * np.abs(oL).max()
+    assert np.max(np.abs(c.cpu().numpy() - oc)) <= 1e-11 * max(np.abs(oc).max(), wl.omega ** 2)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("beta", [0.0, 0.25, 1.0])
+def test_apply(name, beta):
+    wl = CASES[name]()
+    print(f"[apply] {name} shape={wl.shape} beta={beta}", flush=True)
+    ctx = _ctx(wl)
+    p = osolve.Problem(wl.kappa2, wl.tau, wl.gamma, wl.h, wl.omega, wl.src, beta=beta)
+    x = W.random_vector(wl.shape, 11)
+    y = ctx.apply(_t(x), beta=beta).cpu().numpy()
+    ref = (p.Abeta @ x.ravel()).reshape(wl.shape)
+    # Entry-wise bound: rounding of each row's sum, relative to sum_j |A_ij x_j|.
+    scale = (abs(p.Abeta) @ np.abs(x.ravel())).reshape(wl.shape)
+    assert np.max(np.abs(y - ref) / scale) <= 1e-13
+
+
+def test_apply_unfactored_plane_wave():
+    """src[0] < 0 path (plain differences of tau, no near-source rule)."""
+    wl = W.constant_medium(33, 3)
+    xs = W.node_coordinates(wl.shape, wl.h)
+    tau = 0.6 * xs[2] + 0.8 * xs[0]
+    wl.tau = tau
+    print("[apply-unfactored] 3d 33", flush=True)
+    ctx = _ctx(wl, factored=False)
+    g, L, c = ocoef.adr_coefficients(tau, wl.kappa2, wl.gamma, wl.h, wl.omega, src=None)
+    A = oops.assemble_adr(g, L, c, wl.h, wl.omega, 0.0, src=None)
+    x = W.random_vector(wl.shape, 12)
+    y = ctx.apply(_t(x), beta=0.0).cpu().numpy()
+    scale = (abs(A) @ np.abs(x.ravel())).reshape(wl.shape)
+    assert np.max(np.abs(y - (A @ x.ravel()).reshape(wl.shape)) / scale) <= 1e-13
+
+
+def _stencil_to_csr(planes, offsets, shape):
+    """Assemble GPU planes (S, *shape) with (dx, dy, dz) offsets into a CSR matrix."""
+    d = len(shape)
+    st = {}
+    for p, (dx, dy, dz) in enumerate(offsets):
+        key = (dz, dy, dx)[3 - d:]
+        st[key] = planes[p]
+    return oops.stencil_to_csr(st, shape)
+
+
+@pytest.mark.parametrize("name", ["2d_65_const", "3d_33_lin", "3d_noncubic"])
+def test_galerkin_hierarchy(name):
+    wl = CASES[name]()
+    print(f"[galerkin] {name} shape={wl.shape}", flush=True)
+    ctx = _ctx(wl, prec="fp64")
+    p = osolve.Problem(wl.kappa2, wl.tau, wl.gamma, wl.h, wl.omega, wl.src)
+    hier = p.hierarchy(ctx.num_levels)
+    assert ctx.num_levels == osolve.default_levels(wl.shape) == hier.levels
+    for l in range(1, ctx.num_levels):
+        planes, offs = ctx.level_stencil(l)
+        shape, S = ctx.level_info(l)
+        assert shape == hier.shapes[l]
+        assert S == (81 if wl.ndim == 3 else 21)
+        A = _stencil_to_csr(planes.cpu().numpy(), offs, shape)
+        ref = hier.A[l]
+        err = abs(A - ref).max()
+        assert err <= 1e-12 * abs(ref).max(), (l, err)
+
+
+@pytest.mark.parametrize("name", ["2d_65_const", "3d_33_lin", "3d_noncubic"])
+def test_vcycle_fp64(name):
+    """One V-cycle (Jacobi on the finest level, GMRES relaxation below, dense coarsest)
+    equals the oracle's V-cycle up to rounding."""
+    wl = CASES[name]()
+    print(f"[vcycle-fp64] {name} shape={wl.shape}", flush=True)
+    ctx = _ctx(wl, prec="fp64")
+    p = osolve.Problem(wl.kappa2, wl.tau, wl.gamma, wl.h, wl.omega, wl.src)
+    hier = p.hierarchy(ctx.num_levels)
+    r = W.random_vector(wl.shape, 13)
+    z = ctx.vcycle(_t(r)).cpu().numpy()
+    ref = hier.vcycle(r.ravel()).reshape(wl.shape)
+    assert _rel(z, ref) <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["2d_65_const", "3d_33_lin"])
+def test_vcycle_mixed_close(name):
+    """The complex-FP32 V-cycle stays within FP32 rounding of the FP64 one."""
+    wl = CASES[name]()
+    print(f"[vcycle-mixed] {name} shape={wl.shape}", flush=True)
+    ctx = _ctx(wl, prec="mixed")
+    p = osolve.Problem(wl.kappa2, wl.tau, wl.gamma, wl.h, wl.omega, wl.src)
+    hier = p.hierarchy(ctx.num_levels)
+    r = W.random_vector(wl.shape, 14)
+    z = ctx.vcycle(_t(r)).cpu().numpy()
+    ref = hier.vcycle(r.ravel()).reshape(wl.shape)
+    assert _rel(z, ref) <= 1e-4
+
+
+@pytest.mark.parametrize("name", ["2d_65_const", "3d_33_lin", "3d_noncubic"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_solve_matches_direct(name, prec):
+    """Whole solve at tol 1e-10 against the oracle's direct solve: rel L2 <= 1e-6."""
+    wl = CASES[name]()
+    print(f"[solve] {name} shape={wl.shape} prec={prec}", flush=True)
+    ctx = _ctx(wl, prec=prec)
+    p = osolve.Problem(wl.kappa2, wl.tau, wl.gamma, wl.h, wl.omega, wl.src)
+    qh = osolve.rhs_hat(wl.rhs(), wl.tau, wl.omega)
+    ref = osolve.direct_solve(p.H2up, qh).reshape(wl.shape)
+    a, st = ctx.solve(_t(wl.rhs()), tol=1e-10, maxit=400)
+    a = a.cpu().numpy()
+    assert st["relres"] <= 1e-10
+    # true residual from the oracle's matrix
+    assert np.linalg.norm(p.H2up @ a.ravel() - qh.ravel()) / np.linalg.norm(qh) <= 2e-10
+    assert _rel(a, ref) <= 1e-6
+    u = ctx.wavefield(_t(a)).cpu().numpy()
+    assert _rel(u, osolve.wavefield(a, wl.tau, wl.omega)) <= 1e-14
+
+
+def test_solve_initial_guess_and_zero_rhs():
+    wl = W.constant_medium(33, 2)
+    print("[solve-edge] 2d 33", flush=True)
+    ctx = _ctx(wl, prec="fp64")
+    a, st = ctx.solve(_t(wl.rhs()), tol=1e-10, maxit=200)
+    a2, st2 = ctx.solve(_t(wl.rhs()), tol=1e-10, maxit=200, x0=a)
+    assert st2["outer_iters"] == 0 and st2["relres"] <= 1e-10
+    z, st3 = ctx.solve(_t(np.zeros(wl.shape, complex)), tol=1e-10, maxit=10)
+    assert np.all(z.cpu().numpy() == 0)
+    _, st4 = ctx.solve(_t(wl.rhs()), tol=1e-14, maxit=3)
+    from paper_1712_06091_amd import adr
+    assert st4["status"] == adr.ADR_ENOCONV and st4["outer_iters"] == 3
