@@ -1,0 +1,233 @@
+"""Benchmark: ADR amplitude solves on one MI355X.
+
+Metric: Mpoints/s of a whole solve (FGMRES(5) + V-cycle from a zero guess to true
+relative residual <= 1e-6, then the wavefield u = a exp(-i w tau)), mixed precision
+(complex-FP32 V-cycle, FP64 outer) vs FP64, on the 3D 129^3 linear-gradient workload
+(v = 1.5 + 0.8 z km/s on a 1 km cube, analytic travel time, source at (0.5, 0.5, 0.1) km,
+10 points per wavelength).  Setup (coefficients, Galerkin hierarchy, coarsest inverse)
+is timed separately.  Inputs are synthetic and resident in HBM before timing starts.
+
+Prints one JSON line.  --gpus N with N > 1 is refused: this build runs on one GPU.
+"""
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+TOL = 1e-6
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="3d_129", choices=["3d_129", "2d_129", "3d_65"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-iters", type=int, default=8)
+    ap.add_argument("--cpu-sample-child", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--profile-only", action="store_true",
+                    help="setup + warmup + timed steps only (for rocprofv3 runs)")
+    return ap.parse_args()
+
+
+def make_workload(name):
+    from paper_1712_06091_amd import workloads as W
+    if name == "3d_129":
+        return W.config_3d_129()
+    if name == "2d_129":
+        return W.config_2d_129()
+    return W.linear_gradient(65, ndim=3, name="3d_65_linear_gradient")
+
+
+# --------------------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle (NumPy/SciPy, one thread) on a bounded sample
+# --------------------------------------------------------------------------------------
+def cpu_sample_child(args):
+    """Runs in a child process with every BLAS/OpenMP pool limited to one thread."""
+    from oracle import krylov
+    from oracle import solve as osolve
+    wl = make_workload(args.workload)
+    t0 = time.perf_counter()
+    p = osolve.Problem(wl.kappa2, wl.tau, wl.gamma, wl.h, wl.omega, wl.src)
+    hier = p.hierarchy()
+    qh = osolve.rhs_hat(wl.rhs(), wl.tau, wl.omega).ravel()
+    t1 = time.perf_counter()
+    _, info = krylov.fgmres(lambda v: p.H2up @ v, qh, precond=hier.vcycle, restart=5, tol=TOL,
+                            maxit=args.cpu_sample_iters)
+    t2 = time.perf_counter()
+    print(json.dumps({"setup_s": t1 - t0, "iters": info["iters"], "solve_s": t2 - t1,
+                      "relres": info["relres"]}))
+
+
+def cpu_baseline(args, nodes, iters_needed):
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
+        env[k] = "1"
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-sample-child", "--workload", args.workload,
+           "--cpu-sample-iters", str(args.cpu_sample_iters)]
+    out = subprocess.run(cmd, env=env, stdout=subprocess.PIPE, stderr=subprocess.PIPE, check=True, cwd=ROOT)
+    r = json.loads(out.stdout.decode().strip().splitlines()[-1])
+    per_iter = r["solve_s"] / max(r["iters"], 1)
+    est = per_iter * iters_needed
+    return {
+        "value": nodes / est / 1e6,
+        "unit": "Mpoints/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"FP64 oracle FGMRES(5)+V-cycle on the full workload, {r['iters']} outer iterations in "
+                   f"{r['solve_s']:.1f} s ({per_iter:.2f} s/iteration, setup {r['setup_s']:.1f} s not counted), "
+                   f"scaled to the {iters_needed} iterations the FP64 solve needs to reach {TOL:g}"),
+    }
+
+
+# --------------------------------------------------------------------------------------
+# GPU
+# --------------------------------------------------------------------------------------
+def main():
+    args = parse()
+    if args.cpu_sample_child:
+        cpu_sample_child(args)
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+              "(shot-parallel multi-GPU is a design note, not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1712_06091_amd import adr
+
+    dev = torch.device("cuda:0")
+    wl = make_workload(args.workload)
+    N = wl.nodes
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    k2, tau, gam = t(wl.kappa2, torch.float64), t(wl.tau, torch.float64), t(wl.gamma, torch.float64)
+    q = t(wl.rhs(), torch.complex128)
+    a = torch.empty(wl.shape, dtype=torch.complex128, device=dev)
+    u = torch.empty_like(a)
+    torch.cuda.synchronize()
+
+    ctxs, setup_ms = {}, {}
+    for prec in ("mixed", "fp64"):
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        ctxs[prec] = adr.Context(k2, tau, gam, wl.h, wl.omega, wl.src, options=adr.default_options(prec=prec))
+        torch.cuda.synchronize()
+        setup_ms[prec] = (time.perf_counter() - s0) * 1e3
+        log(f"setup {prec}: {setup_ms[prec]:.0f} ms, {ctxs[prec].num_levels} levels")
+
+    def step(ctx):
+        _, st = ctx.solve(q, tol=TOL, maxit=500, out=a)
+        ctx.wavefield(a, out=u)
+        if st["status"] != adr.ADR_OK or not st["relres"] <= TOL:
+            raise RuntimeError(f"solve did not converge: {st}")
+        return st
+
+    def timed(ctx, steps, warmup):
+        for _ in range(warmup):
+            step(ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sts = [step(ctx) for _ in range(steps)]
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps, sts
+
+    ms_mixed, st_mixed = timed(ctxs["mixed"], args.steps, args.warmup)
+    log(f"mixed: {ms_mixed:.2f} ms/solve, {st_mixed[-1]['outer_iters']} iterations")
+    ms_fp64, st_fp64 = timed(ctxs["fp64"], max(1, min(args.steps, 3)), 1)
+    log(f"fp64: {ms_fp64:.2f} ms/solve, {st_fp64[-1]['outer_iters']} iterations")
+    if args.profile_only:
+        print(json.dumps({"ms_mixed": ms_mixed, "ms_fp64": ms_fp64}))
+        return
+
+    # Kernel-class breakdown of one mixed solve (HIP events around each launch of a class,
+    # on the context stream), then the V-cycle alone.
+    classes = list(adr.TIMER_KINDS)
+    breakdown = {}
+    ctx = ctxs["mixed"]
+    for cls in classes:
+        ctx.timer_start(cls)
+        step(ctx)
+        ms, n, by = ctx.timer_stop()
+        breakdown[cls] = {"ms": ms, "launches": n, "bytes": by}
+    dominant = max(breakdown, key=lambda c: breakdown[c]["ms"])
+    dm = breakdown[dominant]
+    avg_ms = dm["ms"] / max(dm["launches"], 1)
+    avg_bytes = dm["bytes"] / max(dm["launches"], 1)
+    achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
+
+    # V-cycle alone: algorithmic bytes summed over its kernel classes, time by events.
+    r = torch.randn(wl.shape, dtype=torch.complex128, device=dev)
+    z = torch.empty_like(r)
+    vc_bytes = 0.0
+    for cls in classes[:5]:
+        ctx.timer_start(cls)
+        ctx.vcycle(r, out=z)
+        _, _, by = ctx.timer_stop()
+        vc_bytes += by
+    reps = 20
+    for _ in range(3):
+        ctx.vcycle(r, out=z)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        ctx.vcycle(r, out=z)
+    e1.record()
+    torch.cuda.synchronize()
+    vc_ms = e0.elapsed_time(e1) / reps
+
+    iters_m = st_mixed[-1]["outer_iters"]
+    iters_d = st_fp64[-1]["outer_iters"]
+    value = N / (ms_mixed * 1e-3) / 1e6
+    fp64_value = N / (ms_fp64 * 1e-3) / 1e6
+    out = {
+        "metric": "ADR amplitude solves: Mpoints/s to 1e-6 residual, mixed vs FP64; V-cycle HBM GB/s",
+        "value": value,
+        "unit": "Mpoints/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_mixed,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64 V-cycle / c128 FGMRES",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "grid": list(wl.shape), "nodes": N, "omega": wl.omega,
+                   "tol": TOL, "restart": 5, "levels": ctx.num_levels, "precision": "mixed"},
+        "fp64": {"value": fp64_value, "ms_per_step": ms_fp64, "outer_iters": iters_d},
+        "mixed_over_fp64": value / fp64_value,
+        "outer_iters": iters_m,
+        "final_relres": st_mixed[-1]["relres"],
+        "setup_ms": setup_ms,
+        "vcycle": {"ms": vc_ms, "algorithmic_bytes": vc_bytes, "GBps": vc_bytes / (vc_ms * 1e-3) / 1e9,
+                   "frac": vc_bytes / (vc_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS},
+        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": avg_bytes},
+        "breakdown_ms": {c: round(v["ms"], 4) for c, v in breakdown.items()},
+    }
+    log(f"breakdown done, dominant {dominant}; V-cycle {vc_ms:.3f} ms")
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, one thread) ...")
+        out["cpu_baseline"] = cpu_baseline(args, N, iters_d)
+    for c in ctxs.values():
+        c.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

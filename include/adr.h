@@ -2,7 +2,7 @@
  * adr.h -- C ABI of the MI355X ADR-amplitude solver.
  *
  * Solves the point-source Helmholtz equation in the factored form of Treister & Haber,
- * "A fast marching algorithm ... / ADR amplitude" (arXiv:1712.06091):
+ * arXiv:1712.06091:
  *   u = a exp(-i w tau)                                    (Sec. 1, eq. new_u)
  *   Lap a - 2 i w grad(tau).grad(a) - i w (Lap tau) a
  *        - w^2 (|grad tau|^2 - kappa^2) a - i w gamma kappa^2 a = q exp(i w tau)
@@ -82,7 +82,7 @@ typedef struct {
   adr_relax relax[8];   /* default JACOBI on level 0, GMRES on coarser levels            */
   double jacobi_weight; /* default 0.8                                                    */
   double beta;          /* preconditioner blend of eq. precADRup; default 0.25 (Sec. 4.2) */
-  int restart;          /* FGMRES restart length m; default 5 (Sec. 4.2); max 16          */
+  int restart;          /* FGMRES restart length m; default 5 (Sec. 4.2); max 8           */
   int use_graph;        /* capture each V-cycle in a hipGraph; default 1                 */
 } adr_options;
 
@@ -145,6 +145,27 @@ int adr_num_levels(const adr_ctx *ctx);
  * offsets[3p..3p+2] = (dx, dy, dz); offsets is a HOST int array of 3*stencil_points
  * (may be NULL).  Entries that point outside the grid are zero. */
 adr_status adr_get_level_stencil(adr_ctx *ctx, int level, void *planes_c128, int *offsets);
+
+/* Kernel classes that adr_timer_start can time. */
+typedef enum {
+  ADR_TIMER_FINE_JACOBI = 0,    /* damped Jacobi sweep on the matrix-free finest level    */
+  ADR_TIMER_FINE_RESIDUAL = 1,  /* V-cycle residual on the finest level                   */
+  ADR_TIMER_COARSE_APPLY = 2,   /* Galerkin-stencil apply (GMRES relaxation and residual) */
+  ADR_TIMER_COARSE_ORTH = 3,    /* GMRES-relaxation orthogonalization step               */
+  ADR_TIMER_TRANSFER = 4,       /* restriction and prolongation                           */
+  ADR_TIMER_OUTER_MATVEC = 5,   /* FP64 H_2up apply with fused Arnoldi dots (FGMRES)      */
+  ADR_TIMER_OUTER_ORTH = 6      /* FP64 Gram-Schmidt passes of the outer FGMRES           */
+} adr_timer_kind;
+
+/* Benchmark instrumentation.  adr_timer_start(ctx, kind, level) makes every later launch
+ * of that kernel class (on `level`, or on any level if level < 0) record a pair of HIP
+ * events on the context stream, up to 8192 launches.  adr_timer_stop synchronizes the
+ * stream and returns (host out-params, any may be NULL) the summed kernel time in ms,
+ * the number of timed launches and their algorithmic bytes: every array the kernel reads
+ * or writes counted once per node (stencil neighbours of a vector count once).  Timing
+ * adds an event record before and after each timed launch and nothing else. */
+adr_status adr_timer_start(adr_ctx *ctx, int kind, int level);
+adr_status adr_timer_stop(adr_ctx *ctx, double *ms, int *launches, double *bytes);
 
 const char *adr_strerror(adr_status s);
 const char *adr_last_error(const adr_ctx *ctx);   /* NULL ctx: last setup error */

@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(HERE, "libadr.so")
 ADR_OK, ADR_EINVAL, ADR_ENOMEM, ADR_EHIP, ADR_ENOCONV, ADR_ENUMERIC, ADR_ENOTSUP = range(7)
 ADR_PREC_FP64, ADR_PREC_MIXED = 0, 1
 ADR_RELAX_JACOBI, ADR_RELAX_GMRES = 0, 1
+TIMER_KINDS = {"fine_jacobi": 0, "fine_residual": 1, "coarse_apply": 2, "coarse_orth": 3, "transfer": 4,
+               "outer_matvec": 5, "outer_orth": 6}
 
 
 class AdrProblem(ctypes.Structure):
@@ -90,6 +92,9 @@ def load_library(path=LIB_PATH):
         "adr_level_info": (I, [P, I, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
         "adr_num_levels": (I, [P]),
         "adr_get_level_stencil": (I, [P, I, P, ctypes.POINTER(ctypes.c_int)]),
+        "adr_timer_start": (I, [P, I, I]),
+        "adr_timer_stop": (I, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
+                               ctypes.POINTER(ctypes.c_double)]),
         "adr_strerror": (ctypes.c_char_p, [I]),
         "adr_last_error": (ctypes.c_char_p, [P]),
     }
@@ -240,6 +245,16 @@ class Context:
         _check(self._lib.adr_get_coefficients(self._ptr, _dev(g, torch.float64), _dev(L, torch.float64),
                                               _dev(c, torch.complex128)), self._ptr)
         return g, L, c
+
+    def timer_start(self, kind, level=-1):
+        kind = TIMER_KINDS.get(kind, kind)
+        _check(self._lib.adr_timer_start(self._ptr, int(kind), int(level)), self._ptr)
+
+    def timer_stop(self):
+        """(total kernel ms, launches, algorithmic bytes) since timer_start."""
+        ms, n, by = ctypes.c_double(), ctypes.c_int(), ctypes.c_double()
+        _check(self._lib.adr_timer_stop(self._ptr, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by)), self._ptr)
+        return ms.value, n.value, by.value
 
     @property
     def num_levels(self):

@@ -46,7 +46,8 @@ struct LevelT {
   cx<T> *planes = nullptr;   // S x N
   cx<T> *dinv = nullptr;
   cx<T> *x = nullptr, *xt = nullptr, *b = nullptr, *r = nullptr, *w = nullptr;
-  cx<T> *V = nullptr;        // (kMaxNu+1) x N
+  cx<T> *V = nullptr;        // (kMaxNu+1) x N Arnoldi basis (unnormalized)
+  cx<T> *Z = nullptr;        // (kMaxNu+1) x N, Z_j = D^{-1} V_j
 };
 
 }  // namespace
@@ -78,7 +79,7 @@ struct adr_ctx {
   int *off_fine = nullptr;     // device xyz table of the fine stencil (Galerkin input)
   std::vector<int> h_off_coarse;
   int S_coarse = 0;
-  cx<double> *Ainv = nullptr;  // coarsest inverse, column-major
+  cx<double> *Ainv = nullptr;  // coarsest inverse, row-major
   int Ncoarsest = 0;
 
   // scalars and reductions
@@ -92,6 +93,15 @@ struct adr_ctx {
   void *Zo = nullptr;          // kMaxRestart x N, c64 (mixed) or c128
   cx<double> *wo = nullptr, *ro = nullptr, *qh = nullptr;
   cx<float> *b32 = nullptr, *z32 = nullptr;   // mixed-mode V-cycle in/out staging
+
+  // Event timing of one kernel class (benchmarks): pairs of events recorded on `stream`
+  // around every launch of that class, plus the algorithmic bytes those launches move.
+  struct {
+    int kind = -1, level = -1;
+    std::vector<hipEvent_t> ev;
+    int used = 0, launches = 0;
+    double bytes = 0.0;
+  } timer;
   std::string err;
 };
 
@@ -185,9 +195,9 @@ Triples galerkin_triples(int D, const std::vector<int> &in, const std::vector<in
 }
 
 // Dense complex inverse by Gauss-Jordan elimination with partial pivoting (host,
-// FP64; the coarsest grid has at most a few thousand nodes).  A is row-major n x n;
-// on return inv is column-major.
-bool dense_inverse(int n, std::vector<std::complex<double>> &A, std::vector<std::complex<double>> &inv_colmajor) {
+// FP64; the coarsest grid has at most a few thousand nodes).  A and the inverse are
+// row-major n x n.
+bool dense_inverse(int n, std::vector<std::complex<double>> &A, std::vector<std::complex<double>> &inv) {
   std::vector<std::complex<double>> I((size_t)n * n, 0.0);
   for (int i = 0; i < n; ++i) I[(size_t)i * n + i] = 1.0;
   for (int k = 0; k < n; ++k) {
@@ -221,9 +231,7 @@ bool dense_inverse(int n, std::vector<std::complex<double>> &A, std::vector<std:
       }
     }
   }
-  inv_colmajor.assign((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) inv_colmajor[(size_t)j * n + i] = I[(size_t)i * n + j];
+  inv.swap(I);
   return true;
 }
 
@@ -267,18 +275,28 @@ FineParams fine_params(adr_ctx *ctx, double beta) {
   return P;
 }
 
-template <typename T>
-Stencil<T> stencil_of(adr_ctx *ctx, const LevelT<T> &L) {
-  Stencil<T> s;
-  s.planes = L.planes;
-  s.S = L.S;
-  s.centre = (L.S - 1) / 2;
-  s.off_lin = nullptr;
-  s.off_xyz = ctx->off_coarse;
-  return s;
-}
-
 double *lscal(adr_ctx *ctx, int l) { return ctx->scal + (size_t)l * kScalPerLevel; }
+
+// Timed-launch brackets: tbegin returns an event slot (or -1 when this launch is not the
+// timed class), tend records the closing event and the launch's algorithmic bytes.
+int tbegin(adr_ctx *ctx, int kind, int level) {
+  auto &T = ctx->timer;
+  if (T.kind != kind || (T.level >= 0 && T.level != level)) return -1;
+  if (T.used + 2 > (int)T.ev.size()) return -1;   // pool exhausted: stop timing
+  hipEventRecord(T.ev[T.used], ctx->stream);
+  return T.used;
+}
+void tend(adr_ctx *ctx, int slot, double bytes) {
+  if (slot < 0) return;
+  auto &T = ctx->timer;
+  hipEventRecord(T.ev[slot + 1], ctx->stream);
+  T.used = slot + 2;
+  T.launches += 1;
+  T.bytes += bytes;
+}
+// Per-node coefficient bytes of the matrix-free fine operator: D gradient planes, L, c.
+template <typename T>
+double fine_coef_bytes(int D) { return (double)(D + 3) * sizeof(T); }
 
 // Allocate the per-level vectors and convert/store the stencil in precision T.
 template <typename T>
@@ -291,6 +309,7 @@ adr_status alloc_level_vectors(adr_ctx *ctx, LevelT<T> &L, int l) {
   if (l > 0) {
     ADR_TRY(dalloc(ctx, &L.w, N));
     ADR_TRY(dalloc(ctx, &L.V, N * (kMaxNu + 1)));
+    ADR_TRY(dalloc(ctx, &L.Z, N * (kMaxNu + 1)));
   }
   return ADR_OK;
 }
@@ -306,24 +325,57 @@ VecSet<T> vecset(std::initializer_list<const cx<T> *> v) {
   return s;
 }
 
-// GMRES relaxation on level l >= 1: x_out = x0 + D^{-1} V y (Sec. 4.2).
+// Finish a reduction whose producer launched `nb` blocks of K partials.
+void fin_norm_inv(adr_ctx *ctx, int nb, double *norm, double *inv) {
+  FinishArgs A{};
+  A.nb = nb;
+  A.K = 1;
+  A.action = FIN_NORM_INV;
+  A.out = norm;
+  A.out_inv = inv;
+  adrk::finish(ctx->stream, A, ctx->rs);
+}
+template <typename T>
+void fin_dots(adr_ctx *ctx, int nb, const VecSet<T> &V, bool norm, double *out, double *inv = nullptr) {
+  FinishArgs A{};
+  A.nb = nb;
+  A.nv = V.count;
+  A.K = 2 * V.count + (norm ? 1 : 0);
+  A.action = FIN_DOTS;
+  for (int i = 0; i < V.count; ++i) A.scale[i] = V.scale[i];
+  A.out = out;
+  A.out_inv = inv;
+  adrk::finish(ctx->stream, A, ctx->rs);
+}
+
+// GMRES relaxation on level l >= 1 (Sec. 4.2): x_out = x0 + D^{-1} V y, y the
+// least-squares minimizer over the Krylov space of A D^{-1} and b - A x0.  The basis V is
+// kept unnormalized with scale factors s_j on the device, and Z_j = D^{-1} V_j is written
+// next to it so the stencil apply gathers a single vector.
 template <typename T>
 void gmres_relax(adr_ctx *ctx, int l, const cx<T> *x0, const cx<T> *b, cx<T> *x_out) {
   LevelT<T> &L = levels_of<T>(ctx)[l];
   hipStream_t s = ctx->stream;
-  const int N = L.G.N, nu = ctx->nu[l];
+  const int N = L.G.N, nu = ctx->nu[l], D = ctx->D;
+  const double cb = sizeof(cx<T>);
   double *sc = lscal(ctx, l);
-  Stencil<T> A = stencil_of(ctx, L);
   const cx<T> *Vp[kMaxNu + 1];
-  for (int j = 0; j <= nu; ++j) Vp[j] = L.V + (size_t)j * N;
+  cx<T> *Zp[kMaxNu + 1];
+  for (int j = 0; j <= nu; ++j) {
+    Vp[j] = L.V + (size_t)j * N;
+    Zp[j] = L.Z + (size_t)j * N;
+  }
+  int nb;
   if (!x0) {
     Vp[0] = b;
-    adrk::norm_inv<T>(s, N, b, sc + kBeta, sc + kS, ctx->rs);
+    nb = adrk::norm2<T>(s, N, b, L.dinv, Zp[0], ctx->rs);
   } else {
-    // V0 = b - A x0, then its norm.
-    adrk::coarse_apply<T>(s, L.G, ctx->D, A, x0, nullptr, nullptr, b, L.V, 1, nullptr, false, nullptr, ctx->rs);
-    adrk::norm_inv<T>(s, N, L.V, sc + kBeta, sc + kS, ctx->rs);
+    int t0 = tbegin(ctx, ADR_TIMER_COARSE_APPLY, l);
+    adrk::coarse_apply<T>(s, L.G, D, L.planes, x0, nullptr, b, L.V, 1, nullptr, false, ctx->rs);
+    tend(ctx, t0, (double)N * cb * (L.S + 3));
+    nb = adrk::norm2<T>(s, N, L.V, L.dinv, Zp[0], ctx->rs);
   }
+  fin_norm_inv(ctx, nb, sc + kBeta, sc + kS);
   for (int j = 0; j < nu; ++j) {
     VecSet<T> Vs{};
     Vs.count = j + 1;
@@ -332,16 +384,35 @@ void gmres_relax(adr_ctx *ctx, int l, const cx<T> *x0, const cx<T> *b, cx<T> *x_
       Vs.scale[i] = sc + kS + i;
     }
     double *hcol = sc + kH + 2 * (j * kLdH);
-    adrk::coarse_apply<T>(s, L.G, ctx->D, A, Vp[j], sc + kS + j, L.dinv, nullptr, L.w, 0, &Vs, false, hcol,
-                          ctx->rs);
-    adrk::orth_step<T>(s, N, L.w, Vs, hcol, L.V + (size_t)(j + 1) * N, hcol + 2 * (j + 1), sc + kS + j + 1,
-                       ctx->rs);
+    int t0 = tbegin(ctx, ADR_TIMER_COARSE_APPLY, l);
+    nb = adrk::coarse_apply<T>(s, L.G, D, L.planes, Zp[j], sc + kS + j, nullptr, L.w, 0, &Vs, false, ctx->rs);
+    tend(ctx, t0, (double)N * cb * (L.S + 2 + (j + 1)));
+    fin_dots<T>(ctx, nb, Vs, false, hcol);
+    int t1 = tbegin(ctx, ADR_TIMER_COARSE_ORTH, l);
+    nb = adrk::orth_step<T>(s, N, L.w, Vs, hcol, L.dinv, L.V + (size_t)(j + 1) * N, Zp[j + 1], ctx->rs);
+    tend(ctx, t1, (double)N * cb * (j + 5));
+    FinishArgs A{};
+    A.nb = nb;
+    A.K = 1;
+    A.action = FIN_ORTH;
+    A.out = hcol + 2 * (j + 1);
+    A.out_inv = sc + kS + j + 1;
+    if (j == nu - 1) {
+      A.lsq_k = nu;
+      A.H = sc + kH;
+      A.ldh = kLdH;
+      A.beta = sc + kBeta;
+      A.s = sc + kS;
+      A.coef = sc + kCoef;
+    }
+    adrk::finish(s, A, ctx->rs);
   }
-  adrk::gmres_lsq(s, sc + kH, kLdH, nu, sc + kBeta, sc + kS, sc + kCoef);
-  VecSet<T> Vs{};
-  Vs.count = nu;
-  for (int i = 0; i < nu; ++i) Vs.v[i] = Vp[i];
-  adrk::gmres_update<T>(s, N, x0, L.dinv, Vs, sc + kCoef, x_out);
+  VecSet<T> Zs{};
+  Zs.count = nu;
+  for (int i = 0; i < nu; ++i) Zs.v[i] = Zp[i];
+  int t2 = tbegin(ctx, ADR_TIMER_COARSE_ORTH, l);
+  adrk::gmres_update<T>(s, N, x0, Zs, sc + kCoef, x_out);
+  tend(ctx, t2, (double)N * cb * (nu + (x0 ? 2 : 1)));
 }
 
 // Jacobi sweeps on the matrix-free level 0: sweep k writes `first` for even k and
@@ -356,7 +427,9 @@ cx<T> *jacobi_sweeps(adr_ctx *ctx, int nu, const cx<T> *x_start, const cx<T> *b,
   cx<T> *out = first;
   for (int k = 0; k < nu; ++k) {
     out = (k % 2 == 0) ? first : second;
+    int t0 = tbegin(ctx, ADR_TIMER_FINE_JACOBI, 0);
     adrk::fine_jacobi<T>(ctx->stream, G, ctx->D, C, P, in, b, out, ctx->opt.jacobi_weight);
+    tend(ctx, t0, (double)G.N * (fine_coef_bytes<T>(ctx->D) + sizeof(cx<T>) * (in ? 3 : 2)));
     in = out;
   }
   return out;
@@ -387,16 +460,24 @@ cx<T> *vcycle(adr_ctx *ctx, int l, const cx<T> *b, cx<T> *out0) {
   }
   // residual and restriction
   LevelT<T> &C = lv[l + 1];
+  const double cb = sizeof(cx<T>);
   if (l == 0) {
+    int t0 = tbegin(ctx, ADR_TIMER_FINE_RESIDUAL, 0);
     adrk::fine_apply<T, T, T>(s, L.G, D, fine_coef<T>(ctx), fine_params(ctx, ctx->opt.beta), x, b, L.r, 1, nullptr,
-                              false, nullptr, ctx->rs);
+                              false, ctx->rs);
+    tend(ctx, t0, (double)L.G.N * (fine_coef_bytes<T>(D) + 3 * cb));
   } else {
-    adrk::coarse_apply<T>(s, L.G, D, stencil_of(ctx, L), x, nullptr, nullptr, b, L.r, 1, nullptr, false, nullptr,
-                          ctx->rs);
+    int t0 = tbegin(ctx, ADR_TIMER_COARSE_APPLY, l);
+    adrk::coarse_apply<T>(s, L.G, D, L.planes, x, nullptr, b, L.r, 1, nullptr, false, ctx->rs);
+    tend(ctx, t0, (double)L.G.N * cb * (L.S + 3));
   }
+  int t1 = tbegin(ctx, ADR_TIMER_TRANSFER, l);
   adrk::restrict_full<T>(s, L.G, C.G, D, L.r, C.b);
+  tend(ctx, t1, cb * ((double)L.G.N + C.G.N));
   cx<T> *ec = vcycle<T>(ctx, l + 1, C.b, nullptr);
+  int t2 = tbegin(ctx, ADR_TIMER_TRANSFER, l);
   adrk::prolong_add<T>(s, L.G, C.G, D, ec, x);
+  tend(ctx, t2, cb * ((double)C.G.N + 2.0 * L.G.N));
   // post-relaxation
   if (ctx->relax[l] == ADR_RELAX_JACOBI && l == 0) {
     cx<T> *other = (x == xa) ? L.xt : xa;
@@ -618,8 +699,8 @@ void free_ctx(adr_ctx *ctx) {
     LevelT<double> &a = ctx->lv64[l];
     LevelT<float> &b = ctx->lv32[l];
     for (void *p : {(void *)a.planes, (void *)a.dinv, (void *)a.x, (void *)a.xt, (void *)a.b, (void *)a.r,
-                    (void *)a.w, (void *)a.V, (void *)b.planes, (void *)b.dinv, (void *)b.x, (void *)b.xt,
-                    (void *)b.b, (void *)b.r, (void *)b.w, (void *)b.V})
+                    (void *)a.w, (void *)a.V, (void *)a.Z, (void *)b.planes, (void *)b.dinv, (void *)b.x,
+                    (void *)b.xt, (void *)b.b, (void *)b.r, (void *)b.w, (void *)b.V, (void *)b.Z})
       F(p);
   }
   F(ctx->off_coarse);
@@ -629,7 +710,6 @@ void free_ctx(adr_ctx *ctx) {
   F(ctx->osc);
   if (ctx->hpin) hipHostFree(ctx->hpin);
   F(ctx->rs.partials);
-  F(ctx->rs.counter);
   F(ctx->Vo);
   F(ctx->Zo);
   F(ctx->wo);
@@ -637,6 +717,7 @@ void free_ctx(adr_ctx *ctx) {
   F(ctx->qh);
   F(ctx->b32);
   F(ctx->z32);
+  for (auto &e : ctx->timer.ev) hipEventDestroy(e);
   delete ctx;
 }
 
@@ -653,9 +734,7 @@ adr_status setup_impl(adr_ctx *ctx, const adr_problem *p) {
                      ctx->g64[1], D == 3 ? ctx->g64[2] : nullptr, ctx->L64, ctx->c64);
   ADR_HIP(hipGetLastError());
   // Reduction scratch and scalars.
-  ADR_TRY(dalloc(ctx, &ctx->rs.partials, (size_t)ADR_MAX_BLOCKS * ADR_MAX_RED));
-  ADR_TRY(dalloc(ctx, &ctx->rs.counter, 1));
-  ADR_HIP(hipMemsetAsync(ctx->rs.counter, 0, sizeof(unsigned int), s));
+  ADR_TRY(dalloc(ctx, &ctx->rs.partials, (size_t)ADR_MAX_RED_BLOCKS * ADR_MAX_RED));
   ADR_TRY(dalloc(ctx, &ctx->scal, (size_t)kMaxLevels * kScalPerLevel));
   ADR_HIP(hipMemsetAsync(ctx->scal, 0, sizeof(double) * kMaxLevels * kScalPerLevel, s));
   ADR_TRY(dalloc(ctx, &ctx->osc, 64));
@@ -823,7 +902,7 @@ adr_status adr_apply(adr_ctx *ctx, double beta, const void *x, void *y) {
   if (!ctx || !x || !y || x == y) return ADR_EINVAL;
   adrk::fine_apply<double, double, double>(ctx->stream, ctx->G0, ctx->D, fine_coef<double>(ctx),
                                            fine_params(ctx, beta), (const cx<double> *)x, nullptr, (cx<double> *)y,
-                                           0, nullptr, false, nullptr, ctx->rs);
+                                           0, nullptr, false, ctx->rs);
   ADR_HIP(hipGetLastError());
   return ADR_OK;
 }
@@ -868,11 +947,12 @@ adr_status adr_solve(adr_ctx *ctx, const void *q, void *a_out, double tol, int m
 
   // q_hat = q exp(i w tau)
   adrk::phase(s, N, (const cx<double> *)q, ctx->tau, ctx->omega, +1, ctx->qh);
-  adrk::norm_inv<double>(s, N, ctx->qh, osc + 0, nullptr, ctx->rs);
+  fin_norm_inv(ctx, adrk::norm2<double>(s, N, ctx->qh, nullptr, nullptr, ctx->rs), osc + 0, nullptr);
   // initial residual
   if (use_initial_guess) {
-    adrk::fine_apply<double, double, double>(s, ctx->G0, D, C, P0, x, ctx->qh, ctx->ro, 1, nullptr, true, osc + 1,
-                                             ctx->rs);
+    int nb = adrk::fine_apply<double, double, double>(s, ctx->G0, D, C, P0, x, ctx->qh, ctx->ro, 1, nullptr, true,
+                                                      ctx->rs);
+    fin_norm_inv(ctx, nb, osc + 1, nullptr);
   } else {
     ADR_HIP(hipMemsetAsync(x, 0, sizeof(cx<double>) * N, s));
     ADR_HIP(hipMemcpyAsync(ctx->ro, ctx->qh, sizeof(cx<double>) * N, hipMemcpyDeviceToDevice, s));
@@ -908,14 +988,28 @@ adr_status adr_solve(adr_ctx *ctx, const void *q, void *a_out, double tol, int m
       Vs.count = j + 1;
       for (int i = 0; i <= j; ++i) Vs.v[i] = Vp(i);
       double *red1 = osc + 2, *red2 = osc + 2 + 2 * (kMaxRestart + 1);
+      int t0 = tbegin(ctx, ADR_TIMER_OUTER_MATVEC, 0);
+      int nb;
       if (mixed)
-        adrk::fine_apply<double, float, double>(s, ctx->G0, D, C, P0, (const cx<float> *)Zp(j), nullptr, ctx->wo, 0,
-                                                &Vs, false, red1, ctx->rs);
+        nb = adrk::fine_apply<double, float, double>(s, ctx->G0, D, C, P0, (const cx<float> *)Zp(j), nullptr,
+                                                     ctx->wo, 0, &Vs, false, ctx->rs);
       else
-        adrk::fine_apply<double, double, double>(s, ctx->G0, D, C, P0, (const cx<double> *)Zp(j), nullptr, ctx->wo,
-                                                 0, &Vs, false, red1, ctx->rs);
-      adrk::outer_orth1(s, N, ctx->wo, Vs, red1, red2, ctx->rs);
+        nb = adrk::fine_apply<double, double, double>(s, ctx->G0, D, C, P0, (const cx<double> *)Zp(j), nullptr,
+                                                      ctx->wo, 0, &Vs, false, ctx->rs);
+      tend(ctx, t0, (double)N * (fine_coef_bytes<double>(D) + (mixed ? 8.0 : 16.0) + 16.0 * (j + 2)));
+      fin_dots<double>(ctx, nb, Vs, false, red1);
+      int t1 = tbegin(ctx, ADR_TIMER_OUTER_ORTH, 0);
+      nb = adrk::outer_orth1(s, N, ctx->wo, Vs, red1, ctx->rs);
+      {
+        FinishArgs A{};
+        A.nb = nb;
+        A.K = 2 * (j + 1) + 1;
+        A.action = FIN_RAW;
+        A.out = red2;
+        adrk::finish(s, A, ctx->rs);
+      }
       adrk::outer_orth2(s, N, ctx->wo, Vs, red2, Vp(j + 1));
+      tend(ctx, t1, (double)N * 16.0 * (2 * (j + 1) + 4));
       const int nred = 2 * (kMaxRestart + 1) * 2 + 1;
       ADR_HIP(hipMemcpyAsync(hp + 2, red1, nred * sizeof(double), hipMemcpyDeviceToHost, s));
       ADR_HIP(hipStreamSynchronize(s));
@@ -977,8 +1071,9 @@ adr_status adr_solve(adr_ctx *ctx, const void *q, void *a_out, double tol, int m
       for (int i = 0; i < k; ++i) Zs.v[i] = (const cx<double> *)Zp(i);
       adrk::multi_axpy<double>(s, N, x, Zs, ydev);
     }
-    adrk::fine_apply<double, double, double>(s, ctx->G0, D, C, P0, x, ctx->qh, ctx->ro, 1, nullptr, true, osc + 1,
-                                             ctx->rs);
+    int nbr = adrk::fine_apply<double, double, double>(s, ctx->G0, D, C, P0, x, ctx->qh, ctx->ro, 1, nullptr, true,
+                                                       ctx->rs);
+    fin_norm_inv(ctx, nbr, osc + 1, nullptr);
     ADR_HIP(hipMemcpyAsync(hp + 1, osc + 1, sizeof(double), hipMemcpyDeviceToHost, s));
     ADR_HIP(hipStreamSynchronize(s));
     rnorm = hp[1];
@@ -994,6 +1089,39 @@ adr_status adr_solve(adr_ctx *ctx, const void *q, void *a_out, double tol, int m
   if (stats) *stats = st;
   if (result == ADR_ENOCONV) ctx->err = "FGMRES reached maxit before tol";
   return result;
+}
+
+adr_status adr_timer_start(adr_ctx *ctx, int kind, int level) {
+  if (!ctx || kind < 0 || kind > ADR_TIMER_OUTER_ORTH) return ADR_EINVAL;
+  auto &T = ctx->timer;
+  if (T.ev.empty()) {
+    T.ev.resize(2 * 8192);
+    for (auto &e : T.ev) ADR_HIP(hipEventCreate(&e));
+  }
+  T.kind = kind;
+  T.level = level;
+  T.used = 0;
+  T.launches = 0;
+  T.bytes = 0.0;
+  return ADR_OK;
+}
+
+adr_status adr_timer_stop(adr_ctx *ctx, double *ms, int *launches, double *bytes) {
+  if (!ctx) return ADR_EINVAL;
+  auto &T = ctx->timer;
+  ADR_HIP(hipStreamSynchronize(ctx->stream));
+  double total = 0.0;
+  for (int i = 0; i + 1 < T.used; i += 2) {
+    float t = 0.f;
+    ADR_HIP(hipEventElapsedTime(&t, T.ev[i], T.ev[i + 1]));
+    total += t;
+  }
+  if (ms) *ms = total;
+  if (launches) *launches = T.launches;
+  if (bytes) *bytes = T.bytes;
+  T.kind = -1;
+  T.used = 0;
+  return ADR_OK;
 }
 
 const char *adr_strerror(adr_status s) {

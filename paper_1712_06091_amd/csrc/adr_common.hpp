@@ -99,21 +99,31 @@ __device__ __forceinline__ void chunk_range(int N, int &beg, int &end) {
 }
 
 // ------------------------------------------------------------------------------------
-// Deterministic reductions: every block reduces its K doubles in a fixed tree, writes
-// them to partials[block*K + k], and the last block to arrive (device-scope counter)
-// sums the partials in block order and runs the finisher.  The counter is left at 0.
+// Deterministic reductions in two launches: every block reduces its K doubles in a
+// fixed tree and writes them to partials[block*K + k] (plain stores); a one-block
+// finish kernel, launched next on the same stream, sums the partials in block order.
+// (No device-scope fences or atomics: on a multi-XCD part those serialize through
+// memory and cost far more than the extra launch.)
 // ------------------------------------------------------------------------------------
 struct RedScratch {
-  double *partials;       // ADR_MAX_BLOCKS * ADR_MAX_RED
-  unsigned int *counter;  // one word, 0 between kernels
+  double *partials;       // ADR_MAX_RED_BLOCKS * ADR_MAX_RED
 };
+
+#define ADR_MAX_RED_BLOCKS 2048
+
+inline int launch_blocks_red(long long N) {
+  long long b = (N + ADR_BLOCK - 1) / ADR_BLOCK;
+  if (b > ADR_MAX_RED_BLOCKS) b = ADR_MAX_RED_BLOCKS;
+  if (b < 1) b = 1;
+  return (int)b;
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
   return v;
 }
 
-// Reduce acc[0..K) over the block into red[0..K) of thread 0 (other threads: undefined).
+// Reduce acc[0..K) over the block; thread 0 ends with the block totals.
 template <int KMAX>
 __device__ __forceinline__ void block_sum(double (&acc)[KMAX], int K, double *lds /*[KMAX*4]*/) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -128,35 +138,10 @@ __device__ __forceinline__ void block_sum(double (&acc)[KMAX], int K, double *ld
   __syncthreads();
 }
 
-__device__ __forceinline__ double load_coherent(const double *p) {
-  unsigned long long v = __hip_atomic_load((const unsigned long long *)p, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-  return __longlong_as_double((long long)v);
-}
-
-// Returns true in the (single) last block, with tot[0..K) holding the grand totals in
-// thread 0.  acc must already hold the per-thread contributions.
 template <int KMAX>
-__device__ bool reduce_last_block(double (&acc)[KMAX], int K, RedScratch rs, double (&tot)[KMAX]) {
+__device__ __forceinline__ void block_partials(double (&acc)[KMAX], int K, RedScratch rs) {
   __shared__ double lds[KMAX * 4];
-  __shared__ bool is_last;
   block_sum<KMAX>(acc, K, lds);
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0)
     for (int k = 0; k < K; ++k) rs.partials[(size_t)blockIdx.x * K + k] = acc[k];
-    __threadfence();
-    unsigned int prev = atomicAdd(rs.counter, 1u);
-    is_last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!is_last) return false;
-  __threadfence();
-  const int nb = gridDim.x;
-  for (int k = 0; k < K; ++k) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += load_coherent(rs.partials + (size_t)b * K + k);
-    tot[k] = s;
-  }
-  block_sum<KMAX>(tot, K, lds);
-  if (threadIdx.x == 0) *rs.counter = 0u;
-  return true;
 }

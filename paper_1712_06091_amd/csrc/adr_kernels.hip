@@ -232,7 +232,7 @@ template <typename T, typename Tin, typename To, int D, int NV, bool NORM>
 __global__ __launch_bounds__(ADR_BLOCK) void k_fine_apply(Grid G, FineCoef<T> C, FineParams P,
                                                           const cx<Tin> *__restrict__ x,
                                                           const cx<To> *__restrict__ b, cx<To> *__restrict__ y,
-                                                          int mode, VecSet<To> V, double *out, RedScratch rs) {
+                                                          int mode, VecSet<To> V, RedScratch rs) {
   constexpr int K = 2 * NV + (NORM ? 1 : 0);
   constexpr int KA = K > 0 ? K : 1;
   double red[KA];
@@ -265,34 +265,23 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_fine_apply(Grid G, FineCoef<T> C,
     }
     if (NORM) red[K - 1] += (double)o.re * o.re + (double)o.im * o.im;
   }
-  if (K > 0) {
-    double tot[KA];
-    if (reduce_last_block<KA>(red, K, rs, tot) && threadIdx.x == 0) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const double sc = V.scale[v] ? *V.scale[v] : 1.0;
-        out[2 * v] = sc * tot[2 * v];
-        out[2 * v + 1] = sc * tot[2 * v + 1];
-      }
-      if (NORM) out[K - 1] = sqrt(tot[K - 1]);
-    }
-  }
+  if (K > 0) block_partials<KA>(red, K, rs);
 }
 
 template <typename T, typename Tin, typename To, int D, int NV, bool NORM>
-static void launch_fine_apply(hipStream_t s, const Grid &G, const FineCoef<T> &C, const FineParams &P,
+static void launch_fine_apply(hipStream_t s, int nb, const Grid &G, const FineCoef<T> &C, const FineParams &P,
                               const cx<Tin> *x, const cx<To> *b, cx<To> *y, int mode, const VecSet<To> &V,
-                              double *out, RedScratch rs) {
-  ADR_LAUNCH((k_fine_apply<T, Tin, To, D, NV, NORM>), launch_blocks(G.N), s, G, C, P, x, b, y, mode, V, out, rs);
+                              RedScratch rs) {
+  ADR_LAUNCH((k_fine_apply<T, Tin, To, D, NV, NORM>), nb, s, G, C, P, x, b, y, mode, V, rs);
 }
 
 template <typename T, typename Tin, typename To, int D, bool NORM>
-static void dispatch_fine_apply_nv(hipStream_t s, const Grid &G, const FineCoef<T> &C, const FineParams &P,
-                                   const cx<Tin> *x, const cx<To> *b, cx<To> *y, int mode, const VecSet<To> &V,
-                                   double *out, RedScratch rs) {
+static void dispatch_fine_apply_nv(hipStream_t s, int nb, const Grid &G, const FineCoef<T> &C,
+                                   const FineParams &P, const cx<Tin> *x, const cx<To> *b, cx<To> *y, int mode,
+                                   const VecSet<To> &V, RedScratch rs) {
   switch (V.count) {
 #define ADR_NV_CASE(n) \
-  case n: launch_fine_apply<T, Tin, To, D, n, NORM>(s, G, C, P, x, b, y, mode, V, out, rs); break;
+  case n: launch_fine_apply<T, Tin, To, D, n, NORM>(s, nb, G, C, P, x, b, y, mode, V, rs); break;
     ADR_NV_CASE(0) ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6)
     ADR_NV_CASE(7) ADR_NV_CASE(8)
 #undef ADR_NV_CASE
@@ -301,30 +290,30 @@ static void dispatch_fine_apply_nv(hipStream_t s, const Grid &G, const FineCoef<
 }
 
 template <typename T, typename Tin, typename To>
-void fine_apply(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P, const cx<Tin> *x,
-                const cx<To> *b, cx<To> *y, int mode, const VecSet<To> *dots, bool want_norm, double *out,
-                RedScratch rs) {
+int fine_apply(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P, const cx<Tin> *x,
+               const cx<To> *b, cx<To> *y, int mode, const VecSet<To> *dots, bool want_norm, RedScratch rs) {
   VecSet<To> V{};
   if (dots) V = *dots;
+  const bool red = want_norm || V.count > 0;
+  const int nb = red ? launch_blocks_red(G.N) : launch_blocks(G.N);
   if (D == 2) {
-    if (want_norm) dispatch_fine_apply_nv<T, Tin, To, 2, true>(s, G, C, P, x, b, y, mode, V, out, rs);
-    else dispatch_fine_apply_nv<T, Tin, To, 2, false>(s, G, C, P, x, b, y, mode, V, out, rs);
+    if (want_norm) dispatch_fine_apply_nv<T, Tin, To, 2, true>(s, nb, G, C, P, x, b, y, mode, V, rs);
+    else dispatch_fine_apply_nv<T, Tin, To, 2, false>(s, nb, G, C, P, x, b, y, mode, V, rs);
   } else {
-    if (want_norm) dispatch_fine_apply_nv<T, Tin, To, 3, true>(s, G, C, P, x, b, y, mode, V, out, rs);
-    else dispatch_fine_apply_nv<T, Tin, To, 3, false>(s, G, C, P, x, b, y, mode, V, out, rs);
+    if (want_norm) dispatch_fine_apply_nv<T, Tin, To, 3, true>(s, nb, G, C, P, x, b, y, mode, V, rs);
+    else dispatch_fine_apply_nv<T, Tin, To, 3, false>(s, nb, G, C, P, x, b, y, mode, V, rs);
   }
+  return nb;
 }
-template void fine_apply<double, double, double>(hipStream_t, const Grid &, int, const FineCoef<double> &,
-                                                 const FineParams &, const cx<double> *, const cx<double> *,
-                                                 cx<double> *, int, const VecSet<double> *, bool, double *,
-                                                 RedScratch);
-template void fine_apply<double, float, double>(hipStream_t, const Grid &, int, const FineCoef<double> &,
-                                                const FineParams &, const cx<float> *, const cx<double> *,
-                                                cx<double> *, int, const VecSet<double> *, bool, double *,
-                                                RedScratch);
-template void fine_apply<float, float, float>(hipStream_t, const Grid &, int, const FineCoef<float> &,
-                                              const FineParams &, const cx<float> *, const cx<float> *,
-                                              cx<float> *, int, const VecSet<float> *, bool, double *, RedScratch);
+template int fine_apply<double, double, double>(hipStream_t, const Grid &, int, const FineCoef<double> &,
+                                                const FineParams &, const cx<double> *, const cx<double> *,
+                                                cx<double> *, int, const VecSet<double> *, bool, RedScratch);
+template int fine_apply<double, float, double>(hipStream_t, const Grid &, int, const FineCoef<double> &,
+                                               const FineParams &, const cx<float> *, const cx<double> *,
+                                               cx<double> *, int, const VecSet<double> *, bool, RedScratch);
+template int fine_apply<float, float, float>(hipStream_t, const Grid &, int, const FineCoef<float> &,
+                                             const FineParams &, const cx<float> *, const cx<float> *,
+                                             cx<float> *, int, const VecSet<float> *, bool, RedScratch);
 
 template <typename T, int D>
 __global__ __launch_bounds__(ADR_BLOCK) void k_fine_jacobi(Grid G, FineCoef<T> C, FineParams P,
@@ -371,37 +360,64 @@ template void fine_jacobi<float>(hipStream_t, const Grid &, int, const FineCoef<
 // =====================================================================================
 // Coarse levels: stored Galerkin stencils (SoA planes)
 // =====================================================================================
+// The coarse stencil set: offsets with |d_k| <= 2 and at most one |d_k| == 2, ordered
+// dz-major then dy then dx (81 points in 3D, 21 in 2D).  Compile-time table so that the
+// fully unrolled apply has constant offsets.
+template <int D>
+struct OffTable {
+  int dx[81], dy[81], dz[81];
+};
+template <int D>
+__host__ __device__ constexpr OffTable<D> make_off_table() {
+  OffTable<D> t{};
+  int c = 0;
+  for (int z = (D == 3 ? -2 : 0); z <= (D == 3 ? 2 : 0); ++z)
+    for (int y = -2; y <= 2; ++y)
+      for (int x = -2; x <= 2; ++x) {
+        const int twos = (x == 2 || x == -2) + (y == 2 || y == -2) + (z == 2 || z == -2);
+        if (twos > 1) continue;
+        t.dx[c] = x;
+        t.dy[c] = y;
+        t.dz[c] = z;
+        ++c;
+      }
+  return t;
+}
+
+// mode 0: y = xscale * (A x);  mode 1: y = b - A x.  Neighbour indices are clamped per
+// axis (the matching stencil entries are exactly zero outside the grid).
 template <typename T, int D, int NV, bool NORM>
-__global__ __launch_bounds__(ADR_BLOCK) void k_coarse_apply(Grid G, Stencil<T> A, const cx<T> *__restrict__ x,
-                                                            const double *xscale, const cx<T> *__restrict__ dinv,
+__global__ __launch_bounds__(ADR_BLOCK) void k_coarse_apply(Grid G, const cx<T> *__restrict__ planes,
+                                                            const cx<T> *__restrict__ x, const double *xscale,
                                                             const cx<T> *__restrict__ b, cx<T> *__restrict__ y,
-                                                            int mode, VecSet<T> V, double *out, RedScratch rs) {
+                                                            int mode, VecSet<T> V, RedScratch rs) {
+  constexpr int S = D == 3 ? 81 : 21;
+  constexpr OffTable<D> OT = make_off_table<D>();
   constexpr int K = 2 * NV + (NORM ? 1 : 0);
   constexpr int KA = K > 0 ? K : 1;
   double red[KA];
 #pragma unroll
   for (int k = 0; k < KA; ++k) red[k] = 0.0;
-  const T xs = xscale ? (T)(*xscale) : T(1);
+  const T xs = (mode == 0 && xscale) ? (T)(*xscale) : T(1);
   int beg, end;
   chunk_range(G.N, beg, end);
-  const int sy = G.n[0], sz = G.n[0] * G.n[1];
+  const int N = G.N, sy = G.n[0], sz = G.n[0] * G.n[1];
   for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
     int ix, iy, iz;
     decode(G, i, ix, iy, iz);
-    const bool inner = ix >= 2 && ix <= G.n[0] - 3 && iy >= 2 && iy <= G.n[1] - 3 &&
-                       (D == 2 || (iz >= 2 && iz <= G.n[2] - 3));
+    int X[5], Y[5], Z[5];
+#pragma unroll
+    for (int d = -2; d <= 2; ++d) {
+      X[d + 2] = min(max(ix + d, 0), G.n[0] - 1);
+      Y[d + 2] = sy * min(max(iy + d, 0), G.n[1] - 1);
+      Z[d + 2] = (D == 3) ? sz * min(max(iz + d, 0), G.n[2] - 1) : 0;
+    }
     cx<T> acc = mk<T>(T(0), T(0));
-    for (int p = 0; p < A.S; ++p) {
-      const int dx = A.off_xyz[3 * p], dy = A.off_xyz[3 * p + 1], dz = A.off_xyz[3 * p + 2];
-      int j = i + dx + sy * dy + sz * dz;
-      if (!inner) {
-        const bool ok = ix + dx >= 0 && ix + dx < G.n[0] && iy + dy >= 0 && iy + dy < G.n[1] && iz + dz >= 0 &&
-                        iz + dz < G.n[2];
-        j = ok ? j : i;
-      }
-      cx<T> xv = x[j];
-      if (mode == 0 && dinv) xv = xv * dinv[j];
-      acc = cfma(A.planes[(size_t)p * G.N + i], xv, acc);
+    const cx<T> *pl = planes + i;
+#pragma unroll
+    for (int p = 0; p < S; ++p) {
+      const int j = X[OT.dx[p] + 2] + Y[OT.dy[p] + 2] + Z[OT.dz[p] + 2];
+      acc = cfma(pl[(size_t)p * N], x[j], acc);
     }
     cx<T> o;
     if (mode == 0) o = xs * acc;
@@ -415,28 +431,16 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_coarse_apply(Grid G, Stencil<T> A
     }
     if (NORM) red[K - 1] += (double)o.re * o.re + (double)o.im * o.im;
   }
-  if (K > 0) {
-    double tot[KA];
-    if (reduce_last_block<KA>(red, K, rs, tot) && threadIdx.x == 0) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const double sc = V.scale[v] ? *V.scale[v] : 1.0;
-        out[2 * v] = sc * tot[2 * v];
-        out[2 * v + 1] = sc * tot[2 * v + 1];
-      }
-      if (NORM) out[K - 1] = sqrt(tot[K - 1]);
-    }
-  }
+  if (K > 0) block_partials<KA>(red, K, rs);
 }
 
 template <typename T, int D, bool NORM>
-static void dispatch_coarse_nv(hipStream_t s, const Grid &G, const Stencil<T> &A, const cx<T> *x, const double *xs,
-                               const cx<T> *dinv, const cx<T> *b, cx<T> *y, int mode, const VecSet<T> &V,
-                               double *out, RedScratch rs) {
-  int nb = launch_blocks(G.N);
+static void dispatch_coarse_nv(hipStream_t s, int nb, const Grid &G, const cx<T> *planes, const cx<T> *x,
+                               const double *xs, const cx<T> *b, cx<T> *y, int mode, const VecSet<T> &V,
+                               RedScratch rs) {
   switch (V.count) {
 #define ADR_NV_CASE(n) \
-  case n: ADR_LAUNCH((k_coarse_apply<T, D, n, NORM>), nb, s, G, A, x, xs, dinv, b, y, mode, V, out, rs); break;
+  case n: ADR_LAUNCH((k_coarse_apply<T, D, n, NORM>), nb, s, G, planes, x, xs, b, y, mode, V, rs); break;
     ADR_NV_CASE(0) ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6)
     ADR_NV_CASE(7) ADR_NV_CASE(8)
 #undef ADR_NV_CASE
@@ -445,25 +449,27 @@ static void dispatch_coarse_nv(hipStream_t s, const Grid &G, const Stencil<T> &A
 }
 
 template <typename T>
-void coarse_apply(hipStream_t s, const Grid &G, int D, const Stencil<T> &A, const cx<T> *x, const double *xscale,
-                  const cx<T> *dinv, const cx<T> *b, cx<T> *y, int mode, const VecSet<T> *dots, bool want_norm,
-                  double *out, RedScratch rs) {
+int coarse_apply(hipStream_t s, const Grid &G, int D, const cx<T> *planes, const cx<T> *x, const double *xscale,
+                 const cx<T> *b, cx<T> *y, int mode, const VecSet<T> *dots, bool want_norm, RedScratch rs) {
   VecSet<T> V{};
   if (dots) V = *dots;
+  const bool red = want_norm || V.count > 0;
+  const int nb = red ? launch_blocks_red(G.N) : launch_blocks(G.N);
   if (D == 2) {
-    if (want_norm) dispatch_coarse_nv<T, 2, true>(s, G, A, x, xscale, dinv, b, y, mode, V, out, rs);
-    else dispatch_coarse_nv<T, 2, false>(s, G, A, x, xscale, dinv, b, y, mode, V, out, rs);
+    if (want_norm) dispatch_coarse_nv<T, 2, true>(s, nb, G, planes, x, xscale, b, y, mode, V, rs);
+    else dispatch_coarse_nv<T, 2, false>(s, nb, G, planes, x, xscale, b, y, mode, V, rs);
   } else {
-    if (want_norm) dispatch_coarse_nv<T, 3, true>(s, G, A, x, xscale, dinv, b, y, mode, V, out, rs);
-    else dispatch_coarse_nv<T, 3, false>(s, G, A, x, xscale, dinv, b, y, mode, V, out, rs);
+    if (want_norm) dispatch_coarse_nv<T, 3, true>(s, nb, G, planes, x, xscale, b, y, mode, V, rs);
+    else dispatch_coarse_nv<T, 3, false>(s, nb, G, planes, x, xscale, b, y, mode, V, rs);
   }
+  return nb;
 }
-template void coarse_apply<double>(hipStream_t, const Grid &, int, const Stencil<double> &, const cx<double> *,
-                                   const double *, const cx<double> *, const cx<double> *, cx<double> *, int,
-                                   const VecSet<double> *, bool, double *, RedScratch);
-template void coarse_apply<float>(hipStream_t, const Grid &, int, const Stencil<float> &, const cx<float> *,
-                                  const double *, const cx<float> *, const cx<float> *, cx<float> *, int,
-                                  const VecSet<float> *, bool, double *, RedScratch);
+template int coarse_apply<double>(hipStream_t, const Grid &, int, const cx<double> *, const cx<double> *,
+                                  const double *, const cx<double> *, cx<double> *, int, const VecSet<double> *,
+                                  bool, RedScratch);
+template int coarse_apply<float>(hipStream_t, const Grid &, int, const cx<float> *, const cx<float> *,
+                                 const double *, const cx<float> *, cx<float> *, int, const VecSet<float> *, bool,
+                                 RedScratch);
 
 // =====================================================================================
 // Transfers: r_c = P^T r_f (nodal full weighting x 2^d), x_f += P e_c (bi/trilinear)
@@ -546,10 +552,12 @@ template void prolong_add<float>(hipStream_t, const Grid &, const Grid &, int, c
 // =====================================================================================
 // GMRES relaxation pieces
 // =====================================================================================
+// v_new = w - sum_i (h_i scale_i) V_i; z_new = dinv o v_new (if dinv); partial ||v_new||^2.
 template <typename T, int NV>
 __global__ __launch_bounds__(ADR_BLOCK) void k_orth_step(int N, const cx<T> *__restrict__ w, VecSet<T> V,
-                                                         const double *hcol, cx<T> *__restrict__ vnew,
-                                                         double *hsub, double *snew, RedScratch rs) {
+                                                         const double *hcol, const cx<T> *__restrict__ dinv,
+                                                         cx<T> *__restrict__ vnew, cx<T> *__restrict__ znew,
+                                                         RedScratch rs) {
   cx<T> coef[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
@@ -562,75 +570,66 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_orth_step(int N, const cx<T> *__r
   for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
     cx<T> o = w[i];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const cx<T> vv = V.v[v][i];
-      o = o - coef[v] * vv;
-    }
+    for (int v = 0; v < NV; ++v) o = o - coef[v] * V.v[v][i];
     vnew[i] = o;
+    if (znew) znew[i] = o * dinv[i];
     red[0] += (double)o.re * o.re + (double)o.im * o.im;
   }
-  double tot[1];
-  if (reduce_last_block<1>(red, 1, rs, tot) && threadIdx.x == 0) {
-    const double nrm = sqrt(tot[0]);
-    hsub[0] = nrm;
-    hsub[1] = 0.0;
-    *snew = nrm > 0.0 ? 1.0 / nrm : 0.0;
-  }
+  block_partials<1>(red, 1, rs);
 }
 
 template <typename T>
-void orth_step(hipStream_t s, int N, const cx<T> *w, const VecSet<T> &V, const double *hcol, cx<T> *vnew,
-               double *hsub, double *snew, RedScratch rs) {
-  int nb = launch_blocks(N);
+int orth_step(hipStream_t s, int N, const cx<T> *w, const VecSet<T> &V, const double *hcol, const cx<T> *dinv,
+              cx<T> *vnew, cx<T> *znew, RedScratch rs) {
+  const int nb = launch_blocks_red(N);
   switch (V.count) {
 #define ADR_NV_CASE(n) \
-  case n: ADR_LAUNCH((k_orth_step<T, n>), nb, s, N, w, V, hcol, vnew, hsub, snew, rs); break;
+  case n: ADR_LAUNCH((k_orth_step<T, n>), nb, s, N, w, V, hcol, dinv, vnew, znew, rs); break;
     ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6) ADR_NV_CASE(7)
     ADR_NV_CASE(8)
 #undef ADR_NV_CASE
     default: break;
   }
+  return nb;
 }
-template void orth_step<double>(hipStream_t, int, const cx<double> *, const VecSet<double> &, const double *,
-                                cx<double> *, double *, double *, RedScratch);
-template void orth_step<float>(hipStream_t, int, const cx<float> *, const VecSet<float> &, const double *,
-                               cx<float> *, double *, double *, RedScratch);
+template int orth_step<double>(hipStream_t, int, const cx<double> *, const VecSet<double> &, const double *,
+                               const cx<double> *, cx<double> *, cx<double> *, RedScratch);
+template int orth_step<float>(hipStream_t, int, const cx<float> *, const VecSet<float> &, const double *,
+                              const cx<float> *, cx<float> *, cx<float> *, RedScratch);
 
+// partial ||x||^2; z = dinv o x if both given.
 template <typename T>
-__global__ __launch_bounds__(ADR_BLOCK) void k_norm_inv(int N, const cx<T> *__restrict__ x, double *out_norm,
-                                                        double *out_inv, RedScratch rs) {
+__global__ __launch_bounds__(ADR_BLOCK) void k_norm2(int N, const cx<T> *__restrict__ x, const cx<T> *__restrict__ dinv,
+                                                     cx<T> *__restrict__ z, RedScratch rs) {
   double red[1] = {0.0};
   int beg, end;
   chunk_range(N, beg, end);
   for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
     const cx<T> o = x[i];
+    if (z) z[i] = o * dinv[i];
     red[0] += (double)o.re * o.re + (double)o.im * o.im;
   }
-  double tot[1];
-  if (reduce_last_block<1>(red, 1, rs, tot) && threadIdx.x == 0) {
-    const double nrm = sqrt(tot[0]);
-    if (out_norm) *out_norm = nrm;
-    if (out_inv) *out_inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-  }
+  block_partials<1>(red, 1, rs);
 }
 template <typename T>
-void norm_inv(hipStream_t s, int N, const cx<T> *x, double *out_norm, double *out_inv, RedScratch rs) {
-  ADR_LAUNCH(k_norm_inv<T>, launch_blocks(N), s, N, x, out_norm, out_inv, rs);
+int norm2(hipStream_t s, int N, const cx<T> *x, const cx<T> *dinv, cx<T> *z, RedScratch rs) {
+  const int nb = launch_blocks_red(N);
+  ADR_LAUNCH(k_norm2<T>, nb, s, N, x, dinv, z, rs);
+  return nb;
 }
-template void norm_inv<double>(hipStream_t, int, const cx<double> *, double *, double *, RedScratch);
-template void norm_inv<float>(hipStream_t, int, const cx<float> *, double *, double *, RedScratch);
+template int norm2<double>(hipStream_t, int, const cx<double> *, const cx<double> *, cx<double> *, RedScratch);
+template int norm2<float>(hipStream_t, int, const cx<float> *, const cx<float> *, cx<float> *, RedScratch);
 
-// Least squares min || beta e1 - H y || for the (k+1) x k upper Hessenberg H by Givens
-// rotations (one thread; k <= 16).  coef_j = y_j * scale_j.
-__global__ void k_gmres_lsq(const double *H, int ldh, int k, const double *beta, const double *scales,
-                            double *coef) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  cx<double> R[ADR_MAXV][ADR_MAXV];
-  cx<double> g[ADR_MAXV + 1];
+// Least squares min || beta e1 - H y || for the (k+1) x k upper Hessenberg H (column-major,
+// leading dimension ldh, complex) by Givens rotations G = [[c, s], [-conj(s), c]];
+// writes coef_j = y_j * scale_j.  One thread.
+__device__ void gmres_lsq_device(const double *H, int ldh, int k, double beta, const double *scales, double *coef) {
+  cx<double> R[ADR_MAXNU + 1][ADR_MAXNU];
+  cx<double> g[ADR_MAXNU + 1];
   for (int j = 0; j < k; ++j)
     for (int i = 0; i <= k; ++i) R[i][j] = mk<double>(H[2 * (j * ldh + i)], H[2 * (j * ldh + i) + 1]);
   for (int i = 0; i <= k; ++i) g[i] = mk<double>(0.0, 0.0);
-  g[0] = mk<double>(*beta, 0.0);
+  g[0] = mk<double>(beta, 0.0);
   for (int j = 0; j < k; ++j) {
     const cx<double> a = R[j][j], b = R[j + 1][j];
     const double aa = sqrt(a.re * a.re + a.im * a.im), bb = sqrt(b.re * b.re + b.im * b.im);
@@ -642,13 +641,11 @@ __global__ void k_gmres_lsq(const double *H, int ldh, int k, const double *beta,
       sn = mk<double>(0.0, 0.0);
     } else if (aa == 0.0) {
       c = 0.0;
-      sn = mk<double>(b.re / bb, -b.im / bb);   // conj(b)/|b|
+      sn = mk<double>(b.re / bb, -b.im / bb);
     } else {
       c = aa / den;
-      const cx<double> ua = mk<double>(a.re / aa, a.im / aa);
-      sn = ua * mk<double>(b.re / den, -b.im / den);  // (a/|a|) conj(b)/den
+      sn = mk<double>(a.re / aa, a.im / aa) * mk<double>(b.re / den, -b.im / den);
     }
-    // Apply G = [[c, s], [-conj(s), c]] to rows j, j+1 of columns j..k-1 and to g.
     for (int jj = j; jj < k; ++jj) {
       const cx<double> x1 = R[j][jj], x2 = R[j + 1][jj];
       R[j][jj] = c * x1 + sn * x2;
@@ -658,7 +655,7 @@ __global__ void k_gmres_lsq(const double *H, int ldh, int k, const double *beta,
     g[j] = c * g1 + sn * g2;
     g[j + 1] = mk<double>(-sn.re, sn.im) * g1 + c * g2;
   }
-  cx<double> y[ADR_MAXV];
+  cx<double> y[ADR_MAXNU];
   for (int j = k - 1; j >= 0; --j) {
     cx<double> acc = g[j];
     for (int jj = j + 1; jj < k; ++jj) acc = acc - R[j][jj] * y[jj];
@@ -671,14 +668,59 @@ __global__ void k_gmres_lsq(const double *H, int ldh, int k, const double *beta,
     coef[2 * j + 1] = y[j].im * sc;
   }
 }
-void gmres_lsq(hipStream_t s, const double *H, int ldh, int k, const double *beta, const double *scales,
-               double *coef) {
-  hipLaunchKernelGGL(k_gmres_lsq, dim3(1), dim3(64), 0, s, H, ldh, k, beta, scales, coef);
+
+// Sum the producer's partials (fixed order) and apply the finishing action.
+__global__ __launch_bounds__(ADR_BLOCK) void k_finish(FinishArgs A, RedScratch rs) {
+  __shared__ double lds[ADR_MAX_RED * 4];
+  double t[ADR_MAX_RED];
+  for (int k = 0; k < A.K; ++k) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < A.nb; b += blockDim.x) acc += rs.partials[(size_t)b * A.K + k];
+    t[k] = acc;
+  }
+  block_sum<ADR_MAX_RED>(t, A.K, lds);
+  if (threadIdx.x != 0) return;
+  switch (A.action) {
+    case FIN_RAW:
+      for (int k = 0; k < A.K; ++k) A.out[k] = t[k];
+      break;
+    case FIN_NORM_INV: {
+      const double nrm = sqrt(t[0]);
+      if (A.out) A.out[0] = nrm;
+      if (A.out_inv) A.out_inv[0] = nrm > 0.0 ? 1.0 / nrm : 0.0;
+      break;
+    }
+    case FIN_DOTS: {
+      for (int v = 0; v < A.nv; ++v) {
+        const double sc = A.scale[v] ? *A.scale[v] : 1.0;
+        A.out[2 * v] = sc * t[2 * v];
+        A.out[2 * v + 1] = sc * t[2 * v + 1];
+      }
+      if (A.K > 2 * A.nv) {
+        const double nrm = sqrt(t[2 * A.nv]);
+        A.out[2 * A.nv] = nrm;
+        if (A.out_inv) A.out_inv[0] = nrm > 0.0 ? 1.0 / nrm : 0.0;
+      }
+      break;
+    }
+    case FIN_ORTH: {
+      const double nrm = sqrt(t[0]);
+      A.out[0] = nrm;   // H[j+1][j] (complex slot)
+      A.out[1] = 0.0;
+      A.out_inv[0] = nrm > 0.0 ? 1.0 / nrm : 0.0;
+      if (A.lsq_k > 0) gmres_lsq_device(A.H, A.ldh, A.lsq_k, *A.beta, A.s, A.coef);
+      break;
+    }
+    default:
+      break;
+  }
+}
+void finish(hipStream_t s, const FinishArgs &A, RedScratch rs) {
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(ADR_BLOCK), 0, s, A, rs);
 }
 
 template <typename T, int NV>
-__global__ __launch_bounds__(ADR_BLOCK) void k_gmres_update(int N, const cx<T> *__restrict__ x0,
-                                                            const cx<T> *__restrict__ dinv, VecSet<T> V,
+__global__ __launch_bounds__(ADR_BLOCK) void k_gmres_update(int N, const cx<T> *__restrict__ x0, VecSet<T> Z,
                                                             const double *coef, cx<T> *__restrict__ xout) {
   cx<T> c[NV];
 #pragma unroll
@@ -686,38 +728,35 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_gmres_update(int N, const cx<T> *
   int beg, end;
   chunk_range(N, beg, end);
   for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
-    cx<T> acc = mk<T>(T(0), T(0));
+    cx<T> acc = x0 ? x0[i] : mk<T>(T(0), T(0));
 #pragma unroll
-    for (int v = 0; v < NV; ++v) acc = cfma(c[v], V.v[v][i], acc);
-    if (dinv) acc = acc * dinv[i];
-    xout[i] = x0 ? x0[i] + acc : acc;
+    for (int v = 0; v < NV; ++v) acc = cfma(c[v], Z.v[v][i], acc);
+    xout[i] = acc;
   }
 }
 template <typename T>
-void gmres_update(hipStream_t s, int N, const cx<T> *x0, const cx<T> *dinv, const VecSet<T> &V, const double *coef,
-                  cx<T> *x_out) {
+void gmres_update(hipStream_t s, int N, const cx<T> *x0, const VecSet<T> &Z, const double *coef, cx<T> *x_out) {
   int nb = launch_blocks(N);
-  switch (V.count) {
+  switch (Z.count) {
 #define ADR_NV_CASE(n) \
-  case n: ADR_LAUNCH((k_gmres_update<T, n>), nb, s, N, x0, dinv, V, coef, x_out); break;
+  case n: ADR_LAUNCH((k_gmres_update<T, n>), nb, s, N, x0, Z, coef, x_out); break;
     ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6) ADR_NV_CASE(7)
-    ADR_NV_CASE(8) ADR_NV_CASE(9) ADR_NV_CASE(10) ADR_NV_CASE(11) ADR_NV_CASE(12) ADR_NV_CASE(13)
-    ADR_NV_CASE(14) ADR_NV_CASE(15) ADR_NV_CASE(16)
+    ADR_NV_CASE(8)
 #undef ADR_NV_CASE
     default: break;
   }
 }
-template void gmres_update<double>(hipStream_t, int, const cx<double> *, const cx<double> *, const VecSet<double> &,
-                                   const double *, cx<double> *);
-template void gmres_update<float>(hipStream_t, int, const cx<float> *, const cx<float> *, const VecSet<float> &,
-                                  const double *, cx<float> *);
+template void gmres_update<double>(hipStream_t, int, const cx<double> *, const VecSet<double> &, const double *,
+                                   cx<double> *);
+template void gmres_update<float>(hipStream_t, int, const cx<float> *, const VecSet<float> &, const double *,
+                                  cx<float> *);
 
 // =====================================================================================
 // Outer FGMRES (FP64) Arnoldi: classical Gram-Schmidt with one re-orthogonalization
 // =====================================================================================
 template <int NV>
 __global__ __launch_bounds__(ADR_BLOCK) void k_outer_orth1(int N, cx<double> *__restrict__ w, VecSet<double> V,
-                                                           const double *hcol, double *out, RedScratch rs) {
+                                                           const double *hcol, RedScratch rs) {
   constexpr int K = 2 * NV + 1;
   cx<double> h[NV];
 #pragma unroll
@@ -744,23 +783,19 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_outer_orth1(int N, cx<double> *__
     }
     red[K - 1] += o.re * o.re + o.im * o.im;
   }
-  double tot[K];
-  if (reduce_last_block<K>(red, K, rs, tot) && threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) out[k] = tot[k];
-  }
+  block_partials<K>(red, K, rs);
 }
-void outer_orth1(hipStream_t s, int N, cx<double> *w, const VecSet<double> &V, const double *hcol, double *out,
-                 RedScratch rs) {
-  int nb = launch_blocks(N);
+int outer_orth1(hipStream_t s, int N, cx<double> *w, const VecSet<double> &V, const double *hcol, RedScratch rs) {
+  const int nb = launch_blocks_red(N);
   switch (V.count) {
 #define ADR_NV_CASE(n) \
-  case n: ADR_LAUNCH((k_outer_orth1<n>), nb, s, N, w, V, hcol, out, rs); break;
+  case n: ADR_LAUNCH((k_outer_orth1<n>), nb, s, N, w, V, hcol, rs); break;
     ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6) ADR_NV_CASE(7)
     ADR_NV_CASE(8)
 #undef ADR_NV_CASE
     default: break;
   }
+  return nb;
 }
 
 template <int NV>
@@ -851,20 +886,31 @@ void phase(hipStream_t s, int N, const cx<double> *in, const double *tau, double
 }
 
 // =====================================================================================
-// Coarsest level: x = A_L^{-1} b with the dense FP64 inverse (column-major)
+// Coarsest level: x = A_L^{-1} b with the dense FP64 inverse (row-major), one
+// wavefront per row, lanes striding over the columns.
 // =====================================================================================
 template <typename T>
 __global__ __launch_bounds__(ADR_BLOCK) void k_dense_gemv(int N, const cx<double> *__restrict__ Ainv,
                                                           const cx<T> *__restrict__ b, cx<T> *__restrict__ x) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  cx<double> acc = mk<double>(0.0, 0.0);
-  for (int j = 0; j < N; ++j) acc = cfma(Ainv[(size_t)j * N + i], cvt<double, T>(b[j]), acc);
-  x[i] = cvt<T, double>(acc);
+  const int row = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (row >= N) return;
+  const cx<double> *a = Ainv + (size_t)row * N;
+  double re = 0.0, im = 0.0;
+  for (int j = lane; j < N; j += 64) {
+    const cx<double> v = cfma(a[j], cvt<double, T>(b[j]), mk<double>(0.0, 0.0));
+    re += v.re;
+    im += v.im;
+  }
+  re = wave_sum(re);
+  im = wave_sum(im);
+  if (lane == 0) x[row] = cvt<T, double>(mk<double>(re, im));
 }
 template <typename T>
 void dense_gemv(hipStream_t s, int N, const cx<double> *Ainv, const cx<T> *b, cx<T> *x) {
-  hipLaunchKernelGGL(k_dense_gemv<T>, dim3((N + ADR_BLOCK - 1) / ADR_BLOCK), dim3(ADR_BLOCK), 0, s, N, Ainv, b, x);
+  const int rows_per_block = ADR_BLOCK / 64;
+  hipLaunchKernelGGL(k_dense_gemv<T>, dim3((N + rows_per_block - 1) / rows_per_block), dim3(ADR_BLOCK), 0, s, N,
+                     Ainv, b, x);
 }
 template void dense_gemv<double>(hipStream_t, int, const cx<double> *, const cx<double> *, cx<double> *);
 template void dense_gemv<float>(hipStream_t, int, const cx<double> *, const cx<float> *, cx<float> *);

@@ -12,15 +12,23 @@ struct VecSet {
   int count;
 };
 
-// Coarse (Galerkin) stencil: S planes of N entries, plane p = neighbour offset
-// (off[p][0..2]) in x, y, z.
-template <typename T>
-struct Stencil {
-  const cx<T> *planes;
-  int S;
-  int centre;            // index of the (0,0,0) plane
-  const int *off_lin;    // device: linear offset of each plane
-  const int *off_xyz;    // device: 3 ints per plane
+#define ADR_MAXNU 8   // GMRES relaxation steps per sweep
+
+// One-block finishing step of a two-launch reduction (see RedScratch).
+enum FinishAction { FIN_RAW = 0, FIN_NORM_INV = 1, FIN_DOTS = 2, FIN_ORTH = 3 };
+struct FinishArgs {
+  int nb, K, action;
+  int nv;                          // FIN_DOTS: number of complex dots
+  const double *scale[ADR_MAXV];   // FIN_DOTS: per-dot scale (NULL = 1)
+  double *out;                     // RAW: K values; NORM_INV: norm; DOTS: 2*nv (+norm);
+                                   // ORTH: complex slot H[j+1][j]
+  double *out_inv;                 // NORM_INV/DOTS: 1/norm; ORTH: new scale factor
+  int lsq_k;                       // ORTH: > 0 -> also solve the k-step least squares
+  const double *H;
+  int ldh;
+  const double *beta;
+  const double *s;
+  double *coef;
 };
 
 namespace adrk {
@@ -45,23 +53,23 @@ void convert_real(hipStream_t s, long long n, const Ti *in, To *out);
 // y = A x (mode 0), r = b - A x (mode 1); optional fused reductions into `out`:
 // dots scale_i * conj(V_i) . y for the basis in `dots` (2 doubles each, first), then
 // ||y|| (the norm, not its square) if want_norm.  Output precision To, compute T, input Tin.
+// Returns the number of blocks launched (the partial count for the finish kernel).
 template <typename T, typename Tin, typename To>
-void fine_apply(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P, const cx<Tin> *x,
-                const cx<To> *b, cx<To> *y, int mode, const VecSet<To> *dots, bool want_norm, double *out,
-                RedScratch rs);
+int fine_apply(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P, const cx<Tin> *x,
+               const cx<To> *b, cx<To> *y, int mode, const VecSet<To> *dots, bool want_norm, RedScratch rs);
 // x_out = x_in + w D^{-1} (b - A x_in); x_in NULL means zero.
 template <typename T>
 void fine_jacobi(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P, const cx<T> *x_in,
                  const cx<T> *b, cx<T> *x_out, double weight);
 
 // ---- coarse levels (stored stencils) ----------------------------------------------
-// mode 0: y = A (dinv o x) * xscale   (xscale device scalar, NULL = 1; dinv NULL = 1)
+// Stencil planes: 81 (3D) / 21 (2D) planes of N entries in the fixed offset order.
+// mode 0: y = (A x) * xscale   (xscale device scalar, NULL = 1)
 // mode 1: y = b - A x
-// Fused reductions as for fine_apply.
+// Fused reductions as for fine_apply; returns the block count.
 template <typename T>
-void coarse_apply(hipStream_t s, const Grid &G, int D, const Stencil<T> &A, const cx<T> *x, const double *xscale,
-                  const cx<T> *dinv, const cx<T> *b, cx<T> *y, int mode, const VecSet<T> *dots, bool want_norm,
-                  double *out, RedScratch rs);
+int coarse_apply(hipStream_t s, const Grid &G, int D, const cx<T> *planes, const cx<T> *x, const double *xscale,
+                 const cx<T> *b, cx<T> *y, int mode, const VecSet<T> *dots, bool want_norm, RedScratch rs);
 
 // ---- transfers ---------------------------------------------------------------------
 template <typename T>
@@ -70,29 +78,24 @@ template <typename T>
 void prolong_add(hipStream_t s, const Grid &Gf, const Grid &Gc, int D, const cx<T> *ec, cx<T> *xf);
 
 // ---- GMRES relaxation / Arnoldi helpers --------------------------------------------
-// v_new = w - sum_i h_i * scale_i * V_i, with h_i = H[hcol + i] (complex, device);
-// reduces ||v_new||^2; the last block stores norm = sqrt into *hsub (complex slot, real
-// part) and 1/norm (0 if norm == 0) into *snew.
+// v_new = w - sum_i h_i * scale_i * V_i (h_i = hcol[2i..2i+1]); z_new = dinv o v_new if
+// z_new; partial ||v_new||^2.  Returns the block count.
 template <typename T>
-void orth_step(hipStream_t s, int N, const cx<T> *w, const VecSet<T> &V, const double *hcol, cx<T> *vnew,
-               double *hsub, double *snew, RedScratch rs);
-// ||x||^2 -> *out_norm = sqrt, *out_inv = 1/sqrt (0 if zero)
+int orth_step(hipStream_t s, int N, const cx<T> *w, const VecSet<T> &V, const double *hcol, const cx<T> *dinv,
+              cx<T> *vnew, cx<T> *znew, RedScratch rs);
+// partial ||x||^2, and z = dinv o x when z != NULL.  Returns the block count.
 template <typename T>
-void norm_inv(hipStream_t s, int N, const cx<T> *x, double *out_norm, double *out_inv, RedScratch rs);
-// Givens least squares on the (k+1) x k Hessenberg H (column-major, ld = ldh complex),
-// rhs beta e1: coef[j] = y_j * scale_j (complex).
-void gmres_lsq(hipStream_t s, const double *H, int ldh, int k, const double *beta, const double *scales,
-               double *coef);
-// x_out = x0 + dinv o sum_j coef_j V_j  (x0 may be NULL, dinv may be NULL)
+int norm2(hipStream_t s, int N, const cx<T> *x, const cx<T> *dinv, cx<T> *z, RedScratch rs);
+// Finishing step of a reduction (one block).
+void finish(hipStream_t s, const FinishArgs &A, RedScratch rs);
+// x_out = x0 + sum_j coef_j Z_j  (x0 may be NULL; x_out may alias x0)
 template <typename T>
-void gmres_update(hipStream_t s, int N, const cx<T> *x0, const cx<T> *dinv, const VecSet<T> &V,
-                  const double *coef, cx<T> *x_out);
+void gmres_update(hipStream_t s, int N, const cx<T> *x0, const VecSet<T> &Z, const double *coef, cx<T> *x_out);
 
 // ---- outer FGMRES (FP64) -----------------------------------------------------------
-// Pass 1 of CGS2: w -= sum_i h_i V_i (h from `hcol`), then reduce conj(V_i).w (2 each) and
-// ||w||^2 into out[0 .. 2k], all in one pass.
-void outer_orth1(hipStream_t s, int N, cx<double> *w, const VecSet<double> &V, const double *hcol, double *out,
-                 RedScratch rs);
+// Pass 1 of CGS2: w -= sum_i h_i V_i (h from `hcol`), with partial conj(V_i).w (2 each)
+// and ||w||^2 (finish with FIN_RAW).  Returns the block count.
+int outer_orth1(hipStream_t s, int N, cx<double> *w, const VecSet<double> &V, const double *hcol, RedScratch rs);
 // Pass 2: V_new = (w - sum_i c_i V_i) / nrm where c = out[0..2k) and
 // nrm = sqrt(||w||^2 - sum |c_i|^2) computed from `red` on the device.
 void outer_orth2(hipStream_t s, int N, const cx<double> *w, const VecSet<double> &V, const double *red,
@@ -107,6 +110,6 @@ void phase(hipStream_t s, int N, const cx<double> *in, const double *tau, double
 
 // ---- coarsest level ------------------------------------------------------------------
 template <typename T>
-void dense_gemv(hipStream_t s, int N, const cx<double> *Ainv_colmajor, const cx<T> *b, cx<T> *x);
+void dense_gemv(hipStream_t s, int N, const cx<double> *Ainv_rowmajor, const cx<T> *b, cx<T> *x);
 
 }  // namespace adrk
