@@ -25,6 +25,7 @@ constexpr int kMaxLevels = 8;
 constexpr int kMaxNu = 8;           // GMRES relaxation steps per sweep (dots fused <= 8)
 constexpr int kMaxRestart = 8;
 constexpr int kScalPerLevel = 256;  // device doubles per level for relaxation scalars
+constexpr int kPin = 1024;          // pinned host doubles (partials and scalars read back)
 // scalar block layout (doubles)
 constexpr int kH = 0;                               // (kMaxNu+1) x kMaxNu complex, col-major
 constexpr int kLdH = kMaxNu + 1;
@@ -85,8 +86,8 @@ struct adr_ctx {
   // scalars and reductions
   double *scal = nullptr;      // kMaxLevels * kScalPerLevel
   double *osc = nullptr;       // outer scalars (64 doubles)
-  double *hpin = nullptr;      // pinned host mirror (64 doubles)
-  RedScratch rs{};
+  double *hpin = nullptr;      // pinned host mirror (kPin doubles)
+  double *part[2] = {nullptr, nullptr};   // alternating reduction partials
 
   // outer FGMRES buffers
   cx<double> *Vo = nullptr;    // (kMaxRestart+1) x N
@@ -325,33 +326,12 @@ VecSet<T> vecset(std::initializer_list<const cx<T> *> v) {
   return s;
 }
 
-// Finish a reduction whose producer launched `nb` blocks of K partials.
-void fin_norm_inv(adr_ctx *ctx, int nb, double *norm, double *inv) {
-  FinishArgs A{};
-  A.nb = nb;
-  A.K = 1;
-  A.action = FIN_NORM_INV;
-  A.out = norm;
-  A.out_inv = inv;
-  adrk::finish(ctx->stream, A, ctx->rs);
-}
-template <typename T>
-void fin_dots(adr_ctx *ctx, int nb, const VecSet<T> &V, bool norm, double *out, double *inv = nullptr) {
-  FinishArgs A{};
-  A.nb = nb;
-  A.nv = V.count;
-  A.K = 2 * V.count + (norm ? 1 : 0);
-  A.action = FIN_DOTS;
-  for (int i = 0; i < V.count; ++i) A.scale[i] = V.scale[i];
-  A.out = out;
-  A.out_inv = inv;
-  adrk::finish(ctx->stream, A, ctx->rs);
-}
-
 // GMRES relaxation on level l >= 1 (Sec. 4.2): x_out = x0 + D^{-1} V y, y the
 // least-squares minimizer over the Krylov space of A D^{-1} and b - A x0.  The basis V is
 // kept unnormalized with scale factors s_j on the device, and Z_j = D^{-1} V_j is written
-// next to it so the stencil apply gathers a single vector.
+// next to it so the stencil apply gathers a single vector.  Every reduction is summed in
+// the prologue of the kernel that consumes it (see reduce_partials), so one step is two
+// launches: the stencil apply with the dots, then the orthogonalization with the norm.
 template <typename T>
 void gmres_relax(adr_ctx *ctx, int l, const cx<T> *x0, const cx<T> *b, cx<T> *x_out) {
   LevelT<T> &L = levels_of<T>(ctx)[l];
@@ -365,53 +345,58 @@ void gmres_relax(adr_ctx *ctx, int l, const cx<T> *x0, const cx<T> *b, cx<T> *x_
     Vp[j] = L.V + (size_t)j * N;
     Zp[j] = L.Z + (size_t)j * N;
   }
-  int nb;
+  int cur = 0, nb;
   if (!x0) {
     Vp[0] = b;
-    nb = adrk::norm2<T>(s, N, b, L.dinv, Zp[0], ctx->rs);
+    nb = adrk::norm2<T>(s, N, b, L.dinv, Zp[0], ctx->part[cur]);
   } else {
+    // V0 = b - A x0, Z0 = D^{-1} V0, with the norm partials.
+    CoarseArgs<T> a{};
+    a.G = L.G;
+    a.planes = L.planes;
+    a.x = x0;
+    a.b = b;
+    a.y = L.V;
+    a.dinv = L.dinv;
+    a.zout = Zp[0];
+    a.mode = 1;
+    a.pout = ctx->part[cur];
     int t0 = tbegin(ctx, ADR_TIMER_COARSE_APPLY, l);
-    adrk::coarse_apply<T>(s, L.G, D, L.planes, x0, nullptr, b, L.V, 1, nullptr, false, ctx->rs);
-    tend(ctx, t0, (double)N * cb * (L.S + 3));
-    nb = adrk::norm2<T>(s, N, L.V, L.dinv, Zp[0], ctx->rs);
+    nb = adrk::coarse_apply<T>(s, D, a, nullptr, true);
+    tend(ctx, t0, (double)N * cb * (L.S + 5));
   }
-  fin_norm_inv(ctx, nb, sc + kBeta, sc + kS);
   for (int j = 0; j < nu; ++j) {
     VecSet<T> Vs{};
     Vs.count = j + 1;
-    for (int i = 0; i <= j; ++i) {
-      Vs.v[i] = Vp[i];
-      Vs.scale[i] = sc + kS + i;
-    }
+    for (int i = 0; i <= j; ++i) Vs.v[i] = Vp[i];
     double *hcol = sc + kH + 2 * (j * kLdH);
+    // w = A Z_j s_j, with s_j = 1/||V_j|| from the previous kernel's partials.
+    CoarseArgs<T> a{};
+    a.G = L.G;
+    a.planes = L.planes;
+    a.x = Zp[j];
+    a.pin = ProIn{ctx->part[cur], nb, 1};
+    a.norm_out = (j == 0) ? sc + kBeta : sc + kH + 2 * ((j - 1) * kLdH + j);
+    a.norm_cplx = (j == 0) ? 0 : 1;
+    a.inv_out = sc + kS + j;
+    a.y = L.w;
+    a.mode = 0;
+    a.pout = ctx->part[cur ^ 1];
     int t0 = tbegin(ctx, ADR_TIMER_COARSE_APPLY, l);
-    nb = adrk::coarse_apply<T>(s, L.G, D, L.planes, Zp[j], sc + kS + j, nullptr, L.w, 0, &Vs, false, ctx->rs);
+    nb = adrk::coarse_apply<T>(s, D, a, &Vs, false);
     tend(ctx, t0, (double)N * cb * (L.S + 2 + (j + 1)));
-    fin_dots<T>(ctx, nb, Vs, false, hcol);
+    cur ^= 1;
     int t1 = tbegin(ctx, ADR_TIMER_COARSE_ORTH, l);
-    nb = adrk::orth_step<T>(s, N, L.w, Vs, hcol, L.dinv, L.V + (size_t)(j + 1) * N, Zp[j + 1], ctx->rs);
+    nb = adrk::orth_step<T>(s, N, L.w, Vs, ProIn{ctx->part[cur], nb, 2 * (j + 1)}, sc + kS, hcol, L.dinv,
+                            L.V + (size_t)(j + 1) * N, Zp[j + 1], ctx->part[cur ^ 1]);
     tend(ctx, t1, (double)N * cb * (j + 5));
-    FinishArgs A{};
-    A.nb = nb;
-    A.K = 1;
-    A.action = FIN_ORTH;
-    A.out = hcol + 2 * (j + 1);
-    A.out_inv = sc + kS + j + 1;
-    if (j == nu - 1) {
-      A.lsq_k = nu;
-      A.H = sc + kH;
-      A.ldh = kLdH;
-      A.beta = sc + kBeta;
-      A.s = sc + kS;
-      A.coef = sc + kCoef;
-    }
-    adrk::finish(s, A, ctx->rs);
+    cur ^= 1;
   }
   VecSet<T> Zs{};
   Zs.count = nu;
   for (int i = 0; i < nu; ++i) Zs.v[i] = Zp[i];
   int t2 = tbegin(ctx, ADR_TIMER_COARSE_ORTH, l);
-  adrk::gmres_update<T>(s, N, x0, Zs, sc + kCoef, x_out);
+  adrk::gmres_update<T>(s, N, x0, Zs, ProIn{ctx->part[cur], nb, 1}, sc + kH, kLdH, sc + kBeta, sc + kS, x_out);
   tend(ctx, t2, (double)N * cb * (nu + (x0 ? 2 : 1)));
 }
 
@@ -464,11 +449,18 @@ cx<T> *vcycle(adr_ctx *ctx, int l, const cx<T> *b, cx<T> *out0) {
   if (l == 0) {
     int t0 = tbegin(ctx, ADR_TIMER_FINE_RESIDUAL, 0);
     adrk::fine_apply<T, T, T>(s, L.G, D, fine_coef<T>(ctx), fine_params(ctx, ctx->opt.beta), x, b, L.r, 1, nullptr,
-                              false, ctx->rs);
+                              false, nullptr);
     tend(ctx, t0, (double)L.G.N * (fine_coef_bytes<T>(D) + 3 * cb));
   } else {
+    CoarseArgs<T> a{};
+    a.G = L.G;
+    a.planes = L.planes;
+    a.x = x;
+    a.b = b;
+    a.y = L.r;
+    a.mode = 1;
     int t0 = tbegin(ctx, ADR_TIMER_COARSE_APPLY, l);
-    adrk::coarse_apply<T>(s, L.G, D, L.planes, x, nullptr, b, L.r, 1, nullptr, false, ctx->rs);
+    adrk::coarse_apply<T>(s, D, a, nullptr, false);
     tend(ctx, t0, (double)L.G.N * cb * (L.S + 3));
   }
   int t1 = tbegin(ctx, ADR_TIMER_TRANSFER, l);
@@ -709,7 +701,8 @@ void free_ctx(adr_ctx *ctx) {
   F(ctx->scal);
   F(ctx->osc);
   if (ctx->hpin) hipHostFree(ctx->hpin);
-  F(ctx->rs.partials);
+  F(ctx->part[0]);
+  F(ctx->part[1]);
   F(ctx->Vo);
   F(ctx->Zo);
   F(ctx->wo);
@@ -734,12 +727,12 @@ adr_status setup_impl(adr_ctx *ctx, const adr_problem *p) {
                      ctx->g64[1], D == 3 ? ctx->g64[2] : nullptr, ctx->L64, ctx->c64);
   ADR_HIP(hipGetLastError());
   // Reduction scratch and scalars.
-  ADR_TRY(dalloc(ctx, &ctx->rs.partials, (size_t)ADR_MAX_RED_BLOCKS * ADR_MAX_RED));
+  for (int i = 0; i < 2; ++i) ADR_TRY(dalloc(ctx, &ctx->part[i], (size_t)ADR_MAX_RED_BLOCKS * ADR_MAX_RED));
   ADR_TRY(dalloc(ctx, &ctx->scal, (size_t)kMaxLevels * kScalPerLevel));
   ADR_HIP(hipMemsetAsync(ctx->scal, 0, sizeof(double) * kMaxLevels * kScalPerLevel, s));
   ADR_TRY(dalloc(ctx, &ctx->osc, 64));
   ADR_HIP(hipMemsetAsync(ctx->osc, 0, sizeof(double) * 64, s));
-  ADR_HIP(hipHostMalloc((void **)&ctx->hpin, 64 * sizeof(double), hipHostMallocDefault));
+  ADR_HIP(hipHostMalloc((void **)&ctx->hpin, kPin * sizeof(double), hipHostMallocDefault));
   if (ctx->opt.prec == ADR_PREC_MIXED) {
     for (int k = 0; k < D; ++k) {
       ADR_TRY(dalloc(ctx, &ctx->g32[k], N));
@@ -902,7 +895,7 @@ adr_status adr_apply(adr_ctx *ctx, double beta, const void *x, void *y) {
   if (!ctx || !x || !y || x == y) return ADR_EINVAL;
   adrk::fine_apply<double, double, double>(ctx->stream, ctx->G0, ctx->D, fine_coef<double>(ctx),
                                            fine_params(ctx, beta), (const cx<double> *)x, nullptr, (cx<double> *)y,
-                                           0, nullptr, false, ctx->rs);
+                                           0, nullptr, false, nullptr);
   ADR_HIP(hipGetLastError());
   return ADR_OK;
 }
@@ -945,23 +938,29 @@ adr_status adr_solve(adr_ctx *ctx, const void *q, void *a_out, double tol, int m
   };
   auto Vp = [&](int j) { return ctx->Vo + (size_t)j * N; };
 
+  // Sum `nb` single-value partials on the host (fixed order) after reading them back.
+  auto host_norm = [&](int nb, double *out) -> adr_status {
+    ADR_HIP(hipMemcpyAsync(hp, ctx->part[0], nb * sizeof(double), hipMemcpyDeviceToHost, s));
+    ADR_HIP(hipStreamSynchronize(s));
+    double acc = 0.0;
+    for (int b = 0; b < nb; ++b) acc += hp[b];
+    *out = std::sqrt(acc);
+    return ADR_OK;
+  };
   // q_hat = q exp(i w tau)
   adrk::phase(s, N, (const cx<double> *)q, ctx->tau, ctx->omega, +1, ctx->qh);
-  fin_norm_inv(ctx, adrk::norm2<double>(s, N, ctx->qh, nullptr, nullptr, ctx->rs), osc + 0, nullptr);
+  double bnorm = 0.0, rnorm = 0.0;
+  ADR_TRY(host_norm(adrk::norm2<double>(s, N, ctx->qh, nullptr, nullptr, ctx->part[0]), &bnorm));
   // initial residual
   if (use_initial_guess) {
     int nb = adrk::fine_apply<double, double, double>(s, ctx->G0, D, C, P0, x, ctx->qh, ctx->ro, 1, nullptr, true,
-                                                      ctx->rs);
-    fin_norm_inv(ctx, nb, osc + 1, nullptr);
+                                                      ctx->part[0]);
+    ADR_TRY(host_norm(nb, &rnorm));
   } else {
     ADR_HIP(hipMemsetAsync(x, 0, sizeof(cx<double>) * N, s));
     ADR_HIP(hipMemcpyAsync(ctx->ro, ctx->qh, sizeof(cx<double>) * N, hipMemcpyDeviceToDevice, s));
-    ADR_HIP(hipMemcpyAsync(osc + 1, osc + 0, sizeof(double), hipMemcpyDeviceToDevice, s));
+    rnorm = bnorm;
   }
-  ADR_HIP(hipMemcpyAsync(hp, osc, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-  ADR_HIP(hipStreamSynchronize(s));
-  const double bnorm = hp[0];
-  double rnorm = hp[1];
   adr_stats st{};
   if (bnorm == 0.0) {
     ADR_HIP(hipMemsetAsync(x, 0, sizeof(cx<double>) * N, s));
@@ -975,7 +974,7 @@ adr_status adr_solve(adr_ctx *ctx, const void *q, void *a_out, double tol, int m
   while (relres > tol && iters < maxit) {
     if (!std::isfinite(relres)) { result = ADR_ENUMERIC; break; }
     // V0 = r / ||r||
-    adrk::scale_by_inv(s, N, ctx->ro, osc + 1, Vp(0));
+    adrk::scale(s, N, ctx->ro, rnorm > 0.0 ? 1.0 / rnorm : 0.0, Vp(0));
     std::complex<double> Hh[kMaxRestart + 1][kMaxRestart], g[kMaxRestart + 1];
     double cs[kMaxRestart];
     std::complex<double> sn[kMaxRestart];
@@ -992,23 +991,14 @@ adr_status adr_solve(adr_ctx *ctx, const void *q, void *a_out, double tol, int m
       int nb;
       if (mixed)
         nb = adrk::fine_apply<double, float, double>(s, ctx->G0, D, C, P0, (const cx<float> *)Zp(j), nullptr,
-                                                     ctx->wo, 0, &Vs, false, ctx->rs);
+                                                     ctx->wo, 0, &Vs, false, ctx->part[0]);
       else
         nb = adrk::fine_apply<double, double, double>(s, ctx->G0, D, C, P0, (const cx<double> *)Zp(j), nullptr,
-                                                      ctx->wo, 0, &Vs, false, ctx->rs);
+                                                      ctx->wo, 0, &Vs, false, ctx->part[0]);
       tend(ctx, t0, (double)N * (fine_coef_bytes<double>(D) + (mixed ? 8.0 : 16.0) + 16.0 * (j + 2)));
-      fin_dots<double>(ctx, nb, Vs, false, red1);
       int t1 = tbegin(ctx, ADR_TIMER_OUTER_ORTH, 0);
-      nb = adrk::outer_orth1(s, N, ctx->wo, Vs, red1, ctx->rs);
-      {
-        FinishArgs A{};
-        A.nb = nb;
-        A.K = 2 * (j + 1) + 1;
-        A.action = FIN_RAW;
-        A.out = red2;
-        adrk::finish(s, A, ctx->rs);
-      }
-      adrk::outer_orth2(s, N, ctx->wo, Vs, red2, Vp(j + 1));
+      nb = adrk::outer_orth1(s, N, ctx->wo, Vs, ProIn{ctx->part[0], nb, 2 * (j + 1)}, red1, ctx->part[1]);
+      adrk::outer_orth2(s, N, ctx->wo, Vs, ProIn{ctx->part[1], nb, 2 * (j + 1) + 1}, red2, Vp(j + 1));
       tend(ctx, t1, (double)N * 16.0 * (2 * (j + 1) + 4));
       const int nred = 2 * (kMaxRestart + 1) * 2 + 1;
       ADR_HIP(hipMemcpyAsync(hp + 2, red1, nred * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1072,11 +1062,8 @@ adr_status adr_solve(adr_ctx *ctx, const void *q, void *a_out, double tol, int m
       adrk::multi_axpy<double>(s, N, x, Zs, ydev);
     }
     int nbr = adrk::fine_apply<double, double, double>(s, ctx->G0, D, C, P0, x, ctx->qh, ctx->ro, 1, nullptr, true,
-                                                       ctx->rs);
-    fin_norm_inv(ctx, nbr, osc + 1, nullptr);
-    ADR_HIP(hipMemcpyAsync(hp + 1, osc + 1, sizeof(double), hipMemcpyDeviceToHost, s));
-    ADR_HIP(hipStreamSynchronize(s));
-    rnorm = hp[1];
+                                                       ctx->part[0]);
+    ADR_TRY(host_norm(nbr, &rnorm));
     relres = rnorm / bnorm;
     ++restarts;
   }

@@ -99,17 +99,16 @@ __device__ __forceinline__ void chunk_range(int N, int &beg, int &end) {
 }
 
 // ------------------------------------------------------------------------------------
-// Deterministic reductions in two launches: every block reduces its K doubles in a
-// fixed tree and writes them to partials[block*K + k] (plain stores); a one-block
-// finish kernel, launched next on the same stream, sums the partials in block order.
-// (No device-scope fences or atomics: on a multi-XCD part those serialize through
-// memory and cost far more than the extra launch.)
+// Deterministic reductions without inter-block synchronization: every block reduces its
+// K doubles in a fixed tree and writes partials[block*K + k] (plain stores).  The next
+// kernel on the stream -- which needs the totals anyway -- sums those partials in block
+// order in a short prologue in every block (block 0 also stores the resulting scalars
+// for later kernels), or the host sums them when it reads them back.  Two partials
+// buffers alternate so a kernel can read its predecessor's partials while writing its
+// own.  (Device-scope fences and atomics would serialize through memory across the 8
+// XCDs; a separate one-block finish kernel costs a launch per reduction.)
 // ------------------------------------------------------------------------------------
-struct RedScratch {
-  double *partials;       // ADR_MAX_RED_BLOCKS * ADR_MAX_RED
-};
-
-#define ADR_MAX_RED_BLOCKS 2048
+#define ADR_MAX_RED_BLOCKS 512
 
 inline int launch_blocks_red(long long N) {
   long long b = (N + ADR_BLOCK - 1) / ADR_BLOCK;
@@ -139,9 +138,22 @@ __device__ __forceinline__ void block_sum(double (&acc)[KMAX], int K, double *ld
 }
 
 template <int KMAX>
-__device__ __forceinline__ void block_partials(double (&acc)[KMAX], int K, RedScratch rs) {
+__device__ __forceinline__ void block_partials(double (&acc)[KMAX], int K, double *partials) {
   __shared__ double lds[KMAX * 4];
   block_sum<KMAX>(acc, K, lds);
   if (threadIdx.x == 0)
-    for (int k = 0; k < K; ++k) rs.partials[(size_t)blockIdx.x * K + k] = acc[k];
+    for (int k = 0; k < K; ++k) partials[(size_t)blockIdx.x * K + k] = acc[k];
+}
+
+// Prologue: tot[k] = sum_b partials[b*K + k] for k < K, the same fixed order in every
+// block (wave w owns k = w, w+4, ...).  tot is shared memory; ends with a barrier.
+__device__ __forceinline__ void reduce_partials(const double *__restrict__ partials, int nb, int K, double *tot) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int k = wid; k < K; k += 4) {
+    double acc = 0.0;
+    for (int b = lane; b < nb; b += 64) acc += partials[(size_t)b * K + k];
+    acc = wave_sum(acc);
+    if (lane == 0) tot[k] = acc;
+  }
+  __syncthreads();
 }

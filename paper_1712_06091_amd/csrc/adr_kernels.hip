@@ -232,7 +232,7 @@ template <typename T, typename Tin, typename To, int D, int NV, bool NORM>
 __global__ __launch_bounds__(ADR_BLOCK) void k_fine_apply(Grid G, FineCoef<T> C, FineParams P,
                                                           const cx<Tin> *__restrict__ x,
                                                           const cx<To> *__restrict__ b, cx<To> *__restrict__ y,
-                                                          int mode, VecSet<To> V, RedScratch rs) {
+                                                          int mode, VecSet<To> V, double *pout) {
   constexpr int K = 2 * NV + (NORM ? 1 : 0);
   constexpr int KA = K > 0 ? K : 1;
   double red[KA];
@@ -265,23 +265,23 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_fine_apply(Grid G, FineCoef<T> C,
     }
     if (NORM) red[K - 1] += (double)o.re * o.re + (double)o.im * o.im;
   }
-  if (K > 0) block_partials<KA>(red, K, rs);
+  if (K > 0) block_partials<KA>(red, K, pout);
 }
 
 template <typename T, typename Tin, typename To, int D, int NV, bool NORM>
 static void launch_fine_apply(hipStream_t s, int nb, const Grid &G, const FineCoef<T> &C, const FineParams &P,
                               const cx<Tin> *x, const cx<To> *b, cx<To> *y, int mode, const VecSet<To> &V,
-                              RedScratch rs) {
-  ADR_LAUNCH((k_fine_apply<T, Tin, To, D, NV, NORM>), nb, s, G, C, P, x, b, y, mode, V, rs);
+                              double *pout) {
+  ADR_LAUNCH((k_fine_apply<T, Tin, To, D, NV, NORM>), nb, s, G, C, P, x, b, y, mode, V, pout);
 }
 
 template <typename T, typename Tin, typename To, int D, bool NORM>
 static void dispatch_fine_apply_nv(hipStream_t s, int nb, const Grid &G, const FineCoef<T> &C,
                                    const FineParams &P, const cx<Tin> *x, const cx<To> *b, cx<To> *y, int mode,
-                                   const VecSet<To> &V, RedScratch rs) {
+                                   const VecSet<To> &V, double *pout) {
   switch (V.count) {
 #define ADR_NV_CASE(n) \
-  case n: launch_fine_apply<T, Tin, To, D, n, NORM>(s, nb, G, C, P, x, b, y, mode, V, rs); break;
+  case n: launch_fine_apply<T, Tin, To, D, n, NORM>(s, nb, G, C, P, x, b, y, mode, V, pout); break;
     ADR_NV_CASE(0) ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6)
     ADR_NV_CASE(7) ADR_NV_CASE(8)
 #undef ADR_NV_CASE
@@ -291,29 +291,29 @@ static void dispatch_fine_apply_nv(hipStream_t s, int nb, const Grid &G, const F
 
 template <typename T, typename Tin, typename To>
 int fine_apply(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P, const cx<Tin> *x,
-               const cx<To> *b, cx<To> *y, int mode, const VecSet<To> *dots, bool want_norm, RedScratch rs) {
+               const cx<To> *b, cx<To> *y, int mode, const VecSet<To> *dots, bool want_norm, double *pout) {
   VecSet<To> V{};
   if (dots) V = *dots;
   const bool red = want_norm || V.count > 0;
   const int nb = red ? launch_blocks_red(G.N) : launch_blocks(G.N);
   if (D == 2) {
-    if (want_norm) dispatch_fine_apply_nv<T, Tin, To, 2, true>(s, nb, G, C, P, x, b, y, mode, V, rs);
-    else dispatch_fine_apply_nv<T, Tin, To, 2, false>(s, nb, G, C, P, x, b, y, mode, V, rs);
+    if (want_norm) dispatch_fine_apply_nv<T, Tin, To, 2, true>(s, nb, G, C, P, x, b, y, mode, V, pout);
+    else dispatch_fine_apply_nv<T, Tin, To, 2, false>(s, nb, G, C, P, x, b, y, mode, V, pout);
   } else {
-    if (want_norm) dispatch_fine_apply_nv<T, Tin, To, 3, true>(s, nb, G, C, P, x, b, y, mode, V, rs);
-    else dispatch_fine_apply_nv<T, Tin, To, 3, false>(s, nb, G, C, P, x, b, y, mode, V, rs);
+    if (want_norm) dispatch_fine_apply_nv<T, Tin, To, 3, true>(s, nb, G, C, P, x, b, y, mode, V, pout);
+    else dispatch_fine_apply_nv<T, Tin, To, 3, false>(s, nb, G, C, P, x, b, y, mode, V, pout);
   }
   return nb;
 }
 template int fine_apply<double, double, double>(hipStream_t, const Grid &, int, const FineCoef<double> &,
                                                 const FineParams &, const cx<double> *, const cx<double> *,
-                                                cx<double> *, int, const VecSet<double> *, bool, RedScratch);
+                                                cx<double> *, int, const VecSet<double> *, bool, double *);
 template int fine_apply<double, float, double>(hipStream_t, const Grid &, int, const FineCoef<double> &,
                                                const FineParams &, const cx<float> *, const cx<double> *,
-                                               cx<double> *, int, const VecSet<double> *, bool, RedScratch);
+                                               cx<double> *, int, const VecSet<double> *, bool, double *);
 template int fine_apply<float, float, float>(hipStream_t, const Grid &, int, const FineCoef<float> &,
                                              const FineParams &, const cx<float> *, const cx<float> *,
-                                             cx<float> *, int, const VecSet<float> *, bool, RedScratch);
+                                             cx<float> *, int, const VecSet<float> *, bool, double *);
 
 template <typename T, int D>
 __global__ __launch_bounds__(ADR_BLOCK) void k_fine_jacobi(Grid G, FineCoef<T> C, FineParams P,
@@ -384,21 +384,39 @@ __host__ __device__ constexpr OffTable<D> make_off_table() {
   return t;
 }
 
-// mode 0: y = xscale * (A x);  mode 1: y = b - A x.  Neighbour indices are clamped per
-// axis (the matching stencil entries are exactly zero outside the grid).
+// mode 0: y = s * (A x), where s = 1/||.|| of the predecessor's partials (prologue
+//         `pin`, K = 1; block 0 stores the norm in norm_out[0] (and 0 in norm_out[1]
+//         when norm_cplx) and s in inv_out), or s = 1 without a prologue;
+// mode 1: y = b - A x, and z = dinv o y when zout is given.
+// Neighbour indices are clamped per axis (the matching stencil entries are exactly zero
+// outside the grid).  Partials: NV dots conj(V_v).y, then ||y||^2 if NORM.
 template <typename T, int D, int NV, bool NORM>
-__global__ __launch_bounds__(ADR_BLOCK) void k_coarse_apply(Grid G, const cx<T> *__restrict__ planes,
-                                                            const cx<T> *__restrict__ x, const double *xscale,
+__global__ __launch_bounds__(ADR_BLOCK) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_coarse_apply(Grid G, const cx<T> *__restrict__ planes,
+                                                            const cx<T> *__restrict__ x, ProIn pin,
+                                                            double *norm_out, int norm_cplx, double *inv_out,
                                                             const cx<T> *__restrict__ b, cx<T> *__restrict__ y,
-                                                            int mode, VecSet<T> V, RedScratch rs) {
+                                                            const cx<T> *__restrict__ dinv, cx<T> *__restrict__ zout,
+                                                            int mode, VecSet<T> V, double *pout) {
   constexpr int S = D == 3 ? 81 : 21;
   constexpr OffTable<D> OT = make_off_table<D>();
   constexpr int K = 2 * NV + (NORM ? 1 : 0);
   constexpr int KA = K > 0 ? K : 1;
+  __shared__ double tot[1];
+  T xs = T(1);
+  if (pin.partials) {
+    reduce_partials(pin.partials, pin.nb, 1, tot);
+    const double nrm = sqrt(tot[0]);
+    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    xs = (T)inv;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      norm_out[0] = nrm;
+      if (norm_cplx) norm_out[1] = 0.0;
+      *inv_out = inv;
+    }
+  }
   double red[KA];
 #pragma unroll
   for (int k = 0; k < KA; ++k) red[k] = 0.0;
-  const T xs = (mode == 0 && xscale) ? (T)(*xscale) : T(1);
   int beg, end;
   chunk_range(G.N, beg, end);
   const int N = G.N, sy = G.n[0], sz = G.n[0] * G.n[1];
@@ -412,16 +430,34 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_coarse_apply(Grid G, const cx<T> 
       Y[d + 2] = sy * min(max(iy + d, 0), G.n[1] - 1);
       Z[d + 2] = (D == 3) ? sz * min(max(iz + d, 0), G.n[2] - 1) : 0;
     }
-    cx<T> acc = mk<T>(T(0), T(0));
+    // Batches of CH entries: issue all loads of a batch, then the FMAs, so that many
+    // plane reads and neighbour gathers are in flight per lane.
+    constexpr int CH = (D == 3) ? 27 : 21;
+    cx<T> acc[2] = {mk<T>(T(0), T(0)), mk<T>(T(0), T(0))};
     const cx<T> *pl = planes + i;
 #pragma unroll
-    for (int p = 0; p < S; ++p) {
-      const int j = X[OT.dx[p] + 2] + Y[OT.dy[p] + 2] + Z[OT.dz[p] + 2];
-      acc = cfma(pl[(size_t)p * N], x[j], acc);
+    for (int c = 0; c < S; c += CH) {
+      cx<T> pv[CH], xv[CH];
+#pragma unroll
+      for (int q = 0; q < CH; ++q) {
+        const int p = c + q;
+        if (p < S) {
+          pv[q] = pl[(size_t)p * N];
+          xv[q] = x[X[OT.dx[p] + 2] + Y[OT.dy[p] + 2] + Z[OT.dz[p] + 2]];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < CH; ++q)
+        if (c + q < S) acc[q & 1] = cfma(pv[q], xv[q], acc[q & 1]);
     }
     cx<T> o;
-    if (mode == 0) o = xs * acc;
-    else o = b[i] - acc;
+    const cx<T> sum = acc[0] + acc[1];
+    if (mode == 0) {
+      o = xs * sum;
+    } else {
+      o = b[i] - sum;
+      if (zout) zout[i] = o * dinv[i];
+    }
     y[i] = o;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -431,16 +467,17 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_coarse_apply(Grid G, const cx<T> 
     }
     if (NORM) red[K - 1] += (double)o.re * o.re + (double)o.im * o.im;
   }
-  if (K > 0) block_partials<KA>(red, K, rs);
+  if (K > 0) block_partials<KA>(red, K, pout);
 }
 
 template <typename T, int D, bool NORM>
-static void dispatch_coarse_nv(hipStream_t s, int nb, const Grid &G, const cx<T> *planes, const cx<T> *x,
-                               const double *xs, const cx<T> *b, cx<T> *y, int mode, const VecSet<T> &V,
-                               RedScratch rs) {
+static void dispatch_coarse_nv(hipStream_t s, int nb, const CoarseArgs<T> &a, const VecSet<T> &V) {
   switch (V.count) {
-#define ADR_NV_CASE(n) \
-  case n: ADR_LAUNCH((k_coarse_apply<T, D, n, NORM>), nb, s, G, planes, x, xs, b, y, mode, V, rs); break;
+#define ADR_NV_CASE(n)                                                                                      \
+  case n:                                                                                                   \
+    ADR_LAUNCH((k_coarse_apply<T, D, n, NORM>), nb, s, a.G, a.planes, a.x, a.pin, a.norm_out, a.norm_cplx, \
+               a.inv_out, a.b, a.y, a.dinv, a.zout, a.mode, V, a.pout);                                     \
+    break;
     ADR_NV_CASE(0) ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6)
     ADR_NV_CASE(7) ADR_NV_CASE(8)
 #undef ADR_NV_CASE
@@ -449,27 +486,22 @@ static void dispatch_coarse_nv(hipStream_t s, int nb, const Grid &G, const cx<T>
 }
 
 template <typename T>
-int coarse_apply(hipStream_t s, const Grid &G, int D, const cx<T> *planes, const cx<T> *x, const double *xscale,
-                 const cx<T> *b, cx<T> *y, int mode, const VecSet<T> *dots, bool want_norm, RedScratch rs) {
+int coarse_apply(hipStream_t s, int D, const CoarseArgs<T> &a, const VecSet<T> *dots, bool want_norm) {
   VecSet<T> V{};
   if (dots) V = *dots;
   const bool red = want_norm || V.count > 0;
-  const int nb = red ? launch_blocks_red(G.N) : launch_blocks(G.N);
+  const int nb = red ? launch_blocks_red(a.G.N) : launch_blocks(a.G.N);
   if (D == 2) {
-    if (want_norm) dispatch_coarse_nv<T, 2, true>(s, nb, G, planes, x, xscale, b, y, mode, V, rs);
-    else dispatch_coarse_nv<T, 2, false>(s, nb, G, planes, x, xscale, b, y, mode, V, rs);
+    if (want_norm) dispatch_coarse_nv<T, 2, true>(s, nb, a, V);
+    else dispatch_coarse_nv<T, 2, false>(s, nb, a, V);
   } else {
-    if (want_norm) dispatch_coarse_nv<T, 3, true>(s, nb, G, planes, x, xscale, b, y, mode, V, rs);
-    else dispatch_coarse_nv<T, 3, false>(s, nb, G, planes, x, xscale, b, y, mode, V, rs);
+    if (want_norm) dispatch_coarse_nv<T, 3, true>(s, nb, a, V);
+    else dispatch_coarse_nv<T, 3, false>(s, nb, a, V);
   }
   return nb;
 }
-template int coarse_apply<double>(hipStream_t, const Grid &, int, const cx<double> *, const cx<double> *,
-                                  const double *, const cx<double> *, cx<double> *, int, const VecSet<double> *,
-                                  bool, RedScratch);
-template int coarse_apply<float>(hipStream_t, const Grid &, int, const cx<float> *, const cx<float> *,
-                                 const double *, const cx<float> *, cx<float> *, int, const VecSet<float> *, bool,
-                                 RedScratch);
+template int coarse_apply<double>(hipStream_t, int, const CoarseArgs<double> &, const VecSet<double> *, bool);
+template int coarse_apply<float>(hipStream_t, int, const CoarseArgs<float> &, const VecSet<float> *, bool);
 
 // =====================================================================================
 // Transfers: r_c = P^T r_f (nodal full weighting x 2^d), x_f += P e_c (bi/trilinear)
@@ -552,17 +584,26 @@ template void prolong_add<float>(hipStream_t, const Grid &, const Grid &, int, c
 // =====================================================================================
 // GMRES relaxation pieces
 // =====================================================================================
-// v_new = w - sum_i (h_i scale_i) V_i; z_new = dinv o v_new (if dinv); partial ||v_new||^2.
+// Prologue: H[i][j] = s_i * (sum of the predecessor's dot partials), i < NV (block 0
+// stores them in hcol).  Then v_new = w - sum_i H[i][j] s_i V_i (the basis is kept
+// unnormalized, v_i = s_i V_i), z_new = dinv o v_new, partial ||v_new||^2.
 template <typename T, int NV>
-__global__ __launch_bounds__(ADR_BLOCK) void k_orth_step(int N, const cx<T> *__restrict__ w, VecSet<T> V,
-                                                         const double *hcol, const cx<T> *__restrict__ dinv,
-                                                         cx<T> *__restrict__ vnew, cx<T> *__restrict__ znew,
-                                                         RedScratch rs) {
+__global__ __launch_bounds__(ADR_BLOCK) void k_orth_step(int N, const cx<T> *__restrict__ w, VecSet<T> V, ProIn pin,
+                                                         const double *scales, double *hcol,
+                                                         const cx<T> *__restrict__ dinv, cx<T> *__restrict__ vnew,
+                                                         cx<T> *__restrict__ znew, double *pout) {
+  __shared__ double tot[2 * NV];
+  reduce_partials(pin.partials, pin.nb, 2 * NV, tot);
   cx<T> coef[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    const double sc = V.scale[v] ? *V.scale[v] : 1.0;
-    coef[v] = mk<T>((T)(hcol[2 * v] * sc), (T)(hcol[2 * v + 1] * sc));
+    const double sc = scales[v];
+    const double hre = sc * tot[2 * v], him = sc * tot[2 * v + 1];
+    coef[v] = mk<T>((T)(hre * sc), (T)(him * sc));
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      hcol[2 * v] = hre;
+      hcol[2 * v + 1] = him;
+    }
   }
   double red[1] = {0.0};
   int beg, end;
@@ -572,19 +613,19 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_orth_step(int N, const cx<T> *__r
 #pragma unroll
     for (int v = 0; v < NV; ++v) o = o - coef[v] * V.v[v][i];
     vnew[i] = o;
-    if (znew) znew[i] = o * dinv[i];
+    znew[i] = o * dinv[i];
     red[0] += (double)o.re * o.re + (double)o.im * o.im;
   }
-  block_partials<1>(red, 1, rs);
+  block_partials<1>(red, 1, pout);
 }
 
 template <typename T>
-int orth_step(hipStream_t s, int N, const cx<T> *w, const VecSet<T> &V, const double *hcol, const cx<T> *dinv,
-              cx<T> *vnew, cx<T> *znew, RedScratch rs) {
+int orth_step(hipStream_t s, int N, const cx<T> *w, const VecSet<T> &V, ProIn pin, const double *scales,
+              double *hcol, const cx<T> *dinv, cx<T> *vnew, cx<T> *znew, double *pout) {
   const int nb = launch_blocks_red(N);
   switch (V.count) {
 #define ADR_NV_CASE(n) \
-  case n: ADR_LAUNCH((k_orth_step<T, n>), nb, s, N, w, V, hcol, dinv, vnew, znew, rs); break;
+  case n: ADR_LAUNCH((k_orth_step<T, n>), nb, s, N, w, V, pin, scales, hcol, dinv, vnew, znew, pout); break;
     ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6) ADR_NV_CASE(7)
     ADR_NV_CASE(8)
 #undef ADR_NV_CASE
@@ -592,15 +633,15 @@ int orth_step(hipStream_t s, int N, const cx<T> *w, const VecSet<T> &V, const do
   }
   return nb;
 }
-template int orth_step<double>(hipStream_t, int, const cx<double> *, const VecSet<double> &, const double *,
-                               const cx<double> *, cx<double> *, cx<double> *, RedScratch);
-template int orth_step<float>(hipStream_t, int, const cx<float> *, const VecSet<float> &, const double *,
-                              const cx<float> *, cx<float> *, cx<float> *, RedScratch);
+template int orth_step<double>(hipStream_t, int, const cx<double> *, const VecSet<double> &, ProIn, const double *,
+                               double *, const cx<double> *, cx<double> *, cx<double> *, double *);
+template int orth_step<float>(hipStream_t, int, const cx<float> *, const VecSet<float> &, ProIn, const double *,
+                              double *, const cx<float> *, cx<float> *, cx<float> *, double *);
 
-// partial ||x||^2; z = dinv o x if both given.
+// partial ||x||^2; z = dinv o x if z is given.
 template <typename T>
 __global__ __launch_bounds__(ADR_BLOCK) void k_norm2(int N, const cx<T> *__restrict__ x, const cx<T> *__restrict__ dinv,
-                                                     cx<T> *__restrict__ z, RedScratch rs) {
+                                                     cx<T> *__restrict__ z, double *pout) {
   double red[1] = {0.0};
   int beg, end;
   chunk_range(N, beg, end);
@@ -609,28 +650,27 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_norm2(int N, const cx<T> *__restr
     if (z) z[i] = o * dinv[i];
     red[0] += (double)o.re * o.re + (double)o.im * o.im;
   }
-  block_partials<1>(red, 1, rs);
+  block_partials<1>(red, 1, pout);
 }
 template <typename T>
-int norm2(hipStream_t s, int N, const cx<T> *x, const cx<T> *dinv, cx<T> *z, RedScratch rs) {
+int norm2(hipStream_t s, int N, const cx<T> *x, const cx<T> *dinv, cx<T> *z, double *pout) {
   const int nb = launch_blocks_red(N);
-  ADR_LAUNCH(k_norm2<T>, nb, s, N, x, dinv, z, rs);
+  ADR_LAUNCH(k_norm2<T>, nb, s, N, x, dinv, z, pout);
   return nb;
 }
-template int norm2<double>(hipStream_t, int, const cx<double> *, const cx<double> *, cx<double> *, RedScratch);
-template int norm2<float>(hipStream_t, int, const cx<float> *, const cx<float> *, cx<float> *, RedScratch);
+template int norm2<double>(hipStream_t, int, const cx<double> *, const cx<double> *, cx<double> *, double *);
+template int norm2<float>(hipStream_t, int, const cx<float> *, const cx<float> *, cx<float> *, double *);
 
-// Least squares min || beta e1 - H y || for the (k+1) x k upper Hessenberg H (column-major,
-// leading dimension ldh, complex) by Givens rotations G = [[c, s], [-conj(s), c]];
-// writes coef_j = y_j * scale_j.  One thread.
-__device__ void gmres_lsq_device(const double *H, int ldh, int k, double beta, const double *scales, double *coef) {
-  cx<double> R[ADR_MAXNU + 1][ADR_MAXNU];
-  cx<double> g[ADR_MAXNU + 1];
-  for (int j = 0; j < k; ++j)
-    for (int i = 0; i <= k; ++i) R[i][j] = mk<double>(H[2 * (j * ldh + i)], H[2 * (j * ldh + i) + 1]);
-  for (int i = 0; i <= k; ++i) g[i] = mk<double>(0.0, 0.0);
+// Least squares min || beta e1 - H y || for the (K+1) x K upper Hessenberg H by Givens
+// rotations G = [[c, s], [-conj(s), c]]; R and g are rotated in place, then y = R^{-1} g.
+template <int K>
+__device__ void gmres_lsq(cx<double> (&R)[K + 1][K], double beta, cx<double> (&y)[K]) {
+  cx<double> g[K + 1];
+#pragma unroll
+  for (int i = 0; i <= K; ++i) g[i] = mk<double>(0.0, 0.0);
   g[0] = mk<double>(beta, 0.0);
-  for (int j = 0; j < k; ++j) {
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
     const cx<double> a = R[j][j], b = R[j + 1][j];
     const double aa = sqrt(a.re * a.re + a.im * a.im), bb = sqrt(b.re * b.re + b.im * b.im);
     const double den = sqrt(aa * aa + bb * bb);
@@ -646,7 +686,8 @@ __device__ void gmres_lsq_device(const double *H, int ldh, int k, double beta, c
       c = aa / den;
       sn = mk<double>(a.re / aa, a.im / aa) * mk<double>(b.re / den, -b.im / den);
     }
-    for (int jj = j; jj < k; ++jj) {
+#pragma unroll
+    for (int jj = j; jj < K; ++jj) {
       const cx<double> x1 = R[j][jj], x2 = R[j + 1][jj];
       R[j][jj] = c * x1 + sn * x2;
       R[j + 1][jj] = mk<double>(-sn.re, sn.im) * x1 + c * x2;
@@ -655,76 +696,47 @@ __device__ void gmres_lsq_device(const double *H, int ldh, int k, double beta, c
     g[j] = c * g1 + sn * g2;
     g[j + 1] = mk<double>(-sn.re, sn.im) * g1 + c * g2;
   }
-  cx<double> y[ADR_MAXNU];
-  for (int j = k - 1; j >= 0; --j) {
+#pragma unroll
+  for (int j = K - 1; j >= 0; --j) {
     cx<double> acc = g[j];
-    for (int jj = j + 1; jj < k; ++jj) acc = acc - R[j][jj] * y[jj];
+#pragma unroll
+    for (int jj = j + 1; jj < K; ++jj) acc = acc - R[j][jj] * y[jj];
     const cx<double> d = R[j][j];
     y[j] = (d.re == 0.0 && d.im == 0.0) ? mk<double>(0.0, 0.0) : acc * cinv(d);
   }
-  for (int j = 0; j < k; ++j) {
-    const double sc = scales ? scales[j] : 1.0;
-    coef[2 * j] = y[j].re * sc;
-    coef[2 * j + 1] = y[j].im * sc;
-  }
 }
 
-// Sum the producer's partials (fixed order) and apply the finishing action.
-__global__ __launch_bounds__(ADR_BLOCK) void k_finish(FinishArgs A, RedScratch rs) {
-  __shared__ double lds[ADR_MAX_RED * 4];
-  double t[ADR_MAX_RED];
-  for (int k = 0; k < A.K; ++k) {
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < A.nb; b += blockDim.x) acc += rs.partials[(size_t)b * A.K + k];
-    t[k] = acc;
-  }
-  block_sum<ADR_MAX_RED>(t, A.K, lds);
-  if (threadIdx.x != 0) return;
-  switch (A.action) {
-    case FIN_RAW:
-      for (int k = 0; k < A.K; ++k) A.out[k] = t[k];
-      break;
-    case FIN_NORM_INV: {
-      const double nrm = sqrt(t[0]);
-      if (A.out) A.out[0] = nrm;
-      if (A.out_inv) A.out_inv[0] = nrm > 0.0 ? 1.0 / nrm : 0.0;
-      break;
-    }
-    case FIN_DOTS: {
-      for (int v = 0; v < A.nv; ++v) {
-        const double sc = A.scale[v] ? *A.scale[v] : 1.0;
-        A.out[2 * v] = sc * t[2 * v];
-        A.out[2 * v + 1] = sc * t[2 * v + 1];
-      }
-      if (A.K > 2 * A.nv) {
-        const double nrm = sqrt(t[2 * A.nv]);
-        A.out[2 * A.nv] = nrm;
-        if (A.out_inv) A.out_inv[0] = nrm > 0.0 ? 1.0 / nrm : 0.0;
-      }
-      break;
-    }
-    case FIN_ORTH: {
-      const double nrm = sqrt(t[0]);
-      A.out[0] = nrm;   // H[j+1][j] (complex slot)
-      A.out[1] = 0.0;
-      A.out_inv[0] = nrm > 0.0 ? 1.0 / nrm : 0.0;
-      if (A.lsq_k > 0) gmres_lsq_device(A.H, A.ldh, A.lsq_k, *A.beta, A.s, A.coef);
-      break;
-    }
-    default:
-      break;
-  }
-}
-void finish(hipStream_t s, const FinishArgs &A, RedScratch rs) {
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(ADR_BLOCK), 0, s, A, rs);
-}
-
+// Prologue: H[NV][NV-1] = sqrt(sum of the last orthogonalization's partials); thread 0
+// solves the least squares with the Hessenberg H (column-major, leading dimension ldh,
+// complex) and beta; coef_j = y_j s_j goes through shared memory.  Then
+// x_out = x0 + sum_j coef_j Z_j  (Z_j = D^{-1} V_j, so this is x0 + D^{-1} V y).
 template <typename T, int NV>
 __global__ __launch_bounds__(ADR_BLOCK) void k_gmres_update(int N, const cx<T> *__restrict__ x0, VecSet<T> Z,
-                                                            const double *coef, cx<T> *__restrict__ xout) {
+                                                            ProIn pin, const double *H, int ldh, const double *beta,
+                                                            const double *scales, cx<T> *__restrict__ xout) {
+  __shared__ double tot[1];
+  __shared__ double cs[2 * NV];
+  reduce_partials(pin.partials, pin.nb, 1, tot);
+  if (threadIdx.x == 0) {
+    cx<double> R[NV + 1][NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+#pragma unroll
+      for (int i = 0; i <= NV; ++i)
+        R[i][j] = (i <= j + 1) ? mk<double>(H[2 * (j * ldh + i)], H[2 * (j * ldh + i) + 1]) : mk<double>(0.0, 0.0);
+    R[NV][NV - 1] = mk<double>(sqrt(tot[0]), 0.0);
+    cx<double> y[NV];
+    gmres_lsq<NV>(R, *beta, y);
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      cs[2 * j] = y[j].re * scales[j];
+      cs[2 * j + 1] = y[j].im * scales[j];
+    }
+  }
+  __syncthreads();
   cx<T> c[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) c[v] = mk<T>((T)coef[2 * v], (T)coef[2 * v + 1]);
+  for (int v = 0; v < NV; ++v) c[v] = mk<T>((T)cs[2 * v], (T)cs[2 * v + 1]);
   int beg, end;
   chunk_range(N, beg, end);
   for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
@@ -735,32 +747,42 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_gmres_update(int N, const cx<T> *
   }
 }
 template <typename T>
-void gmres_update(hipStream_t s, int N, const cx<T> *x0, const VecSet<T> &Z, const double *coef, cx<T> *x_out) {
+void gmres_update(hipStream_t s, int N, const cx<T> *x0, const VecSet<T> &Z, ProIn pin, const double *H, int ldh,
+                  const double *beta, const double *scales, cx<T> *x_out) {
   int nb = launch_blocks(N);
   switch (Z.count) {
 #define ADR_NV_CASE(n) \
-  case n: ADR_LAUNCH((k_gmres_update<T, n>), nb, s, N, x0, Z, coef, x_out); break;
+  case n: ADR_LAUNCH((k_gmres_update<T, n>), nb, s, N, x0, Z, pin, H, ldh, beta, scales, x_out); break;
     ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6) ADR_NV_CASE(7)
     ADR_NV_CASE(8)
 #undef ADR_NV_CASE
     default: break;
   }
 }
-template void gmres_update<double>(hipStream_t, int, const cx<double> *, const VecSet<double> &, const double *,
-                                   cx<double> *);
-template void gmres_update<float>(hipStream_t, int, const cx<float> *, const VecSet<float> &, const double *,
-                                  cx<float> *);
+template void gmres_update<double>(hipStream_t, int, const cx<double> *, const VecSet<double> &, ProIn,
+                                   const double *, int, const double *, const double *, cx<double> *);
+template void gmres_update<float>(hipStream_t, int, const cx<float> *, const VecSet<float> &, ProIn, const double *,
+                                  int, const double *, const double *, cx<float> *);
 
 // =====================================================================================
 // Outer FGMRES (FP64) Arnoldi: classical Gram-Schmidt with one re-orthogonalization
 // =====================================================================================
+// Prologue: h = sums of the matvec's dot partials (block 0 stores them in h_out).
 template <int NV>
 __global__ __launch_bounds__(ADR_BLOCK) void k_outer_orth1(int N, cx<double> *__restrict__ w, VecSet<double> V,
-                                                           const double *hcol, RedScratch rs) {
+                                                           ProIn pin, double *h_out, double *pout) {
   constexpr int K = 2 * NV + 1;
+  __shared__ double tot[2 * NV];
+  reduce_partials(pin.partials, pin.nb, 2 * NV, tot);
   cx<double> h[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) h[v] = mk<double>(hcol[2 * v], hcol[2 * v + 1]);
+  for (int v = 0; v < NV; ++v) {
+    h[v] = mk<double>(tot[2 * v], tot[2 * v + 1]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      h_out[2 * v] = tot[2 * v];
+      h_out[2 * v + 1] = tot[2 * v + 1];
+    }
+  }
   double red[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) red[k] = 0.0;
@@ -783,13 +805,14 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_outer_orth1(int N, cx<double> *__
     }
     red[K - 1] += o.re * o.re + o.im * o.im;
   }
-  block_partials<K>(red, K, rs);
+  block_partials<K>(red, K, pout);
 }
-int outer_orth1(hipStream_t s, int N, cx<double> *w, const VecSet<double> &V, const double *hcol, RedScratch rs) {
+int outer_orth1(hipStream_t s, int N, cx<double> *w, const VecSet<double> &V, ProIn pin, double *h_out,
+                double *pout) {
   const int nb = launch_blocks_red(N);
   switch (V.count) {
 #define ADR_NV_CASE(n) \
-  case n: ADR_LAUNCH((k_outer_orth1<n>), nb, s, N, w, V, hcol, rs); break;
+  case n: ADR_LAUNCH((k_outer_orth1<n>), nb, s, N, w, V, pin, h_out, pout); break;
     ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6) ADR_NV_CASE(7)
     ADR_NV_CASE(8)
 #undef ADR_NV_CASE
@@ -798,9 +821,15 @@ int outer_orth1(hipStream_t s, int N, cx<double> *w, const VecSet<double> &V, co
   return nb;
 }
 
+// Prologue: c_i and ||w||^2 from the first pass's partials (block 0 stores them in
+// red_out for the host).  V_new = (w - sum_i c_i V_i) / sqrt(||w||^2 - sum |c_i|^2).
 template <int NV>
 __global__ __launch_bounds__(ADR_BLOCK) void k_outer_orth2(int N, const cx<double> *__restrict__ w, VecSet<double> V,
-                                                           const double *red, cx<double> *__restrict__ vnew) {
+                                                           ProIn pin, double *red_out, cx<double> *__restrict__ vnew) {
+  __shared__ double red[2 * NV + 1];
+  reduce_partials(pin.partials, pin.nb, 2 * NV + 1, red);
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    for (int k = 0; k < 2 * NV + 1; ++k) red_out[k] = red[k];
   cx<double> c[NV];
   double n2 = red[2 * NV];
 #pragma unroll
@@ -819,12 +848,12 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_outer_orth2(int N, const cx<doubl
     vnew[i] = inv * o;
   }
 }
-void outer_orth2(hipStream_t s, int N, const cx<double> *w, const VecSet<double> &V, const double *red,
+void outer_orth2(hipStream_t s, int N, const cx<double> *w, const VecSet<double> &V, ProIn pin, double *red_out,
                  cx<double> *vnew) {
   int nb = launch_blocks(N);
   switch (V.count) {
 #define ADR_NV_CASE(n) \
-  case n: ADR_LAUNCH((k_outer_orth2<n>), nb, s, N, w, V, red, vnew); break;
+  case n: ADR_LAUNCH((k_outer_orth2<n>), nb, s, N, w, V, pin, red_out, vnew); break;
     ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6) ADR_NV_CASE(7)
     ADR_NV_CASE(8)
 #undef ADR_NV_CASE
@@ -862,14 +891,12 @@ void multi_axpy(hipStream_t s, int N, cx<double> *x, const VecSet<Tz> &Z, const 
 template void multi_axpy<double>(hipStream_t, int, cx<double> *, const VecSet<double> &, const double *);
 template void multi_axpy<float>(hipStream_t, int, cx<double> *, const VecSet<float> &, const double *);
 
-__global__ __launch_bounds__(ADR_BLOCK) void k_scale_by_inv(int N, const cx<double> *__restrict__ x,
-                                                            const double *scale, cx<double> *__restrict__ y) {
-  const double s = *scale;
-  const double inv = s > 0.0 ? 1.0 / s : 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) y[i] = inv * x[i];
+__global__ __launch_bounds__(ADR_BLOCK) void k_scale(int N, const cx<double> *__restrict__ x, double a,
+                                                     cx<double> *__restrict__ y) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) y[i] = a * x[i];
 }
-void scale_by_inv(hipStream_t s, int N, const cx<double> *x, const double *scale, cx<double> *y) {
-  ADR_LAUNCH(k_scale_by_inv, launch_blocks(N), s, N, x, scale, y);
+void scale(hipStream_t s, int N, const cx<double> *x, double a, cx<double> *y) {
+  ADR_LAUNCH(k_scale, launch_blocks(N), s, N, x, a, y);
 }
 
 __global__ __launch_bounds__(ADR_BLOCK) void k_phase(int N, const cx<double> *__restrict__ in,

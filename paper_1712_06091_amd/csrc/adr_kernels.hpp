@@ -14,21 +14,28 @@ struct VecSet {
 
 #define ADR_MAXNU 8   // GMRES relaxation steps per sweep
 
-// One-block finishing step of a two-launch reduction (see RedScratch).
-enum FinishAction { FIN_RAW = 0, FIN_NORM_INV = 1, FIN_DOTS = 2, FIN_ORTH = 3 };
-struct FinishArgs {
-  int nb, K, action;
-  int nv;                          // FIN_DOTS: number of complex dots
-  const double *scale[ADR_MAXV];   // FIN_DOTS: per-dot scale (NULL = 1)
-  double *out;                     // RAW: K values; NORM_INV: norm; DOTS: 2*nv (+norm);
-                                   // ORTH: complex slot H[j+1][j]
-  double *out_inv;                 // NORM_INV/DOTS: 1/norm; ORTH: new scale factor
-  int lsq_k;                       // ORTH: > 0 -> also solve the k-step least squares
-  const double *H;
-  int ldh;
-  const double *beta;
-  const double *s;
-  double *coef;
+// Prologue input: the predecessor kernel's per-block partials (see reduce_partials).
+struct ProIn {
+  const double *partials;
+  int nb, K;
+};
+
+// Arguments of the Galerkin-stencil apply (see k_coarse_apply).
+template <typename T>
+struct CoarseArgs {
+  Grid G;
+  const cx<T> *planes;   // 81 (3D) / 21 (2D) planes of N entries, fixed offset order
+  const cx<T> *x;
+  ProIn pin;             // mode 0: scale = 1/||.|| of these partials (K = 1); none if NULL
+  double *norm_out;      // mode 0 with pin: block 0 stores the norm here ...
+  int norm_cplx;         // ... and 0 in norm_out[1] if set (complex Hessenberg slot)
+  double *inv_out;       // ... and the scale here
+  const cx<T> *b;        // mode 1
+  cx<T> *y;
+  const cx<T> *dinv;     // mode 1: z = dinv o y when zout != NULL
+  cx<T> *zout;
+  int mode;
+  double *pout;          // partials (when reducing)
 };
 
 namespace adrk {
@@ -53,23 +60,20 @@ void convert_real(hipStream_t s, long long n, const Ti *in, To *out);
 // y = A x (mode 0), r = b - A x (mode 1); optional fused reductions into `out`:
 // dots scale_i * conj(V_i) . y for the basis in `dots` (2 doubles each, first), then
 // ||y|| (the norm, not its square) if want_norm.  Output precision To, compute T, input Tin.
-// Returns the number of blocks launched (the partial count for the finish kernel).
+// Partials go to pout; returns the number of blocks launched.
 template <typename T, typename Tin, typename To>
 int fine_apply(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P, const cx<Tin> *x,
-               const cx<To> *b, cx<To> *y, int mode, const VecSet<To> *dots, bool want_norm, RedScratch rs);
+               const cx<To> *b, cx<To> *y, int mode, const VecSet<To> *dots, bool want_norm, double *pout);
 // x_out = x_in + w D^{-1} (b - A x_in); x_in NULL means zero.
 template <typename T>
 void fine_jacobi(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P, const cx<T> *x_in,
                  const cx<T> *b, cx<T> *x_out, double weight);
 
 // ---- coarse levels (stored stencils) ----------------------------------------------
-// Stencil planes: 81 (3D) / 21 (2D) planes of N entries in the fixed offset order.
-// mode 0: y = (A x) * xscale   (xscale device scalar, NULL = 1)
-// mode 1: y = b - A x
-// Fused reductions as for fine_apply; returns the block count.
+// Galerkin-stencil apply (see CoarseArgs); fused dot/norm partials; returns the block
+// count.
 template <typename T>
-int coarse_apply(hipStream_t s, const Grid &G, int D, const cx<T> *planes, const cx<T> *x, const double *xscale,
-                 const cx<T> *b, cx<T> *y, int mode, const VecSet<T> *dots, bool want_norm, RedScratch rs);
+int coarse_apply(hipStream_t s, int D, const CoarseArgs<T> &a, const VecSet<T> *dots, bool want_norm);
 
 // ---- transfers ---------------------------------------------------------------------
 template <typename T>
@@ -78,33 +82,34 @@ template <typename T>
 void prolong_add(hipStream_t s, const Grid &Gf, const Grid &Gc, int D, const cx<T> *ec, cx<T> *xf);
 
 // ---- GMRES relaxation / Arnoldi helpers --------------------------------------------
-// v_new = w - sum_i h_i * scale_i * V_i (h_i = hcol[2i..2i+1]); z_new = dinv o v_new if
-// z_new; partial ||v_new||^2.  Returns the block count.
+// Prologue H[i][j] = scales_i * (dot partials), stored by block 0 in hcol; then
+// v_new = w - sum_i H[i][j] scales_i V_i, z_new = dinv o v_new, norm partials to pout.
 template <typename T>
-int orth_step(hipStream_t s, int N, const cx<T> *w, const VecSet<T> &V, const double *hcol, const cx<T> *dinv,
-              cx<T> *vnew, cx<T> *znew, RedScratch rs);
-// partial ||x||^2, and z = dinv o x when z != NULL.  Returns the block count.
+int orth_step(hipStream_t s, int N, const cx<T> *w, const VecSet<T> &V, ProIn pin, const double *scales,
+              double *hcol, const cx<T> *dinv, cx<T> *vnew, cx<T> *znew, double *pout);
+// partial ||x||^2 to pout, and z = dinv o x when z != NULL.  Returns the block count.
 template <typename T>
-int norm2(hipStream_t s, int N, const cx<T> *x, const cx<T> *dinv, cx<T> *z, RedScratch rs);
-// Finishing step of a reduction (one block).
-void finish(hipStream_t s, const FinishArgs &A, RedScratch rs);
-// x_out = x0 + sum_j coef_j Z_j  (x0 may be NULL; x_out may alias x0)
+int norm2(hipStream_t s, int N, const cx<T> *x, const cx<T> *dinv, cx<T> *z, double *pout);
+// Prologue: last subdiagonal from pin, least squares with H/beta, coef_j = y_j scales_j;
+// x_out = x0 + sum_j coef_j Z_j  (x0 may be NULL; x_out may alias x0).
 template <typename T>
-void gmres_update(hipStream_t s, int N, const cx<T> *x0, const VecSet<T> &Z, const double *coef, cx<T> *x_out);
+void gmres_update(hipStream_t s, int N, const cx<T> *x0, const VecSet<T> &Z, ProIn pin, const double *H, int ldh,
+                  const double *beta, const double *scales, cx<T> *x_out);
 
 // ---- outer FGMRES (FP64) -----------------------------------------------------------
-// Pass 1 of CGS2: w -= sum_i h_i V_i (h from `hcol`), with partial conj(V_i).w (2 each)
-// and ||w||^2 (finish with FIN_RAW).  Returns the block count.
-int outer_orth1(hipStream_t s, int N, cx<double> *w, const VecSet<double> &V, const double *hcol, RedScratch rs);
-// Pass 2: V_new = (w - sum_i c_i V_i) / nrm where c = out[0..2k) and
-// nrm = sqrt(||w||^2 - sum |c_i|^2) computed from `red` on the device.
-void outer_orth2(hipStream_t s, int N, const cx<double> *w, const VecSet<double> &V, const double *red,
+// Pass 1 of CGS2: h = dot partials of the matvec (prologue; block 0 stores them in
+// h_out), w -= sum_i h_i V_i, partial conj(V_i).w (2 each) and ||w||^2 to pout.
+int outer_orth1(hipStream_t s, int N, cx<double> *w, const VecSet<double> &V, ProIn pin, double *h_out,
+                double *pout);
+// Pass 2: c and ||w||^2 from pass 1's partials (block 0 stores them in red_out);
+// V_new = (w - sum_i c_i V_i) / sqrt(||w||^2 - sum |c_i|^2).
+void outer_orth2(hipStream_t s, int N, const cx<double> *w, const VecSet<double> &V, ProIn pin, double *red_out,
                  cx<double> *vnew);
 // x += sum_j y_j Z_j (y host-provided via device array of complex doubles)
 template <typename Tz>
 void multi_axpy(hipStream_t s, int N, cx<double> *x, const VecSet<Tz> &Z, const double *y);
-// y = x * (1/scale), scale = device scalar (real)
-void scale_by_inv(hipStream_t s, int N, const cx<double> *x, const double *scale, cx<double> *y);
+// y = a x
+void scale(hipStream_t s, int N, const cx<double> *x, double a, cx<double> *y);
 // q_hat = q exp(+i w tau)  (sign = +1) or u = a exp(-i w tau) (sign = -1)
 void phase(hipStream_t s, int N, const cx<double> *in, const double *tau, double omega, int sign, cx<double> *out);
 
