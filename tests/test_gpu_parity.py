@@ -190,3 +190,59 @@ def test_solve_initial_guess_and_zero_rhs():
     _, st4 = ctx.solve(_t(wl.rhs()), tol=1e-14, maxit=3)
     from paper_1712_06091_amd import adr
     assert st4["status"] == adr.ADR_ENOCONV and st4["outer_iters"] == 3
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_graph_replays_match_eager(prec):
+    """Captured V-cycles replayed several times, with unrelated eager work and
+    synchronizations between replays, equal the eager V-cycle bit for bit; so do whole
+    solves."""
+    wl = W.linear_gradient(33, 3)
+    print(f"[graph] 3d 33 prec={prec}", flush=True)
+    cg = _ctx(wl, prec=prec, use_graph=1)
+    ce = _ctx(wl, prec=prec, use_graph=0)
+    r = torch.empty(wl.shape, dtype=torch.complex128, device="cuda")
+    zg = torch.empty_like(r)
+    ze = torch.empty_like(r)
+    for k in range(4):
+        r.copy_(_t(W.random_vector(wl.shape, 100 + k)))
+        cg.vcycle(r, out=zg)
+        junk = torch.randn(1000, device="cuda").cumsum(0)   # eager work between replays
+        torch.cuda.synchronize()
+        ce.vcycle(r, out=ze)
+        torch.cuda.synchronize()
+        assert torch.equal(zg, ze), f"replay {k} differs"
+        del junk
+    q = _t(wl.rhs())
+    ag, sg = cg.solve(q, tol=1e-10, maxit=300)
+    ae, se = ce.solve(q, tol=1e-10, maxit=300)
+    assert sg["outer_iters"] == se["outer_iters"]
+    assert torch.equal(ag, ae)
+
+
+def test_full_size_3d_129_bench_configuration():
+    """The benchmark workload (3D 129^3, v = 1.5 + 0.8 z) in the benchmark's launch
+    configuration (mixed precision, FGMRES(5), tol 1e-6): coefficients and the FP64
+    matvec match the oracle at every node, and the oracle's own H_2up confirms the true
+    residual of the GPU solution."""
+    wl = W.config_3d_129()
+    print(f"[full-size] {wl.name} shape={wl.shape}", flush=True)
+    ctx = _ctx(wl, prec="mixed")
+    g, L, c = ctx.coefficients()
+    og, oL, oc = ocoef.adr_coefficients(wl.tau, wl.kappa2, wl.gamma, wl.h, wl.omega, src=wl.src)
+    for k in range(3):
+        assert np.max(np.abs(g[k].cpu().numpy() - og[2 - k])) <= 1e-12 * np.abs(og[2 - k]).max()
+    assert np.max(np.abs(L.cpu().numpy() - oL)) <= 1e-12 * np.abs(oL).max()
+    H = oops.assemble_adr(og, oL, oc, wl.h, wl.omega, 0.0, src=wl.src)
+    x = W.random_vector(wl.shape, 21)
+    y = ctx.apply(_t(x), beta=0.0).cpu().numpy()
+    scale = (abs(H) @ np.abs(x.ravel())).reshape(wl.shape)
+    assert np.max(np.abs(y - (H @ x.ravel()).reshape(wl.shape)) / scale) <= 1e-13
+    del x, y, scale
+    a, st = ctx.solve(_t(wl.rhs()), tol=1e-6, maxit=500)
+    assert st["status"] == 0 and st["relres"] <= 1e-6
+    a = a.cpu().numpy().ravel()
+    qh = osolve.rhs_hat(wl.rhs(), wl.tau, wl.omega).ravel()
+    rel = np.linalg.norm(qh - H @ a) / np.linalg.norm(qh)
+    assert rel <= 1e-6 * (1 + 1e-6), rel
+    assert abs(rel - st["relres"]) <= 1e-9
