@@ -95,6 +95,20 @@ struct adr_ctx {
   cx<double> *wo = nullptr, *ro = nullptr, *qh = nullptr;
   cx<float> *b32 = nullptr, *z32 = nullptr;   // mixed-mode V-cycle in/out staging
 
+  // Captured V-cycles (Alg. TwoCycle applied recursively; no host synchronization
+  // inside), keyed by their input/output buffers, replayed on `stream`.  Captured on a
+  // private stream because the legacy default stream cannot be captured.
+  struct GraphEntry {
+    const void *in = nullptr;
+    void *out = nullptr;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t e = nullptr;
+    unsigned long long last_use = 0;
+  };
+  std::vector<GraphEntry> graphs;
+  unsigned long long graph_clock = 0;
+  hipStream_t cap_stream = nullptr;
+
   // Event timing of one kernel class (benchmarks): pairs of events recorded on `stream`
   // around every launch of that class, plus the algorithmic bytes those launches move.
   struct {
@@ -711,6 +725,11 @@ void free_ctx(adr_ctx *ctx) {
   F(ctx->b32);
   F(ctx->z32);
   for (auto &e : ctx->timer.ev) hipEventDestroy(e);
+  for (auto &g : ctx->graphs) {
+    hipGraphExecDestroy(g.e);
+    hipGraphDestroy(g.g);
+  }
+  if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
   delete ctx;
 }
 
@@ -768,16 +787,67 @@ adr_status setup_impl(adr_ctx *ctx, const adr_problem *p) {
   return ADR_OK;
 }
 
-// Preconditioner application into the mixed / FP64 Z slot.
-adr_status precondition(adr_ctx *ctx, const cx<double> *v, void *z) {
+// Enqueue one preconditioner application on ctx->stream: z = V-cycle(v).  v is c128;
+// z is c64 (mixed, `z_is_c128` = 0) or c128.  In mixed mode the input is converted to
+// c64 first (and the result back to c128 when z_is_c128).
+void enqueue_vcycle(adr_ctx *ctx, const cx<double> *v, void *z, bool z_is_c128) {
   hipStream_t s = ctx->stream;
   const int N = ctx->G0.N;
   if (ctx->opt.prec == ADR_PREC_MIXED) {
     adrk::convert<float, double>(s, N, v, ctx->b32);
-    vcycle<float>(ctx, 0, ctx->b32, (cx<float> *)z);
+    if (z_is_c128) {
+      vcycle<float>(ctx, 0, ctx->b32, ctx->z32);
+      adrk::convert<double, float>(s, N, ctx->z32, (cx<double> *)z);
+    } else {
+      vcycle<float>(ctx, 0, ctx->b32, (cx<float> *)z);
+    }
   } else {
     vcycle<double>(ctx, 0, v, (cx<double> *)z);
   }
+}
+
+// Preconditioner application, replayed from a captured graph when enabled (the per-kernel
+// timer needs eager launches, so it bypasses graphs).
+adr_status precondition(adr_ctx *ctx, const cx<double> *v, void *z, bool z_is_c128) {
+  if (!ctx->opt.use_graph || ctx->timer.kind >= 0) {
+    enqueue_vcycle(ctx, v, z, z_is_c128);
+    return ADR_OK;
+  }
+  adr_ctx::GraphEntry *hit = nullptr;
+  for (auto &g : ctx->graphs)
+    if (g.in == v && g.out == z) hit = &g;
+  if (!hit) {
+    if (!ctx->cap_stream) ADR_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    if (ctx->graphs.size() >= 16) {   // evict the least recently used capture
+      auto it = std::min_element(ctx->graphs.begin(), ctx->graphs.end(),
+                                 [](const adr_ctx::GraphEntry &x, const adr_ctx::GraphEntry &y) {
+                                   return x.last_use < y.last_use;
+                                 });
+      hipGraphExecDestroy(it->e);
+      hipGraphDestroy(it->g);
+      ctx->graphs.erase(it);
+    }
+    adr_ctx::GraphEntry ge;
+    ge.in = v;
+    ge.out = z;
+    hipStream_t user = ctx->stream;
+    ctx->stream = ctx->cap_stream;
+    hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+      enqueue_vcycle(ctx, v, z, z_is_c128);
+      e = hipStreamEndCapture(ctx->cap_stream, &ge.g);
+    }
+    ctx->stream = user;
+    if (e != hipSuccess) {
+      ctx->err = std::string("V-cycle graph capture failed: ") + hipGetErrorString(e);
+      return ADR_EHIP;
+    }
+    ADR_HIP(hipGraphInstantiate(&ge.e, ge.g, nullptr, nullptr, 0));
+    ctx->graphs.push_back(ge);
+    hit = &ctx->graphs.back();
+  }
+  hit->last_use = ++ctx->graph_clock;
+  ADR_HIP(hipGraphLaunch(hit->e, ctx->stream));
   return ADR_OK;
 }
 
@@ -902,15 +972,7 @@ adr_status adr_apply(adr_ctx *ctx, double beta, const void *x, void *y) {
 
 adr_status adr_vcycle(adr_ctx *ctx, const void *r, void *z) {
   if (!ctx || !r || !z || r == z) return ADR_EINVAL;
-  hipStream_t s = ctx->stream;
-  const int N = ctx->G0.N;
-  if (ctx->opt.prec == ADR_PREC_MIXED) {
-    adrk::convert<float, double>(s, N, (const cx<double> *)r, ctx->b32);
-    vcycle<float>(ctx, 0, ctx->b32, ctx->z32);
-    adrk::convert<double, float>(s, N, ctx->z32, (cx<double> *)z);
-  } else {
-    vcycle<double>(ctx, 0, (const cx<double> *)r, (cx<double> *)z);
-  }
+  ADR_TRY(precondition(ctx, (const cx<double> *)r, z, true));
   ADR_HIP(hipGetLastError());
   return ADR_OK;
 }
@@ -982,7 +1044,7 @@ adr_status adr_solve(adr_ctx *ctx, const void *q, void *a_out, double tol, int m
     g[0] = rnorm;
     int k = 0;
     for (int j = 0; j < m; ++j) {
-      precondition(ctx, Vp(j), Zp(j));
+      ADR_TRY(precondition(ctx, Vp(j), Zp(j), !mixed));
       VecSet<double> Vs{};
       Vs.count = j + 1;
       for (int i = 0; i <= j; ++i) Vs.v[i] = Vp(i);
