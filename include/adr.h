@@ -126,6 +126,35 @@ adr_status adr_vcycle(adr_ctx *ctx, const void *r_c128, void *z_c128);
 adr_status adr_solve(adr_ctx *ctx, const void *q_c128, void *a_c128, double tol, int maxit,
                      int use_initial_guess, adr_stats *stats);
 
+/* Adjoint solve (not in the paper; the gradient of a receiver misfit needs it):
+ * H_2up^H lam = s exp(i w tau), with the conjugate-transposed fine operator and the
+ * conjugate-transposed multigrid hierarchy ((P^T A P)^H = P^T A^H P, P real), built on
+ * the first call.  For J = 1/2 ||R u - d||^2, u = a exp(-i w tau), the right-hand side is
+ * s = R^T (R u - d) (see adr_adjoint_source); then dJ/dkappa2 = adr_grad_kappa2(a, lam).
+ * Same arguments, precision and stopping rule as adr_solve.  Synchronizes the stream. */
+adr_status adr_solve_adjoint(adr_ctx *ctx, const void *s_c128, void *lam_c128, double tol, int maxit,
+                             int use_initial_guess, adr_stats *stats);
+
+/* y = H_2up^H x in FP64 (conjugate transpose of adr_apply with beta = 0); x, y c128,
+ * distinct.  Enqueued. */
+adr_status adr_apply_adjoint(adr_ctx *ctx, const void *x_c128, void *y_c128);
+
+/* grad[i] += -Re(conj(lam_i) (w^2 - i w gamma_i) a_i): the kappa^2 derivative of the misfit
+ * at fixed travel time (dH_2up/dkappa2_i = (w^2 - i w gamma_i) e_i e_i^T through the
+ * reaction term).  a, lam c128; grad FP64 device array of n nodes, accumulated into.
+ * Enqueued. */
+adr_status adr_grad_kappa2(adr_ctx *ctx, const void *a_c128, const void *lam_c128, double *grad);
+
+/* Receivers: r_k = u[idx_k] - d_k for k < nrec (idx: device int32 linear node indices;
+ * d, r: c128 device arrays of nrec).  If misfit != NULL (host), *misfit = 1/2 sum |r_k|^2
+ * and the stream is synchronized; otherwise enqueued only. */
+adr_status adr_receiver_residual(adr_ctx *ctx, const void *u_c128, const int *idx, const void *d_c128, int nrec,
+                                 void *r_c128, double *misfit);
+
+/* Adjoint source s = R^T r: s = 0, then s[idx_k] += r_k for k in order (repeated indices
+ * accumulate).  s: c128 of n nodes.  Enqueued. */
+adr_status adr_adjoint_source(adr_ctx *ctx, const int *idx, const void *r_c128, int nrec, void *s_c128);
+
 /* u = a exp(-i w tau) (eq. new_u); a, u c128 (may alias).  Enqueued, no sync. */
 adr_status adr_wavefield(adr_ctx *ctx, const void *a_c128, void *u_c128);
 

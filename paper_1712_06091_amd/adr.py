@@ -92,6 +92,11 @@ def load_library(path=LIB_PATH):
         "adr_level_info": (I, [P, I, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
         "adr_num_levels": (I, [P]),
         "adr_get_level_stencil": (I, [P, I, P, ctypes.POINTER(ctypes.c_int)]),
+        "adr_solve_adjoint": (I, [P, P, P, D, I, I, ctypes.POINTER(AdrStats)]),
+        "adr_apply_adjoint": (I, [P, P, P]),
+        "adr_grad_kappa2": (I, [P, P, P, P]),
+        "adr_receiver_residual": (I, [P, P, P, P, I, P, ctypes.POINTER(ctypes.c_double)]),
+        "adr_adjoint_source": (I, [P, P, P, I, P]),
         "adr_timer_start": (I, [P, I, I]),
         "adr_timer_stop": (I, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
                                ctypes.POINTER(ctypes.c_double)]),
@@ -228,6 +233,53 @@ class Context:
         d = st.as_dict()
         d["status"] = status
         return a, d
+
+    def solve_adjoint(self, s, tol=1e-6, maxit=500, x0=None, out=None):
+        """lam with H_2up^H lam = s exp(i w tau); returns (lam, stats dict)."""
+        import torch
+        lam = self._new(torch.complex128) if out is None else out
+        use_guess = 0
+        if x0 is not None:
+            lam.copy_(x0)
+            use_guess = 1
+        st = AdrStats()
+        status = _check(self._lib.adr_solve_adjoint(self._ptr, _dev(s, torch.complex128), _dev(lam, torch.complex128),
+                                                    float(tol), int(maxit), use_guess, ctypes.byref(st)), self._ptr)
+        d = st.as_dict()
+        d["status"] = status
+        return lam, d
+
+    def apply_adjoint(self, x, out=None):
+        import torch
+        y = self._new(torch.complex128) if out is None else out
+        _check(self._lib.adr_apply_adjoint(self._ptr, _dev(x, torch.complex128), _dev(y, torch.complex128)),
+               self._ptr)
+        return y
+
+    def grad_kappa2(self, a, lam, grad):
+        """grad += -Re(conj(lam) (w^2 - i w gamma) a)  (grad: float64 tensor, accumulated)."""
+        import torch
+        _check(self._lib.adr_grad_kappa2(self._ptr, _dev(a, torch.complex128), _dev(lam, torch.complex128),
+                                         _dev(grad, torch.float64)), self._ptr)
+        return grad
+
+    def receiver_residual(self, u, idx, d, out=None):
+        """(r, misfit): r_k = u[idx_k] - d_k, misfit = 1/2 sum |r_k|^2 (idx: int32 linear indices)."""
+        import torch
+        n = int(idx.numel())
+        r = torch.empty(n, dtype=torch.complex128, device=self.device) if out is None else out
+        J = ctypes.c_double()
+        _check(self._lib.adr_receiver_residual(self._ptr, _dev(u, torch.complex128), _dev(idx, torch.int32),
+                                               _dev(d, torch.complex128), n, _dev(r, torch.complex128),
+                                               ctypes.byref(J)), self._ptr)
+        return r, J.value
+
+    def adjoint_source(self, idx, r, out=None):
+        import torch
+        s = self._new(torch.complex128) if out is None else out
+        _check(self._lib.adr_adjoint_source(self._ptr, _dev(idx, torch.int32), _dev(r, torch.complex128),
+                                            int(idx.numel()), _dev(s, torch.complex128)), self._ptr)
+        return s
 
     def wavefield(self, a, out=None):
         import torch

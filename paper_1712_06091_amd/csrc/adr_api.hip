@@ -49,6 +49,8 @@ struct LevelT {
   cx<T> *x = nullptr, *xt = nullptr, *b = nullptr, *r = nullptr, *w = nullptr;
   cx<T> *V = nullptr;        // (kMaxNu+1) x N Arnoldi basis (unnormalized)
   cx<T> *Z = nullptr;        // (kMaxNu+1) x N, Z_j = D^{-1} V_j
+  cx<T> *planes_adj = nullptr;   // conjugate-transposed stencil (adjoint solves)
+  cx<T> *dinv_adj = nullptr;
 };
 
 }  // namespace
@@ -81,7 +83,12 @@ struct adr_ctx {
   std::vector<int> h_off_coarse;
   int S_coarse = 0;
   cx<double> *Ainv = nullptr;  // coarsest inverse, row-major
+  cx<double> *Ainv_adj = nullptr;   // its conjugate transpose (adjoint solves)
+  std::vector<std::complex<double>> h_inv;   // host copy of the coarsest inverse
   int Ncoarsest = 0;
+  double *gamma = nullptr;     // FP64 copy of gamma (kappa^2 gradient), NULL if none
+  bool adj = false;            // direction of the current solve: false = H, true = H^H
+  bool adj_ready = false;
 
   // scalars and reductions
   double *scal = nullptr;      // kMaxLevels * kScalPerLevel
@@ -101,6 +108,7 @@ struct adr_ctx {
   struct GraphEntry {
     const void *in = nullptr;
     void *out = nullptr;
+    bool adj = false;
     hipGraph_t g = nullptr;
     hipGraphExec_t e = nullptr;
     unsigned long long last_use = 0;
@@ -292,6 +300,14 @@ FineParams fine_params(adr_ctx *ctx, double beta) {
 
 double *lscal(adr_ctx *ctx, int l) { return ctx->scal + (size_t)l * kScalPerLevel; }
 
+// Direction-dependent operators: the forward hierarchy of A_beta, or its conjugate
+// transpose for adjoint solves (the Galerkin product commutes with ^H since P is real:
+// (P^T A P)^H = P^T A^H P).
+template <typename T>
+const cx<T> *lvl_planes(const adr_ctx *ctx, const LevelT<T> &L) { return ctx->adj ? L.planes_adj : L.planes; }
+template <typename T>
+const cx<T> *lvl_dinv(const adr_ctx *ctx, const LevelT<T> &L) { return ctx->adj ? L.dinv_adj : L.dinv; }
+
 // Timed-launch brackets: tbegin returns an event slot (or -1 when this launch is not the
 // timed class), tend records the closing event and the launch's algorithmic bytes.
 int tbegin(adr_ctx *ctx, int kind, int level) {
@@ -359,19 +375,20 @@ void gmres_relax(adr_ctx *ctx, int l, const cx<T> *x0, const cx<T> *b, cx<T> *x_
     Vp[j] = L.V + (size_t)j * N;
     Zp[j] = L.Z + (size_t)j * N;
   }
+  const cx<T> *planes = lvl_planes(ctx, L), *dinv = lvl_dinv(ctx, L);
   int cur = 0, nb;
   if (!x0) {
     Vp[0] = b;
-    nb = adrk::norm2<T>(s, N, b, L.dinv, Zp[0], ctx->part[cur]);
+    nb = adrk::norm2<T>(s, N, b, dinv, Zp[0], ctx->part[cur]);
   } else {
     // V0 = b - A x0, Z0 = D^{-1} V0, with the norm partials.
     CoarseArgs<T> a{};
     a.G = L.G;
-    a.planes = L.planes;
+    a.planes = planes;
     a.x = x0;
     a.b = b;
     a.y = L.V;
-    a.dinv = L.dinv;
+    a.dinv = dinv;
     a.zout = Zp[0];
     a.mode = 1;
     a.pout = ctx->part[cur];
@@ -387,7 +404,7 @@ void gmres_relax(adr_ctx *ctx, int l, const cx<T> *x0, const cx<T> *b, cx<T> *x_
     // w = A Z_j s_j, with s_j = 1/||V_j|| from the previous kernel's partials.
     CoarseArgs<T> a{};
     a.G = L.G;
-    a.planes = L.planes;
+    a.planes = planes;
     a.x = Zp[j];
     a.pin = ProIn{ctx->part[cur], nb, 1};
     a.norm_out = (j == 0) ? sc + kBeta : sc + kH + 2 * ((j - 1) * kLdH + j);
@@ -401,7 +418,7 @@ void gmres_relax(adr_ctx *ctx, int l, const cx<T> *x0, const cx<T> *b, cx<T> *x_
     tend(ctx, t0, (double)N * cb * (L.S + 2 + (j + 1)));
     cur ^= 1;
     int t1 = tbegin(ctx, ADR_TIMER_COARSE_ORTH, l);
-    nb = adrk::orth_step<T>(s, N, L.w, Vs, ProIn{ctx->part[cur], nb, 2 * (j + 1)}, sc + kS, hcol, L.dinv,
+    nb = adrk::orth_step<T>(s, N, L.w, Vs, ProIn{ctx->part[cur], nb, 2 * (j + 1)}, sc + kS, hcol, dinv,
                             L.V + (size_t)(j + 1) * N, Zp[j + 1], ctx->part[cur ^ 1]);
     tend(ctx, t1, (double)N * cb * (j + 5));
     cur ^= 1;
@@ -427,7 +444,8 @@ cx<T> *jacobi_sweeps(adr_ctx *ctx, int nu, const cx<T> *x_start, const cx<T> *b,
   for (int k = 0; k < nu; ++k) {
     out = (k % 2 == 0) ? first : second;
     int t0 = tbegin(ctx, ADR_TIMER_FINE_JACOBI, 0);
-    adrk::fine_jacobi<T>(ctx->stream, G, ctx->D, C, P, in, b, out, ctx->opt.jacobi_weight);
+    if (ctx->adj) adrk::fine_jacobi_adj<T>(ctx->stream, G, ctx->D, C, P, in, b, out, ctx->opt.jacobi_weight);
+    else adrk::fine_jacobi<T>(ctx->stream, G, ctx->D, C, P, in, b, out, ctx->opt.jacobi_weight);
     tend(ctx, t0, (double)G.N * (fine_coef_bytes<T>(ctx->D) + sizeof(cx<T>) * (in ? 3 : 2)));
     in = out;
   }
@@ -444,7 +462,7 @@ cx<T> *vcycle(adr_ctx *ctx, int l, const cx<T> *b, cx<T> *out0) {
   const int D = ctx->D;
   if (l == ctx->levels - 1) {
     cx<T> *x = (l == 0 && out0) ? out0 : L.x;
-    adrk::dense_gemv<T>(s, L.G.N, ctx->Ainv, b, x);
+    adrk::dense_gemv<T>(s, L.G.N, ctx->adj ? ctx->Ainv_adj : ctx->Ainv, b, x);
     return x;
   }
   cx<T> *xa = (l == 0 && out0) ? out0 : L.x;
@@ -462,13 +480,17 @@ cx<T> *vcycle(adr_ctx *ctx, int l, const cx<T> *b, cx<T> *out0) {
   const double cb = sizeof(cx<T>);
   if (l == 0) {
     int t0 = tbegin(ctx, ADR_TIMER_FINE_RESIDUAL, 0);
-    adrk::fine_apply<T, T, T>(s, L.G, D, fine_coef<T>(ctx), fine_params(ctx, ctx->opt.beta), x, b, L.r, 1, nullptr,
-                              false, nullptr);
+    if (ctx->adj)
+      adrk::fine_apply_adj<T, T, T>(s, L.G, D, fine_coef<T>(ctx), fine_params(ctx, ctx->opt.beta), x, b, L.r, 1,
+                                    nullptr, false, nullptr);
+    else
+      adrk::fine_apply<T, T, T>(s, L.G, D, fine_coef<T>(ctx), fine_params(ctx, ctx->opt.beta), x, b, L.r, 1,
+                                nullptr, false, nullptr);
     tend(ctx, t0, (double)L.G.N * (fine_coef_bytes<T>(D) + 3 * cb));
   } else {
     CoarseArgs<T> a{};
     a.G = L.G;
-    a.planes = L.planes;
+    a.planes = lvl_planes(ctx, L);
     a.x = x;
     a.b = b;
     a.y = L.r;
@@ -683,6 +705,7 @@ adr_status build_hierarchy(adr_ctx *ctx) {
   }
   ADR_TRY(dalloc(ctx, &ctx->Ainv, (size_t)n * n));
   ADR_HIP(hipMemcpy(ctx->Ainv, inv.data(), inv.size() * sizeof(cx<double>), hipMemcpyHostToDevice));
+  ctx->h_inv.swap(inv);
   for (int l = 0; l < ctx->levels; ++l) ADR_TRY(alloc_level_vectors<T>(ctx, lv[l], l));
   return ADR_OK;
 }
@@ -701,12 +724,15 @@ void free_ctx(adr_ctx *ctx) {
   F(ctx->c64);
   F(ctx->c32);
   F(ctx->tau);
+  F(ctx->gamma);
+  F(ctx->Ainv_adj);
   for (int l = 0; l < kMaxLevels; ++l) {
     LevelT<double> &a = ctx->lv64[l];
     LevelT<float> &b = ctx->lv32[l];
     for (void *p : {(void *)a.planes, (void *)a.dinv, (void *)a.x, (void *)a.xt, (void *)a.b, (void *)a.r,
-                    (void *)a.w, (void *)a.V, (void *)a.Z, (void *)b.planes, (void *)b.dinv, (void *)b.x,
-                    (void *)b.xt, (void *)b.b, (void *)b.r, (void *)b.w, (void *)b.V, (void *)b.Z})
+                    (void *)a.w, (void *)a.V, (void *)a.Z, (void *)a.planes_adj, (void *)a.dinv_adj,
+                    (void *)b.planes, (void *)b.dinv, (void *)b.x, (void *)b.xt, (void *)b.b, (void *)b.r,
+                    (void *)b.w, (void *)b.V, (void *)b.Z, (void *)b.planes_adj, (void *)b.dinv_adj})
       F(p);
   }
   F(ctx->off_coarse);
@@ -742,6 +768,10 @@ adr_status setup_impl(adr_ctx *ctx, const adr_problem *p) {
   ADR_TRY(dalloc(ctx, &ctx->c64, N));
   ADR_TRY(dalloc(ctx, &ctx->tau, N));
   ADR_HIP(hipMemcpyAsync(ctx->tau, p->tau, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+  if (p->gamma) {
+    ADR_TRY(dalloc(ctx, &ctx->gamma, N));
+    ADR_HIP(hipMemcpyAsync(ctx->gamma, p->gamma, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+  }
   adrk::coefficients(s, ctx->G0, D, ctx->h, ctx->omega, ctx->src, p->kappa2, p->tau, p->gamma, ctx->g64[0],
                      ctx->g64[1], D == 3 ? ctx->g64[2] : nullptr, ctx->L64, ctx->c64);
   ADR_HIP(hipGetLastError());
@@ -815,7 +845,7 @@ adr_status precondition(adr_ctx *ctx, const cx<double> *v, void *z, bool z_is_c1
   }
   adr_ctx::GraphEntry *hit = nullptr;
   for (auto &g : ctx->graphs)
-    if (g.in == v && g.out == z) hit = &g;
+    if (g.in == v && g.out == z && g.adj == ctx->adj) hit = &g;
   if (!hit) {
     if (!ctx->cap_stream) ADR_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
     if (ctx->graphs.size() >= 16) {   // evict the least recently used capture
@@ -830,6 +860,7 @@ adr_status precondition(adr_ctx *ctx, const cx<double> *v, void *z, bool z_is_c1
     adr_ctx::GraphEntry ge;
     ge.in = v;
     ge.out = z;
+    ge.adj = ctx->adj;
     hipStream_t user = ctx->stream;
     ctx->stream = ctx->cap_stream;
     hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed);
@@ -984,8 +1015,55 @@ adr_status adr_wavefield(adr_ctx *ctx, const void *a, void *u) {
   return ADR_OK;
 }
 
-adr_status adr_solve(adr_ctx *ctx, const void *q, void *a_out, double tol, int maxit, int use_initial_guess,
-                     adr_stats *stats) {
+}  // extern "C"
+
+namespace {
+// r = rhs - (H or H^H) x in FP64 with the norm partials in part[0]; returns the block count.
+int fine_residual64(adr_ctx *ctx, const cx<double> *x, const cx<double> *rhs, cx<double> *r) {
+  FineCoef<double> C = fine_coef<double>(ctx);
+  FineParams P0 = fine_params(ctx, 0.0);
+  if (ctx->adj)
+    return adrk::fine_apply_adj<double, double, double>(ctx->stream, ctx->G0, ctx->D, C, P0, x, rhs, r, 1, nullptr,
+                                                        true, ctx->part[0]);
+  return adrk::fine_apply<double, double, double>(ctx->stream, ctx->G0, ctx->D, C, P0, x, rhs, r, 1, nullptr, true,
+                                                  ctx->part[0]);
+}
+
+// Conjugate-transposed hierarchy, built on the first adjoint solve.
+template <typename T>
+adr_status prepare_adjoint_levels(adr_ctx *ctx) {
+  LevelT<T> *lv = levels_of<T>(ctx);
+  for (int l = 1; l < ctx->levels; ++l) {
+    LevelT<T> &L = lv[l];
+    if (L.S == 0) continue;
+    ADR_TRY(dalloc(ctx, &L.planes_adj, (size_t)L.S * L.G.N));
+    adrk::adjoint_planes<T>(ctx->stream, L.G, ctx->D, L.planes, L.planes_adj);
+    ADR_TRY(dalloc(ctx, &L.dinv_adj, L.G.N));
+    adrk::stencil_diag_inv<T>(ctx->stream, L.G.N, L.planes_adj + (size_t)((L.S - 1) / 2) * L.G.N, L.dinv_adj);
+  }
+  return ADR_OK;
+}
+adr_status prepare_adjoint(adr_ctx *ctx) {
+  if (ctx->adj_ready) return ADR_OK;
+  if (ctx->opt.prec == ADR_PREC_MIXED) ADR_TRY(prepare_adjoint_levels<float>(ctx));
+  else ADR_TRY(prepare_adjoint_levels<double>(ctx));
+  const int n = ctx->Ncoarsest;
+  std::vector<std::complex<double>> t((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) t[(size_t)i * n + j] = std::conj(ctx->h_inv[(size_t)j * n + i]);
+  ADR_TRY(dalloc(ctx, &ctx->Ainv_adj, (size_t)n * n));
+  ADR_HIP(hipMemcpyAsync(ctx->Ainv_adj, t.data(), t.size() * sizeof(cx<double>), hipMemcpyHostToDevice,
+                         ctx->stream));
+  ADR_HIP(hipStreamSynchronize(ctx->stream));
+  ADR_HIP(hipGetLastError());
+  ctx->adj_ready = true;
+  return ADR_OK;
+}
+
+// FGMRES(m) on H_2up (ctx->adj false) or its conjugate transpose (true), preconditioned
+// by the matching V-cycle; rhs_hat = rhs exp(i w tau).
+adr_status solve_impl(adr_ctx *ctx, const void *q, void *a_out, double tol, int maxit, int use_initial_guess,
+                      adr_stats *stats) {
   if (!ctx || !q || !a_out || maxit < 0 || !(tol >= 0)) return ADR_EINVAL;
   const double t0 = now_ms();
   hipStream_t s = ctx->stream;
@@ -1015,8 +1093,7 @@ adr_status adr_solve(adr_ctx *ctx, const void *q, void *a_out, double tol, int m
   ADR_TRY(host_norm(adrk::norm2<double>(s, N, ctx->qh, nullptr, nullptr, ctx->part[0]), &bnorm));
   // initial residual
   if (use_initial_guess) {
-    int nb = adrk::fine_apply<double, double, double>(s, ctx->G0, D, C, P0, x, ctx->qh, ctx->ro, 1, nullptr, true,
-                                                      ctx->part[0]);
+    int nb = fine_residual64(ctx, x, ctx->qh, ctx->ro);
     ADR_TRY(host_norm(nb, &rnorm));
   } else {
     ADR_HIP(hipMemsetAsync(x, 0, sizeof(cx<double>) * N, s));
@@ -1051,9 +1128,15 @@ adr_status adr_solve(adr_ctx *ctx, const void *q, void *a_out, double tol, int m
       double *red1 = osc + 2, *red2 = osc + 2 + 2 * (kMaxRestart + 1);
       int t0 = tbegin(ctx, ADR_TIMER_OUTER_MATVEC, 0);
       int nb;
-      if (mixed)
+      if (mixed && ctx->adj)
+        nb = adrk::fine_apply_adj<double, float, double>(s, ctx->G0, D, C, P0, (const cx<float> *)Zp(j), nullptr,
+                                                         ctx->wo, 0, &Vs, false, ctx->part[0]);
+      else if (mixed)
         nb = adrk::fine_apply<double, float, double>(s, ctx->G0, D, C, P0, (const cx<float> *)Zp(j), nullptr,
                                                      ctx->wo, 0, &Vs, false, ctx->part[0]);
+      else if (ctx->adj)
+        nb = adrk::fine_apply_adj<double, double, double>(s, ctx->G0, D, C, P0, (const cx<double> *)Zp(j), nullptr,
+                                                          ctx->wo, 0, &Vs, false, ctx->part[0]);
       else
         nb = adrk::fine_apply<double, double, double>(s, ctx->G0, D, C, P0, (const cx<double> *)Zp(j), nullptr,
                                                       ctx->wo, 0, &Vs, false, ctx->part[0]);
@@ -1123,8 +1206,7 @@ adr_status adr_solve(adr_ctx *ctx, const void *q, void *a_out, double tol, int m
       for (int i = 0; i < k; ++i) Zs.v[i] = (const cx<double> *)Zp(i);
       adrk::multi_axpy<double>(s, N, x, Zs, ydev);
     }
-    int nbr = adrk::fine_apply<double, double, double>(s, ctx->G0, D, C, P0, x, ctx->qh, ctx->ro, 1, nullptr, true,
-                                                       ctx->part[0]);
+    int nbr = fine_residual64(ctx, x, ctx->qh, ctx->ro);
     ADR_TRY(host_norm(nbr, &rnorm));
     relres = rnorm / bnorm;
     ++restarts;
@@ -1138,6 +1220,68 @@ adr_status adr_solve(adr_ctx *ctx, const void *q, void *a_out, double tol, int m
   if (stats) *stats = st;
   if (result == ADR_ENOCONV) ctx->err = "FGMRES reached maxit before tol";
   return result;
+}
+
+}  // namespace
+
+extern "C" {
+
+adr_status adr_solve(adr_ctx *ctx, const void *q, void *a_out, double tol, int maxit, int use_initial_guess,
+                     adr_stats *stats) {
+  if (!ctx || !q || !a_out || maxit < 0 || !(tol >= 0)) return ADR_EINVAL;
+  ctx->adj = false;
+  return solve_impl(ctx, q, a_out, tol, maxit, use_initial_guess, stats);
+}
+
+adr_status adr_solve_adjoint(adr_ctx *ctx, const void *s_c128, void *lam_c128, double tol, int maxit,
+                             int use_initial_guess, adr_stats *stats) {
+  if (!ctx || !s_c128 || !lam_c128 || maxit < 0 || !(tol >= 0)) return ADR_EINVAL;
+  ADR_TRY(prepare_adjoint(ctx));
+  ctx->adj = true;
+  adr_status st = solve_impl(ctx, s_c128, lam_c128, tol, maxit, use_initial_guess, stats);
+  ctx->adj = false;
+  return st;
+}
+
+adr_status adr_apply_adjoint(adr_ctx *ctx, const void *x, void *y) {
+  if (!ctx || !x || !y || x == y) return ADR_EINVAL;
+  adrk::fine_apply_adj<double, double, double>(ctx->stream, ctx->G0, ctx->D, fine_coef<double>(ctx),
+                                               fine_params(ctx, 0.0), (const cx<double> *)x, nullptr,
+                                               (cx<double> *)y, 0, nullptr, false, nullptr);
+  ADR_HIP(hipGetLastError());
+  return ADR_OK;
+}
+
+adr_status adr_grad_kappa2(adr_ctx *ctx, const void *a, const void *lam, double *grad) {
+  if (!ctx || !a || !lam || !grad) return ADR_EINVAL;
+  adrk::grad_kappa2(ctx->stream, ctx->G0.N, ctx->omega, ctx->gamma, (const cx<double> *)a,
+                    (const cx<double> *)lam, grad);
+  ADR_HIP(hipGetLastError());
+  return ADR_OK;
+}
+
+adr_status adr_receiver_residual(adr_ctx *ctx, const void *u, const int *idx, const void *d, int nrec, void *r,
+                                 double *misfit) {
+  if (!ctx || !u || !idx || !d || !r || nrec <= 0) return ADR_EINVAL;
+  hipStream_t s = ctx->stream;
+  adrk::receiver_residual(s, nrec, idx, (const cx<double> *)u, (const cx<double> *)d, (cx<double> *)r);
+  if (misfit) {
+    const int nb = adrk::norm2<double>(s, nrec, (const cx<double> *)r, nullptr, nullptr, ctx->part[0]);
+    ADR_HIP(hipMemcpyAsync(ctx->hpin, ctx->part[0], nb * sizeof(double), hipMemcpyDeviceToHost, s));
+    ADR_HIP(hipStreamSynchronize(s));
+    double acc = 0.0;
+    for (int b = 0; b < nb; ++b) acc += ctx->hpin[b];
+    *misfit = 0.5 * acc;
+  }
+  ADR_HIP(hipGetLastError());
+  return ADR_OK;
+}
+
+adr_status adr_adjoint_source(adr_ctx *ctx, const int *idx, const void *r, int nrec, void *src) {
+  if (!ctx || !idx || !r || !src || nrec <= 0) return ADR_EINVAL;
+  adrk::adjoint_source(ctx->stream, ctx->G0.N, nrec, idx, (const cx<double> *)r, (cx<double> *)src);
+  ADR_HIP(hipGetLastError());
+  return ADR_OK;
 }
 
 adr_status adr_timer_start(adr_ctx *ctx, int kind, int level) {

@@ -122,3 +122,53 @@ __device__ __forceinline__ void load_fine_coef(const FineCoef<T> &C, int i, T (&
   L = C.L[i];
   c = C.c[i];
 }
+
+// Off-diagonal entry of the fine row of node j (index idx, coefficients gk, L) towards its
+// neighbour at offset o in {-2, -1, +1, +2} along axis k -- the same value fine_row puts
+// in e[1 + 4k + {0,1,2,3}].  Used by the conjugate-transposed (adjoint) operator, which
+// gathers, for each node i, the entries of the neighbours' rows that point back to i.
+template <typename T, int D>
+__device__ __forceinline__ cx<T> fine_offdiag(const Grid &G, const FineParams &P, const int idx[3], const T gk[3],
+                                              T L, int k, int o) {
+  const T h = (T)P.h, w = (T)P.omega, beta = (T)P.beta;
+  const T ih = T(1) / h, ih2 = ih * ih;
+  bool on_face = false;
+  bool near = P.src[0] >= 0;
+#pragma unroll
+  for (int m = 0; m < D; ++m) {
+    on_face |= (idx[m] == 0) | (idx[m] == G.n[m] - 1);
+    const int dm = idx[m] - P.src[m];
+    near &= (dm >= -1) & (dm <= 1);
+  }
+  const int i = idx[k], n = G.n[k];
+  const T g = gk[k];
+  const bool low = (i == 0), high = (i == n - 1);
+  T lap = 0;
+  if (o == -1) lap = low ? T(0) : (high ? T(2) * ih2 : ih2);
+  if (o == 1) lap = high ? T(0) : (low ? T(2) * ih2 : ih2);
+  T d = 0;
+  if (near) {
+    if (o == -1) d = T(-0.5) * ih;
+    if (o == 1) d = T(0.5) * ih;
+  } else {
+    const bool backward = (g >= T(0));
+    int mode;
+    if (backward) mode = (i >= 2) ? 0 : ((i == 1) ? 1 : 2);
+    else mode = (i <= n - 3) ? 2 : ((i == n - 2) ? 3 : 0);
+    const T a2 = T(1) - beta;
+    if (mode == 0) {
+      if (o == -1) d = a2 * T(-2) * ih - beta * ih;
+      if (o == -2) d = a2 * T(0.5) * ih;
+    } else if (mode == 1) {
+      if (o == -1) d = -ih;
+    } else if (mode == 2) {
+      if (o == 1) d = a2 * T(2) * ih + beta * ih;
+      if (o == 2) d = a2 * T(-0.5) * ih;
+    } else {
+      if (o == 1) d = ih;
+    }
+  }
+  T im = T(-2) * w * g * d;
+  if (!on_face && (o == -1 || o == 1)) im += -w * L / T(2 * D);
+  return mk<T>(lap, im);
+}

@@ -357,9 +357,6 @@ template void fine_jacobi<double>(hipStream_t, const Grid &, int, const FineCoef
 template void fine_jacobi<float>(hipStream_t, const Grid &, int, const FineCoef<float> &, const FineParams &,
                                  const cx<float> *, const cx<float> *, cx<float> *, double);
 
-// =====================================================================================
-// Coarse levels: stored Galerkin stencils (SoA planes)
-// =====================================================================================
 // The coarse stencil set: offsets with |d_k| <= 2 and at most one |d_k| == 2, ordered
 // dz-major then dy then dx (81 points in 3D, 21 in 2D).  Compile-time table so that the
 // fully unrolled apply has constant offsets.
@@ -384,6 +381,248 @@ __host__ __device__ constexpr OffTable<D> make_off_table() {
   return t;
 }
 
+// =====================================================================================
+// Fine level, conjugate-transposed operator A^H (adjoint solves)
+// =====================================================================================
+// (A^H x)_i = conj(A_ii) x_i + sum over neighbours j = i - o e_k of conj(A_{j, j + o e_k}) x_j:
+// the entries of the neighbours' rows that point back to node i.  Returns the sum and
+// conj(A_ii) (the adjoint diagonal).
+template <typename T, typename Tin, int D>
+__device__ __forceinline__ cx<T> fine_adjoint_row(const Grid &G, const FineCoef<T> &C, const FineParams &P, int i,
+                                                  const int idx[3], const cx<Tin> *__restrict__ x, cx<T> &dconj) {
+  T gk[3], L;
+  cx<T> c;
+  load_fine_coef<T, D>(C, i, gk, L, c);
+  cx<T> e[1 + 4 * D];
+  int id[3] = {idx[0], idx[1], idx[2]};
+  fine_row<T, D>(G, P, id, gk, L, c, e);
+  dconj = mk<T>(e[0].re, -e[0].im);
+  cx<T> acc = dconj * cvt<T, Tin>(x[i]);
+  int stride = 1;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int o = (q < 2) ? q - 2 : q - 1;   // -2, -1, +1, +2
+      const int pj = idx[k] - o;
+      if (pj < 0 || pj >= G.n[k]) continue;
+      const int j = i - o * stride;
+      int jdx[3] = {idx[0], idx[1], idx[2]};
+      jdx[k] = pj;
+      T gj[3];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) gj[m] = (m == k) ? C.g[k][j] : T(0);
+      const cx<T> a = fine_offdiag<T, D>(G, P, jdx, gj, C.L[j], k, o);
+      acc = cfma(mk<T>(a.re, -a.im), cvt<T, Tin>(x[j]), acc);
+    }
+    stride *= G.n[k];
+  }
+  return acc;
+}
+
+template <typename T, typename Tin, typename To, int D, int NV, bool NORM>
+__global__ __launch_bounds__(ADR_BLOCK) void k_fine_apply_adj(Grid G, FineCoef<T> C, FineParams P,
+                                                              const cx<Tin> *__restrict__ x,
+                                                              const cx<To> *__restrict__ b, cx<To> *__restrict__ y,
+                                                              int mode, VecSet<To> V, double *pout) {
+  constexpr int K = 2 * NV + (NORM ? 1 : 0);
+  constexpr int KA = K > 0 ? K : 1;
+  double red[KA];
+#pragma unroll
+  for (int k = 0; k < KA; ++k) red[k] = 0.0;
+  int beg, end;
+  chunk_range(G.N, beg, end);
+  for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    int idx[3];
+    decode(G, i, idx[0], idx[1], idx[2]);
+    cx<T> dc;
+    const cx<T> acc = fine_adjoint_row<T, Tin, D>(G, C, P, i, idx, x, dc);
+    cx<To> o = cvt<To, T>(acc);
+    if (mode == 1) o = b[i] - o;
+    y[i] = o;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const cx<double> d = cdotc(cvt<double, To>(V.v[v][i]), cvt<double, To>(o));
+      red[2 * v] += d.re;
+      red[2 * v + 1] += d.im;
+    }
+    if (NORM) red[K - 1] += (double)o.re * o.re + (double)o.im * o.im;
+  }
+  if (K > 0) block_partials<KA>(red, K, pout);
+}
+
+template <typename T, typename Tin, typename To, int D, bool NORM>
+static void dispatch_fine_adj_nv(hipStream_t s, int nb, const Grid &G, const FineCoef<T> &C, const FineParams &P,
+                                 const cx<Tin> *x, const cx<To> *b, cx<To> *y, int mode, const VecSet<To> &V,
+                                 double *pout) {
+  switch (V.count) {
+#define ADR_NV_CASE(n) \
+  case n: ADR_LAUNCH((k_fine_apply_adj<T, Tin, To, D, n, NORM>), nb, s, G, C, P, x, b, y, mode, V, pout); break;
+    ADR_NV_CASE(0) ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6)
+    ADR_NV_CASE(7) ADR_NV_CASE(8)
+#undef ADR_NV_CASE
+    default: break;
+  }
+}
+
+template <typename T, typename Tin, typename To>
+int fine_apply_adj(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P, const cx<Tin> *x,
+                   const cx<To> *b, cx<To> *y, int mode, const VecSet<To> *dots, bool want_norm, double *pout) {
+  VecSet<To> V{};
+  if (dots) V = *dots;
+  const bool red = want_norm || V.count > 0;
+  const int nb = red ? launch_blocks_red(G.N) : launch_blocks(G.N);
+  if (D == 2) {
+    if (want_norm) dispatch_fine_adj_nv<T, Tin, To, 2, true>(s, nb, G, C, P, x, b, y, mode, V, pout);
+    else dispatch_fine_adj_nv<T, Tin, To, 2, false>(s, nb, G, C, P, x, b, y, mode, V, pout);
+  } else {
+    if (want_norm) dispatch_fine_adj_nv<T, Tin, To, 3, true>(s, nb, G, C, P, x, b, y, mode, V, pout);
+    else dispatch_fine_adj_nv<T, Tin, To, 3, false>(s, nb, G, C, P, x, b, y, mode, V, pout);
+  }
+  return nb;
+}
+template int fine_apply_adj<double, double, double>(hipStream_t, const Grid &, int, const FineCoef<double> &,
+                                                    const FineParams &, const cx<double> *, const cx<double> *,
+                                                    cx<double> *, int, const VecSet<double> *, bool, double *);
+template int fine_apply_adj<double, float, double>(hipStream_t, const Grid &, int, const FineCoef<double> &,
+                                                   const FineParams &, const cx<float> *, const cx<double> *,
+                                                   cx<double> *, int, const VecSet<double> *, bool, double *);
+template int fine_apply_adj<float, float, float>(hipStream_t, const Grid &, int, const FineCoef<float> &,
+                                                 const FineParams &, const cx<float> *, const cx<float> *,
+                                                 cx<float> *, int, const VecSet<float> *, bool, double *);
+
+// x_out = x_in + w conj(A_ii)^{-1} (b - A^H x_in); x_in NULL means zero.
+template <typename T, int D>
+__global__ __launch_bounds__(ADR_BLOCK) void k_fine_jacobi_adj(Grid G, FineCoef<T> C, FineParams P,
+                                                               const cx<T> *__restrict__ xin,
+                                                               const cx<T> *__restrict__ b, cx<T> *__restrict__ xout,
+                                                               T weight) {
+  int beg, end;
+  chunk_range(G.N, beg, end);
+  for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    int idx[3];
+    decode(G, i, idx[0], idx[1], idx[2]);
+    cx<T> r = b[i], x0 = mk<T>(T(0), T(0)), dc;
+    if (xin) {
+      const cx<T> acc = fine_adjoint_row<T, T, D>(G, C, P, i, idx, xin, dc);
+      r = r - acc;
+      x0 = xin[i];
+    } else {
+      T gk[3], L;
+      cx<T> c;
+      load_fine_coef<T, D>(C, i, gk, L, c);
+      cx<T> e[1 + 4 * D];
+      fine_row<T, D>(G, P, idx, gk, L, c, e);
+      dc = mk<T>(e[0].re, -e[0].im);
+    }
+    xout[i] = cfma(weight * cinv(dc), r, x0);
+  }
+}
+template <typename T>
+void fine_jacobi_adj(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P,
+                     const cx<T> *x_in, const cx<T> *b, cx<T> *x_out, double weight) {
+  int nb = launch_blocks(G.N);
+  if (D == 2) ADR_LAUNCH((k_fine_jacobi_adj<T, 2>), nb, s, G, C, P, x_in, b, x_out, (T)weight);
+  else ADR_LAUNCH((k_fine_jacobi_adj<T, 3>), nb, s, G, C, P, x_in, b, x_out, (T)weight);
+}
+template void fine_jacobi_adj<double>(hipStream_t, const Grid &, int, const FineCoef<double> &, const FineParams &,
+                                      const cx<double> *, const cx<double> *, cx<double> *, double);
+template void fine_jacobi_adj<float>(hipStream_t, const Grid &, int, const FineCoef<float> &, const FineParams &,
+                                     const cx<float> *, const cx<float> *, cx<float> *, double);
+
+// Conjugate transpose of a Galerkin level: AH[t][i] = conj(A[-t][i + t]) (zero when i + t
+// is outside the grid).  The offset set is symmetric and ordered so that -t is plane
+// S-1-t.
+template <typename T, int D>
+__global__ __launch_bounds__(ADR_BLOCK) void k_adjoint_planes(Grid G, const cx<T> *__restrict__ A,
+                                                              cx<T> *__restrict__ AH) {
+  constexpr int S = D == 3 ? 81 : 21;
+  constexpr OffTable<D> OT = make_off_table<D>();
+  const long long total = (long long)S * G.N;
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+       q += (long long)gridDim.x * blockDim.x) {
+    const int t = (int)(q / G.N), i = (int)(q - (long long)t * G.N);
+    int ix, iy, iz;
+    decode(G, i, ix, iy, iz);
+    int dx = 0, dy = 0, dz = 0;
+#pragma unroll
+    for (int p = 0; p < S; ++p)
+      if (p == t) {
+        dx = OT.dx[p];
+        dy = OT.dy[p];
+        dz = OT.dz[p];
+      }
+    const int jx = ix + dx, jy = iy + dy, jz = iz + dz;
+    cx<T> v = mk<T>(T(0), T(0));
+    if (jx >= 0 && jx < G.n[0] && jy >= 0 && jy < G.n[1] && jz >= 0 && jz < G.n[2]) {
+      const cx<T> a = A[(size_t)(S - 1 - t) * G.N + jx + G.n[0] * (jy + G.n[1] * jz)];
+      v = mk<T>(a.re, -a.im);
+    }
+    AH[(size_t)t * G.N + i] = v;
+  }
+}
+template <typename T>
+void adjoint_planes(hipStream_t s, const Grid &G, int D, const cx<T> *A, cx<T> *AH) {
+  long long total = (long long)(D == 3 ? 81 : 21) * G.N;
+  long long nb = (total + ADR_BLOCK - 1) / ADR_BLOCK;
+  if (nb > 65536) nb = 65536;
+  if (D == 2) ADR_LAUNCH((k_adjoint_planes<T, 2>), (int)nb, s, G, A, AH);
+  else ADR_LAUNCH((k_adjoint_planes<T, 3>), (int)nb, s, G, A, AH);
+}
+template void adjoint_planes<double>(hipStream_t, const Grid &, int, const cx<double> *, cx<double> *);
+template void adjoint_planes<float>(hipStream_t, const Grid &, int, const cx<float> *, cx<float> *);
+
+// grad[i] += -Re(conj(lam_i) (w^2 - i w gamma_i) a_i): the derivative of a receiver misfit
+// with respect to kappa^2_i at fixed travel time, given the forward amplitude a and the
+// adjoint state lam (dH_2up / dkappa2_i = (w^2 - i w gamma_i) e_i e_i^T).
+__global__ __launch_bounds__(ADR_BLOCK) void k_grad_kappa2(int N, double omega, const double *__restrict__ gamma,
+                                                           const cx<double> *__restrict__ a,
+                                                           const cx<double> *__restrict__ lam, double *grad) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+    const double gm = gamma ? gamma[i] : 0.0;
+    const cx<double> t = cdotc(lam[i], mk<double>(omega * omega, -omega * gm) * a[i]);
+    grad[i] -= t.re;
+  }
+}
+void grad_kappa2(hipStream_t s, int N, double omega, const double *gamma, const cx<double> *a, const cx<double> *lam,
+                 double *grad) {
+  ADR_LAUNCH(k_grad_kappa2, launch_blocks(N), s, N, omega, gamma, a, lam, grad);
+}
+
+// Receivers: r_k = u[idx_k] - d_k; adjoint source s = sum_k e_{idx_k} r_k (s is zeroed
+// first; one lane adds the receivers in order, so repeated indices accumulate
+// deterministically).
+__global__ __launch_bounds__(ADR_BLOCK) void k_receiver_residual(int nrec, const int *__restrict__ idx,
+                                                                 const cx<double> *__restrict__ u,
+                                                                 const cx<double> *__restrict__ d,
+                                                                 cx<double> *__restrict__ r) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nrec; k += gridDim.x * blockDim.x)
+    r[k] = u[idx[k]] - d[k];
+}
+void receiver_residual(hipStream_t s, int nrec, const int *idx, const cx<double> *u, const cx<double> *d,
+                       cx<double> *r) {
+  hipLaunchKernelGGL(k_receiver_residual, dim3((nrec + ADR_BLOCK - 1) / ADR_BLOCK), dim3(ADR_BLOCK), 0, s, nrec, idx,
+                     u, d, r);
+}
+__global__ __launch_bounds__(ADR_BLOCK) void k_zero(long long n, cx<double> *x) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    x[i] = mk<double>(0.0, 0.0);
+}
+__global__ void k_scatter_add(int nrec, const int *__restrict__ idx, const cx<double> *__restrict__ r,
+                              cx<double> *__restrict__ s) {
+  // One lane walks the receivers in order so repeated indices add deterministically.
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    for (int k = 0; k < nrec; ++k) s[idx[k]] = s[idx[k]] + r[k];
+}
+void adjoint_source(hipStream_t s, int N, int nrec, const int *idx, const cx<double> *r, cx<double> *src) {
+  ADR_LAUNCH(k_zero, launch_blocks(N), s, (long long)N, src);
+  hipLaunchKernelGGL(k_scatter_add, dim3(1), dim3(64), 0, s, nrec, idx, r, src);
+}
+void zero(hipStream_t s, long long n, cx<double> *x) { ADR_LAUNCH(k_zero, launch_blocks(n), s, n, x); }
+
+// =====================================================================================
+// Coarse levels: stored Galerkin stencils (SoA planes)
+// =====================================================================================
 // mode 0: y = s * (A x), where s = 1/||.|| of the predecessor's partials (prologue
 //         `pin`, K = 1; block 0 stores the norm in norm_out[0] (and 0 in norm_out[1]
 //         when norm_cplx) and s in inv_out), or s = 1 without a prologue;

@@ -69,6 +69,27 @@ template <typename T>
 void fine_jacobi(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P, const cx<T> *x_in,
                  const cx<T> *b, cx<T> *x_out, double weight);
 
+// A^H x on the fine level (conjugate transpose, matrix-free), same conventions.
+template <typename T, typename Tin, typename To>
+int fine_apply_adj(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P, const cx<Tin> *x,
+                   const cx<To> *b, cx<To> *y, int mode, const VecSet<To> *dots, bool want_norm, double *pout);
+// x_out = x_in + w conj(diag)^{-1} (b - A^H x_in); x_in NULL means zero.
+template <typename T>
+void fine_jacobi_adj(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P,
+                     const cx<T> *x_in, const cx<T> *b, cx<T> *x_out, double weight);
+// AH[t][i] = conj(A[-t][i+t]) for a Galerkin level (zero outside the grid).
+template <typename T>
+void adjoint_planes(hipStream_t s, const Grid &G, int D, const cx<T> *A, cx<T> *AH);
+// grad[i] += -Re(conj(lam_i) (w^2 - i w gamma_i) a_i)  (gamma may be NULL)
+void grad_kappa2(hipStream_t s, int N, double omega, const double *gamma, const cx<double> *a, const cx<double> *lam,
+                 double *grad);
+// r_k = u[idx_k] - d_k
+void receiver_residual(hipStream_t s, int nrec, const int *idx, const cx<double> *u, const cx<double> *d,
+                       cx<double> *r);
+// src = 0, then src[idx_k] += r_k in receiver order
+void adjoint_source(hipStream_t s, int N, int nrec, const int *idx, const cx<double> *r, cx<double> *src);
+void zero(hipStream_t s, long long n, cx<double> *x);
+
 // ---- coarse levels (stored stencils) ----------------------------------------------
 // Galerkin-stencil apply (see CoarseArgs); fused dot/norm partials; returns the block
 // count.

@@ -1,0 +1,129 @@
+"""GPU adjoint: conjugate-transposed operator and hierarchy, adjoint solves, and the kappa^2
+gradient of a receiver misfit, against the FP64 oracle and finite differences."""
+import numpy as np
+import pytest
+
+from oracle import multigrid as omg
+from oracle import solve as osolve
+from paper_1712_06091_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _t(a, dtype=None):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+def _ctx(wl, prec="fp64", kappa2=None, **opts):
+    from paper_1712_06091_amd import adr
+    k2 = wl.kappa2 if kappa2 is None else kappa2
+    o = adr.default_options(prec=prec, **opts)
+    return adr.Context(_t(k2, torch.float64), _t(wl.tau, torch.float64), _t(wl.gamma, torch.float64), wl.h,
+                       wl.omega, wl.src, options=o)
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
+
+
+CASES = {"2d_65": lambda: W.linear_gradient(65, 2), "3d_33": lambda: W.linear_gradient(33, 3)}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_adjoint_apply_and_dot_test(name):
+    wl = CASES[name]()
+    print(f"[adj-apply] {name} shape={wl.shape}", flush=True)
+    c = _ctx(wl)
+    p = osolve.Problem(wl.kappa2, wl.tau, wl.gamma, wl.h, wl.omega, wl.src)
+    x = W.random_vector(wl.shape, 31)
+    y = W.random_vector(wl.shape, 32)
+    Hx = c.apply(_t(x), beta=0.0).cpu().numpy()
+    Hy = c.apply_adjoint(_t(y)).cpu().numpy()
+    AH = p.H2up.conj().T.tocsr()
+    scale = (abs(AH) @ np.abs(y.ravel())).reshape(wl.shape)
+    assert np.max(np.abs(Hy - (AH @ y.ravel()).reshape(wl.shape)) / scale) <= 1e-13
+    lhs = np.vdot(y.ravel(), Hx.ravel())
+    rhs = np.vdot(Hy.ravel(), x.ravel())
+    assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(Hx) * np.linalg.norm(y)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_adjoint_vcycle_matches_oracle(name):
+    """The adjoint V-cycle equals the oracle's V-cycle built on A_beta^H (Galerkin of A^H)."""
+    wl = CASES[name]()
+    print(f"[adj-vcycle] {name} shape={wl.shape}", flush=True)
+    c = _ctx(wl)
+    p = osolve.Problem(wl.kappa2, wl.tau, wl.gamma, wl.h, wl.omega, wl.src)
+    hier = omg.Hierarchy(p.Abeta.conj().T.tocsr(), wl.shape, c.num_levels)
+    r = W.random_vector(wl.shape, 33)
+    # One FGMRES step from a zero guess applies one adjoint V-cycle z = M^-H rh (M^-H is
+    # homogeneous, so the normalization of the Arnoldi vector cancels) and returns y z
+    # with y the least-squares coefficient.  rh = r exp(i w tau) as for every solve.
+    rh = osolve.rhs_hat(r, wl.tau, wl.omega).ravel()
+    z_ref = hier.vcycle(rh)
+    AHz = p.H2up.conj().T @ z_ref
+    y1 = np.vdot(AHz, rh) / np.vdot(AHz, AHz)
+    lam, st = c.solve_adjoint(_t(r), tol=0.0, maxit=1)
+    assert st["outer_iters"] == 1
+    assert _rel(lam.cpu().numpy().ravel(), y1 * z_ref) <= 1e-10
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_adjoint_solve_matches_direct(name, prec):
+    wl = CASES[name]()
+    print(f"[adj-solve] {name} prec={prec}", flush=True)
+    c = _ctx(wl, prec=prec)
+    p = osolve.Problem(wl.kappa2, wl.tau, wl.gamma, wl.h, wl.omega, wl.src)
+    s = W.random_vector(wl.shape, 34)
+    ref = osolve.direct_solve(p.H2up.conj().T.tocsr(), osolve.rhs_hat(s, wl.tau, wl.omega)).reshape(wl.shape)
+    lam, st = c.solve_adjoint(_t(s), tol=1e-10, maxit=400)
+    assert st["relres"] <= 1e-10
+    assert _rel(lam.cpu().numpy(), ref) <= 1e-6
+
+
+def _receivers(shape):
+    """Every third node of the top face (depth index 1), as linear indices."""
+    d = len(shape)
+    grids = np.meshgrid(*[np.arange(2, n - 2, 3) for n in shape[1:]], indexing="ij")
+    idx = np.stack([np.full(grids[0].size, 1)] + [g.ravel() for g in grids])
+    return np.ravel_multi_index(tuple(idx), shape).astype(np.int32)
+
+
+def test_gradient_finite_differences_and_oracle():
+    """dJ/dkappa^2 from the adjoint against central finite differences of GPU solves
+    (FP64, tol 1e-12, direction zero at the source node) and against the oracle's
+    adjoint gradient."""
+    from paper_1712_06091_amd import adr, misfit
+    wl = W.linear_gradient(17, 3)
+    print("[gradient] 3d 17", flush=True)
+    rec = _receivers(wl.shape)
+    rng = np.random.default_rng(35)
+    d_obs = (rng.standard_normal(rec.size) + 1j * rng.standard_normal(rec.size)) * 1e-3
+    opts = adr.default_options(prec="fp64")
+    k2 = _t(wl.kappa2, torch.float64).requires_grad_(True)
+    tau, gam = _t(wl.tau, torch.float64), _t(wl.gamma, torch.float64)
+    recs, dd = _t(rec, torch.int32), _t(d_obs, torch.complex128)
+    J = misfit.receiver_misfit(k2, gam, [tau], [wl.src], wl.h, wl.omega, recs, [dd], options=opts, tol=1e-12)
+    J.backward()
+    g = k2.grad.cpu().numpy()
+    # oracle gradient (same J, same fixed-tau convention)
+    p = osolve.Problem(wl.kappa2, wl.tau, wl.gamma, wl.h, wl.omega, wl.src)
+    a = osolve.direct_solve(p.H2up, osolve.rhs_hat(wl.rhs(), wl.tau, wl.omega)).reshape(wl.shape)
+    Jo, go, _ = osolve.adjoint_gradient(p, a, np.unravel_index(rec, wl.shape), d_obs)
+    assert abs(J.item() - Jo) <= 1e-8 * Jo
+    assert _rel(g, go) <= 1e-6
+    # finite differences along a smooth direction that vanishes at the source node
+    xs = W.node_coordinates(wl.shape, wl.h)
+    dk = np.sin(3 * xs[0]) * np.cos(2 * xs[1] + xs[2])
+    dk[wl.src] = 0.0
+    eps = 1e-4 * np.abs(wl.kappa2).max()
+    vals = []
+    for sgn in (+1, -1):
+        kk = _t(wl.kappa2 + sgn * eps * dk, torch.float64)
+        vals.append(misfit.receiver_misfit(kk, gam, [tau], [wl.src], wl.h, wl.omega, recs, [dd],
+                                           options=opts, tol=1e-12).item())
+    fd = (vals[0] - vals[1]) / (2 * eps)
+    an = float(np.sum(g * dk))
+    assert abs(fd - an) <= 1e-5 * abs(an), (fd, an)
