@@ -9,6 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libadr.so")
+FM_LIB = os.path.join(HERE, "libfm.so")
 SOURCES = ["adr_kernels.hip", "adr_api.hip"]
 ARCH = "gfx950"
 
@@ -60,7 +61,19 @@ def build(verbose=False, jobs=2):
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout.decode(errors="replace"))
     os.replace(tmp, LIB)
+    build_fm()
     return LIB
+
+
+def build_fm():
+    """The CPU fast-marching input generator (plain C++)."""
+    tmp = FM_LIB + ".tmp"
+    cmd = ["g++", "-O3", "-std=c++17", "-shared", "-fPIC", os.path.join(CSRC, "fm.cpp"), "-o", tmp]
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
+    if r.returncode != 0:
+        raise RuntimeError("fm build failed:\n" + r.stdout.decode(errors="replace"))
+    os.replace(tmp, FM_LIB)
+    return FM_LIB
 
 
 if __name__ == "__main__":

@@ -11,6 +11,8 @@ the interior of a unit square / cube.
 Arrays are C-ordered with the last axis = x (fastest); axis 0 is depth (y in 2D, z in
 3D).  Source indices are NumPy index tuples in the same order.
 """
+import ctypes
+import os
 from dataclasses import dataclass, field
 from typing import Optional, Tuple
 
@@ -137,3 +139,75 @@ def random_vector(shape, seed, dtype=np.complex128):
     if np.dtype(dtype).kind == "c":
         return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(dtype)
     return rng.standard_normal(shape).astype(dtype)
+
+
+# ---------------------------------------------------------------------------------------
+# Random media and fast-marching travel times (configurations with heterogeneous media)
+# ---------------------------------------------------------------------------------------
+def smooth_random_field(shape, h, seed, corr_len=0.1):
+    """eta = G_sigma * xi, xi iid N(0, 1) (seeded), sigma = corr_len in domain units,
+    normalized to unit standard deviation, then clipped to [-1, 1]."""
+    from scipy.ndimage import gaussian_filter
+    rng = np.random.default_rng(seed)
+    xi = rng.standard_normal(shape)
+    eta = gaussian_filter(xi, sigma=corr_len / h, mode="reflect")
+    eta = eta / eta.std()
+    return np.clip(eta, -1.0, 1.0)
+
+
+def smooth_random_velocity(shape, h, seed, v0=2.0, amp=0.2, corr_len=0.1):
+    """v = v0 (1 + amp * eta) km/s (eta from smooth_random_field)."""
+    return v0 * (1.0 + amp * smooth_random_field(shape, h, seed, corr_len))
+
+
+_fm = None
+
+
+def _fm_lib():
+    global _fm
+    if _fm is None:
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfm.so")
+        if not os.path.exists(path):
+            raise RuntimeError("libfm.so not built (run __graft_entry__.build())")
+        lib = ctypes.CDLL(path)
+        lib.fm_factored.restype = ctypes.c_int
+        lib.fm_factored.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_double, ctypes.c_void_p,
+                                    ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_void_p]
+        _fm = lib
+    return _fm
+
+
+def factored_traveltime(kappa2, h, src, order=2):
+    """First-arrival travel time from node ``src`` (NumPy index order) by factored fast
+    marching (CPU, libfm.so)."""
+    kappa2 = np.ascontiguousarray(kappa2, dtype=np.float64)
+    d = kappa2.ndim
+    n = (ctypes.c_int * 3)(*[kappa2.shape[d - 1 - k] if k < d else 1 for k in range(3)])
+    s = (ctypes.c_int * 3)(*[int(src[d - 1 - k]) if k < d else 0 for k in range(3)])
+    tau = np.empty_like(kappa2)
+    rc = _fm_lib().fm_factored(d, n, float(h), kappa2.ctypes.data, s, int(order), tau.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"fast marching failed ({rc})")
+    return tau
+
+
+def random_medium(n, ndim, seed, src_frac=None, ppw=10.0, absorb=True, name="random_medium", order=2):
+    """Unit square/cube, v = 2 (1 + 0.2 eta) km/s with eta seeded and smoothed over 0.1 km,
+    tau by factored fast marching, 10 points per wavelength at the slowest velocity."""
+    shape = (n,) * ndim
+    h = 1.0 / (n - 1)
+    if src_frac is None:
+        src_frac = (0.5,) * (ndim - 1) + (0.1,)
+    src = tuple(int(round(f / h)) for f in reversed(src_frac))
+    v = smooth_random_velocity(shape, h, seed)
+    kappa2 = 1.0 / v ** 2
+    tau = factored_traveltime(kappa2, h, src, order=order)
+    omega = omega_for_ppw(float(v.min()), h, ppw)
+    gamma = absorbing_layer(shape, h, omega, 10 * h) if absorb else None
+    return Workload(name, shape, h, omega, src, kappa2, tau, gamma, extra={"seed": seed})
+
+
+def config_3d_257():
+    """3D 257^3 unit cube, v = 2 (1 + 0.2 eta) km/s (seed 3), tau by factored fast
+    marching, source (0.5, 0.5, 0.1) km, 10 points per wavelength."""
+    return random_medium(257, 3, seed=3, name="3d_257_random")
