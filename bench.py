@@ -32,7 +32,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="3d_129", choices=["3d_129", "2d_129", "3d_65"])
+    ap.add_argument("--workload", default="3d_129", choices=["3d_129", "2d_129", "3d_65", "3d_257", "batch_2d"])
+    ap.add_argument("--streams", type=int, default=4, help="streams of the batched-shot solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=8)
     ap.add_argument("--cpu-sample-child", action="store_true", help=argparse.SUPPRESS)
@@ -47,6 +48,8 @@ def make_workload(name):
         return W.config_3d_129()
     if name == "2d_129":
         return W.config_2d_129()
+    if name == "3d_257":
+        return W.config_3d_257()
     return W.linear_gradient(65, ndim=3, name="3d_65_linear_gradient")
 
 
@@ -94,6 +97,74 @@ def cpu_baseline(args, nodes, iters_needed):
 # --------------------------------------------------------------------------------------
 # GPU
 # --------------------------------------------------------------------------------------
+def run_batch(args):
+    """64 2D shots (sizes from {257^2, 513^2, 1025^2}, random media, fast-marching tau):
+    one lockstep batched solve over several streams vs. the same shots solved one after
+    another; mixed precision, tol 1e-6."""
+    import numpy as np
+    import torch
+
+    from paper_1712_06091_amd import adr
+    from paper_1712_06091_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    wls = W.batch_2d()
+    log(f"batch: {len(wls)} shots, {sum(w.nodes for w in wls) / 1e6:.1f} M nodes")
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    shots = [{"kappa2": t(w.kappa2, torch.float64), "tau": t(w.tau, torch.float64),
+              "gamma": t(w.gamma, torch.float64), "h": w.h, "omega": w.omega, "src": w.src} for w in wls]
+    qs = [t(w.rhs(), torch.complex128) for w in wls]
+    outs = [torch.empty(w.shape, dtype=torch.complex128, device=dev) for w in wls]
+    nodes = sum(w.nodes for w in wls)
+    opts = adr.default_options(prec="mixed")
+    torch.cuda.synchronize()
+    s0 = time.perf_counter()
+    b = adr.Batch(shots, options=opts, nstreams=args.streams)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - s0
+    for _ in range(args.warmup):
+        b.solve(qs, outs, tol=TOL)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st, stats = b.solve(qs, outs, tol=TOL)
+        if st != adr.ADR_OK:
+            raise RuntimeError("batched solve did not converge")
+    torch.cuda.synchronize()
+    ms_batch = (time.perf_counter() - t0) * 1e3 / args.steps
+    log(f"batched: {ms_batch:.1f} ms per batch")
+    # The same shots one after another through adr_solve on the default stream.
+    ctxs = [adr.Context(s["kappa2"], s["tau"], s["gamma"], s["h"], s["omega"], s["src"], options=opts)
+            for s in shots]
+    for c, q, a in zip(ctxs, qs, outs):
+        c.solve(q, tol=TOL, out=a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters_loop = 0
+    for c, q, a in zip(ctxs, qs, outs):
+        _, s1 = c.solve(q, tol=TOL, out=a)
+        iters_loop += s1["outer_iters"]
+    torch.cuda.synchronize()
+    ms_loop = (time.perf_counter() - t0) * 1e3
+    for c in ctxs:
+        c.close()
+    b.close()
+    value = nodes / (ms_batch * 1e-3) / 1e6
+    out = {
+        "metric": "ADR amplitude solves: Mpoints/s to 1e-6 residual (batched shots)",
+        "value": value, "unit": "Mpoints/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_batch, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64 V-cycle / c128 FGMRES", "data": "synthetic",
+        "config": {"workload": "batch_2d_64_shots", "shots": len(wls), "nodes": nodes,
+                   "sizes": sorted({w.shape[0] for w in wls}), "streams": args.streams, "tol": TOL},
+        "looped": {"value": nodes / (ms_loop * 1e-3) / 1e6, "ms": ms_loop, "outer_iters": iters_loop},
+        "batched_over_looped": ms_loop / ms_batch,
+        "outer_iters": sum(s["outer_iters"] for s in stats),
+        "setup_s": setup_s,
+    }
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.cpu_sample_child:
@@ -103,6 +174,9 @@ def main():
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
               "(shot-parallel multi-GPU is a design note, not built).", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch_2d":
+        run_batch(args)
+        return
 
     import numpy as np
     import torch

@@ -175,6 +175,24 @@ int adr_num_levels(const adr_ctx *ctx);
  * (may be NULL).  Entries that point outside the grid are zero. */
 adr_status adr_get_level_stencil(adr_ctx *ctx, int level, void *planes_c128, int *offsets);
 
+/* Batched shots: `count` independent problems (own source, tau and grid each) solved
+ * together.  adr_setup_batch creates `nstreams` (1..64) non-blocking streams of default
+ * priority and one context per shot on stream i % nstreams.  adr_solve_batch runs the
+ * FGMRES of every shot in lockstep: each round enqueues the next step of every
+ * unconverged shot, synchronizes the streams once and updates all shots on the host, so
+ * shots on different streams overlap on the GPU; converged shots drop out (mask).
+ * q[i], a[i]: per-shot c128 device arrays as in adr_solve (zero initial guess).  stats:
+ * host array of count entries, or NULL.  Returns ADR_OK if every shot converged, else
+ * the first non-convergence/error status; every a[i] holds its best iterate. */
+typedef struct adr_batch adr_batch;
+adr_status adr_setup_batch(int count, const adr_problem *probs, const adr_options *opt, int nstreams,
+                           adr_batch **out);
+adr_status adr_solve_batch(adr_batch *b, const void *const *q_c128, void *const *a_c128, double tol, int maxit,
+                           adr_stats *stats);
+int adr_batch_size(const adr_batch *b);
+adr_ctx *adr_batch_context(adr_batch *b, int i);   /* borrowed; owned by the batch */
+void adr_destroy_batch(adr_batch *b);               /* NULL is a no-op */
+
 /* Kernel classes that adr_timer_start can time. */
 typedef enum {
   ADR_TIMER_FINE_JACOBI = 0,    /* damped Jacobi sweep on the matrix-free finest level    */

@@ -97,6 +97,11 @@ def load_library(path=LIB_PATH):
         "adr_grad_kappa2": (I, [P, P, P, P]),
         "adr_receiver_residual": (I, [P, P, P, P, I, P, ctypes.POINTER(ctypes.c_double)]),
         "adr_adjoint_source": (I, [P, P, P, I, P]),
+        "adr_setup_batch": (I, [I, ctypes.POINTER(AdrProblem), ctypes.POINTER(AdrOptions), I, ctypes.POINTER(P)]),
+        "adr_solve_batch": (I, [P, ctypes.POINTER(P), ctypes.POINTER(P), D, I, ctypes.POINTER(AdrStats)]),
+        "adr_batch_size": (I, [P]),
+        "adr_batch_context": (P, [P, I]),
+        "adr_destroy_batch": (None, [P]),
         "adr_timer_start": (I, [P, I, I]),
         "adr_timer_stop": (I, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
                                ctypes.POINTER(ctypes.c_double)]),
@@ -152,42 +157,55 @@ def _dev(t, dtype):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def make_problem(kappa2, tau, gamma, h, omega, src, factored=True):
+    """adr_problem for device tensors (NumPy axis order; reversed for the ABI)."""
+    import torch
+    shape = tuple(tau.shape)
+    d = len(shape)
+    prob = AdrProblem()
+    prob.ndim = d
+    for k in range(3):
+        prob.n[k] = shape[d - 1 - k] if k < d else 1
+    prob.h = float(h)
+    prob.omega = float(omega)
+    prob.kappa2 = _dev(kappa2, torch.float64)
+    prob.tau = _dev(tau, torch.float64)
+    prob.gamma = _dev(gamma, torch.float64) if gamma is not None else None
+    if factored and src is not None:
+        for k in range(3):
+            prob.src[k] = int(src[d - 1 - k]) if k < d else 0
+    else:
+        prob.src[0], prob.src[1], prob.src[2] = -1, 0, 0
+    return prob
+
+
 class Context:
     """An adr_ctx: coefficients, multigrid hierarchy and solver buffers for one source."""
 
-    def __init__(self, kappa2, tau, gamma, h, omega, src, options=None, stream=None, factored=True):
-        import torch
+    def __init__(self, kappa2, tau, gamma, h, omega, src, options=None, stream=None, factored=True, _borrowed=None):
         lib = load_library()
-        shape = tuple(tau.shape)
-        d = len(shape)
-        prob = AdrProblem()
-        prob.ndim = d
-        for k in range(3):
-            prob.n[k] = shape[d - 1 - k] if k < d else 1
-        prob.h = float(h)
-        prob.omega = float(omega)
-        prob.kappa2 = _dev(kappa2, torch.float64)
-        prob.tau = _dev(tau, torch.float64)
-        prob.gamma = _dev(gamma, torch.float64) if gamma is not None else None
-        if factored and src is not None:
-            for k in range(3):
-                prob.src[k] = int(src[d - 1 - k]) if k < d else 0
-        else:
-            prob.src[0], prob.src[1], prob.src[2] = -1, 0, 0
-        self.options = options if options is not None else default_options()
-        self.shape = shape
+        self._lib = lib
+        self.shape = tuple(tau.shape)
         self.device = tau.device
+        if _borrowed is not None:   # a context owned by a Batch
+            self._ptr = _borrowed
+            self._owned = False
+            self.options = options
+            return
+        prob = make_problem(kappa2, tau, gamma, h, omega, src, factored)
+        self.options = options if options is not None else default_options()
         self._stream = stream
         ptr = ctypes.c_void_p()
         status = lib.adr_setup(ctypes.byref(prob), ctypes.byref(self.options), _stream_ptr(stream), ctypes.byref(ptr))
         if status != ADR_OK:
             raise AdrError(status, (lib.adr_last_error(None) or b"").decode())
         self._ptr = ptr
-        self._lib = lib
+        self._owned = True
 
     def close(self):
         if getattr(self, "_ptr", None):
-            self._lib.adr_destroy(self._ptr)
+            if self._owned:
+                self._lib.adr_destroy(self._ptr)
             self._ptr = None
 
     def __del__(self):
@@ -328,3 +346,51 @@ class Context:
         offs = (ctypes.c_int * (3 * S))()
         _check(self._lib.adr_get_level_stencil(self._ptr, level, _dev(planes, torch.complex128), offs), self._ptr)
         return planes, [tuple(offs[3 * p:3 * p + 3]) for p in range(S)]
+
+
+class Batch:
+    """Many shots solved together (adr_setup_batch / adr_solve_batch).  Each entry of
+    ``shots`` is a dict with kappa2, tau, gamma (device tensors), h, omega, src."""
+
+    def __init__(self, shots, options=None, nstreams=4):
+        lib = load_library()
+        self._lib = lib
+        self.options = options if options is not None else default_options()
+        probs = (AdrProblem * len(shots))()
+        for i, s in enumerate(shots):
+            probs[i] = make_problem(s["kappa2"], s["tau"], s.get("gamma"), s["h"], s["omega"], s["src"])
+        self.shapes = [tuple(s["tau"].shape) for s in shots]
+        self.device = shots[0]["tau"].device
+        ptr = ctypes.c_void_p()
+        st = lib.adr_setup_batch(len(shots), probs, ctypes.byref(self.options), int(nstreams), ctypes.byref(ptr))
+        if st != ADR_OK:
+            raise AdrError(st, (lib.adr_last_error(None) or b"").decode())
+        self._ptr = ptr
+        self.contexts = [Context(None, s["tau"], None, s["h"], s["omega"], s["src"], options=self.options,
+                                 _borrowed=ctypes.c_void_p(lib.adr_batch_context(ptr, i)))
+                         for i, s in enumerate(shots)]
+
+    def solve(self, qs, outs, tol=1e-6, maxit=500):
+        """Solve every shot; returns (status, list of stats dicts)."""
+        import torch
+        n = len(self.contexts)
+        qp = (ctypes.c_void_p * n)(*[_dev(q, torch.complex128).value for q in qs])
+        ap = (ctypes.c_void_p * n)(*[_dev(a, torch.complex128).value for a in outs])
+        stats = (AdrStats * n)()
+        st = self._lib.adr_solve_batch(self._ptr, qp, ap, float(tol), int(maxit), stats)
+        if st not in (ADR_OK, ADR_ENOCONV):
+            raise AdrError(st, "batch solve failed")
+        return st, [s.as_dict() for s in stats]
+
+    def close(self):
+        if getattr(self, "_ptr", None):
+            for c in self.contexts:
+                c.close()
+            self._lib.adr_destroy_batch(self._ptr)
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

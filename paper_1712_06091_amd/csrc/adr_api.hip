@@ -25,7 +25,7 @@ constexpr int kMaxLevels = 8;
 constexpr int kMaxNu = 8;           // GMRES relaxation steps per sweep (dots fused <= 8)
 constexpr int kMaxRestart = 8;
 constexpr int kScalPerLevel = 256;  // device doubles per level for relaxation scalars
-constexpr int kPin = 1024;          // pinned host doubles (partials and scalars read back)
+constexpr int kPin = 2048;          // pinned host doubles (partials and scalars read back)
 // scalar block layout (doubles)
 constexpr int kH = 0;                               // (kMaxNu+1) x kMaxNu complex, col-major
 constexpr int kLdH = kMaxNu + 1;
@@ -1061,167 +1061,257 @@ adr_status prepare_adjoint(adr_ctx *ctx) {
 }
 
 // FGMRES(m) on H_2up (ctx->adj false) or its conjugate transpose (true), preconditioned
-// by the matching V-cycle; rhs_hat = rhs exp(i w tau).
-adr_status solve_impl(adr_ctx *ctx, const void *q, void *a_out, double tol, int maxit, int use_initial_guess,
-                      adr_stats *stats) {
-  if (!ctx || !q || !a_out || maxit < 0 || !(tol >= 0)) return ADR_EINVAL;
-  const double t0 = now_ms();
-  hipStream_t s = ctx->stream;
-  const int N = ctx->G0.N, m = ctx->opt.restart, D = ctx->D;
-  cx<double> *x = (cx<double> *)a_out;
-  FineCoef<double> C = fine_coef<double>(ctx);
-  FineParams P0 = fine_params(ctx, 0.0);
-  double *osc = ctx->osc, *hp = ctx->hpin;
-  const bool mixed = ctx->opt.prec == ADR_PREC_MIXED;
-  auto Zp = [&](int j) -> void * {
-    return mixed ? (void *)((cx<float> *)ctx->Zo + (size_t)j * N) : (void *)((cx<double> *)ctx->Zo + (size_t)j * N);
-  };
-  auto Vp = [&](int j) { return ctx->Vo + (size_t)j * N; };
+// by the matching V-cycle; rhs_hat = rhs exp(i w tau).  Written as a state machine whose
+// every action is enqueued on the context stream and ends with one asynchronous
+// read-back into pinned host memory; `finish` consumes it on the host after the stream
+// (or, for a batch, every stream) has been synchronized and decides the next action.
+// Pinned layout (doubles): [0, 512) and [512, 1024) reduction partials, [1024, 1100)
+// Hessenberg column read-back, [1100, 1140) least-squares coefficients for upload.
+constexpr int kPinA = 0, kPinB = 512, kPinRed = 1024, kPinY = 1100;
 
-  // Sum `nb` single-value partials on the host (fixed order) after reading them back.
-  auto host_norm = [&](int nb, double *out) -> adr_status {
-    ADR_HIP(hipMemcpyAsync(hp, ctx->part[0], nb * sizeof(double), hipMemcpyDeviceToHost, s));
-    ADR_HIP(hipStreamSynchronize(s));
-    double acc = 0.0;
-    for (int b = 0; b < nb; ++b) acc += hp[b];
-    *out = std::sqrt(acc);
-    return ADR_OK;
-  };
-  // q_hat = q exp(i w tau)
-  adrk::phase(s, N, (const cx<double> *)q, ctx->tau, ctx->omega, +1, ctx->qh);
-  double bnorm = 0.0, rnorm = 0.0;
-  ADR_TRY(host_norm(adrk::norm2<double>(s, N, ctx->qh, nullptr, nullptr, ctx->part[0]), &bnorm));
-  // initial residual
-  if (use_initial_guess) {
-    int nb = fine_residual64(ctx, x, ctx->qh, ctx->ro);
-    ADR_TRY(host_norm(nb, &rnorm));
-  } else {
-    ADR_HIP(hipMemsetAsync(x, 0, sizeof(cx<double>) * N, s));
-    ADR_HIP(hipMemcpyAsync(ctx->ro, ctx->qh, sizeof(cx<double>) * N, hipMemcpyDeviceToDevice, s));
-    rnorm = bnorm;
-  }
-  adr_stats st{};
-  if (bnorm == 0.0) {
-    ADR_HIP(hipMemsetAsync(x, 0, sizeof(cx<double>) * N, s));
-    ADR_HIP(hipStreamSynchronize(s));
-    if (stats) *stats = st;
-    return ADR_OK;
-  }
-  double relres = rnorm / bnorm;
-  int iters = 0, restarts = 0;
+struct Solver {
+  enum Action { START, STEP, CYCLE_END, DONE };
+  adr_ctx *ctx = nullptr;
+  const cx<double> *q = nullptr;
+  cx<double> *x = nullptr;
+  double tol = 0;
+  int maxit = 0;
+  bool guess = false;
+  Action next = START;
+  int nb = 0;
+  double bnorm = 0, rnorm = 0, relres = 0, t0 = 0;
+  int iters = 0, restarts = 0, j = 0, k = 0;
   adr_status result = ADR_OK;
-  while (relres > tol && iters < maxit) {
-    if (!std::isfinite(relres)) { result = ADR_ENUMERIC; break; }
-    // V0 = r / ||r||
-    adrk::scale(s, N, ctx->ro, rnorm > 0.0 ? 1.0 / rnorm : 0.0, Vp(0));
-    std::complex<double> Hh[kMaxRestart + 1][kMaxRestart], g[kMaxRestart + 1];
-    double cs[kMaxRestart];
-    std::complex<double> sn[kMaxRestart];
-    for (int i = 0; i <= m; ++i) g[i] = 0.0;
-    g[0] = rnorm;
-    int k = 0;
-    for (int j = 0; j < m; ++j) {
-      ADR_TRY(precondition(ctx, Vp(j), Zp(j), !mixed));
+  std::complex<double> Hh[kMaxRestart + 1][kMaxRestart], g[kMaxRestart + 1], sn[kMaxRestart];
+  double cs[kMaxRestart];
+};
+
+void *zslot(adr_ctx *ctx, int j) {
+  const size_t N = ctx->G0.N;
+  return ctx->opt.prec == ADR_PREC_MIXED ? (void *)((cx<float> *)ctx->Zo + (size_t)j * N)
+                                         : (void *)((cx<double> *)ctx->Zo + (size_t)j * N);
+}
+
+// Enqueue the action S.next (the cycle's first step also scales V0 = r / ||r||).
+adr_status solver_enqueue(Solver &S) {
+  adr_ctx *ctx = S.ctx;
+  hipStream_t s = ctx->stream;
+  const int N = ctx->G0.N, D = ctx->D;
+  const bool mixed = ctx->opt.prec == ADR_PREC_MIXED;
+  double *hp = ctx->hpin;
+  auto Vp = [&](int j) { return ctx->Vo + (size_t)j * N; };
+  switch (S.next) {
+    case Solver::START: {
+      adrk::phase(s, N, S.q, ctx->tau, ctx->omega, +1, ctx->qh);
+      S.nb = adrk::norm2<double>(s, N, ctx->qh, nullptr, nullptr, ctx->part[0]);
+      ADR_HIP(hipMemcpyAsync(hp + kPinA, ctx->part[0], S.nb * sizeof(double), hipMemcpyDeviceToHost, s));
+      if (S.guess) {
+        fine_residual64(ctx, S.x, ctx->qh, ctx->ro);   // partials in part[0] after the copy above
+        ADR_HIP(hipMemcpyAsync(hp + kPinB, ctx->part[0], S.nb * sizeof(double), hipMemcpyDeviceToHost, s));
+      } else {
+        ADR_HIP(hipMemsetAsync(S.x, 0, sizeof(cx<double>) * N, s));
+        ADR_HIP(hipMemcpyAsync(ctx->ro, ctx->qh, sizeof(cx<double>) * N, hipMemcpyDeviceToDevice, s));
+      }
+      return ADR_OK;
+    }
+    case Solver::STEP: {
+      const int j = S.j;
+      if (j == 0) adrk::scale(s, N, ctx->ro, S.rnorm > 0.0 ? 1.0 / S.rnorm : 0.0, Vp(0));
+      ADR_TRY(precondition(ctx, Vp(j), zslot(ctx, j), !mixed));
       VecSet<double> Vs{};
       Vs.count = j + 1;
       for (int i = 0; i <= j; ++i) Vs.v[i] = Vp(i);
-      double *red1 = osc + 2, *red2 = osc + 2 + 2 * (kMaxRestart + 1);
+      double *red1 = ctx->osc + 2, *red2 = ctx->osc + 2 + 2 * (kMaxRestart + 1);
+      FineCoef<double> C = fine_coef<double>(ctx);
+      FineParams P0 = fine_params(ctx, 0.0);
       int t0 = tbegin(ctx, ADR_TIMER_OUTER_MATVEC, 0);
       int nb;
       if (mixed && ctx->adj)
-        nb = adrk::fine_apply_adj<double, float, double>(s, ctx->G0, D, C, P0, (const cx<float> *)Zp(j), nullptr,
-                                                         ctx->wo, 0, &Vs, false, ctx->part[0]);
+        nb = adrk::fine_apply_adj<double, float, double>(s, ctx->G0, D, C, P0, (const cx<float> *)zslot(ctx, j),
+                                                         nullptr, ctx->wo, 0, &Vs, false, ctx->part[0]);
       else if (mixed)
-        nb = adrk::fine_apply<double, float, double>(s, ctx->G0, D, C, P0, (const cx<float> *)Zp(j), nullptr,
-                                                     ctx->wo, 0, &Vs, false, ctx->part[0]);
+        nb = adrk::fine_apply<double, float, double>(s, ctx->G0, D, C, P0, (const cx<float> *)zslot(ctx, j),
+                                                     nullptr, ctx->wo, 0, &Vs, false, ctx->part[0]);
       else if (ctx->adj)
-        nb = adrk::fine_apply_adj<double, double, double>(s, ctx->G0, D, C, P0, (const cx<double> *)Zp(j), nullptr,
-                                                          ctx->wo, 0, &Vs, false, ctx->part[0]);
+        nb = adrk::fine_apply_adj<double, double, double>(s, ctx->G0, D, C, P0,
+                                                          (const cx<double> *)zslot(ctx, j), nullptr, ctx->wo, 0,
+                                                          &Vs, false, ctx->part[0]);
       else
-        nb = adrk::fine_apply<double, double, double>(s, ctx->G0, D, C, P0, (const cx<double> *)Zp(j), nullptr,
-                                                      ctx->wo, 0, &Vs, false, ctx->part[0]);
+        nb = adrk::fine_apply<double, double, double>(s, ctx->G0, D, C, P0, (const cx<double> *)zslot(ctx, j),
+                                                      nullptr, ctx->wo, 0, &Vs, false, ctx->part[0]);
       tend(ctx, t0, (double)N * (fine_coef_bytes<double>(D) + (mixed ? 8.0 : 16.0) + 16.0 * (j + 2)));
       int t1 = tbegin(ctx, ADR_TIMER_OUTER_ORTH, 0);
       nb = adrk::outer_orth1(s, N, ctx->wo, Vs, ProIn{ctx->part[0], nb, 2 * (j + 1)}, red1, ctx->part[1]);
       adrk::outer_orth2(s, N, ctx->wo, Vs, ProIn{ctx->part[1], nb, 2 * (j + 1) + 1}, red2, Vp(j + 1));
       tend(ctx, t1, (double)N * 16.0 * (2 * (j + 1) + 4));
       const int nred = 2 * (kMaxRestart + 1) * 2 + 1;
-      ADR_HIP(hipMemcpyAsync(hp + 2, red1, nred * sizeof(double), hipMemcpyDeviceToHost, s));
-      ADR_HIP(hipStreamSynchronize(s));
-      const double *h1 = hp + 2, *h2 = hp + 2 + 2 * (kMaxRestart + 1);
+      ADR_HIP(hipMemcpyAsync(hp + kPinRed, red1, nred * sizeof(double), hipMemcpyDeviceToHost, s));
+      return ADR_OK;
+    }
+    case Solver::CYCLE_END: {
+      // y = R^{-1} g, x += Z y, then the true residual.
+      const int k = S.k;
+      std::complex<double> y[kMaxRestart];
+      for (int i = k - 1; i >= 0; --i) {
+        std::complex<double> acc = S.g[i];
+        for (int jj = i + 1; jj < k; ++jj) acc -= S.Hh[i][jj] * y[jj];
+        y[i] = (S.Hh[i][i] == 0.0) ? 0.0 : acc / S.Hh[i][i];
+      }
+      for (int i = 0; i < k; ++i) {
+        hp[kPinY + 2 * i] = y[i].real();
+        hp[kPinY + 2 * i + 1] = y[i].imag();
+      }
+      double *ydev = ctx->osc + 48;
+      ADR_HIP(hipMemcpyAsync(ydev, hp + kPinY, 2 * k * sizeof(double), hipMemcpyHostToDevice, s));
+      if (mixed) {
+        VecSet<float> Zs{};
+        Zs.count = k;
+        for (int i = 0; i < k; ++i) Zs.v[i] = (const cx<float> *)zslot(ctx, i);
+        adrk::multi_axpy<float>(s, N, S.x, Zs, ydev);
+      } else {
+        VecSet<double> Zs{};
+        Zs.count = k;
+        for (int i = 0; i < k; ++i) Zs.v[i] = (const cx<double> *)zslot(ctx, i);
+        adrk::multi_axpy<double>(s, N, S.x, Zs, ydev);
+      }
+      S.nb = fine_residual64(ctx, S.x, ctx->qh, ctx->ro);
+      ADR_HIP(hipMemcpyAsync(hp + kPinA, ctx->part[0], S.nb * sizeof(double), hipMemcpyDeviceToHost, s));
+      return ADR_OK;
+    }
+    case Solver::DONE:
+      return ADR_OK;
+  }
+  return ADR_OK;
+}
+
+// Consume the read-back of the last action (its stream has been synchronized) and set
+// S.next; DONE ends the solve.
+void solver_finish(Solver &S) {
+  adr_ctx *ctx = S.ctx;
+  const double *hp = ctx->hpin;
+  const int m = ctx->opt.restart;
+  auto sum_sqrt = [&](const double *p, int nb) {
+    double acc = 0.0;
+    for (int b = 0; b < nb; ++b) acc += p[b];
+    return std::sqrt(acc);
+  };
+  auto start_cycle_or_stop = [&]() {
+    if (!std::isfinite(S.relres)) {
+      S.result = ADR_ENUMERIC;
+      S.next = Solver::DONE;
+    } else if (S.relres <= S.tol || S.iters >= S.maxit) {
+      S.next = Solver::DONE;
+    } else {
+      for (int i = 0; i <= m; ++i) S.g[i] = 0.0;
+      S.g[0] = S.rnorm;
+      S.j = 0;
+      S.next = Solver::STEP;
+    }
+  };
+  switch (S.next) {
+    case Solver::START: {
+      S.bnorm = sum_sqrt(hp + kPinA, S.nb);
+      S.rnorm = S.guess ? sum_sqrt(hp + kPinB, S.nb) : S.bnorm;
+      if (S.bnorm == 0.0) {
+        S.relres = 0.0;
+        S.next = Solver::DONE;
+        return;
+      }
+      S.relres = S.rnorm / S.bnorm;
+      start_cycle_or_stop();
+      return;
+    }
+    case Solver::STEP: {
+      const int j = S.j;
+      const double *h1 = hp + kPinRed, *h2 = hp + kPinRed + 2 * (kMaxRestart + 1);
       double n2 = h2[2 * (j + 1)];
       for (int i = 0; i <= j; ++i) {
         std::complex<double> c(h2[2 * i], h2[2 * i + 1]);
-        Hh[i][j] = std::complex<double>(h1[2 * i], h1[2 * i + 1]) + c;
+        S.Hh[i][j] = std::complex<double>(h1[2 * i], h1[2 * i + 1]) + c;
         n2 -= std::norm(c);
       }
-      Hh[j + 1][j] = std::sqrt(n2 > 0 ? n2 : 0.0);
-      // Givens rotations.
-      for (int i = 0; i < j; ++i) {
-        std::complex<double> t = cs[i] * Hh[i][j] + sn[i] * Hh[i + 1][j];
-        Hh[i + 1][j] = -std::conj(sn[i]) * Hh[i][j] + cs[i] * Hh[i + 1][j];
-        Hh[i][j] = t;
+      S.Hh[j + 1][j] = std::sqrt(n2 > 0 ? n2 : 0.0);
+      for (int i = 0; i < j; ++i) {   // earlier Givens rotations
+        std::complex<double> t = S.cs[i] * S.Hh[i][j] + S.sn[i] * S.Hh[i + 1][j];
+        S.Hh[i + 1][j] = -std::conj(S.sn[i]) * S.Hh[i][j] + S.cs[i] * S.Hh[i + 1][j];
+        S.Hh[i][j] = t;
       }
-      std::complex<double> aa = Hh[j][j], bb = Hh[j + 1][j];
+      std::complex<double> aa = S.Hh[j][j], bb = S.Hh[j + 1][j];
       double den = std::sqrt(std::norm(aa) + std::norm(bb));
       if (std::abs(aa) == 0.0) {
-        cs[j] = 0.0;
-        sn[j] = 1.0;
+        S.cs[j] = 0.0;
+        S.sn[j] = 1.0;
       } else {
-        cs[j] = std::abs(aa) / den;
-        sn[j] = (aa / std::abs(aa)) * std::conj(bb) / den;
+        S.cs[j] = std::abs(aa) / den;
+        S.sn[j] = (aa / std::abs(aa)) * std::conj(bb) / den;
       }
-      Hh[j][j] = cs[j] * aa + sn[j] * bb;
-      Hh[j + 1][j] = 0.0;
-      g[j + 1] = -std::conj(sn[j]) * g[j];
-      g[j] = cs[j] * g[j];
-      k = j + 1;
-      ++iters;
-      const double est = std::abs(g[j + 1]) / bnorm;
-      if (!std::isfinite(est)) { result = ADR_ENUMERIC; break; }
-      if (est <= tol || iters >= maxit) break;
+      S.Hh[j][j] = S.cs[j] * aa + S.sn[j] * bb;
+      S.Hh[j + 1][j] = 0.0;
+      S.g[j + 1] = -std::conj(S.sn[j]) * S.g[j];
+      S.g[j] = S.cs[j] * S.g[j];
+      ++S.iters;
+      const double est = std::abs(S.g[j + 1]) / S.bnorm;
+      if (!std::isfinite(est)) {
+        S.result = ADR_ENUMERIC;
+        S.next = Solver::DONE;
+      } else if (est <= S.tol || S.iters >= S.maxit || j == m - 1) {
+        S.k = j + 1;
+        S.next = Solver::CYCLE_END;
+      } else {
+        S.j = j + 1;
+      }
+      return;
     }
-    if (result != ADR_OK) break;
-    // y = R^{-1} g, x += Z y
-    std::complex<double> y[kMaxRestart];
-    for (int i = k - 1; i >= 0; --i) {
-      std::complex<double> acc = g[i];
-      for (int jj = i + 1; jj < k; ++jj) acc -= Hh[i][jj] * y[jj];
-      y[i] = (Hh[i][i] == 0.0) ? 0.0 : acc / Hh[i][i];
+    case Solver::CYCLE_END: {
+      S.rnorm = sum_sqrt(hp + kPinA, S.nb);
+      S.relres = S.rnorm / S.bnorm;
+      ++S.restarts;
+      start_cycle_or_stop();
+      return;
     }
-    for (int i = 0; i < k; ++i) {
-      hp[2 + 2 * i] = y[i].real();
-      hp[3 + 2 * i] = y[i].imag();
-    }
-    double *ydev = osc + 48;
-    ADR_HIP(hipMemcpyAsync(ydev, hp + 2, 2 * k * sizeof(double), hipMemcpyHostToDevice, s));
-    if (mixed) {
-      VecSet<float> Zs{};
-      Zs.count = k;
-      for (int i = 0; i < k; ++i) Zs.v[i] = (const cx<float> *)Zp(i);
-      adrk::multi_axpy<float>(s, N, x, Zs, ydev);
-    } else {
-      VecSet<double> Zs{};
-      Zs.count = k;
-      for (int i = 0; i < k; ++i) Zs.v[i] = (const cx<double> *)Zp(i);
-      adrk::multi_axpy<double>(s, N, x, Zs, ydev);
-    }
-    int nbr = fine_residual64(ctx, x, ctx->qh, ctx->ro);
-    ADR_TRY(host_norm(nbr, &rnorm));
-    relres = rnorm / bnorm;
-    ++restarts;
+    case Solver::DONE:
+      return;
   }
-  ADR_HIP(hipGetLastError());
-  if (result == ADR_OK && relres > tol) result = std::isfinite(relres) ? ADR_ENOCONV : ADR_ENUMERIC;
-  st.outer_iters = iters;
-  st.restarts = restarts;
-  st.relres = relres;
-  st.solve_ms = now_ms() - t0;
-  if (stats) *stats = st;
-  if (result == ADR_ENOCONV) ctx->err = "FGMRES reached maxit before tol";
-  return result;
 }
 
+void solver_init(Solver &S, adr_ctx *ctx, const void *q, void *a_out, double tol, int maxit, int guess) {
+  S.ctx = ctx;
+  S.q = (const cx<double> *)q;
+  S.x = (cx<double> *)a_out;
+  S.tol = tol;
+  S.maxit = maxit;
+  S.guess = guess != 0;
+  S.next = Solver::START;
+  S.t0 = now_ms();
+}
+
+adr_status solver_result(Solver &S, adr_stats *stats) {
+  adr_status r = S.result;
+  if (r == ADR_OK && S.relres > S.tol) r = std::isfinite(S.relres) ? ADR_ENOCONV : ADR_ENUMERIC;
+  if (stats) {
+    adr_stats st{};
+    st.outer_iters = S.iters;
+    st.restarts = S.restarts;
+    st.relres = S.relres;
+    st.solve_ms = now_ms() - S.t0;
+    *stats = st;
+  }
+  if (r == ADR_ENOCONV) S.ctx->err = "FGMRES reached maxit before tol";
+  return r;
+}
+
+adr_status solve_impl(adr_ctx *ctx, const void *q, void *a_out, double tol, int maxit, int use_initial_guess,
+                      adr_stats *stats) {
+  Solver S;
+  solver_init(S, ctx, q, a_out, tol, maxit, use_initial_guess);
+  while (S.next != Solver::DONE) {
+    ADR_TRY(solver_enqueue(S));
+    ADR_HIP(hipStreamSynchronize(ctx->stream));
+    solver_finish(S);
+  }
+  ADR_HIP(hipGetLastError());
+  return solver_result(S, stats);
+}
 }  // namespace
 
 extern "C" {
@@ -1282,6 +1372,110 @@ adr_status adr_adjoint_source(adr_ctx *ctx, const int *idx, const void *r, int n
   adrk::adjoint_source(ctx->stream, ctx->G0.N, nrec, idx, (const cx<double> *)r, (cx<double> *)src);
   ADR_HIP(hipGetLastError());
   return ADR_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// Batched shots: many independent problems solved in lockstep.  Each shot has its own
+// context; the contexts are spread over `nstreams` streams (shots on one stream run one
+// after another, shots on different streams overlap on the GPU).  Every round enqueues
+// the next FGMRES action of every unconverged shot, synchronizes the streams once, and
+// consumes all read-backs; converged shots drop out.
+// ---------------------------------------------------------------------------------------
+}  // extern "C"
+
+struct adr_batch {
+  std::vector<adr_ctx *> ctx;
+  std::vector<hipStream_t> streams;
+  std::string err;
+};
+
+extern "C" {
+
+adr_status adr_setup_batch(int count, const adr_problem *probs, const adr_options *opt, int nstreams,
+                           adr_batch **out) {
+  if (!out) return ADR_EINVAL;
+  *out = nullptr;
+  if (count <= 0 || !probs || nstreams <= 0 || nstreams > 64) {
+    g_setup_error = "bad batch arguments";
+    return ADR_EINVAL;
+  }
+  adr_batch *b = new adr_batch();
+  for (int i = 0; i < nstreams; ++i) {
+    hipStream_t s;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      g_setup_error = "hipStreamCreate failed";
+      adr_destroy_batch(b);
+      return ADR_EHIP;
+    }
+    b->streams.push_back(s);
+  }
+  for (int i = 0; i < count; ++i) {
+    adr_ctx *c = nullptr;
+    adr_status st = adr_setup(&probs[i], opt, b->streams[i % nstreams], &c);
+    if (st != ADR_OK) {
+      g_setup_error = "shot " + std::to_string(i) + ": " + g_setup_error;
+      adr_destroy_batch(b);
+      return st;
+    }
+    b->ctx.push_back(c);
+  }
+  *out = b;
+  return ADR_OK;
+}
+
+int adr_batch_size(const adr_batch *b) { return b ? (int)b->ctx.size() : 0; }
+
+adr_ctx *adr_batch_context(adr_batch *b, int i) {
+  if (!b || i < 0 || i >= (int)b->ctx.size()) return nullptr;
+  return b->ctx[i];
+}
+
+adr_status adr_solve_batch(adr_batch *b, const void *const *q, void *const *a, double tol, int maxit,
+                           adr_stats *stats) {
+  if (!b || !q || !a || maxit < 0 || !(tol >= 0)) return ADR_EINVAL;
+  const int n = (int)b->ctx.size();
+  for (int i = 0; i < n; ++i)
+    if (!q[i] || !a[i]) return ADR_EINVAL;
+  std::vector<Solver> S(n);
+  for (int i = 0; i < n; ++i) {
+    b->ctx[i]->adj = false;
+    solver_init(S[i], b->ctx[i], q[i], a[i], tol, maxit, 0);
+  }
+  int active = n;
+  while (active > 0) {
+    for (int i = 0; i < n; ++i)
+      if (S[i].next != Solver::DONE) {
+        adr_status st = solver_enqueue(S[i]);
+        if (st != ADR_OK) {
+          b->err = "shot " + std::to_string(i) + ": " + b->ctx[i]->err;
+          return st;
+        }
+      }
+    for (hipStream_t s : b->streams)
+      if (hipStreamSynchronize(s) != hipSuccess) {
+        b->err = "stream synchronization failed";
+        return ADR_EHIP;
+      }
+    active = 0;
+    for (int i = 0; i < n; ++i)
+      if (S[i].next != Solver::DONE) {
+        solver_finish(S[i]);
+        if (S[i].next != Solver::DONE) ++active;
+      }
+  }
+  adr_status worst = ADR_OK;
+  for (int i = 0; i < n; ++i) {
+    adr_status st = solver_result(S[i], stats ? &stats[i] : nullptr);
+    if (st != ADR_OK && (worst == ADR_OK || st != ADR_ENOCONV)) worst = st;
+  }
+  return worst;
+}
+
+void adr_destroy_batch(adr_batch *b) {
+  if (!b) return;
+  for (adr_ctx *c : b->ctx) adr_destroy(c);
+  for (hipStream_t s : b->streams) hipStreamDestroy(s);
+  delete b;
 }
 
 adr_status adr_timer_start(adr_ctx *ctx, int kind, int level) {

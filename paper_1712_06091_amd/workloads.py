@@ -145,12 +145,14 @@ def random_vector(shape, seed, dtype=np.complex128):
 # Random media and fast-marching travel times (configurations with heterogeneous media)
 # ---------------------------------------------------------------------------------------
 def smooth_random_field(shape, h, seed, corr_len=0.1):
-    """eta = G_sigma * xi, xi iid N(0, 1) (seeded), sigma = corr_len in domain units,
-    normalized to unit standard deviation, then clipped to [-1, 1]."""
-    from scipy.ndimage import gaussian_filter
+    """eta = G_sigma * xi, xi iid N(0, 1) (seeded), sigma = corr_len in domain units (a
+    periodic Gaussian filter applied in Fourier space), normalized to unit standard
+    deviation, then clipped to [-1, 1]."""
+    from scipy.ndimage import fourier_gaussian
     rng = np.random.default_rng(seed)
     xi = rng.standard_normal(shape)
-    eta = gaussian_filter(xi, sigma=corr_len / h, mode="reflect")
+    axes = tuple(range(len(shape)))
+    eta = np.fft.irfftn(fourier_gaussian(np.fft.rfftn(xi), sigma=corr_len / h, n=shape[-1]), s=shape, axes=axes)
     eta = eta / eta.std()
     return np.clip(eta, -1.0, 1.0)
 
@@ -211,3 +213,24 @@ def config_3d_257():
     """3D 257^3 unit cube, v = 2 (1 + 0.2 eta) km/s (seed 3), tau by factored fast
     marching, source (0.5, 0.5, 0.1) km, 10 points per wavelength."""
     return random_medium(257, 3, seed=3, name="3d_257_random")
+
+
+def batch_2d(count=64, seed=4, sizes=(257, 513, 1025), margin=12, name="batch_2d"):
+    """``count`` 2D shots on the unit square: grid sizes drawn uniformly from ``sizes``
+    and source nodes uniformly at least ``margin`` nodes from the faces (both seeded by
+    ``seed``), medium v = 2 (1 + 0.2 eta) with eta seeded by 1000*seed + i, tau by factored
+    fast marching, 10 points per wavelength per shot."""
+    rng = np.random.default_rng(seed)
+    ns = rng.choice(np.asarray(sizes), size=count)
+    shots = []
+    for i, n in enumerate(ns):
+        n = int(n)
+        h = 1.0 / (n - 1)
+        src = tuple(int(v) for v in rng.integers(margin, n - margin, size=2))
+        v = smooth_random_velocity((n, n), h, 1000 * seed + i)
+        kappa2 = 1.0 / v ** 2
+        tau = factored_traveltime(kappa2, h, src)
+        omega = omega_for_ppw(float(v.min()), h)
+        gamma = absorbing_layer((n, n), h, omega, 10 * h)
+        shots.append(Workload(f"{name}_{i}", (n, n), h, omega, src, kappa2, tau, gamma, extra={"seed": 1000 * seed + i}))
+    return shots
