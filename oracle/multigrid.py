@@ -14,6 +14,12 @@ V-cycle.  Relaxation (Sec. 3.1, Sec. 4.2) on level l uses l+1 pre- and post-rela
 The coarsest system is solved exactly (dense LU); this replaces the paper's ten inexact
 GMRES steps.
 
+The Krylov cycle (Sec. 3.1, Alg. KrylovCycle) replaces the recursive coarse solve of
+every level that is not the coarsest by flexible GMRES with two steps, started from
+zero and preconditioned by the Krylov cycle one level down.  The second step is left
+out when the first one already reduced the coarse residual below a threshold times its
+initial norm (0.1, Sec. 4.2.2, following Notay and Vassilevski).
+
 Grids are nodal with n_c = (n_f - 1)/2 + 1 nodes per axis; coarse node I coincides with
 fine node 2I.  P is real, so P^T = P^H (complex data).
 """
@@ -118,6 +124,55 @@ class Hierarchy:
         if self.smoothers[l] == "gmres":
             return self.gmres_relax(l, x, b, self.nu[l])
         raise ValueError(self.smoothers[l])
+
+    def kcycle(self, b, l=0, threshold=0.1):
+        """One Krylov cycle from a zero initial guess on level l: x ~ A_l^{-1} b.
+        ``self.kcalls[l]`` counts the cycles entered on level l."""
+        if not hasattr(self, "kcalls"):
+            self.kcalls = [0] * self.levels
+        self.kcalls[l] += 1
+        if l == self.levels - 1:
+            return sla.lu_solve(self.coarse_lu, b)
+        x = np.zeros_like(b)
+        x = self.relax(l, x, b)
+        r = b - self.A[l] @ x
+        rc = self.P[l].T @ r
+        if l + 1 == self.levels - 1:
+            ec = sla.lu_solve(self.coarse_lu, rc)
+        else:
+            ec = self.coarse_fgmres(l + 1, rc, threshold)
+        x = x + self.P[l] @ ec
+        x = self.relax(l, x, b)
+        return x
+
+    def coarse_fgmres(self, l, r, threshold):
+        """Flexible GMRES(2) on A_l e = r from e = 0, preconditioned by the Krylov cycle
+        on level l; one step only if its residual is <= threshold * ||r||."""
+        A = self.A[l]
+        beta = np.linalg.norm(r)
+        if beta == 0.0:
+            return np.zeros_like(r)
+        V = [r / beta]
+        Z = []
+        H = np.zeros((3, 2), dtype=np.complex128)
+        k = 0
+        for j in range(2):
+            Z.append(self.kcycle(V[j], l, threshold))
+            w = A @ Z[j]
+            for i in range(j + 1):
+                H[i, j] = np.vdot(V[i], w)
+                w = w - H[i, j] * V[i]
+            H[j + 1, j] = np.linalg.norm(w)
+            k = j + 1
+            rhs = np.zeros(k + 1, dtype=np.complex128)
+            rhs[0] = beta
+            y, *_ = np.linalg.lstsq(H[:k + 1, :k], rhs, rcond=None)
+            res = np.linalg.norm(rhs - H[:k + 1, :k] @ y)
+            if j == 0 and (res <= threshold * beta or H[1, 0] == 0.0):
+                break
+            if j == 0:
+                V.append(w / H[1, 0])
+        return np.array(Z[:k]).T @ y
 
     def vcycle(self, b, l=0):
         """One V-cycle from a zero initial guess on level l: returns x ~ A_l^{-1} b."""
