@@ -71,6 +71,14 @@ typedef struct {
   int src[3];
 } adr_problem;
 
+/* Multigrid cycle used as the preconditioner. */
+typedef enum {
+  ADR_CYCLE_V = 0,   /* two-grid cycle applied recursively (Alg. TwoCycle)               */
+  ADR_CYCLE_K = 1    /* Krylov cycle (Sec. 3.1, Alg. KrylovCycle): every coarse level    */
+                     /* that is not the coarsest is solved by flexible GMRES(2) from     */
+                     /* zero, preconditioned by the cycle one level down                 */
+} adr_cycle;
+
 /* Solver options; adr_default_options() fills the defaults named below. */
 typedef struct {
   adr_precision prec;   /* default ADR_PREC_MIXED                                        */
@@ -84,6 +92,10 @@ typedef struct {
   double beta;          /* preconditioner blend of eq. precADRup; default 0.25 (Sec. 4.2) */
   int restart;          /* FGMRES restart length m; default 5 (Sec. 4.2); max 8           */
   int use_graph;        /* capture each V-cycle in a hipGraph; default 1                 */
+  adr_cycle cycle;      /* default ADR_CYCLE_V                                            */
+  double kcycle_threshold; /* Krylov cycle: keep only the first coarse GMRES step when its */
+                        /* residual is <= this times the initial one; default 0.1       */
+                        /* (Sec. 4.2.2); 0 always takes both steps                       */
 } adr_options;
 
 typedef struct {
@@ -112,8 +124,10 @@ void adr_destroy(adr_ctx *ctx);
  * of n nodes, distinct buffers.  Enqueued on the context stream. */
 adr_status adr_apply(adr_ctx *ctx, double beta, const void *x_c128, void *y_c128);
 
-/* One preconditioner application z = M^{-1} r: a V-cycle (Alg. TwoCycle, recursive) on
- * A_beta from a zero guess, in the context's precision; r and z c128, distinct.
+/* One preconditioner application z = M^{-1} r: the configured cycle (a V-cycle, Alg.
+ * TwoCycle applied recursively, or a Krylov cycle, Alg. KrylovCycle) on A_beta from a
+ * zero guess, in the context's precision; r and z c128, distinct.  The Krylov cycle is
+ * not linear in r (it is homogeneous: scaling r scales z).
  * Enqueued on the context stream; no host synchronization. */
 adr_status adr_vcycle(adr_ctx *ctx, const void *r_c128, void *z_c128);
 

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libadr.so")
 ADR_OK, ADR_EINVAL, ADR_ENOMEM, ADR_EHIP, ADR_ENOCONV, ADR_ENUMERIC, ADR_ENOTSUP = range(7)
 ADR_PREC_FP64, ADR_PREC_MIXED = 0, 1
 ADR_RELAX_JACOBI, ADR_RELAX_GMRES = 0, 1
+ADR_CYCLE_V, ADR_CYCLE_K = 0, 1
 TIMER_KINDS = {"fine_jacobi": 0, "fine_residual": 1, "coarse_apply": 2, "coarse_orth": 3, "transfer": 4,
                "outer_matvec": 5, "outer_orth": 6}
 
@@ -45,6 +46,8 @@ class AdrOptions(ctypes.Structure):
         ("beta", ctypes.c_double),
         ("restart", ctypes.c_int),
         ("use_graph", ctypes.c_int),
+        ("cycle", ctypes.c_int),
+        ("kcycle_threshold", ctypes.c_double),
     ]
 
 
@@ -127,6 +130,8 @@ def default_options(**kw):
                 arr[i] = int(x)
         elif k == "prec":
             o.prec = {"fp64": ADR_PREC_FP64, "mixed": ADR_PREC_MIXED}.get(v, v)
+        elif k == "cycle":
+            o.cycle = {"v": ADR_CYCLE_V, "k": ADR_CYCLE_K}.get(v, v)
         else:
             setattr(o, k, v)
     return o

@@ -32,7 +32,12 @@ constexpr int kLdH = kMaxNu + 1;
 constexpr int kS = kH + 2 * kLdH * kMaxNu;          // kMaxNu+1 scale factors
 constexpr int kBeta = kS + kMaxNu + 1;              // norm of the initial residual
 constexpr int kCoef = kBeta + 1;                    // kMaxNu complex update coefficients
-static_assert(kCoef + 2 * kMaxNu <= kScalPerLevel, "scalar block too small");
+// Krylov cycle: flexible GMRES(2) on this level (3 x 2 complex Hessenberg, column-major,
+// leading dimension 3; scale factors of the two basis vectors; norm of the first).
+constexpr int kKH = kCoef + 2 * kMaxNu;
+constexpr int kKS = kKH + 12;
+constexpr int kKBeta = kKS + 2;
+static_assert(kKBeta + 1 <= kScalPerLevel, "scalar block too small");
 
 std::string g_setup_error;
 
@@ -49,6 +54,8 @@ struct LevelT {
   cx<T> *x = nullptr, *xt = nullptr, *b = nullptr, *r = nullptr, *w = nullptr;
   cx<T> *V = nullptr;        // (kMaxNu+1) x N Arnoldi basis (unnormalized)
   cx<T> *Z = nullptr;        // (kMaxNu+1) x N, Z_j = D^{-1} V_j
+  cx<T> *ku = nullptr;       // Krylov cycle: second coarse basis vector u_1
+  cx<T> *kz = nullptr;       // Krylov cycle: first preconditioned direction K(u_0)
   cx<T> *planes_adj = nullptr;   // conjugate-transposed stencil (adjoint solves)
   cx<T> *dinv_adj = nullptr;
 };
@@ -341,6 +348,10 @@ adr_status alloc_level_vectors(adr_ctx *ctx, LevelT<T> &L, int l) {
     ADR_TRY(dalloc(ctx, &L.w, N));
     ADR_TRY(dalloc(ctx, &L.V, N * (kMaxNu + 1)));
     ADR_TRY(dalloc(ctx, &L.Z, N * (kMaxNu + 1)));
+    if (ctx->opt.cycle == ADR_CYCLE_K && l < ctx->levels - 1) {
+      ADR_TRY(dalloc(ctx, &L.ku, N));
+      ADR_TRY(dalloc(ctx, &L.kz, N));
+    }
   }
   return ADR_OK;
 }
@@ -452,8 +463,14 @@ cx<T> *jacobi_sweeps(adr_ctx *ctx, int nu, const cx<T> *x_start, const cx<T> *b,
   return out;
 }
 
-// One V-cycle on level l from a zero guess; b is the level right-hand side.  Returns
-// the buffer holding x_l.  On level 0 `out0` is the preferred output buffer.
+template <typename T>
+cx<T> *coarse_fgmres2(adr_ctx *ctx, int k);
+
+// One cycle on level l from a zero guess; b is the level right-hand side.  Returns the
+// buffer holding x_l; `out0` (if not NULL) is the preferred output buffer.  The coarse
+// problem is solved by the same cycle one level down (V-cycle, Alg. TwoCycle applied
+// recursively), or, for the Krylov cycle (Alg. KrylovCycle), by flexible GMRES(2)
+// preconditioned by it unless the coarse level is the coarsest.
 template <typename T>
 cx<T> *vcycle(adr_ctx *ctx, int l, const cx<T> *b, cx<T> *out0) {
   LevelT<T> *lv = levels_of<T>(ctx);
@@ -461,11 +478,11 @@ cx<T> *vcycle(adr_ctx *ctx, int l, const cx<T> *b, cx<T> *out0) {
   hipStream_t s = ctx->stream;
   const int D = ctx->D;
   if (l == ctx->levels - 1) {
-    cx<T> *x = (l == 0 && out0) ? out0 : L.x;
+    cx<T> *x = out0 ? out0 : L.x;
     adrk::dense_gemv<T>(s, L.G.N, ctx->adj ? ctx->Ainv_adj : ctx->Ainv, b, x);
     return x;
   }
-  cx<T> *xa = (l == 0 && out0) ? out0 : L.x;
+  cx<T> *xa = out0 ? out0 : L.x;
   cx<T> *x;
   // pre-relaxation (Jacobi: the first sweep writes the scratch buffer, so that the
   // post-relaxation, which alternates from the pre-relaxed iterate, ends in xa)
@@ -502,7 +519,8 @@ cx<T> *vcycle(adr_ctx *ctx, int l, const cx<T> *b, cx<T> *out0) {
   int t1 = tbegin(ctx, ADR_TIMER_TRANSFER, l);
   adrk::restrict_full<T>(s, L.G, C.G, D, L.r, C.b);
   tend(ctx, t1, cb * ((double)L.G.N + C.G.N));
-  cx<T> *ec = vcycle<T>(ctx, l + 1, C.b, nullptr);
+  cx<T> *ec = (ctx->opt.cycle == ADR_CYCLE_K && l + 1 < ctx->levels - 1) ? coarse_fgmres2<T>(ctx, l + 1)
+                                                                          : vcycle<T>(ctx, l + 1, C.b, nullptr);
   int t2 = tbegin(ctx, ADR_TIMER_TRANSFER, l);
   adrk::prolong_add<T>(s, L.G, C.G, D, ec, x);
   tend(ctx, t2, cb * ((double)C.G.N + 2.0 * L.G.N));
@@ -513,6 +531,64 @@ cx<T> *vcycle(adr_ctx *ctx, int l, const cx<T> *b, cx<T> *out0) {
   }
   gmres_relax<T>(ctx, l, x, b, x);
   return x;
+}
+
+// Flexible GMRES(2) from zero on A_k e = u_0 (u_0 = the restricted residual in level k's
+// b), preconditioned by the cycle on level k (Alg. KrylovCycle).  The basis is kept
+// unnormalized: u_1 = A z_0 - H00 v_0 with v_j = s_j u_j, s_j = 1/||u_j||; since the
+// cycle is homogeneous, K(v_j) = s_j K(u_j), so the directions Z_j = K(u_j) enter with
+// the factors s_j.  Both steps always run; the threshold (one-step residual <= t ||u_0||)
+// only selects the one-column solution, which is what stopping after one step gives.
+// Returns level k's w, which holds e.
+template <typename T>
+cx<T> *coarse_fgmres2(adr_ctx *ctx, int k) {
+  LevelT<T> &L = levels_of<T>(ctx)[k];
+  hipStream_t s = ctx->stream;
+  const int N = L.G.N, D = ctx->D;
+  const double cb = sizeof(cx<T>);
+  double *sc = lscal(ctx, k);
+  double *KH = sc + kKH, *KS = sc + kKS, *KB = sc + kKBeta;
+  const cx<T> *planes = lvl_planes(ctx, L);
+  // beta = ||u_0||, s_0
+  int nb = adrk::norm2<T>(s, N, L.b, nullptr, nullptr, ctx->part[0]);
+  adrk::reduce_norm(s, ProIn{ctx->part[0], nb, 1}, KB, 0, KS + 0);
+  // Z_0 = K(u_0)
+  vcycle<T>(ctx, k, L.b, L.kz);
+  // w = s_0 A Z_0 with the dot against u_0; u_1 = w - H00 s_0 u_0 and its norm
+  VecSet<T> V1 = vecset<T>({L.b});
+  CoarseArgs<T> a{};
+  a.G = L.G;
+  a.planes = planes;
+  a.x = L.kz;
+  a.sdev = KS + 0;
+  a.y = L.w;
+  a.mode = 0;
+  a.pout = ctx->part[0];
+  int t0 = tbegin(ctx, ADR_TIMER_COARSE_APPLY, k);
+  nb = adrk::coarse_apply<T>(s, D, a, &V1, false);
+  tend(ctx, t0, (double)N * cb * (L.S + 3));
+  int t1 = tbegin(ctx, ADR_TIMER_COARSE_ORTH, k);
+  nb = adrk::orth_step<T>(s, N, L.w, V1, ProIn{ctx->part[0], nb, 2}, KS, KH + 0, nullptr, L.ku, nullptr,
+                          ctx->part[1]);
+  tend(ctx, t1, (double)N * cb * 3);
+  adrk::reduce_norm(s, ProIn{ctx->part[1], nb, 1}, KH + 2 * 1, 1, KS + 1);
+  // Z_1 = K(u_1)
+  cx<T> *z1 = vcycle<T>(ctx, k, L.ku, L.x);
+  // w = s_1 A Z_1 with dots against u_0, u_1; u_2 (into r) only for its norm H21
+  VecSet<T> V2 = vecset<T>({L.b, L.ku});
+  a.x = z1;
+  a.sdev = KS + 1;
+  int t2 = tbegin(ctx, ADR_TIMER_COARSE_APPLY, k);
+  nb = adrk::coarse_apply<T>(s, D, a, &V2, false);
+  tend(ctx, t2, (double)N * cb * (L.S + 4));
+  int t3 = tbegin(ctx, ADR_TIMER_COARSE_ORTH, k);
+  nb = adrk::orth_step<T>(s, N, L.w, V2, ProIn{ctx->part[0], nb, 4}, KS, KH + 2 * 3, nullptr, L.r, nullptr,
+                          ctx->part[1]);
+  tend(ctx, t3, (double)N * cb * 4);
+  int t4 = tbegin(ctx, ADR_TIMER_COARSE_ORTH, k);
+  adrk::fgmres2_update<T>(s, N, L.kz, z1, ProIn{ctx->part[1], nb, 1}, KH, KB, KS, ctx->opt.kcycle_threshold, L.w);
+  tend(ctx, t4, (double)N * cb * 3);
+  return L.w;
 }
 
 adr_status check_levels(adr_ctx *ctx) {
@@ -557,6 +633,8 @@ adr_status validate(const adr_problem *p, const adr_options *o, std::string &err
   if (o->levels < 0 || o->levels > kMaxLevels) { err = "levels must be in [0, 8]"; return ADR_EINVAL; }
   if (o->prec != ADR_PREC_FP64 && o->prec != ADR_PREC_MIXED) { err = "bad precision"; return ADR_EINVAL; }
   if (!(o->beta >= 0.0 && o->beta <= 1.0)) { err = "beta must be in [0, 1]"; return ADR_EINVAL; }
+  if (o->cycle != ADR_CYCLE_V && o->cycle != ADR_CYCLE_K) { err = "bad cycle"; return ADR_EINVAL; }
+  if (!(o->kcycle_threshold >= 0.0)) { err = "kcycle_threshold must be >= 0"; return ADR_EINVAL; }
   return ADR_OK;
 }
 
@@ -730,9 +808,10 @@ void free_ctx(adr_ctx *ctx) {
     LevelT<double> &a = ctx->lv64[l];
     LevelT<float> &b = ctx->lv32[l];
     for (void *p : {(void *)a.planes, (void *)a.dinv, (void *)a.x, (void *)a.xt, (void *)a.b, (void *)a.r,
-                    (void *)a.w, (void *)a.V, (void *)a.Z, (void *)a.planes_adj, (void *)a.dinv_adj,
-                    (void *)b.planes, (void *)b.dinv, (void *)b.x, (void *)b.xt, (void *)b.b, (void *)b.r,
-                    (void *)b.w, (void *)b.V, (void *)b.Z, (void *)b.planes_adj, (void *)b.dinv_adj})
+                    (void *)a.w, (void *)a.V, (void *)a.Z, (void *)a.ku, (void *)a.kz, (void *)a.planes_adj,
+                    (void *)a.dinv_adj, (void *)b.planes, (void *)b.dinv, (void *)b.x, (void *)b.xt, (void *)b.b,
+                    (void *)b.r, (void *)b.w, (void *)b.V, (void *)b.Z, (void *)b.ku, (void *)b.kz,
+                    (void *)b.planes_adj, (void *)b.dinv_adj})
       F(p);
   }
   F(ctx->off_coarse);
@@ -903,6 +982,8 @@ void adr_default_options(adr_options *o) {
   o->beta = 0.25;
   o->restart = 5;
   o->use_graph = 1;
+  o->cycle = ADR_CYCLE_V;
+  o->kcycle_threshold = 0.1;
 }
 
 adr_status adr_setup(const adr_problem *prob, const adr_options *opt, void *stream, adr_ctx **out) {

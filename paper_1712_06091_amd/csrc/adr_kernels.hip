@@ -631,7 +631,7 @@ void zero(hipStream_t s, long long n, cx<double> *x) { ADR_LAUNCH(k_zero, launch
 // outside the grid).  Partials: NV dots conj(V_v).y, then ||y||^2 if NORM.
 template <typename T, int D, int NV, bool NORM>
 __global__ __launch_bounds__(ADR_BLOCK) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_coarse_apply(Grid G, const cx<T> *__restrict__ planes,
-                                                            const cx<T> *__restrict__ x, ProIn pin,
+                                                            const cx<T> *__restrict__ x, ProIn pin, const double *sdev,
                                                             double *norm_out, int norm_cplx, double *inv_out,
                                                             const cx<T> *__restrict__ b, cx<T> *__restrict__ y,
                                                             const cx<T> *__restrict__ dinv, cx<T> *__restrict__ zout,
@@ -652,6 +652,8 @@ __global__ __launch_bounds__(ADR_BLOCK) __attribute__((amdgpu_waves_per_eu(1, 4)
       if (norm_cplx) norm_out[1] = 0.0;
       *inv_out = inv;
     }
+  } else if (sdev) {
+    xs = (T)*sdev;
   }
   double red[KA];
 #pragma unroll
@@ -714,7 +716,7 @@ static void dispatch_coarse_nv(hipStream_t s, int nb, const CoarseArgs<T> &a, co
   switch (V.count) {
 #define ADR_NV_CASE(n)                                                                                      \
   case n:                                                                                                   \
-    ADR_LAUNCH((k_coarse_apply<T, D, n, NORM>), nb, s, a.G, a.planes, a.x, a.pin, a.norm_out, a.norm_cplx, \
+    ADR_LAUNCH((k_coarse_apply<T, D, n, NORM>), nb, s, a.G, a.planes, a.x, a.pin, a.sdev, a.norm_out, a.norm_cplx, \
                a.inv_out, a.b, a.y, a.dinv, a.zout, a.mode, V, a.pout);                                     \
     break;
     ADR_NV_CASE(0) ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6)
@@ -852,7 +854,7 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_orth_step(int N, const cx<T> *__r
 #pragma unroll
     for (int v = 0; v < NV; ++v) o = o - coef[v] * V.v[v][i];
     vnew[i] = o;
-    znew[i] = o * dinv[i];
+    if (znew) znew[i] = o * dinv[i];
     red[0] += (double)o.re * o.re + (double)o.im * o.im;
   }
   block_partials<1>(red, 1, pout);
@@ -1002,6 +1004,81 @@ template void gmres_update<double>(hipStream_t, int, const cx<double> *, const V
                                    const double *, int, const double *, const double *, cx<double> *);
 template void gmres_update<float>(hipStream_t, int, const cx<float> *, const VecSet<float> &, ProIn, const double *,
                                   int, const double *, const double *, cx<float> *);
+
+// =====================================================================================
+// Krylov cycle: flexible GMRES(2) on a coarse level
+// =====================================================================================
+__global__ __launch_bounds__(ADR_BLOCK) void k_reduce_norm(ProIn pin, double *norm_out, int norm_cplx,
+                                                           double *inv_out) {
+  __shared__ double tot[1];
+  reduce_partials(pin.partials, pin.nb, 1, tot);
+  if (threadIdx.x == 0) {
+    const double nrm = sqrt(tot[0]);
+    norm_out[0] = nrm;
+    if (norm_cplx) norm_out[1] = 0.0;
+    inv_out[0] = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  }
+}
+void reduce_norm(hipStream_t s, ProIn pin, double *norm_out, int norm_cplx, double *inv_out) {
+  hipLaunchKernelGGL(k_reduce_norm, dim3(1), dim3(ADR_BLOCK), 0, s, pin, norm_out, norm_cplx, inv_out);
+}
+
+// Thread 0 of every block solves the 1- or 2-column least squares (the same in every
+// block, from the same device scalars and partials), then e = c_0 Z0 + c_1 Z1.
+template <typename T>
+__global__ __launch_bounds__(ADR_BLOCK) void k_fgmres2_update(int N, const cx<T> *__restrict__ Z0,
+                                                              const cx<T> *__restrict__ Z1, ProIn pin,
+                                                              const double *H, const double *beta,
+                                                              const double *scales, double threshold,
+                                                              cx<T> *__restrict__ e) {
+  __shared__ double tot[1];
+  __shared__ double cs[4];
+  reduce_partials(pin.partials, pin.nb, 1, tot);
+  if (threadIdx.x == 0) {
+    auto at = [&](int i, int j) { return mk<double>(H[2 * (j * 3 + i)], H[2 * (j * 3 + i) + 1]); };
+    const double b = *beta;
+    const cx<double> h00 = at(0, 0), h10 = at(1, 0);
+    const double a0 = h00.re * h00.re + h00.im * h00.im, a1 = h10.re * h10.re + h10.im * h10.im;
+    // residual of the one-step least squares: beta |h10| / sqrt(|h00|^2 + |h10|^2)
+    const double res1 = (a0 + a1) > 0.0 ? b * sqrt(a1 / (a0 + a1)) : b;
+    if (res1 <= threshold * b || a1 == 0.0) {
+      cx<double> R[2][1] = {{h00}, {h10}};
+      cx<double> y[1];
+      gmres_lsq<1>(R, b, y);
+      cs[0] = y[0].re * scales[0];
+      cs[1] = y[0].im * scales[0];
+      cs[2] = 0.0;
+      cs[3] = 0.0;
+    } else {
+      cx<double> R[3][2] = {{h00, at(0, 1)}, {h10, at(1, 1)}, {mk<double>(0.0, 0.0), mk<double>(sqrt(tot[0]), 0.0)}};
+      cx<double> y[2];
+      gmres_lsq<2>(R, b, y);
+      cs[0] = y[0].re * scales[0];
+      cs[1] = y[0].im * scales[0];
+      cs[2] = y[1].re * scales[1];
+      cs[3] = y[1].im * scales[1];
+    }
+  }
+  __syncthreads();
+  const cx<T> c0 = mk<T>((T)cs[0], (T)cs[1]), c1 = mk<T>((T)cs[2], (T)cs[3]);
+  const bool two = cs[2] != 0.0 || cs[3] != 0.0;
+  int beg, end;
+  chunk_range(N, beg, end);
+  for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    cx<T> acc = c0 * Z0[i];
+    if (two) acc = cfma(c1, Z1[i], acc);
+    e[i] = acc;
+  }
+}
+template <typename T>
+void fgmres2_update(hipStream_t s, int N, const cx<T> *Z0, const cx<T> *Z1, ProIn pin, const double *H,
+                    const double *beta, const double *scales, double threshold, cx<T> *e) {
+  ADR_LAUNCH(k_fgmres2_update<T>, launch_blocks(N), s, N, Z0, Z1, pin, H, beta, scales, threshold, e);
+}
+template void fgmres2_update<double>(hipStream_t, int, const cx<double> *, const cx<double> *, ProIn,
+                                     const double *, const double *, const double *, double, cx<double> *);
+template void fgmres2_update<float>(hipStream_t, int, const cx<float> *, const cx<float> *, ProIn, const double *,
+                                    const double *, const double *, double, cx<float> *);
 
 // =====================================================================================
 // Outer FGMRES (FP64) Arnoldi: classical Gram-Schmidt with one re-orthogonalization

@@ -27,6 +27,7 @@ struct CoarseArgs {
   const cx<T> *planes;   // 81 (3D) / 21 (2D) planes of N entries, fixed offset order
   const cx<T> *x;
   ProIn pin;             // mode 0: scale = 1/||.|| of these partials (K = 1); none if NULL
+  const double *sdev;    // mode 0 without pin: scale = *sdev when not NULL
   double *norm_out;      // mode 0 with pin: block 0 stores the norm here ...
   int norm_cplx;         // ... and 0 in norm_out[1] if set (complex Hessenberg slot)
   double *inv_out;       // ... and the scale here
@@ -104,7 +105,8 @@ void prolong_add(hipStream_t s, const Grid &Gf, const Grid &Gc, int D, const cx<
 
 // ---- GMRES relaxation / Arnoldi helpers --------------------------------------------
 // Prologue H[i][j] = scales_i * (dot partials), stored by block 0 in hcol; then
-// v_new = w - sum_i H[i][j] scales_i V_i, z_new = dinv o v_new, norm partials to pout.
+// v_new = w - sum_i H[i][j] scales_i V_i, z_new = dinv o v_new (skipped when z_new is
+// NULL), norm partials to pout.
 template <typename T>
 int orth_step(hipStream_t s, int N, const cx<T> *w, const VecSet<T> &V, ProIn pin, const double *scales,
               double *hcol, const cx<T> *dinv, cx<T> *vnew, cx<T> *znew, double *pout);
@@ -116,6 +118,18 @@ int norm2(hipStream_t s, int N, const cx<T> *x, const cx<T> *dinv, cx<T> *z, dou
 template <typename T>
 void gmres_update(hipStream_t s, int N, const cx<T> *x0, const VecSet<T> &Z, ProIn pin, const double *H, int ldh,
                   const double *beta, const double *scales, cx<T> *x_out);
+
+// One block: tot = sum of the partials (K = 1); norm_out[0] = sqrt(tot) (and
+// norm_out[1] = 0 when norm_cplx), inv_out[0] = 1/sqrt(tot) (0 for a zero norm).
+void reduce_norm(hipStream_t s, ProIn pin, double *norm_out, int norm_cplx, double *inv_out);
+// Flexible GMRES(2) update of the Krylov cycle.  H (3 x 2 complex, column-major,
+// leading dimension 3) holds columns 0 and 1 except H[2][1] = sqrt(partials of pin);
+// beta = ||u_0||; scales s_j = 1/||u_j||.  If the one-step residual is <= threshold *
+// beta (or H[1][0] = 0) e = y_0 s_0 Z0 with the one-column least squares, else
+// e = y_0 s_0 Z0 + y_1 s_1 Z1 with the two-column one.
+template <typename T>
+void fgmres2_update(hipStream_t s, int N, const cx<T> *Z0, const cx<T> *Z1, ProIn pin, const double *H,
+                    const double *beta, const double *scales, double threshold, cx<T> *e);
 
 // ---- outer FGMRES (FP64) -----------------------------------------------------------
 // Pass 1 of CGS2: h = dot partials of the matvec (prologue; block 0 stores them in
