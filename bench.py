@@ -7,7 +7,7 @@ relative residual <= 1e-6, then the wavefield u = a exp(-i w tau)), mixed precis
 10 points per wavelength).  Setup (coefficients, Galerkin hierarchy, coarsest inverse)
 is timed separately.  Inputs are synthetic and resident in HBM before timing starts.
 
-Prints one JSON line.  --gpus N with N > 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus N with N > 1 is refused: the benchmark runs on one GPU.
 """
 import argparse
 import json
@@ -34,12 +34,49 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="3d_129", choices=["3d_129", "2d_129", "3d_65", "3d_257", "batch_2d"])
     ap.add_argument("--streams", type=int, default=4, help="streams of the batched-shot solve")
+    ap.add_argument("--cycle", default="v", choices=["v", "k"], help="V-cycle or Krylov cycle preconditioner")
+    ap.add_argument("--batch-maxit", type=int, default=3000, help="FGMRES iteration cap per shot (batch)")
+    ap.add_argument("--mixed-only", action="store_true", help="with --profile-only: skip the FP64 solves")
+    ap.add_argument("--no-graph", action="store_true", help="launch the cycles eagerly (no hipGraph)")
+    ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (HBM counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=8)
     ap.add_argument("--cpu-sample-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--profile-only", action="store_true",
                     help="setup + warmup + timed steps only (for rocprofv3 runs)")
     return ap.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_coarse_apply_level1_3d_129.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1712_06091_amd", "csrc", f)
+                  for f in ("adr_kernels.hip", "adr_kernels.hpp", "adr_common.hpp")]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the level-1 Galerkin apply from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when there is no
+    summary for this workload or the kernel sources changed since it was taken."""
+    if workload != "3d_129" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if ":" in line and line.strip().startswith("- `"):
+                k, v = line.strip()[3:].split("`", 1)
+                vals[k] = v.split(":", 1)[1].strip().strip("`")
+    if vals.get("kernel_sources_sha256") != kernel_source_hash():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
 
 
 def make_workload(name):
@@ -97,6 +134,19 @@ def cpu_baseline(args, nodes, iters_needed):
 # --------------------------------------------------------------------------------------
 # GPU
 # --------------------------------------------------------------------------------------
+def copy_probe(args):
+    """A plain device-to-device copy of a known size (reads and writes args.copy_probe MiB
+    once each): the reference dispatch for scaling the HBM byte counters."""
+    import torch
+    n = int(args.copy_probe * 2 ** 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": 8 * n}))
+
+
 def run_batch(args):
     """64 2D shots (sizes from {257^2, 513^2, 1025^2}, random media, fast-marching tau):
     one lockstep batched solve over several streams vs. the same shots solved one after
@@ -116,33 +166,40 @@ def run_batch(args):
     qs = [t(w.rhs(), torch.complex128) for w in wls]
     outs = [torch.empty(w.shape, dtype=torch.complex128, device=dev) for w in wls]
     nodes = sum(w.nodes for w in wls)
-    opts = adr.default_options(prec="mixed")
+    opts = adr.default_options(prec="mixed", cycle=args.cycle)
+    maxit = args.batch_maxit
     torch.cuda.synchronize()
     s0 = time.perf_counter()
     b = adr.Batch(shots, options=opts, nstreams=args.streams)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - s0
+    log(f"batch setup {setup_s:.1f} s")
     for _ in range(args.warmup):
-        b.solve(qs, outs, tol=TOL)
+        b.solve(qs, outs, tol=TOL, maxit=maxit)
     torch.cuda.synchronize()
+    log("batch warm-up done")
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        st, stats = b.solve(qs, outs, tol=TOL)
+        st, stats = b.solve(qs, outs, tol=TOL, maxit=maxit)
         if st != adr.ADR_OK:
-            raise RuntimeError("batched solve did not converge")
+            bad = [(i, s["outer_iters"], s["relres"]) for i, s in enumerate(stats) if not s["relres"] <= TOL]
+            raise RuntimeError(f"batched solve did not converge within {maxit} iterations: {bad[:8]}")
+        log("batch step done")
     torch.cuda.synchronize()
     ms_batch = (time.perf_counter() - t0) * 1e3 / args.steps
-    log(f"batched: {ms_batch:.1f} ms per batch")
+    its = sorted(s["outer_iters"] for s in stats)
+    log(f"batched: {ms_batch:.1f} ms per batch; iterations min {its[0]} median {its[len(its) // 2]} max {its[-1]}")
     # The same shots one after another through adr_solve on the default stream.
     ctxs = [adr.Context(s["kappa2"], s["tau"], s["gamma"], s["h"], s["omega"], s["src"], options=opts)
             for s in shots]
     for c, q, a in zip(ctxs, qs, outs):
-        c.solve(q, tol=TOL, out=a)
+        c.solve(q, tol=TOL, maxit=maxit, out=a)
     torch.cuda.synchronize()
+    log("looped warm-up done")
     t0 = time.perf_counter()
     iters_loop = 0
     for c, q, a in zip(ctxs, qs, outs):
-        _, s1 = c.solve(q, tol=TOL, out=a)
+        _, s1 = c.solve(q, tol=TOL, maxit=maxit, out=a)
         iters_loop += s1["outer_iters"]
     torch.cuda.synchronize()
     ms_loop = (time.perf_counter() - t0) * 1e3
@@ -156,10 +213,12 @@ def run_batch(args):
         "ms_per_step": ms_batch, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "c64 V-cycle / c128 FGMRES", "data": "synthetic",
         "config": {"workload": "batch_2d_64_shots", "shots": len(wls), "nodes": nodes,
-                   "sizes": sorted({w.shape[0] for w in wls}), "streams": args.streams, "tol": TOL},
+                   "sizes": sorted({w.shape[0] for w in wls}), "streams": args.streams, "tol": TOL,
+                   "cycle": args.cycle, "maxit": maxit},
         "looped": {"value": nodes / (ms_loop * 1e-3) / 1e6, "ms": ms_loop, "outer_iters": iters_loop},
         "batched_over_looped": ms_loop / ms_batch,
-        "outer_iters": sum(s["outer_iters"] for s in stats),
+        "outer_iters": sum(its),
+        "outer_iters_per_shot": {"min": its[0], "median": its[len(its) // 2], "max": its[-1]},
         "setup_s": setup_s,
     }
     print(json.dumps(out))
@@ -171,9 +230,12 @@ def main():
         cpu_sample_child(args)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
-              "(shot-parallel multi-GPU is a design note, not built).", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(multi-GPU shot sharding is not implemented).", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe > 0:
+        copy_probe(args)
+        return
     if args.workload == "batch_2d":
         run_batch(args)
         return
@@ -194,10 +256,12 @@ def main():
     torch.cuda.synchronize()
 
     ctxs, setup_ms = {}, {}
-    for prec in ("mixed", "fp64"):
+    for prec in (("mixed",) if args.mixed_only else ("mixed", "fp64")):
         torch.cuda.synchronize()
         s0 = time.perf_counter()
-        ctxs[prec] = adr.Context(k2, tau, gam, wl.h, wl.omega, wl.src, options=adr.default_options(prec=prec))
+        ctxs[prec] = adr.Context(k2, tau, gam, wl.h, wl.omega, wl.src,
+                                 options=adr.default_options(prec=prec, cycle=args.cycle,
+                                                             use_graph=0 if args.no_graph else 1))
         torch.cuda.synchronize()
         setup_ms[prec] = (time.perf_counter() - s0) * 1e3
         log(f"setup {prec}: {setup_ms[prec]:.0f} ms, {ctxs[prec].num_levels} levels")
@@ -220,6 +284,9 @@ def main():
 
     ms_mixed, st_mixed = timed(ctxs["mixed"], args.steps, args.warmup)
     log(f"mixed: {ms_mixed:.2f} ms/solve, {st_mixed[-1]['outer_iters']} iterations")
+    if args.profile_only and args.mixed_only:
+        print(json.dumps({"ms_mixed": ms_mixed}))
+        return
     ms_fp64, st_fp64 = timed(ctxs["fp64"], max(1, min(args.steps, 3)), 1)
     log(f"fp64: {ms_fp64:.2f} ms/solve, {st_fp64[-1]['outer_iters']} iterations")
     if args.profile_only:
@@ -295,7 +362,7 @@ def main():
         "vcycle": {"ms": vc_ms, "algorithmic_bytes": vc_bytes, "GBps": vc_bytes / (vc_ms * 1e-3) / 1e9,
                    "frac": vc_bytes / (vc_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS},
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(args.workload),
                      "avg_launch_ms": avg_ms, "launches": dm_n, "algorithmic_bytes_per_launch": avg_bytes},
         "breakdown_ms": {c: round(v["ms"], 4) for c, v in breakdown.items()},
     }
