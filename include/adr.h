@@ -96,6 +96,10 @@ typedef struct {
   double kcycle_threshold; /* Krylov cycle: keep only the first coarse GMRES step when its */
                         /* residual is <= this times the initial one; default 0.1       */
                         /* (Sec. 4.2.2); 0 always takes both steps                       */
+  int coarse_split;     /* Galerkin-stencil apply on coarse levels: 1 = one lane per     */
+                        /* node, 4 = four wavefronts per 64 nodes, 0 (default) = the     */
+                        /* faster of the two per level, timed at setup and cached per    */
+                        /* grid shape and precision for the process                      */
 } adr_options;
 
 typedef struct {

@@ -48,6 +48,7 @@ class AdrOptions(ctypes.Structure):
         ("use_graph", ctypes.c_int),
         ("cycle", ctypes.c_int),
         ("kcycle_threshold", ctypes.c_double),
+        ("coarse_split", ctypes.c_int),
     ]
 
 

@@ -12,7 +12,10 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <array>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -56,6 +59,7 @@ struct LevelT {
   cx<T> *Z = nullptr;        // (kMaxNu+1) x N, Z_j = D^{-1} V_j
   cx<T> *ku = nullptr;       // Krylov cycle: second coarse basis vector u_1
   cx<T> *kz = nullptr;       // Krylov cycle: first preconditioned direction K(u_0)
+  int split = 1;             // Galerkin-apply variant (wavefronts per node), tuned at setup
   cx<T> *planes_adj = nullptr;   // conjugate-transposed stencil (adjoint solves)
   cx<T> *dinv_adj = nullptr;
 };
@@ -373,8 +377,12 @@ VecSet<T> vecset(std::initializer_list<const cx<T> *> v) {
 // next to it so the stencil apply gathers a single vector.  Every reduction is summed in
 // the prologue of the kernel that consumes it (see reduce_partials), so one step is two
 // launches: the stencil apply with the dots, then the orthogonalization with the norm.
+// From a zero guess, `bpin` (if set) holds the partials of ||b||^2 in part[0] with
+// Z_0 = D^{-1} b already written (the restriction fuses both), and `r_out` (if set)
+// receives the new residual b - A x_out from the Arnoldi relation (no extra apply).
 template <typename T>
-void gmres_relax(adr_ctx *ctx, int l, const cx<T> *x0, const cx<T> *b, cx<T> *x_out) {
+void gmres_relax(adr_ctx *ctx, int l, const cx<T> *x0, const cx<T> *b, cx<T> *x_out, ProIn bpin = ProIn{},
+                 cx<T> *r_out = nullptr) {
   LevelT<T> &L = levels_of<T>(ctx)[l];
   hipStream_t s = ctx->stream;
   const int N = L.G.N, nu = ctx->nu[l], D = ctx->D;
@@ -390,10 +398,12 @@ void gmres_relax(adr_ctx *ctx, int l, const cx<T> *x0, const cx<T> *b, cx<T> *x_
   int cur = 0, nb;
   if (!x0) {
     Vp[0] = b;
-    nb = adrk::norm2<T>(s, N, b, dinv, Zp[0], ctx->part[cur]);
+    if (bpin.partials == ctx->part[cur]) nb = bpin.nb;
+    else nb = adrk::norm2<T>(s, N, b, dinv, Zp[0], ctx->part[cur]);
   } else {
     // V0 = b - A x0, Z0 = D^{-1} V0, with the norm partials.
     CoarseArgs<T> a{};
+    a.split = L.split;
     a.G = L.G;
     a.planes = planes;
     a.x = x0;
@@ -414,6 +424,7 @@ void gmres_relax(adr_ctx *ctx, int l, const cx<T> *x0, const cx<T> *b, cx<T> *x_
     double *hcol = sc + kH + 2 * (j * kLdH);
     // w = A Z_j s_j, with s_j = 1/||V_j|| from the previous kernel's partials.
     CoarseArgs<T> a{};
+    a.split = L.split;
     a.G = L.G;
     a.planes = planes;
     a.x = Zp[j];
@@ -437,9 +448,13 @@ void gmres_relax(adr_ctx *ctx, int l, const cx<T> *x0, const cx<T> *b, cx<T> *x_
   VecSet<T> Zs{};
   Zs.count = nu;
   for (int i = 0; i < nu; ++i) Zs.v[i] = Zp[i];
+  VecSet<T> Vr{};
+  Vr.count = nu + 1;
+  for (int i = 0; i <= nu; ++i) Vr.v[i] = Vp[i];
   int t2 = tbegin(ctx, ADR_TIMER_COARSE_ORTH, l);
-  adrk::gmres_update<T>(s, N, x0, Zs, ProIn{ctx->part[cur], nb, 1}, sc + kH, kLdH, sc + kBeta, sc + kS, x_out);
-  tend(ctx, t2, (double)N * cb * (nu + (x0 ? 2 : 1)));
+  adrk::gmres_update<T>(s, N, x0, Zs, ProIn{ctx->part[cur], nb, 1}, sc + kH, kLdH, sc + kBeta, sc + kS, x_out,
+                        r_out ? &Vr : nullptr, r_out);
+  tend(ctx, t2, (double)N * cb * (nu + (x0 ? 2 : 1) + (r_out ? nu + 2 : 0)));
 }
 
 // Jacobi sweeps on the matrix-free level 0: sweep k writes `first` for even k and
@@ -464,15 +479,17 @@ cx<T> *jacobi_sweeps(adr_ctx *ctx, int nu, const cx<T> *x_start, const cx<T> *b,
 }
 
 template <typename T>
-cx<T> *coarse_fgmres2(adr_ctx *ctx, int k);
+cx<T> *coarse_fgmres2(adr_ctx *ctx, int k, ProIn bpin);
 
 // One cycle on level l from a zero guess; b is the level right-hand side.  Returns the
 // buffer holding x_l; `out0` (if not NULL) is the preferred output buffer.  The coarse
 // problem is solved by the same cycle one level down (V-cycle, Alg. TwoCycle applied
 // recursively), or, for the Krylov cycle (Alg. KrylovCycle), by flexible GMRES(2)
 // preconditioned by it unless the coarse level is the coarsest.
+// `bpin`: see gmres_relax (the restriction into b already produced D^{-1} b and the
+// partials of ||b||^2).
 template <typename T>
-cx<T> *vcycle(adr_ctx *ctx, int l, const cx<T> *b, cx<T> *out0) {
+cx<T> *vcycle(adr_ctx *ctx, int l, const cx<T> *b, cx<T> *out0, ProIn bpin = ProIn{}) {
   LevelT<T> *lv = levels_of<T>(ctx);
   LevelT<T> &L = lv[l];
   hipStream_t s = ctx->stream;
@@ -484,15 +501,17 @@ cx<T> *vcycle(adr_ctx *ctx, int l, const cx<T> *b, cx<T> *out0) {
   }
   cx<T> *xa = out0 ? out0 : L.x;
   cx<T> *x;
-  // pre-relaxation (Jacobi: the first sweep writes the scratch buffer, so that the
-  // post-relaxation, which alternates from the pre-relaxed iterate, ends in xa)
-  if (ctx->relax[l] == ADR_RELAX_JACOBI && l == 0) {
+  // Pre-relaxation.  Level 0 relaxes by damped Jacobi (the first sweep writes the
+  // scratch buffer, so that the post-relaxation, which alternates from the pre-relaxed
+  // iterate, ends in xa) and computes its residual with one more matrix-free apply; the
+  // coarse levels' GMRES pre-relaxation also returns the residual in L.r.
+  // (check_levels enforces this split.)
+  if (l == 0) {
     x = jacobi_sweeps<T>(ctx, ctx->nu[l], nullptr, b, L.xt, xa);
   } else {
-    gmres_relax<T>(ctx, l, nullptr, b, xa);
+    gmres_relax<T>(ctx, l, nullptr, b, xa, bpin, L.r);
     x = xa;
   }
-  // residual and restriction
   LevelT<T> &C = lv[l + 1];
   const double cb = sizeof(cx<T>);
   if (l == 0) {
@@ -504,28 +523,22 @@ cx<T> *vcycle(adr_ctx *ctx, int l, const cx<T> *b, cx<T> *out0) {
       adrk::fine_apply<T, T, T>(s, L.G, D, fine_coef<T>(ctx), fine_params(ctx, ctx->opt.beta), x, b, L.r, 1,
                                 nullptr, false, nullptr);
     tend(ctx, t0, (double)L.G.N * (fine_coef_bytes<T>(D) + 3 * cb));
-  } else {
-    CoarseArgs<T> a{};
-    a.G = L.G;
-    a.planes = lvl_planes(ctx, L);
-    a.x = x;
-    a.b = b;
-    a.y = L.r;
-    a.mode = 1;
-    int t0 = tbegin(ctx, ADR_TIMER_COARSE_APPLY, l);
-    adrk::coarse_apply<T>(s, D, a, nullptr, false);
-    tend(ctx, t0, (double)L.G.N * cb * (L.S + 3));
   }
+  // The coarse level (unless it is the coarsest) starts with a GMRES relaxation from
+  // zero: the restriction also writes its D^{-1} b and the partials of ||b||^2.
+  const bool coarse_relaxes = l + 1 < ctx->levels - 1;
   int t1 = tbegin(ctx, ADR_TIMER_TRANSFER, l);
-  adrk::restrict_full<T>(s, L.G, C.G, D, L.r, C.b);
-  tend(ctx, t1, cb * ((double)L.G.N + C.G.N));
-  cx<T> *ec = (ctx->opt.cycle == ADR_CYCLE_K && l + 1 < ctx->levels - 1) ? coarse_fgmres2<T>(ctx, l + 1)
-                                                                          : vcycle<T>(ctx, l + 1, C.b, nullptr);
+  int rnb = adrk::restrict_full<T>(s, L.G, C.G, D, L.r, C.b, coarse_relaxes ? lvl_dinv(ctx, C) : nullptr,
+                                   coarse_relaxes ? C.Z : nullptr, coarse_relaxes ? ctx->part[0] : nullptr);
+  tend(ctx, t1, cb * ((double)L.G.N + C.G.N * (coarse_relaxes ? 3.0 : 1.0)));
+  const ProIn cpin = coarse_relaxes ? ProIn{ctx->part[0], rnb, 1} : ProIn{};
+  cx<T> *ec = (ctx->opt.cycle == ADR_CYCLE_K && coarse_relaxes) ? coarse_fgmres2<T>(ctx, l + 1, cpin)
+                                                                : vcycle<T>(ctx, l + 1, C.b, nullptr, cpin);
   int t2 = tbegin(ctx, ADR_TIMER_TRANSFER, l);
   adrk::prolong_add<T>(s, L.G, C.G, D, ec, x);
   tend(ctx, t2, cb * ((double)C.G.N + 2.0 * L.G.N));
   // post-relaxation
-  if (ctx->relax[l] == ADR_RELAX_JACOBI && l == 0) {
+  if (l == 0) {
     cx<T> *other = (x == xa) ? L.xt : xa;
     return jacobi_sweeps<T>(ctx, ctx->nu[l], x, b, other, x);
   }
@@ -541,7 +554,7 @@ cx<T> *vcycle(adr_ctx *ctx, int l, const cx<T> *b, cx<T> *out0) {
 // only selects the one-column solution, which is what stopping after one step gives.
 // Returns level k's w, which holds e.
 template <typename T>
-cx<T> *coarse_fgmres2(adr_ctx *ctx, int k) {
+cx<T> *coarse_fgmres2(adr_ctx *ctx, int k, ProIn bpin) {
   LevelT<T> &L = levels_of<T>(ctx)[k];
   hipStream_t s = ctx->stream;
   const int N = L.G.N, D = ctx->D;
@@ -549,14 +562,16 @@ cx<T> *coarse_fgmres2(adr_ctx *ctx, int k) {
   double *sc = lscal(ctx, k);
   double *KH = sc + kKH, *KS = sc + kKS, *KB = sc + kKBeta;
   const cx<T> *planes = lvl_planes(ctx, L);
-  // beta = ||u_0||, s_0
-  int nb = adrk::norm2<T>(s, N, L.b, nullptr, nullptr, ctx->part[0]);
-  adrk::reduce_norm(s, ProIn{ctx->part[0], nb, 1}, KB, 0, KS + 0);
+  // beta = ||u_0||, s_0 (the restriction into u_0 left the partials in part[0] and
+  // D^{-1} u_0 in Z, which the first cycle's relaxation consumes as well)
+  adrk::reduce_norm(s, bpin, KB, 0, KS + 0);
   // Z_0 = K(u_0)
-  vcycle<T>(ctx, k, L.b, L.kz);
+  vcycle<T>(ctx, k, L.b, L.kz, bpin);
+  int nb;
   // w = s_0 A Z_0 with the dot against u_0; u_1 = w - H00 s_0 u_0 and its norm
   VecSet<T> V1 = vecset<T>({L.b});
   CoarseArgs<T> a{};
+  a.split = L.split;
   a.G = L.G;
   a.planes = planes;
   a.x = L.kz;
@@ -634,6 +649,10 @@ adr_status validate(const adr_problem *p, const adr_options *o, std::string &err
   if (o->prec != ADR_PREC_FP64 && o->prec != ADR_PREC_MIXED) { err = "bad precision"; return ADR_EINVAL; }
   if (!(o->beta >= 0.0 && o->beta <= 1.0)) { err = "beta must be in [0, 1]"; return ADR_EINVAL; }
   if (o->cycle != ADR_CYCLE_V && o->cycle != ADR_CYCLE_K) { err = "bad cycle"; return ADR_EINVAL; }
+  if (o->coarse_split != 0 && o->coarse_split != 1 && o->coarse_split != 4) {
+    err = "coarse_split must be 0, 1 or 4";
+    return ADR_EINVAL;
+  }
   if (!(o->kcycle_threshold >= 0.0)) { err = "kcycle_threshold must be >= 0"; return ADR_EINVAL; }
   return ADR_OK;
 }
@@ -651,6 +670,75 @@ int auto_levels(int D, const int n[3], int coarsest_max) {
     ++levels;
   }
   return levels;
+}
+
+// Galerkin-apply variant per coarse level (one lane per node, or four wavefronts per
+// 64 nodes): adr_options.coarse_split if set, else the faster of the two in a short
+// timing on this level (mode 0 with one fused dot, as in the GMRES relaxation).  The
+// choice is cached per grid shape and precision for the life of the process, so every
+// context on a given shape launches the same kernels and sums in the same order.
+template <typename T>
+adr_status tune_split(adr_ctx *ctx, int l) {
+  LevelT<T> &L = levels_of<T>(ctx)[l];
+  if (ctx->opt.coarse_split == 1 || ctx->opt.coarse_split == 4) {
+    L.split = ctx->opt.coarse_split;
+    return ADR_OK;
+  }
+  static std::mutex mu;
+  static std::map<std::array<int, 5>, int> cache;
+  const std::array<int, 5> key = {ctx->D, L.G.n[0], L.G.n[1], L.G.n[2], (int)sizeof(T)};
+  {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      L.split = it->second;
+      return ADR_OK;
+    }
+  }
+  hipStream_t s = ctx->stream;
+  const size_t N = L.G.N;
+  ADR_HIP(hipMemsetAsync(L.x, 0, N * sizeof(cx<T>), s));
+  ADR_HIP(hipMemsetAsync(L.r, 0, N * sizeof(cx<T>), s));
+  hipEvent_t e0, e1;
+  ADR_HIP(hipEventCreate(&e0));
+  ADR_HIP(hipEventCreate(&e1));
+  VecSet<T> V1 = vecset<T>({L.r});
+  float best_ms = 0.f;
+  int best = 1;
+  for (int split : {1, 4}) {
+    CoarseArgs<T> a{};
+    a.split = split;
+    a.G = L.G;
+    a.planes = L.planes;
+    a.x = L.x;
+    a.y = L.w;
+    a.mode = 0;
+    a.pout = ctx->part[0];
+    for (int w = 0; w < 2; ++w) adrk::coarse_apply<T>(s, ctx->D, a, &V1, false);
+    hipEventRecord(e0, s);
+    constexpr int reps = 8;
+    for (int r = 0; r < reps; ++r) adrk::coarse_apply<T>(s, ctx->D, a, &V1, false);
+    hipEventRecord(e1, s);
+    hipError_t e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      ctx->err = std::string("split tuning: ") + hipGetErrorString(e);
+      return ADR_EHIP;
+    }
+    if (split == 1 || ms < best_ms) {
+      best_ms = ms;
+      best = split;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  std::lock_guard<std::mutex> g(mu);
+  auto ins = cache.emplace(key, best);
+  L.split = ins.first->second;
+  return ADR_OK;
 }
 
 template <typename T>
@@ -785,6 +873,7 @@ adr_status build_hierarchy(adr_ctx *ctx) {
   ADR_HIP(hipMemcpy(ctx->Ainv, inv.data(), inv.size() * sizeof(cx<double>), hipMemcpyHostToDevice));
   ctx->h_inv.swap(inv);
   for (int l = 0; l < ctx->levels; ++l) ADR_TRY(alloc_level_vectors<T>(ctx, lv[l], l));
+  for (int l = 1; l < ctx->levels - 1; ++l) ADR_TRY(tune_split<T>(ctx, l));
   return ADR_OK;
 }
 

@@ -623,21 +623,71 @@ void zero(hipStream_t s, long long n, cx<double> *x) { ADR_LAUNCH(k_zero, launch
 // =====================================================================================
 // Coarse levels: stored Galerkin stencils (SoA planes)
 // =====================================================================================
+// Sum of the stencil entries p = W, W + SPLIT, W + 2 SPLIT, ... of one node (every entry
+// for SPLIT = 1), in batches of up to 27 loads in flight per lane; `pl` points at the
+// node's entry in plane 0.  Neighbour indices are clamped per axis (the matching stencil
+// entries are exactly zero outside the grid).
+template <typename T, int D, int W, int SPLIT>
+__device__ __forceinline__ cx<T> stencil_part(const cx<T> *__restrict__ pl, int N, const cx<T> *__restrict__ x,
+                                              const int (&X)[5], const int (&Y)[5], const int (&Z)[5]) {
+  constexpr int S = D == 3 ? 81 : 21;
+  constexpr OffTable<D> OT = make_off_table<D>();
+  constexpr int CNT = (S - W + SPLIT - 1) / SPLIT;
+  constexpr int CH = CNT < 27 ? CNT : 27;
+  cx<T> acc[2] = {mk<T>(T(0), T(0)), mk<T>(T(0), T(0))};
+#pragma unroll
+  for (int c = 0; c < CNT; c += CH) {
+    cx<T> pv[CH], xv[CH];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int k = c + q;
+      if (k < CNT) {
+        const int p = W + SPLIT * k;
+        pv[q] = pl[(size_t)p * N];
+        xv[q] = x[X[OT.dx[p] + 2] + Y[OT.dy[p] + 2] + Z[OT.dz[p] + 2]];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < CH; ++q)
+      if (c + q < CNT) acc[q & 1] = cfma(pv[q], xv[q], acc[q & 1]);
+  }
+  return acc[0] + acc[1];
+}
+
+template <typename T, int D, int SPLIT>
+__device__ __forceinline__ cx<T> stencil_part_of(int w, const cx<T> *__restrict__ pl, int N,
+                                                 const cx<T> *__restrict__ x, const int (&X)[5], const int (&Y)[5],
+                                                 const int (&Z)[5]) {
+  // w is uniform across a wavefront, so each wave takes one branch.
+  if constexpr (SPLIT == 1) {
+    return stencil_part<T, D, 0, 1>(pl, N, x, X, Y, Z);
+  } else if constexpr (SPLIT == 2) {
+    return w == 0 ? stencil_part<T, D, 0, 2>(pl, N, x, X, Y, Z) : stencil_part<T, D, 1, 2>(pl, N, x, X, Y, Z);
+  } else {
+    switch (w) {
+      case 0: return stencil_part<T, D, 0, 4>(pl, N, x, X, Y, Z);
+      case 1: return stencil_part<T, D, 1, 4>(pl, N, x, X, Y, Z);
+      case 2: return stencil_part<T, D, 2, 4>(pl, N, x, X, Y, Z);
+      default: return stencil_part<T, D, 3, 4>(pl, N, x, X, Y, Z);
+    }
+  }
+}
+
 // mode 0: y = s * (A x), where s = 1/||.|| of the predecessor's partials (prologue
 //         `pin`, K = 1; block 0 stores the norm in norm_out[0] (and 0 in norm_out[1]
-//         when norm_cplx) and s in inv_out), or s = 1 without a prologue;
+//         when norm_cplx) and s in inv_out), or s = *sdev, or s = 1;
 // mode 1: y = b - A x, and z = dinv o y when zout is given.
-// Neighbour indices are clamped per axis (the matching stencil entries are exactly zero
-// outside the grid).  Partials: NV dots conj(V_v).y, then ||y||^2 if NORM.
-template <typename T, int D, int NV, bool NORM>
+// SPLIT = 1: one lane per node.  SPLIT = 2 or 4: SPLIT wavefronts share 64 nodes, each
+// summing every SPLIT-th stencil entry; the parts are added in LDS in wave order (fewer
+// loads in flight per lane and SPLIT times more blocks, for the small coarse levels).
+// Partials: NV dots conj(V_v).y, then ||y||^2 if NORM.
+template <typename T, int D, int NV, bool NORM, int SPLIT>
 __global__ __launch_bounds__(ADR_BLOCK) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_coarse_apply(Grid G, const cx<T> *__restrict__ planes,
                                                             const cx<T> *__restrict__ x, ProIn pin, const double *sdev,
                                                             double *norm_out, int norm_cplx, double *inv_out,
                                                             const cx<T> *__restrict__ b, cx<T> *__restrict__ y,
                                                             const cx<T> *__restrict__ dinv, cx<T> *__restrict__ zout,
                                                             int mode, VecSet<T> V, double *pout) {
-  constexpr int S = D == 3 ? 81 : 21;
-  constexpr OffTable<D> OT = make_off_table<D>();
   constexpr int K = 2 * NV + (NORM ? 1 : 0);
   constexpr int KA = K > 0 ? K : 1;
   __shared__ double tot[1];
@@ -661,38 +711,18 @@ __global__ __launch_bounds__(ADR_BLOCK) __attribute__((amdgpu_waves_per_eu(1, 4)
   int beg, end;
   chunk_range(G.N, beg, end);
   const int N = G.N, sy = G.n[0], sz = G.n[0] * G.n[1];
-  for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+  auto neighbours = [&](int i, int (&X)[5], int (&Y)[5], int (&Z)[5]) {
     int ix, iy, iz;
     decode(G, i, ix, iy, iz);
-    int X[5], Y[5], Z[5];
 #pragma unroll
     for (int d = -2; d <= 2; ++d) {
       X[d + 2] = min(max(ix + d, 0), G.n[0] - 1);
       Y[d + 2] = sy * min(max(iy + d, 0), G.n[1] - 1);
       Z[d + 2] = (D == 3) ? sz * min(max(iz + d, 0), G.n[2] - 1) : 0;
     }
-    // Batches of CH entries: issue all loads of a batch, then the FMAs, so that many
-    // plane reads and neighbour gathers are in flight per lane.
-    constexpr int CH = (D == 3) ? 27 : 21;
-    cx<T> acc[2] = {mk<T>(T(0), T(0)), mk<T>(T(0), T(0))};
-    const cx<T> *pl = planes + i;
-#pragma unroll
-    for (int c = 0; c < S; c += CH) {
-      cx<T> pv[CH], xv[CH];
-#pragma unroll
-      for (int q = 0; q < CH; ++q) {
-        const int p = c + q;
-        if (p < S) {
-          pv[q] = pl[(size_t)p * N];
-          xv[q] = x[X[OT.dx[p] + 2] + Y[OT.dy[p] + 2] + Z[OT.dz[p] + 2]];
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < CH; ++q)
-        if (c + q < S) acc[q & 1] = cfma(pv[q], xv[q], acc[q & 1]);
-    }
+  };
+  auto finish = [&](int i, const cx<T> &sum) {
     cx<T> o;
-    const cx<T> sum = acc[0] + acc[1];
     if (mode == 0) {
       o = xs * sum;
     } else {
@@ -707,17 +737,48 @@ __global__ __launch_bounds__(ADR_BLOCK) __attribute__((amdgpu_waves_per_eu(1, 4)
       red[2 * v + 1] += d.im;
     }
     if (NORM) red[K - 1] += (double)o.re * o.re + (double)o.im * o.im;
+  };
+  if constexpr (SPLIT == 1) {
+    for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+      int X[5], Y[5], Z[5];
+      neighbours(i, X, Y, Z);
+      finish(i, stencil_part<T, D, 0, 1>(planes + i, N, x, X, Y, Z));
+    }
+  } else {
+    constexpr int GROUPS = ADR_BLOCK / 64 / SPLIT;   // node groups of 64 per block
+    __shared__ cx<T> part[GROUPS][SPLIT - 1][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int grp = wave / SPLIT, sub = wave % SPLIT;
+    // Every wave runs the same trip count, so the barriers are uniform.
+    for (int base = beg; base < end; base += GROUPS * 64) {
+      const int i = base + grp * 64 + lane;
+      const bool act = i < end;
+      cx<T> sum = mk<T>(T(0), T(0));
+      if (act) {
+        int X[5], Y[5], Z[5];
+        neighbours(i, X, Y, Z);
+        sum = stencil_part_of<T, D, SPLIT>(sub, planes + i, N, x, X, Y, Z);
+        if (sub > 0) part[grp][sub - 1][lane] = sum;
+      }
+      __syncthreads();
+      if (act && sub == 0) {
+#pragma unroll
+        for (int w = 1; w < SPLIT; ++w) sum = sum + part[grp][w - 1][lane];
+        finish(i, sum);
+      }
+      __syncthreads();
+    }
   }
   if (K > 0) block_partials<KA>(red, K, pout);
 }
 
-template <typename T, int D, bool NORM>
+template <typename T, int D, bool NORM, int SPLIT>
 static void dispatch_coarse_nv(hipStream_t s, int nb, const CoarseArgs<T> &a, const VecSet<T> &V) {
   switch (V.count) {
-#define ADR_NV_CASE(n)                                                                                      \
-  case n:                                                                                                   \
-    ADR_LAUNCH((k_coarse_apply<T, D, n, NORM>), nb, s, a.G, a.planes, a.x, a.pin, a.sdev, a.norm_out, a.norm_cplx, \
-               a.inv_out, a.b, a.y, a.dinv, a.zout, a.mode, V, a.pout);                                     \
+#define ADR_NV_CASE(n)                                                                                              \
+  case n:                                                                                                           \
+    ADR_LAUNCH((k_coarse_apply<T, D, n, NORM, SPLIT>), nb, s, a.G, a.planes, a.x, a.pin, a.sdev, a.norm_out,        \
+               a.norm_cplx, a.inv_out, a.b, a.y, a.dinv, a.zout, a.mode, V, a.pout);                               \
     break;
     ADR_NV_CASE(0) ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6)
     ADR_NV_CASE(7) ADR_NV_CASE(8)
@@ -726,18 +787,25 @@ static void dispatch_coarse_nv(hipStream_t s, int nb, const CoarseArgs<T> &a, co
   }
 }
 
+template <typename T, int D, bool NORM>
+static void dispatch_coarse_split(hipStream_t s, int nb, const CoarseArgs<T> &a, const VecSet<T> &V) {
+  if (a.split == 4) dispatch_coarse_nv<T, D, NORM, 4>(s, nb, a, V);
+  else dispatch_coarse_nv<T, D, NORM, 1>(s, nb, a, V);
+}
+
 template <typename T>
 int coarse_apply(hipStream_t s, int D, const CoarseArgs<T> &a, const VecSet<T> *dots, bool want_norm) {
   VecSet<T> V{};
   if (dots) V = *dots;
   const bool red = want_norm || V.count > 0;
-  const int nb = red ? launch_blocks_red(a.G.N) : launch_blocks(a.G.N);
+  const long long lanes = (long long)a.G.N * (a.split == 4 ? 4 : 1);
+  const int nb = red ? launch_blocks_red(lanes) : launch_blocks(lanes);
   if (D == 2) {
-    if (want_norm) dispatch_coarse_nv<T, 2, true>(s, nb, a, V);
-    else dispatch_coarse_nv<T, 2, false>(s, nb, a, V);
+    if (want_norm) dispatch_coarse_split<T, 2, true>(s, nb, a, V);
+    else dispatch_coarse_split<T, 2, false>(s, nb, a, V);
   } else {
-    if (want_norm) dispatch_coarse_nv<T, 3, true>(s, nb, a, V);
-    else dispatch_coarse_nv<T, 3, false>(s, nb, a, V);
+    if (want_norm) dispatch_coarse_split<T, 3, true>(s, nb, a, V);
+    else dispatch_coarse_split<T, 3, false>(s, nb, a, V);
   }
   return nb;
 }
@@ -747,9 +815,13 @@ template int coarse_apply<float>(hipStream_t, int, const CoarseArgs<float> &, co
 // =====================================================================================
 // Transfers: r_c = P^T r_f (nodal full weighting x 2^d), x_f += P e_c (bi/trilinear)
 // =====================================================================================
+// With pout: also z_c = dinv_c o r_c and the partials of ||r_c||^2 (the coarse
+// relaxation's first Krylov vector and its norm).
 template <typename T, int D>
 __global__ __launch_bounds__(ADR_BLOCK) void k_restrict(Grid Gf, Grid Gc, const cx<T> *__restrict__ rf,
-                                                        cx<T> *__restrict__ rc) {
+                                                        cx<T> *__restrict__ rc, const cx<T> *__restrict__ dinv_c,
+                                                        cx<T> *__restrict__ z_c, double *pout) {
+  double red[1] = {0.0};
   int beg, end;
   chunk_range(Gc.N, beg, end);
   for (int J = beg + threadIdx.x; J < end; J += blockDim.x) {
@@ -777,17 +849,26 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_restrict(Grid Gf, Grid Gc, const 
       }
     }
     rc[J] = acc;
+    if (pout) {
+      z_c[J] = acc * dinv_c[J];
+      red[0] += (double)acc.re * acc.re + (double)acc.im * acc.im;
+    }
   }
+  if (pout) block_partials<1>(red, 1, pout);
 }
 
 template <typename T>
-void restrict_full(hipStream_t s, const Grid &Gf, const Grid &Gc, int D, const cx<T> *rf, cx<T> *rc) {
-  int nb = launch_blocks(Gc.N);
-  if (D == 2) ADR_LAUNCH((k_restrict<T, 2>), nb, s, Gf, Gc, rf, rc);
-  else ADR_LAUNCH((k_restrict<T, 3>), nb, s, Gf, Gc, rf, rc);
+int restrict_full(hipStream_t s, const Grid &Gf, const Grid &Gc, int D, const cx<T> *rf, cx<T> *rc,
+                  const cx<T> *dinv_c, cx<T> *z_c, double *pout) {
+  int nb = pout ? launch_blocks_red(Gc.N) : launch_blocks(Gc.N);
+  if (D == 2) ADR_LAUNCH((k_restrict<T, 2>), nb, s, Gf, Gc, rf, rc, dinv_c, z_c, pout);
+  else ADR_LAUNCH((k_restrict<T, 3>), nb, s, Gf, Gc, rf, rc, dinv_c, z_c, pout);
+  return nb;
 }
-template void restrict_full<double>(hipStream_t, const Grid &, const Grid &, int, const cx<double> *, cx<double> *);
-template void restrict_full<float>(hipStream_t, const Grid &, const Grid &, int, const cx<float> *, cx<float> *);
+template int restrict_full<double>(hipStream_t, const Grid &, const Grid &, int, const cx<double> *, cx<double> *,
+                                   const cx<double> *, cx<double> *, double *);
+template int restrict_full<float>(hipStream_t, const Grid &, const Grid &, int, const cx<float> *, cx<float> *,
+                                  const cx<float> *, cx<float> *, double *);
 
 template <typename T, int D>
 __global__ __launch_bounds__(ADR_BLOCK) void k_prolong_add(Grid Gf, Grid Gc, const cx<T> *__restrict__ ec,
@@ -951,27 +1032,48 @@ __device__ void gmres_lsq(cx<double> (&R)[K + 1][K], double beta, cx<double> (&y
 // solves the least squares with the Hessenberg H (column-major, leading dimension ldh,
 // complex) and beta; coef_j = y_j s_j goes through shared memory.  Then
 // x_out = x0 + sum_j coef_j Z_j  (Z_j = D^{-1} V_j, so this is x0 + D^{-1} V y).
+// With rout, also the new residual from the Arnoldi relation A Z = V Hbar:
+// b - A x_out = (b - A x0) - V Hbar y = sum_{i <= NV} (beta e_1 - Hbar y)_i s_i V_i, where
+// V_NV is the last (unnormalized) Arnoldi vector, s_NV = 1/H[NV][NV-1].
 template <typename T, int NV>
 __global__ __launch_bounds__(ADR_BLOCK) void k_gmres_update(int N, const cx<T> *__restrict__ x0, VecSet<T> Z,
                                                             ProIn pin, const double *H, int ldh, const double *beta,
-                                                            const double *scales, cx<T> *__restrict__ xout) {
+                                                            const double *scales, cx<T> *__restrict__ xout,
+                                                            VecSet<T> Vr, cx<T> *__restrict__ rout) {
   __shared__ double tot[1];
   __shared__ double cs[2 * NV];
+  __shared__ double rs[2 * (NV + 1)];
   reduce_partials(pin.partials, pin.nb, 1, tot);
   if (threadIdx.x == 0) {
-    cx<double> R[NV + 1][NV];
+    cx<double> R[NV + 1][NV], Hb[NV + 1][NV];
 #pragma unroll
     for (int j = 0; j < NV; ++j)
 #pragma unroll
       for (int i = 0; i <= NV; ++i)
         R[i][j] = (i <= j + 1) ? mk<double>(H[2 * (j * ldh + i)], H[2 * (j * ldh + i) + 1]) : mk<double>(0.0, 0.0);
-    R[NV][NV - 1] = mk<double>(sqrt(tot[0]), 0.0);
+    const double hlast = sqrt(tot[0]);
+    R[NV][NV - 1] = mk<double>(hlast, 0.0);
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+#pragma unroll
+      for (int i = 0; i <= NV; ++i) Hb[i][j] = R[i][j];
     cx<double> y[NV];
     gmres_lsq<NV>(R, *beta, y);
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
       cs[2 * j] = y[j].re * scales[j];
       cs[2 * j + 1] = y[j].im * scales[j];
+    }
+    if (rout) {
+#pragma unroll
+      for (int i = 0; i <= NV; ++i) {
+        cx<double> c = mk<double>(i == 0 ? *beta : 0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < NV; ++j) c = c - Hb[i][j] * y[j];
+        const double si = (i < NV) ? scales[i] : (hlast > 0.0 ? 1.0 / hlast : 0.0);
+        rs[2 * i] = c.re * si;
+        rs[2 * i + 1] = c.im * si;
+      }
     }
   }
   __syncthreads();
@@ -986,14 +1088,28 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_gmres_update(int N, const cx<T> *
     for (int v = 0; v < NV; ++v) acc = cfma(c[v], Z.v[v][i], acc);
     xout[i] = acc;
   }
+  if (rout) {
+    cx<T> cr[NV + 1];
+#pragma unroll
+    for (int v = 0; v <= NV; ++v) cr[v] = mk<T>((T)rs[2 * v], (T)rs[2 * v + 1]);
+    for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+      cx<T> acc = cr[0] * Vr.v[0][i];
+#pragma unroll
+      for (int v = 1; v <= NV; ++v) acc = cfma(cr[v], Vr.v[v][i], acc);
+      rout[i] = acc;
+    }
+  }
 }
 template <typename T>
 void gmres_update(hipStream_t s, int N, const cx<T> *x0, const VecSet<T> &Z, ProIn pin, const double *H, int ldh,
-                  const double *beta, const double *scales, cx<T> *x_out) {
+                  const double *beta, const double *scales, cx<T> *x_out, const VecSet<T> *Vr, cx<T> *r_out) {
   int nb = launch_blocks(N);
+  VecSet<T> V{};
+  if (Vr) V = *Vr;
+  if (r_out && V.count != Z.count + 1) return;
   switch (Z.count) {
 #define ADR_NV_CASE(n) \
-  case n: ADR_LAUNCH((k_gmres_update<T, n>), nb, s, N, x0, Z, pin, H, ldh, beta, scales, x_out); break;
+  case n: ADR_LAUNCH((k_gmres_update<T, n>), nb, s, N, x0, Z, pin, H, ldh, beta, scales, x_out, V, r_out); break;
     ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6) ADR_NV_CASE(7)
     ADR_NV_CASE(8)
 #undef ADR_NV_CASE
@@ -1001,9 +1117,11 @@ void gmres_update(hipStream_t s, int N, const cx<T> *x0, const VecSet<T> &Z, Pro
   }
 }
 template void gmres_update<double>(hipStream_t, int, const cx<double> *, const VecSet<double> &, ProIn,
-                                   const double *, int, const double *, const double *, cx<double> *);
+                                   const double *, int, const double *, const double *, cx<double> *,
+                                   const VecSet<double> *, cx<double> *);
 template void gmres_update<float>(hipStream_t, int, const cx<float> *, const VecSet<float> &, ProIn, const double *,
-                                  int, const double *, const double *, cx<float> *);
+                                  int, const double *, const double *, cx<float> *, const VecSet<float> *,
+                                  cx<float> *);
 
 // =====================================================================================
 // Krylov cycle: flexible GMRES(2) on a coarse level

@@ -37,6 +37,7 @@ struct CoarseArgs {
   cx<T> *zout;
   int mode;
   double *pout;          // partials (when reducing)
+  int split;             // 4: four wavefronts share each node's stencil sum; else one lane
 };
 
 namespace adrk {
@@ -98,8 +99,11 @@ template <typename T>
 int coarse_apply(hipStream_t s, int D, const CoarseArgs<T> &a, const VecSet<T> *dots, bool want_norm);
 
 // ---- transfers ---------------------------------------------------------------------
+// With pout (else NULL): also z_c = dinv_c o r_c and the partials of ||r_c||^2; returns
+// the block count.
 template <typename T>
-void restrict_full(hipStream_t s, const Grid &Gf, const Grid &Gc, int D, const cx<T> *rf, cx<T> *rc);
+int restrict_full(hipStream_t s, const Grid &Gf, const Grid &Gc, int D, const cx<T> *rf, cx<T> *rc,
+                  const cx<T> *dinv_c, cx<T> *z_c, double *pout);
 template <typename T>
 void prolong_add(hipStream_t s, const Grid &Gf, const Grid &Gc, int D, const cx<T> *ec, cx<T> *xf);
 
@@ -114,10 +118,11 @@ int orth_step(hipStream_t s, int N, const cx<T> *w, const VecSet<T> &V, ProIn pi
 template <typename T>
 int norm2(hipStream_t s, int N, const cx<T> *x, const cx<T> *dinv, cx<T> *z, double *pout);
 // Prologue: last subdiagonal from pin, least squares with H/beta, coef_j = y_j scales_j;
-// x_out = x0 + sum_j coef_j Z_j  (x0 may be NULL; x_out may alias x0).
+// x_out = x0 + sum_j coef_j Z_j  (x0 may be NULL; x_out may alias x0).  With r_out (and
+// Vr = the NV + 1 Arnoldi vectors), also r_out = b - A x_out by the Arnoldi relation.
 template <typename T>
 void gmres_update(hipStream_t s, int N, const cx<T> *x0, const VecSet<T> &Z, ProIn pin, const double *H, int ldh,
-                  const double *beta, const double *scales, cx<T> *x_out);
+                  const double *beta, const double *scales, cx<T> *x_out, const VecSet<T> *Vr, cx<T> *r_out);
 
 // One block: tot = sum of the partials (K = 1); norm_out[0] = sqrt(tot) (and
 // norm_out[1] = 0 when norm_cplx), inv_out[0] = 1/sqrt(tot) (0 for a zero norm).

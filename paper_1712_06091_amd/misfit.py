@@ -26,13 +26,15 @@ def point_source(shape, src, h, device):
 
 class ReceiverMisfit(torch.autograd.Function):
     @staticmethod
-    def forward(fctx, kappa2, gamma, taus, sources, h, omega, rec_idx, d_obs, options, tol):
+    def forward(fctx, kappa2, gamma, taus, sources, h, omega, rec_idx, d_obs, options, tol, stats):
         saved = []
         J = 0.0
         for tau, src, d in zip(taus, sources, d_obs):
             c = adr.Context(kappa2.detach(), tau, gamma, h, omega, src, options=options)
             q = point_source(tau.shape, src, h, tau.device)
             a, st = c.solve(q, tol=tol, maxit=1000)
+            if stats is not None:
+                stats.append(("forward", st))
             if st["status"] != adr.ADR_OK:
                 raise adr.AdrError(st["status"], f"forward solve did not converge: {st}")
             u = c.wavefield(a)
@@ -40,6 +42,7 @@ class ReceiverMisfit(torch.autograd.Function):
             J += Js
             saved.append((c, a, r))
         fctx.saved_solves = saved
+        fctx.stats = stats
         fctx.rec_idx = rec_idx
         fctx.tol = tol
         fctx.shape = kappa2.shape
@@ -51,19 +54,22 @@ class ReceiverMisfit(torch.autograd.Function):
         for c, a, r in fctx.saved_solves:
             s = c.adjoint_source(fctx.rec_idx, r)
             lam, st = c.solve_adjoint(s, tol=fctx.tol, maxit=1000)
+            if fctx.stats is not None:
+                fctx.stats.append(("adjoint", st))
             if st["status"] != adr.ADR_OK:
                 raise adr.AdrError(st["status"], f"adjoint solve did not converge: {st}")
             c.grad_kappa2(a, lam, grad)
         for c, _, _ in fctx.saved_solves:
             c.close()
         fctx.saved_solves = []
-        return grad * grad_out, None, None, None, None, None, None, None, None, None
+        return grad * grad_out, None, None, None, None, None, None, None, None, None, None
 
 
-def receiver_misfit(kappa2, gamma, taus, sources, h, omega, rec_idx, d_obs, options=None, tol=1e-8):
+def receiver_misfit(kappa2, gamma, taus, sources, h, omega, rec_idx, d_obs, options=None, tol=1e-8, stats=None):
     """J(kappa^2) = 1/2 sum_s ||R u_s - d_s||^2 with a differentiable kappa^2 (float64 CUDA
     tensor).  taus: list of float64 tensors; sources: list of NumPy-order node tuples;
-    rec_idx: int32 tensor of linear node indices; d_obs: list of complex128 tensors."""
+    rec_idx: int32 tensor of linear node indices; d_obs: list of complex128 tensors.
+    ``stats``, if a list, receives ("forward" | "adjoint", solve stats) per solve."""
     if options is None:
         options = adr.default_options()
-    return ReceiverMisfit.apply(kappa2, gamma, taus, sources, h, omega, rec_idx, d_obs, options, tol)
+    return ReceiverMisfit.apply(kappa2, gamma, taus, sources, h, omega, rec_idx, d_obs, options, tol, stats)

@@ -234,3 +234,55 @@ def batch_2d(count=64, seed=4, sizes=(257, 513, 1025), margin=12, name="batch_2d
         gamma = absorbing_layer((n, n), h, omega, 10 * h)
         shots.append(Workload(f"{name}_{i}", (n, n), h, omega, src, kappa2, tau, gamma, extra={"seed": 1000 * seed + i}))
     return shots
+
+
+def _fm_worker(args):
+    kappa2, h, src = args
+    return factored_traveltime(kappa2, h, src)
+
+
+def factored_traveltimes(kappa2, h, sources, workers=8):
+    """Fast-marching travel times for several sources in a pool of forked CPU processes
+    (each source is independent).  Call it before the process initializes the GPU."""
+    import multiprocessing as mp
+    if workers <= 1 or len(sources) <= 1:
+        return [factored_traveltime(kappa2, h, s) for s in sources]
+    with mp.get_context("fork").Pool(min(workers, len(sources))) as pool:
+        return pool.map(_fm_worker, [(kappa2, h, s) for s in sources])
+
+
+@dataclass
+class AdjointWorkload:
+    name: str
+    shape: Tuple[int, ...]
+    h: float
+    omega: float
+    kappa2: np.ndarray          # model at which the gradient is taken
+    kappa2_true: np.ndarray     # model that produced the observed data
+    gamma: np.ndarray
+    sources: list               # NumPy-order node tuples
+    taus: list                  # travel times in kappa2 (held fixed)
+    receivers: np.ndarray       # int32 linear node indices
+
+
+def adjoint_3d(n=193, seed=5, nsrc_axis=4, nrec_axis=64, pert=0.02, workers=8, name=None):
+    """3D n^3 unit cube, v = 2 (1 + 0.2 eta) km/s (seed), nsrc_axis^2 sources on a regular
+    grid at depth 0.1 km (x, y in {1, ..., nsrc_axis} / (nsrc_axis + 1) km), an
+    nrec_axis^2 receiver plane on the top face (z = 0, evenly spaced in x and y), observed
+    data from kappa2_true = kappa2 (1 + pert * eta2) with eta2 seeded by seed + 1, tau by
+    factored fast marching in kappa2, 10 points per wavelength."""
+    shape = (n,) * 3
+    h = 1.0 / (n - 1)
+    v = smooth_random_velocity(shape, h, seed)
+    kappa2 = 1.0 / v ** 2
+    kappa2_true = kappa2 * (1.0 + pert * smooth_random_field(shape, h, seed + 1))
+    omega = omega_for_ppw(float(v.min()), h)
+    gamma = absorbing_layer(shape, h, omega, 10 * h)
+    fr = [(k + 1) / (nsrc_axis + 1) for k in range(nsrc_axis)]
+    sources = [(int(round(0.1 / h)), int(round(y / h)), int(round(x / h))) for y in fr for x in fr]
+    taus = factored_traveltimes(kappa2, h, sources, workers)
+    line = np.round(np.linspace(0, n - 1, nrec_axis)).astype(np.int64)
+    yy, xx = np.meshgrid(line, line, indexing="ij")
+    receivers = np.ravel_multi_index((np.zeros(yy.size, dtype=np.int64), yy.ravel(), xx.ravel()), shape)
+    return AdjointWorkload(name or f"adjoint_3d_{n}", shape, h, omega, kappa2, kappa2_true, gamma, sources, taus,
+                           receivers.astype(np.int32))

@@ -130,12 +130,13 @@ def test_galerkin_hierarchy(name):
 
 
 @pytest.mark.parametrize("name", ["2d_65_const", "3d_33_lin", "3d_noncubic"])
-def test_vcycle_fp64(name):
+@pytest.mark.parametrize("split", [1, 4])
+def test_vcycle_fp64(name, split):
     """One V-cycle (Jacobi on the finest level, GMRES relaxation below, dense coarsest)
-    equals the oracle's V-cycle up to rounding."""
+    equals the oracle's V-cycle up to rounding, with either Galerkin-apply variant."""
     wl = CASES[name]()
-    print(f"[vcycle-fp64] {name} shape={wl.shape}", flush=True)
-    ctx = _ctx(wl, prec="fp64")
+    print(f"[vcycle-fp64] {name} shape={wl.shape} split={split}", flush=True)
+    ctx = _ctx(wl, prec="fp64", coarse_split=split)
     p = osolve.Problem(wl.kappa2, wl.tau, wl.gamma, wl.h, wl.omega, wl.src)
     hier = p.hierarchy(ctx.num_levels)
     r = W.random_vector(wl.shape, 13)
@@ -145,11 +146,12 @@ def test_vcycle_fp64(name):
 
 
 @pytest.mark.parametrize("name", ["2d_65_const", "3d_33_lin"])
-def test_vcycle_mixed_close(name):
+@pytest.mark.parametrize("split", [1, 4])
+def test_vcycle_mixed_close(name, split):
     """The complex-FP32 V-cycle stays within FP32 rounding of the FP64 one."""
     wl = CASES[name]()
-    print(f"[vcycle-mixed] {name} shape={wl.shape}", flush=True)
-    ctx = _ctx(wl, prec="mixed")
+    print(f"[vcycle-mixed] {name} shape={wl.shape} split={split}", flush=True)
+    ctx = _ctx(wl, prec="mixed", coarse_split=split)
     p = osolve.Problem(wl.kappa2, wl.tau, wl.gamma, wl.h, wl.omega, wl.src)
     hier = p.hierarchy(ctx.num_levels)
     r = W.random_vector(wl.shape, 14)
@@ -246,3 +248,20 @@ def test_full_size_3d_129_bench_configuration():
     rel = np.linalg.norm(qh - H @ a) / np.linalg.norm(qh)
     assert rel <= 1e-6 * (1 + 1e-6), rel
     assert abs(rel - st["relres"]) <= 1e-9
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_split_variants_agree_on_solve(prec):
+    """The two Galerkin-apply variants only reorder the stencil sums: whole solves agree to
+    rounding, and the autotuned default picks one of them."""
+    wl = W.linear_gradient(65, 3)
+    print(f"[split-solve] shape={wl.shape} prec={prec}", flush=True)
+    out = {}
+    for split in (1, 4, 0):
+        ctx = _ctx(wl, prec=prec, coarse_split=split)
+        a, st = ctx.solve(_t(wl.rhs()), tol=1e-10, maxit=300)
+        assert st["relres"] <= 1e-10
+        out[split] = a.cpu().numpy()
+        ctx.close()
+    assert _rel(out[4], out[1]) <= 1e-9
+    assert _rel(out[0], out[1]) <= 1e-9
