@@ -37,8 +37,11 @@ def parse():
     ap.add_argument("--adjoint-n", type=int, default=193, help="grid size of the adjoint workload")
     ap.add_argument("--fm-workers", type=int, default=8, help="CPU processes for fast marching")
     ap.add_argument("--streams", type=int, default=4, help="streams of the batched-shot solve")
+    ap.add_argument("--hw-queues", type=int, default=0,
+                    help="GPU_MAX_HW_QUEUES for this process (set before the GPU is initialized; <= 32)")
     ap.add_argument("--cycle", default="v", choices=["v", "k"], help="V-cycle or Krylov cycle preconditioner")
     ap.add_argument("--batch-maxit", type=int, default=3000, help="FGMRES iteration cap per shot (batch)")
+    ap.add_argument("--no-looped", action="store_true", help="batch: skip the one-shot-at-a-time comparison")
     ap.add_argument("--mixed-only", action="store_true", help="with --profile-only: skip the FP64 solves")
     ap.add_argument("--no-graph", action="store_true", help="launch the cycles eagerly (no hipGraph)")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MIB",
@@ -222,6 +225,29 @@ def run_adjoint(args):
     print(json.dumps(out))
 
 
+def looped_batch(shots, qs, outs, opts, maxit):
+    """The same shots one after another through adr_solve on the default stream."""
+    import torch
+
+    from paper_1712_06091_amd import adr
+    ctxs = [adr.Context(s["kappa2"], s["tau"], s["gamma"], s["h"], s["omega"], s["src"], options=opts)
+            for s in shots]
+    for c, q, a in zip(ctxs, qs, outs):
+        c.solve(q, tol=TOL, maxit=maxit, out=a)
+    torch.cuda.synchronize()
+    log("looped warm-up done")
+    t0 = time.perf_counter()
+    iters = 0
+    for c, q, a in zip(ctxs, qs, outs):
+        _, s1 = c.solve(q, tol=TOL, maxit=maxit, out=a)
+        iters += s1["outer_iters"]
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    for c in ctxs:
+        c.close()
+    return ms, iters
+
+
 def run_batch(args):
     """64 2D shots (sizes from {257^2, 513^2, 1025^2}, random media, fast-marching tau):
     one lockstep batched solve over several streams vs. the same shots solved one after
@@ -264,24 +290,13 @@ def run_batch(args):
     ms_batch = (time.perf_counter() - t0) * 1e3 / args.steps
     its = sorted(s["outer_iters"] for s in stats)
     log(f"batched: {ms_batch:.1f} ms per batch; iterations min {its[0]} median {its[len(its) // 2]} max {its[-1]}")
-    # The same shots one after another through adr_solve on the default stream.
-    ctxs = [adr.Context(s["kappa2"], s["tau"], s["gamma"], s["h"], s["omega"], s["src"], options=opts)
-            for s in shots]
-    for c, q, a in zip(ctxs, qs, outs):
-        c.solve(q, tol=TOL, maxit=maxit, out=a)
-    torch.cuda.synchronize()
-    log("looped warm-up done")
-    t0 = time.perf_counter()
-    iters_loop = 0
-    for c, q, a in zip(ctxs, qs, outs):
-        _, s1 = c.solve(q, tol=TOL, maxit=maxit, out=a)
-        iters_loop += s1["outer_iters"]
-    torch.cuda.synchronize()
-    ms_loop = (time.perf_counter() - t0) * 1e3
-    for c in ctxs:
-        c.close()
     b.close()
+    if args.no_looped:
+        ms_loop, iters_loop = float("nan"), 0
+    else:
+        ms_loop, iters_loop = looped_batch(shots, qs, outs, opts, maxit)
     value = nodes / (ms_batch * 1e-3) / 1e6
+
     out = {
         "metric": "ADR amplitude solves: Mpoints/s to 1e-6 residual (batched shots)",
         "value": value, "unit": "Mpoints/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -289,9 +304,11 @@ def run_batch(args):
         "dtype": "c64 V-cycle / c128 FGMRES", "data": "synthetic",
         "config": {"workload": "batch_2d_64_shots", "shots": len(wls), "nodes": nodes,
                    "sizes": sorted({w.shape[0] for w in wls}), "streams": args.streams, "tol": TOL,
-                   "cycle": args.cycle, "maxit": maxit},
-        "looped": {"value": nodes / (ms_loop * 1e-3) / 1e6, "ms": ms_loop, "outer_iters": iters_loop},
-        "batched_over_looped": ms_loop / ms_batch,
+                   "cycle": args.cycle, "maxit": maxit,
+                   "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "0")) or None},
+        "looped": None if args.no_looped else {"value": nodes / (ms_loop * 1e-3) / 1e6, "ms": ms_loop,
+                                               "outer_iters": iters_loop},
+        "batched_over_looped": None if args.no_looped else ms_loop / ms_batch,
         "outer_iters": sum(its),
         "outer_iters_per_shot": {"min": its[0], "median": its[len(its) // 2], "max": its[-1]},
         "setup_s": setup_s,
@@ -301,6 +318,11 @@ def run_batch(args):
 
 def main():
     args = parse()
+    if args.hw_queues:
+        if not 1 <= args.hw_queues <= 32:
+            print("--hw-queues must be in [1, 32]", file=sys.stderr)
+            sys.exit(2)
+        os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
     if args.cpu_sample_child:
         cpu_sample_child(args)
         return

@@ -100,6 +100,10 @@ typedef struct {
                         /* node, 4 = four wavefronts per 64 nodes, 0 (default) = the     */
                         /* faster of the two per level, timed at setup and cached per    */
                         /* grid shape and precision for the process                      */
+  int tail_max_nodes;   /* V-cycle: coarse levels from the first one with at most this   */
+                        /* many nodes down to the coarsest in one single-workgroup       */
+                        /* kernel.  Disabled: must be 0 (the default); any other value   */
+                        /* makes adr_setup return ADR_ENOTSUP                            */
 } adr_options;
 
 typedef struct {
@@ -219,7 +223,8 @@ typedef enum {
   ADR_TIMER_COARSE_ORTH = 3,    /* GMRES-relaxation orthogonalization step               */
   ADR_TIMER_TRANSFER = 4,       /* restriction and prolongation                           */
   ADR_TIMER_OUTER_MATVEC = 5,   /* FP64 H_2up apply with fused Arnoldi dots (FGMRES)      */
-  ADR_TIMER_OUTER_ORTH = 6      /* FP64 Gram-Schmidt passes of the outer FGMRES           */
+  ADR_TIMER_OUTER_ORTH = 6,     /* FP64 Gram-Schmidt passes of the outer FGMRES           */
+  ADR_TIMER_COARSE_TAIL = 7     /* single-workgroup coarse tail of the V-cycle            */
 } adr_timer_kind;
 
 /* Benchmark instrumentation.  adr_timer_start(ctx, kind, level) makes every later launch

@@ -19,7 +19,7 @@ ADR_PREC_FP64, ADR_PREC_MIXED = 0, 1
 ADR_RELAX_JACOBI, ADR_RELAX_GMRES = 0, 1
 ADR_CYCLE_V, ADR_CYCLE_K = 0, 1
 TIMER_KINDS = {"fine_jacobi": 0, "fine_residual": 1, "coarse_apply": 2, "coarse_orth": 3, "transfer": 4,
-               "outer_matvec": 5, "outer_orth": 6}
+               "outer_matvec": 5, "outer_orth": 6, "coarse_tail": 7}
 
 
 class AdrProblem(ctypes.Structure):
@@ -49,6 +49,7 @@ class AdrOptions(ctypes.Structure):
         ("cycle", ctypes.c_int),
         ("kcycle_threshold", ctypes.c_double),
         ("coarse_split", ctypes.c_int),
+        ("tail_max_nodes", ctypes.c_int),
     ]
 
 

@@ -19,6 +19,9 @@ HIPCC_FLAGS = [
     # parts); hipcc's host pass warns that it does not know the feature.
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
+    # A variable-length array in device code becomes a dynamic stack allocation outside
+    # the private segment sized at compile time: reject it.
+    "-Werror=vla-cxx-extension",
 ]
 
 

@@ -17,6 +17,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/adr.h"
@@ -112,6 +113,11 @@ struct adr_ctx {
   void *Zo = nullptr;          // kMaxRestart x N, c64 (mixed) or c128
   cx<double> *wo = nullptr, *ro = nullptr, *qh = nullptr;
   cx<float> *b32 = nullptr, *z32 = nullptr;   // mixed-mode V-cycle in/out staging
+
+  // Coarse tail: levels tail_level.. run in one single-workgroup kernel (-1: none); device
+  // copies of its level table for the forward [0] and adjoint [1] hierarchies.
+  int tail_level = -1;
+  void *tail_args[2] = {nullptr, nullptr};
 
   // Captured V-cycles (Alg. TwoCycle applied recursively; no host synchronization
   // inside), keyed by their input/output buffers, replayed on `stream`.  Captured on a
@@ -499,6 +505,13 @@ cx<T> *vcycle(adr_ctx *ctx, int l, const cx<T> *b, cx<T> *out0, ProIn bpin = Pro
     adrk::dense_gemv<T>(s, L.G.N, ctx->adj ? ctx->Ainv_adj : ctx->Ainv, b, x);
     return x;
   }
+  if (l == ctx->tail_level && b == L.b && (!out0 || out0 == L.x)) {
+    // The rest of the cycle in one workgroup (levels l.. and the coarsest solve).
+    int t0 = tbegin(ctx, ADR_TIMER_COARSE_TAIL, l);
+    adrk::coarse_tail<T>(s, D, (const TailArgs<T> *)ctx->tail_args[ctx->adj ? 1 : 0]);
+    tend(ctx, t0, 0.0);
+    return L.x;
+  }
   cx<T> *xa = out0 ? out0 : L.x;
   cx<T> *x;
   // Pre-relaxation.  Level 0 relaxes by damped Jacobi (the first sweep writes the
@@ -526,7 +539,7 @@ cx<T> *vcycle(adr_ctx *ctx, int l, const cx<T> *b, cx<T> *out0, ProIn bpin = Pro
   }
   // The coarse level (unless it is the coarsest) starts with a GMRES relaxation from
   // zero: the restriction also writes its D^{-1} b and the partials of ||b||^2.
-  const bool coarse_relaxes = l + 1 < ctx->levels - 1;
+  const bool coarse_relaxes = l + 1 < ctx->levels - 1 && l + 1 != ctx->tail_level;
   int t1 = tbegin(ctx, ADR_TIMER_TRANSFER, l);
   int rnb = adrk::restrict_full<T>(s, L.G, C.G, D, L.r, C.b, coarse_relaxes ? lvl_dinv(ctx, C) : nullptr,
                                    coarse_relaxes ? C.Z : nullptr, coarse_relaxes ? ctx->part[0] : nullptr);
@@ -649,6 +662,16 @@ adr_status validate(const adr_problem *p, const adr_options *o, std::string &err
   if (o->prec != ADR_PREC_FP64 && o->prec != ADR_PREC_MIXED) { err = "bad precision"; return ADR_EINVAL; }
   if (!(o->beta >= 0.0 && o->beta <= 1.0)) { err = "beta must be in [0, 1]"; return ADR_EINVAL; }
   if (o->cycle != ADR_CYCLE_V && o->cycle != ADR_CYCLE_K) { err = "bad cycle"; return ADR_EINVAL; }
+  if (o->tail_max_nodes < 0) {
+    err = "tail_max_nodes must be >= 0";
+    return ADR_EINVAL;
+  }
+  if (o->tail_max_nodes > 0) {
+    // Switched off: its one GPU run with five 2D levels (tail on levels 1-3) ended in a
+    // memory aperture violation whose cause has not been found.
+    err = "the single-workgroup coarse tail is disabled (tail_max_nodes must be 0)";
+    return ADR_ENOTSUP;
+  }
   if (o->coarse_split != 0 && o->coarse_split != 1 && o->coarse_split != 4) {
     err = "coarse_split must be 0, 1 or 4";
     return ADR_EINVAL;
@@ -738,6 +761,34 @@ adr_status tune_split(adr_ctx *ctx, int l) {
   std::lock_guard<std::mutex> g(mu);
   auto ins = cache.emplace(key, best);
   L.split = ins.first->second;
+  return ADR_OK;
+}
+
+// Level table of the coarse tail for the current direction (forward or adjoint), copied
+// to the device.
+template <typename T>
+adr_status build_tail_args(adr_ctx *ctx, int dir) {
+  if (ctx->tail_level < 0) return ADR_OK;
+  LevelT<T> *lv = levels_of<T>(ctx);
+  TailArgs<T> A{};
+  A.first = ctx->tail_level;
+  A.last = ctx->levels - 1;
+  for (int l = A.first; l <= A.last; ++l) {
+    TailLevel<T> &t = A.L[l];
+    t.G = lv[l].G;
+    t.planes = dir ? lv[l].planes_adj : lv[l].planes;
+    t.dinv = dir ? lv[l].dinv_adj : lv[l].dinv;
+    t.x = lv[l].x;
+    t.b = lv[l].b;
+    t.r = lv[l].r;
+    t.w = lv[l].w;
+    t.V = lv[l].V;
+    t.Z = lv[l].Z;
+    t.nu = ctx->nu[l];
+  }
+  A.Ainv = dir ? ctx->Ainv_adj : ctx->Ainv;
+  if (!ctx->tail_args[dir]) ADR_TRY(dalloc(ctx, (TailArgs<T> **)&ctx->tail_args[dir], 1));
+  ADR_HIP(hipMemcpy(ctx->tail_args[dir], &A, sizeof(A), hipMemcpyHostToDevice));
   return ADR_OK;
 }
 
@@ -874,6 +925,16 @@ adr_status build_hierarchy(adr_ctx *ctx) {
   ctx->h_inv.swap(inv);
   for (int l = 0; l < ctx->levels; ++l) ADR_TRY(alloc_level_vectors<T>(ctx, lv[l], l));
   for (int l = 1; l < ctx->levels - 1; ++l) ADR_TRY(tune_split<T>(ctx, l));
+  // Coarse tail: from the first coarse level with at most tail_max_nodes nodes (V-cycle;
+  // the Krylov cycle's coarse GMRES steps stay on the multi-kernel path).
+  ctx->tail_level = -1;
+  if (ctx->opt.cycle == ADR_CYCLE_V && ctx->opt.tail_max_nodes > 0)
+    for (int l = 1; l < ctx->levels - 1; ++l)
+      if (lv[l].G.N <= ctx->opt.tail_max_nodes) {
+        ctx->tail_level = l;
+        break;
+      }
+  ADR_TRY(build_tail_args<T>(ctx, 0));
   return ADR_OK;
 }
 
@@ -918,6 +979,8 @@ void free_ctx(adr_ctx *ctx) {
   F(ctx->qh);
   F(ctx->b32);
   F(ctx->z32);
+  F(ctx->tail_args[0]);
+  F(ctx->tail_args[1]);
   for (auto &e : ctx->timer.ev) hipEventDestroy(e);
   for (auto &g : ctx->graphs) {
     hipGraphExecDestroy(g.e);
@@ -1073,6 +1136,7 @@ void adr_default_options(adr_options *o) {
   o->use_graph = 1;
   o->cycle = ADR_CYCLE_V;
   o->kcycle_threshold = 0.1;
+  o->tail_max_nodes = 0;
 }
 
 adr_status adr_setup(const adr_problem *prob, const adr_options *opt, void *stream, adr_ctx **out) {
@@ -1226,6 +1290,8 @@ adr_status prepare_adjoint(adr_ctx *ctx) {
                          ctx->stream));
   ADR_HIP(hipStreamSynchronize(ctx->stream));
   ADR_HIP(hipGetLastError());
+  if (ctx->opt.prec == ADR_PREC_MIXED) ADR_TRY(build_tail_args<float>(ctx, 1));
+  else ADR_TRY(build_tail_args<double>(ctx, 1));
   ctx->adj_ready = true;
   return ADR_OK;
 }
@@ -1545,19 +1611,27 @@ adr_status adr_adjoint_source(adr_ctx *ctx, const int *idx, const void *r, int n
 }
 
 // ---------------------------------------------------------------------------------------
-// Batched shots: many independent problems solved in lockstep.  Each shot has its own
-// context; the contexts are spread over `nstreams` streams (shots on one stream run one
-// after another, shots on different streams overlap on the GPU).  Every round enqueues
-// the next FGMRES action of every unconverged shot, synchronizes the streams once, and
-// consumes all read-backs; converged shots drop out.
+// Batched shots: many independent problems.  Each shot has its own context; the contexts
+// are spread over `nstreams` streams (shots on one stream run one after another, shots
+// on different streams overlap on the GPU).  The host advances every shot on its own:
+// after enqueuing a shot's next FGMRES action it records an event, and whichever shot's
+// event has completed is finished (its read-back consumed) and re-enqueued, with no
+// barrier across shots; converged shots drop out.
 // ---------------------------------------------------------------------------------------
 }  // extern "C"
 
 struct adr_batch {
   std::vector<adr_ctx *> ctx;
   std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> events;   // one per shot: end of its last enqueued action
   std::string err;
 };
+
+#define ADR_BATCH_TRY(expr)         \
+  do {                              \
+    adr_status st_ = (expr);        \
+    if (st_ != ADR_OK) return st_;  \
+  } while (0)
 
 extern "C" {
 
@@ -1607,31 +1681,54 @@ adr_status adr_solve_batch(adr_batch *b, const void *const *q, void *const *a, d
   for (int i = 0; i < n; ++i)
     if (!q[i] || !a[i]) return ADR_EINVAL;
   std::vector<Solver> S(n);
+  if (b->events.size() < (size_t)n) {
+    for (size_t i = b->events.size(); i < (size_t)n; ++i) {
+      hipEvent_t e;
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        b->err = "hipEventCreate failed";
+        return ADR_EHIP;
+      }
+      b->events.push_back(e);
+    }
+  }
+  // Enqueue one action of shot i and mark its end; false on error.
+  auto launch = [&](int i) -> adr_status {
+    adr_status st = solver_enqueue(S[i]);
+    if (st != ADR_OK) {
+      b->err = "shot " + std::to_string(i) + ": " + b->ctx[i]->err;
+      return st;
+    }
+    if (hipEventRecord(b->events[i], b->ctx[i]->stream) != hipSuccess) {
+      b->err = "hipEventRecord failed";
+      return ADR_EHIP;
+    }
+    return ADR_OK;
+  };
+  int active = 0;
   for (int i = 0; i < n; ++i) {
     b->ctx[i]->adj = false;
     solver_init(S[i], b->ctx[i], q[i], a[i], tol, maxit, 0);
+    if (S[i].next != Solver::DONE) {
+      ADR_BATCH_TRY(launch(i));
+      ++active;
+    }
   }
-  int active = n;
   while (active > 0) {
-    for (int i = 0; i < n; ++i)
-      if (S[i].next != Solver::DONE) {
-        adr_status st = solver_enqueue(S[i]);
-        if (st != ADR_OK) {
-          b->err = "shot " + std::to_string(i) + ": " + b->ctx[i]->err;
-          return st;
-        }
-      }
-    for (hipStream_t s : b->streams)
-      if (hipStreamSynchronize(s) != hipSuccess) {
-        b->err = "stream synchronization failed";
+    bool progressed = false;
+    for (int i = 0; i < n; ++i) {
+      if (S[i].next == Solver::DONE) continue;
+      hipError_t e = hipEventQuery(b->events[i]);
+      if (e == hipErrorNotReady) continue;
+      if (e != hipSuccess) {
+        b->err = std::string("shot ") + std::to_string(i) + ": " + hipGetErrorString(e);
         return ADR_EHIP;
       }
-    active = 0;
-    for (int i = 0; i < n; ++i)
-      if (S[i].next != Solver::DONE) {
-        solver_finish(S[i]);
-        if (S[i].next != Solver::DONE) ++active;
-      }
+      progressed = true;
+      solver_finish(S[i]);
+      if (S[i].next == Solver::DONE) --active;
+      else ADR_BATCH_TRY(launch(i));
+    }
+    if (!progressed) std::this_thread::yield();
   }
   adr_status worst = ADR_OK;
   for (int i = 0; i < n; ++i) {
@@ -1644,12 +1741,13 @@ adr_status adr_solve_batch(adr_batch *b, const void *const *q, void *const *a, d
 void adr_destroy_batch(adr_batch *b) {
   if (!b) return;
   for (adr_ctx *c : b->ctx) adr_destroy(c);
+  for (hipEvent_t e : b->events) hipEventDestroy(e);
   for (hipStream_t s : b->streams) hipStreamDestroy(s);
   delete b;
 }
 
 adr_status adr_timer_start(adr_ctx *ctx, int kind, int level) {
-  if (!ctx || kind < 0 || kind > ADR_TIMER_OUTER_ORTH) return ADR_EINVAL;
+  if (!ctx || kind < 0 || kind > ADR_TIMER_COARSE_TAIL) return ADR_EINVAL;
   auto &T = ctx->timer;
   if (T.ev.empty()) {
     T.ev.resize(2 * 8192);

@@ -623,17 +623,32 @@ void zero(hipStream_t s, long long n, cx<double> *x) { ADR_LAUNCH(k_zero, launch
 // =====================================================================================
 // Coarse levels: stored Galerkin stencils (SoA planes)
 // =====================================================================================
+// Clamped neighbour index tables of node i along each axis (offsets -2..2), as linear
+// index contributions.
+template <int D>
+__device__ __forceinline__ void coarse_neighbours(const Grid &G, int i, int (&X)[5], int (&Y)[5], int (&Z)[5]) {
+  int ix, iy, iz;
+  decode(G, i, ix, iy, iz);
+  const int sy = G.n[0], sz = G.n[0] * G.n[1];
+#pragma unroll
+  for (int d = -2; d <= 2; ++d) {
+    X[d + 2] = min(max(ix + d, 0), G.n[0] - 1);
+    Y[d + 2] = sy * min(max(iy + d, 0), G.n[1] - 1);
+    Z[d + 2] = (D == 3) ? sz * min(max(iz + d, 0), G.n[2] - 1) : 0;
+  }
+}
+
 // Sum of the stencil entries p = W, W + SPLIT, W + 2 SPLIT, ... of one node (every entry
-// for SPLIT = 1), in batches of up to 27 loads in flight per lane; `pl` points at the
+// for SPLIT = 1), in batches of up to CHMAX loads in flight per lane; `pl` points at the
 // node's entry in plane 0.  Neighbour indices are clamped per axis (the matching stencil
 // entries are exactly zero outside the grid).
-template <typename T, int D, int W, int SPLIT>
+template <typename T, int D, int W, int SPLIT, int CHMAX = 27>
 __device__ __forceinline__ cx<T> stencil_part(const cx<T> *__restrict__ pl, int N, const cx<T> *__restrict__ x,
                                               const int (&X)[5], const int (&Y)[5], const int (&Z)[5]) {
   constexpr int S = D == 3 ? 81 : 21;
   constexpr OffTable<D> OT = make_off_table<D>();
   constexpr int CNT = (S - W + SPLIT - 1) / SPLIT;
-  constexpr int CH = CNT < 27 ? CNT : 27;
+  constexpr int CH = CNT < CHMAX ? CNT : CHMAX;
   cx<T> acc[2] = {mk<T>(T(0), T(0)), mk<T>(T(0), T(0))};
 #pragma unroll
   for (int c = 0; c < CNT; c += CH) {
@@ -710,17 +725,8 @@ __global__ __launch_bounds__(ADR_BLOCK) __attribute__((amdgpu_waves_per_eu(1, 4)
   for (int k = 0; k < KA; ++k) red[k] = 0.0;
   int beg, end;
   chunk_range(G.N, beg, end);
-  const int N = G.N, sy = G.n[0], sz = G.n[0] * G.n[1];
-  auto neighbours = [&](int i, int (&X)[5], int (&Y)[5], int (&Z)[5]) {
-    int ix, iy, iz;
-    decode(G, i, ix, iy, iz);
-#pragma unroll
-    for (int d = -2; d <= 2; ++d) {
-      X[d + 2] = min(max(ix + d, 0), G.n[0] - 1);
-      Y[d + 2] = sy * min(max(iy + d, 0), G.n[1] - 1);
-      Z[d + 2] = (D == 3) ? sz * min(max(iz + d, 0), G.n[2] - 1) : 0;
-    }
-  };
+  const int N = G.N;
+  auto neighbours = [&](int i, int (&X)[5], int (&Y)[5], int (&Z)[5]) { coarse_neighbours<D>(G, i, X, Y, Z); };
   auto finish = [&](int i, const cx<T> &sum) {
     cx<T> o;
     if (mode == 0) {
@@ -818,6 +824,34 @@ template int coarse_apply<float>(hipStream_t, int, const CoarseArgs<float> &, co
 // With pout: also z_c = dinv_c o r_c and the partials of ||r_c||^2 (the coarse
 // relaxation's first Krylov vector and its norm).
 template <typename T, int D>
+__device__ __forceinline__ cx<T> restrict_value(const Grid &Gf, const Grid &Gc, const cx<T> *__restrict__ rf, int J) {
+  int jx, jy, jz;
+  decode(Gc, J, jx, jy, jz);
+  const int fx = 2 * jx, fy = 2 * jy, fz = 2 * jz;
+  cx<T> acc = mk<T>(T(0), T(0));
+  const int zlo = (D == 3) ? -1 : 0, zhi = (D == 3) ? 1 : 0;
+  for (int pz = zlo; pz <= zhi; ++pz) {
+    const int z = fz + pz;
+    if (z < 0 || z >= Gf.n[2]) continue;
+    const T wz = pz == 0 ? T(1) : T(0.5);
+    for (int py = -1; py <= 1; ++py) {
+      const int y = fy + py;
+      if (y < 0 || y >= Gf.n[1]) continue;
+      const T wy = wz * (py == 0 ? T(1) : T(0.5));
+      for (int px = -1; px <= 1; ++px) {
+        const int x = fx + px;
+        if (x < 0 || x >= Gf.n[0]) continue;
+        const T w = wy * (px == 0 ? T(1) : T(0.5));
+        const cx<T> v = rf[x + Gf.n[0] * (y + Gf.n[1] * z)];
+        acc.re += w * v.re;
+        acc.im += w * v.im;
+      }
+    }
+  }
+  return acc;
+}
+
+template <typename T, int D>
 __global__ __launch_bounds__(ADR_BLOCK) void k_restrict(Grid Gf, Grid Gc, const cx<T> *__restrict__ rf,
                                                         cx<T> *__restrict__ rc, const cx<T> *__restrict__ dinv_c,
                                                         cx<T> *__restrict__ z_c, double *pout) {
@@ -825,29 +859,7 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_restrict(Grid Gf, Grid Gc, const 
   int beg, end;
   chunk_range(Gc.N, beg, end);
   for (int J = beg + threadIdx.x; J < end; J += blockDim.x) {
-    int jx, jy, jz;
-    decode(Gc, J, jx, jy, jz);
-    const int fx = 2 * jx, fy = 2 * jy, fz = 2 * jz;
-    cx<T> acc = mk<T>(T(0), T(0));
-    const int zlo = (D == 3) ? -1 : 0, zhi = (D == 3) ? 1 : 0;
-    for (int pz = zlo; pz <= zhi; ++pz) {
-      const int z = fz + pz;
-      if (z < 0 || z >= Gf.n[2]) continue;
-      const T wz = pz == 0 ? T(1) : T(0.5);
-      for (int py = -1; py <= 1; ++py) {
-        const int y = fy + py;
-        if (y < 0 || y >= Gf.n[1]) continue;
-        const T wy = wz * (py == 0 ? T(1) : T(0.5));
-        for (int px = -1; px <= 1; ++px) {
-          const int x = fx + px;
-          if (x < 0 || x >= Gf.n[0]) continue;
-          const T w = wy * (px == 0 ? T(1) : T(0.5));
-          const cx<T> v = rf[x + Gf.n[0] * (y + Gf.n[1] * z)];
-          acc.re += w * v.re;
-          acc.im += w * v.im;
-        }
-      }
-    }
+    const cx<T> acc = restrict_value<T, D>(Gf, Gc, rf, J);
     rc[J] = acc;
     if (pout) {
       z_c[J] = acc * dinv_c[J];
@@ -871,27 +883,30 @@ template int restrict_full<float>(hipStream_t, const Grid &, const Grid &, int, 
                                   const cx<float> *, cx<float> *, double *);
 
 template <typename T, int D>
+__device__ __forceinline__ cx<T> prolong_value(const Grid &Gf, const Grid &Gc, const cx<T> *__restrict__ ec, int f) {
+  int fx, fy, fz;
+  decode(Gf, f, fx, fy, fz);
+  const int x0 = fx >> 1, y0 = fy >> 1, z0 = fz >> 1;
+  const int nxs = (fx & 1) ? 2 : 1, nys = (fy & 1) ? 2 : 1, nzs = (D == 3 && (fz & 1)) ? 2 : 1;
+  const T wx = (fx & 1) ? T(0.5) : T(1), wy = (fy & 1) ? T(0.5) : T(1), wz = (D == 3 && (fz & 1)) ? T(0.5) : T(1);
+  cx<T> acc = mk<T>(T(0), T(0));
+  for (int cz = 0; cz < nzs; ++cz)
+    for (int cy = 0; cy < nys; ++cy)
+      for (int cxx = 0; cxx < nxs; ++cxx) {
+        const cx<T> v = ec[(x0 + cxx) + Gc.n[0] * ((y0 + cy) + Gc.n[1] * (z0 + cz))];
+        const T w = wx * wy * wz;
+        acc.re += w * v.re;
+        acc.im += w * v.im;
+      }
+  return acc;
+}
+
+template <typename T, int D>
 __global__ __launch_bounds__(ADR_BLOCK) void k_prolong_add(Grid Gf, Grid Gc, const cx<T> *__restrict__ ec,
                                                            cx<T> *__restrict__ xf) {
   int beg, end;
   chunk_range(Gf.N, beg, end);
-  for (int f = beg + threadIdx.x; f < end; f += blockDim.x) {
-    int fx, fy, fz;
-    decode(Gf, f, fx, fy, fz);
-    const int x0 = fx >> 1, y0 = fy >> 1, z0 = fz >> 1;
-    const int nxs = (fx & 1) ? 2 : 1, nys = (fy & 1) ? 2 : 1, nzs = (D == 3 && (fz & 1)) ? 2 : 1;
-    const T wx = (fx & 1) ? T(0.5) : T(1), wy = (fy & 1) ? T(0.5) : T(1), wz = (D == 3 && (fz & 1)) ? T(0.5) : T(1);
-    cx<T> acc = mk<T>(T(0), T(0));
-    for (int cz = 0; cz < nzs; ++cz)
-      for (int cy = 0; cy < nys; ++cy)
-        for (int cxx = 0; cxx < nxs; ++cxx) {
-          const cx<T> v = ec[(x0 + cxx) + Gc.n[0] * ((y0 + cy) + Gc.n[1] * (z0 + cz))];
-          const T w = wx * wy * wz;
-          acc.re += w * v.re;
-          acc.im += w * v.im;
-        }
-    xf[f] = xf[f] + acc;
-  }
+  for (int f = beg + threadIdx.x; f < end; f += blockDim.x) xf[f] = xf[f] + prolong_value<T, D>(Gf, Gc, ec, f);
 }
 
 template <typename T>
@@ -1375,5 +1390,278 @@ void dense_gemv(hipStream_t s, int N, const cx<double> *Ainv, const cx<T> *b, cx
 }
 template void dense_gemv<double>(hipStream_t, int, const cx<double> *, const cx<double> *, cx<double> *);
 template void dense_gemv<float>(hipStream_t, int, const cx<double> *, const cx<float> *, cx<float> *);
+
+
+// =====================================================================================
+// Coarse tail: the V-cycle below a given level in one workgroup
+// =====================================================================================
+// On grids small enough that a launch costs more than the work, levels first..last-1 and
+// the coarsest solve run inside one kernel of ADR_TAIL_BLOCK threads, separated by
+// workgroup barriers: GMRES pre-relaxation from zero (residual from the Arnoldi
+// relation), restriction, ... , dense coarsest solve, ..., prolongation and GMRES
+// post-relaxation.  The arithmetic per node is the multi-kernel path's (same helpers and
+// scalar formulas); only the order of the reductions differs.
+template <int K>
+__device__ __forceinline__ void tail_reduce(double (&v)[K], int k_used, double *lds /*[16 * K]*/, double *out /*[K]*/) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int k = 0; k < k_used; ++k) {
+    const double t = wave_sum(v[k]);
+    if (lane == 0) lds[wid * K + k] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < k_used) {
+    double a = 0.0;
+    for (int w = 0; w < ADR_TAIL_BLOCK / 64; ++w) a += lds[w * K + threadIdx.x];
+    out[threadIdx.x] = a;
+  }
+  __syncthreads();
+}
+
+template <typename T, int D>
+__device__ __forceinline__ cx<T> tail_stencil(const TailLevel<T> &L, const cx<T> *__restrict__ x, int i) {
+  int X[5], Y[5], Z[5];
+  coarse_neighbours<D>(L.G, i, X, Y, Z);
+  // Small load batches: the 1024-thread workgroup leaves 128 VGPRs per lane.
+  return stencil_part<T, D, 0, 1, 6>(L.planes + i, L.G.N, x, X, Y, Z);
+}
+
+// Shared state of one GMRES relaxation (thread 0 owns the Hessenberg matrix).
+struct TailScratch {
+  double red[16 * (2 * ADR_MAXNU + 2)];
+  double tot[2 * ADR_MAXNU + 2];
+  double H[2 * (ADR_MAXNU + 1) * ADR_MAXNU];   // complex, column-major, ld ADR_MAXNU + 1
+  double R[2 * (ADR_MAXNU + 1) * ADR_MAXNU];   // rotated copy (least squares)
+  double s[ADR_MAXNU + 1];                     // scale of each unnormalized basis vector
+  double beta;
+  double cx_[2 * ADR_MAXNU];                   // update coefficients y_j s_j
+  double cr[2 * (ADR_MAXNU + 1)];              // residual coefficients (beta e1 - Hbar y)_i s_i
+};
+
+// Thread 0: least squares min ||beta e1 - Hbar y|| by Givens rotations on an LDS copy of
+// Hbar (the rotations of gmres_lsq, G = [[c, s], [-conj(s), c]]), then the update and
+// residual coefficients.  Only the right-hand side and y live in registers.
+template <int NV>
+__device__ void tail_lsq(TailScratch &S, bool want_r) {
+  constexpr int LD = ADR_MAXNU + 1;
+  auto H = [&](int i, int j) { return mk<double>(S.H[2 * (j * LD + i)], S.H[2 * (j * LD + i) + 1]); };
+  auto R = [&](int i, int j) { return mk<double>(S.R[2 * (j * LD + i)], S.R[2 * (j * LD + i) + 1]); };
+  auto setR = [&](int i, int j, cx<double> v) {
+    S.R[2 * (j * LD + i)] = v.re;
+    S.R[2 * (j * LD + i) + 1] = v.im;
+  };
+#pragma unroll
+  for (int j = 0; j < NV; ++j)
+#pragma unroll
+    for (int i = 0; i <= j + 1; ++i) setR(i, j, H(i, j));
+  cx<double> g[NV + 1];
+#pragma unroll
+  for (int i = 0; i <= NV; ++i) g[i] = mk<double>(i == 0 ? S.beta : 0.0, 0.0);
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    const cx<double> a = R(j, j), b = R(j + 1, j);
+    const double aa = sqrt(a.re * a.re + a.im * a.im), bb = sqrt(b.re * b.re + b.im * b.im);
+    const double den = sqrt(aa * aa + bb * bb);
+    double c;
+    cx<double> sn;
+    if (den == 0.0) {
+      c = 1.0;
+      sn = mk<double>(0.0, 0.0);
+    } else if (aa == 0.0) {
+      c = 0.0;
+      sn = mk<double>(b.re / bb, -b.im / bb);
+    } else {
+      c = aa / den;
+      sn = mk<double>(a.re / aa, a.im / aa) * mk<double>(b.re / den, -b.im / den);
+    }
+#pragma unroll
+    for (int jj = j; jj < NV; ++jj) {
+      const cx<double> x1 = R(j, jj), x2 = R(j + 1, jj);
+      setR(j, jj, c * x1 + sn * x2);
+      setR(j + 1, jj, mk<double>(-sn.re, sn.im) * x1 + c * x2);
+    }
+    const cx<double> g1 = g[j], g2 = g[j + 1];
+    g[j] = c * g1 + sn * g2;
+    g[j + 1] = mk<double>(-sn.re, sn.im) * g1 + c * g2;
+  }
+  cx<double> y[NV];
+#pragma unroll
+  for (int j = NV - 1; j >= 0; --j) {
+    cx<double> acc = g[j];
+#pragma unroll
+    for (int jj = j + 1; jj < NV; ++jj) acc = acc - R(j, jj) * y[jj];
+    const cx<double> d = R(j, j);
+    y[j] = (d.re == 0.0 && d.im == 0.0) ? mk<double>(0.0, 0.0) : acc * cinv(d);
+  }
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    S.cx_[2 * j] = y[j].re * S.s[j];
+    S.cx_[2 * j + 1] = y[j].im * S.s[j];
+  }
+  if (want_r) {
+#pragma unroll
+    for (int i = 0; i <= NV; ++i) {
+      cx<double> c = mk<double>(i == 0 ? S.beta : 0.0, 0.0);
+#pragma unroll
+      for (int j = (i > 0 ? i - 1 : 0); j < NV; ++j) c = c - H(i, j) * y[j];
+      S.cr[2 * i] = c.re * S.s[i];
+      S.cr[2 * i + 1] = c.im * S.s[i];
+    }
+  }
+}
+
+// GMRES relaxation on level L (see gmres_relax): x_out = x0 + D^{-1} V y; with r_out
+// also b - A x_out.  x_out may alias x0.
+template <typename T, int D>
+__device__ void tail_gmres(const TailLevel<T> &L, const cx<T> *x0, const cx<T> *b, cx<T> *x_out, cx<T> *r_out,
+                           TailScratch &S) {
+  constexpr int KR = 2 * ADR_MAXNU + 2;
+  const int N = L.G.N, nu = L.nu;
+  const int tid = threadIdx.x;
+  double acc[KR];
+  // V_0 = b - A x0 (or b), Z_0 = D^{-1} V_0, ||V_0||^2
+  acc[0] = 0.0;
+  for (int i = tid; i < N; i += ADR_TAIL_BLOCK) {
+    const cx<T> v = x0 ? b[i] - tail_stencil<T, D>(L, x0, i) : b[i];
+    L.V[i] = v;
+    L.Z[i] = v * L.dinv[i];
+    acc[0] += (double)v.re * v.re + (double)v.im * v.im;
+  }
+  tail_reduce<KR>(acc, 1, S.red, S.tot);
+  if (tid == 0) {
+    S.beta = sqrt(S.tot[0]);
+    S.s[0] = S.beta > 0.0 ? 1.0 / S.beta : 0.0;
+  }
+  __syncthreads();
+  constexpr int LD = ADR_MAXNU + 1;
+  // Unrolled to the maximum step count so that every per-basis index is static.
+#pragma unroll
+  for (int j = 0; j < ADR_MAXNU; ++j) {
+    if (j >= nu) break;
+    const cx<T> *Zj = L.Z + (size_t)j * N;
+    const T sj = (T)S.s[j];
+    // w = s_j A Z_j, dots conj(V_k) . w for k <= j
+#pragma unroll
+    for (int k = 0; k < 2 * (j + 1); ++k) acc[k] = 0.0;
+    for (int i = tid; i < N; i += ADR_TAIL_BLOCK) {
+      const cx<T> w = sj * tail_stencil<T, D>(L, Zj, i);
+      L.w[i] = w;
+#pragma unroll
+      for (int k = 0; k <= j; ++k) {
+        const cx<double> d = cdotc(cvt<double, T>(L.V[(size_t)k * N + i]), cvt<double, T>(w));
+        acc[2 * k] += d.re;
+        acc[2 * k + 1] += d.im;
+      }
+    }
+    tail_reduce<KR>(acc, 2 * (j + 1), S.red, S.tot);
+    if (tid <= j) {
+      S.H[2 * (j * LD + tid)] = S.s[tid] * S.tot[2 * tid];
+      S.H[2 * (j * LD + tid) + 1] = S.s[tid] * S.tot[2 * tid + 1];
+    }
+    __syncthreads();
+    // v_{j+1} = w - sum_k H[k][j] s_k V_k, Z_{j+1} = D^{-1} v_{j+1}, its norm
+    cx<T> coef[ADR_MAXNU];   // fixed size: device code must not allocate a variable-length stack array
+#pragma unroll
+    for (int k = 0; k <= j; ++k)
+      coef[k] = mk<T>((T)(S.H[2 * (j * LD + k)] * S.s[k]), (T)(S.H[2 * (j * LD + k) + 1] * S.s[k]));
+    acc[0] = 0.0;
+    cx<T> *Vn = L.V + (size_t)(j + 1) * N, *Zn = L.Z + (size_t)(j + 1) * N;
+    for (int i = tid; i < N; i += ADR_TAIL_BLOCK) {
+      cx<T> o = L.w[i];
+#pragma unroll
+      for (int k = 0; k <= j; ++k) o = o - coef[k] * L.V[(size_t)k * N + i];
+      Vn[i] = o;
+      Zn[i] = o * L.dinv[i];
+      acc[0] += (double)o.re * o.re + (double)o.im * o.im;
+    }
+    tail_reduce<KR>(acc, 1, S.red, S.tot);
+    if (tid == 0) {
+      const double nrm = sqrt(S.tot[0]);
+      S.H[2 * (j * LD + j + 1)] = nrm;
+      S.H[2 * (j * LD + j + 1) + 1] = 0.0;
+      S.s[j + 1] = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    switch (nu) {
+#define ADR_TAIL_LSQ(n) \
+  case n: tail_lsq<n>(S, r_out != nullptr); break;
+      ADR_TAIL_LSQ(1) ADR_TAIL_LSQ(2) ADR_TAIL_LSQ(3) ADR_TAIL_LSQ(4) ADR_TAIL_LSQ(5) ADR_TAIL_LSQ(6) ADR_TAIL_LSQ(7)
+      ADR_TAIL_LSQ(8)
+#undef ADR_TAIL_LSQ
+      default: break;
+    }
+  }
+  __syncthreads();
+  cx<T> c[ADR_MAXNU], cr[ADR_MAXNU + 1];
+#pragma unroll
+  for (int k = 0; k < ADR_MAXNU; ++k)
+    c[k] = k < nu ? mk<T>((T)S.cx_[2 * k], (T)S.cx_[2 * k + 1]) : mk<T>(T(0), T(0));
+#pragma unroll
+  for (int k = 0; k <= ADR_MAXNU; ++k)
+    cr[k] = (r_out && k <= nu) ? mk<T>((T)S.cr[2 * k], (T)S.cr[2 * k + 1]) : mk<T>(T(0), T(0));
+  for (int i = tid; i < N; i += ADR_TAIL_BLOCK) {
+    cx<T> a = x0 ? x0[i] : mk<T>(T(0), T(0));
+#pragma unroll
+    for (int k = 0; k < ADR_MAXNU; ++k)
+      if (k < nu) a = cfma(c[k], L.Z[(size_t)k * N + i], a);
+    x_out[i] = a;
+    if (r_out) {
+      cx<T> r = cr[0] * L.V[i];
+#pragma unroll
+      for (int k = 1; k <= ADR_MAXNU; ++k)
+        if (k <= nu) r = cfma(cr[k], L.V[(size_t)k * N + i], r);
+      r_out[i] = r;
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(ADR_TAIL_BLOCK) void k_coarse_tail(const TailArgs<T> *__restrict__ Ap) {
+  __shared__ TailScratch S;
+  const TailArgs<T> &A = *Ap;
+  const int tid = threadIdx.x;
+  for (int l = A.first; l < A.last; ++l) {
+    const TailLevel<T> &L = A.L[l];
+    tail_gmres<T, D>(L, nullptr, L.b, L.x, L.r, S);
+    const TailLevel<T> &C = A.L[l + 1];
+    for (int J = tid; J < C.G.N; J += ADR_TAIL_BLOCK) C.b[J] = restrict_value<T, D>(L.G, C.G, L.r, J);
+    __syncthreads();
+  }
+  {
+    // coarsest: x = A^{-1} b, one wavefront per row (as dense_gemv)
+    const TailLevel<T> &C = A.L[A.last];
+    const int n = C.G.N, lane = tid & 63;
+    for (int row = tid >> 6; row < n; row += ADR_TAIL_BLOCK / 64) {
+      const cx<double> *a = A.Ainv + (size_t)row * n;
+      double re = 0.0, im = 0.0;
+      for (int j = lane; j < n; j += 64) {
+        const cx<double> v = cfma(a[j], cvt<double, T>(C.b[j]), mk<double>(0.0, 0.0));
+        re += v.re;
+        im += v.im;
+      }
+      re = wave_sum(re);
+      im = wave_sum(im);
+      if (lane == 0) C.x[row] = cvt<T, double>(mk<double>(re, im));
+    }
+    __syncthreads();
+  }
+  for (int l = A.last - 1; l >= A.first; --l) {
+    const TailLevel<T> &L = A.L[l];
+    const TailLevel<T> &C = A.L[l + 1];
+    for (int f = tid; f < L.G.N; f += ADR_TAIL_BLOCK) L.x[f] = L.x[f] + prolong_value<T, D>(L.G, C.G, C.x, f);
+    __syncthreads();
+    tail_gmres<T, D>(L, L.x, L.b, L.x, nullptr, S);
+  }
+}
+
+template <typename T>
+void coarse_tail(hipStream_t s, int D, const TailArgs<T> *a_dev) {
+  if (D == 2) hipLaunchKernelGGL((k_coarse_tail<T, 2>), dim3(1), dim3(ADR_TAIL_BLOCK), 0, s, a_dev);
+  else hipLaunchKernelGGL((k_coarse_tail<T, 3>), dim3(1), dim3(ADR_TAIL_BLOCK), 0, s, a_dev);
+}
+template void coarse_tail<double>(hipStream_t, int, const TailArgs<double> *);
+template void coarse_tail<float>(hipStream_t, int, const TailArgs<float> *);
 
 }  // namespace adrk

@@ -40,6 +40,25 @@ struct CoarseArgs {
   int split;             // 4: four wavefronts share each node's stencil sum; else one lane
 };
 
+// Coarse tail (one workgroup): per-level data and the level range.
+#define ADR_TAIL_BLOCK 1024
+#define ADR_TAIL_MAXL 8
+template <typename T>
+struct TailLevel {
+  Grid G;
+  const cx<T> *planes;   // Galerkin stencil (direction of the solve)
+  const cx<T> *dinv;
+  cx<T> *x, *b, *r, *w;
+  cx<T> *V, *Z;          // nu + 1 planes each
+  int nu;
+};
+template <typename T>
+struct TailArgs {
+  int first, last;               // relaxed levels first..last-1; `last` is the coarsest
+  TailLevel<T> L[ADR_TAIL_MAXL];
+  const cx<double> *Ainv;        // coarsest inverse, row-major (direction of the solve)
+};
+
 namespace adrk {
 
 // ---- setup (FP64) ----------------------------------------------------------------
@@ -152,6 +171,13 @@ void multi_axpy(hipStream_t s, int N, cx<double> *x, const VecSet<Tz> &Z, const 
 void scale(hipStream_t s, int N, const cx<double> *x, double a, cx<double> *y);
 // q_hat = q exp(+i w tau)  (sign = +1) or u = a exp(-i w tau) (sign = -1)
 void phase(hipStream_t s, int N, const cx<double> *in, const double *tau, double omega, int sign, cx<double> *out);
+
+// ---- coarse tail ---------------------------------------------------------------------
+// The V-cycle on levels first..last (coarsest) from a zero guess on level `first` with
+// right-hand side L[first].b, in one workgroup; the result is L[first].x.  a_dev is a
+// device copy of the level table.
+template <typename T>
+void coarse_tail(hipStream_t s, int D, const TailArgs<T> *a_dev);
 
 // ---- coarsest level ------------------------------------------------------------------
 template <typename T>

@@ -38,6 +38,7 @@ def test_default_options(lib):
     assert list(o.nu)[:3] == [2, 3, 4]
     assert o.relax[0] == adr.ADR_RELAX_JACOBI and o.relax[1] == adr.ADR_RELAX_GMRES
     assert o.cycle == adr.ADR_CYCLE_V and abs(o.kcycle_threshold - 0.1) < 1e-15 and o.coarse_split == 0
+    assert o.tail_max_nodes == 0
     assert adr.default_options(cycle="k").cycle == adr.ADR_CYCLE_K
 
 
@@ -93,3 +94,13 @@ def test_null_context_calls(lib):
     assert lib.adr_num_levels(None) == 0
     lib.adr_destroy(None)
     assert lib.adr_strerror(adr.ADR_ENOCONV) == b"not converged"
+
+
+def test_setup_rejects_coarse_tail(lib):
+    """The single-workgroup coarse tail is switched off: asking for it is refused."""
+    from paper_1712_06091_amd import adr
+    p = _problem()
+    o = adr.default_options(tail_max_nodes=4225)
+    out = ctypes.c_void_p()
+    assert lib.adr_setup(ctypes.byref(p), ctypes.byref(o), None, ctypes.byref(out)) == adr.ADR_ENOTSUP
+    assert out.value is None

@@ -265,3 +265,55 @@ def test_split_variants_agree_on_solve(prec):
         ctx.close()
     assert _rel(out[4], out[1]) <= 1e-9
     assert _rel(out[0], out[1]) <= 1e-9
+
+
+TAIL_CASES = {
+    # (workload, levels, tail_max_nodes): the tail starts at the first coarse level with
+    # at most tail_max_nodes nodes
+    "2d_129_rand_5lv": (lambda: W.random_medium(129, 2, seed=21), 5, 4225),
+    "3d_33_lin_3lv": (lambda: W.linear_gradient(33, 3), 3, 5000),
+}
+
+
+TAIL_SKIP = ("single-workgroup coarse tail disabled: its first GPU run (2d_129_rand_5lv, tail on levels 1-3, "
+             "FP64) ended in a memory aperture violation with no cause found; adr_setup rejects it")
+
+
+@pytest.mark.skip(reason=TAIL_SKIP)
+@pytest.mark.parametrize("name", list(TAIL_CASES))
+@pytest.mark.parametrize("tail", [False, True])
+def test_vcycle_coarse_tail_fp64(name, tail):
+    """The single-workgroup coarse tail gives the oracle's V-cycle up to rounding, like
+    the multi-kernel path."""
+    make, levels, tmax = TAIL_CASES[name]
+    wl = make()
+    print(f"[tail-fp64] {name} shape={wl.shape} tail={tail}", flush=True)
+    ctx = _ctx(wl, prec="fp64", levels=levels, tail_max_nodes=tmax if tail else 0)
+    p = osolve.Problem(wl.kappa2, wl.tau, wl.gamma, wl.h, wl.omega, wl.src)
+    hier = p.hierarchy(levels)
+    r = W.random_vector(wl.shape, 41)
+    z = ctx.vcycle(_t(r)).cpu().numpy()
+    ref = hier.vcycle(r.ravel()).reshape(wl.shape)
+    assert _rel(z, ref) <= 1e-10
+
+
+@pytest.mark.skip(reason=TAIL_SKIP)
+@pytest.mark.parametrize("name", list(TAIL_CASES))
+def test_vcycle_coarse_tail_mixed_and_solves(name):
+    make, levels, tmax = TAIL_CASES[name]
+    wl = make()
+    print(f"[tail-mixed] {name} shape={wl.shape}", flush=True)
+    ctx = _ctx(wl, prec="mixed", levels=levels, tail_max_nodes=tmax)
+    p = osolve.Problem(wl.kappa2, wl.tau, wl.gamma, wl.h, wl.omega, wl.src)
+    hier = p.hierarchy(levels)
+    r = W.random_vector(wl.shape, 42)
+    z = ctx.vcycle(_t(r)).cpu().numpy()
+    assert _rel(z, hier.vcycle(r.ravel()).reshape(wl.shape)) <= 1e-4
+    qh = osolve.rhs_hat(wl.rhs(), wl.tau, wl.omega)
+    ref = osolve.direct_solve(p.H2up, qh).reshape(wl.shape)
+    a, st = ctx.solve(_t(wl.rhs()), tol=1e-10, maxit=300)
+    assert st["relres"] <= 1e-10 and _rel(a.cpu().numpy(), ref) <= 1e-6
+    g = W.random_vector(wl.shape, 43)
+    refl = osolve.direct_solve(p.H2up.conj().T.tocsr(), osolve.rhs_hat(g, wl.tau, wl.omega)).reshape(wl.shape)
+    lam, st = ctx.solve_adjoint(_t(g), tol=1e-10, maxit=300)
+    assert st["relres"] <= 1e-10 and _rel(lam.cpu().numpy(), refl) <= 1e-6
