@@ -281,6 +281,8 @@ Grid make_grid(int D, const int n[3]) {
   G.n[1] = n[1];
   G.n[2] = D == 3 ? n[2] : 1;
   G.N = G.n[0] * G.n[1] * G.n[2];
+  G.r0 = 1.0 / G.n[0];
+  G.r01 = 1.0 / ((double)G.n[0] * G.n[1]);
   return G;
 }
 Grid coarsen(int D, const Grid &G) {

@@ -55,16 +55,37 @@ __host__ __device__ __forceinline__ cx<To> cvt(cx<Ti> a) { return mk<To>((To)a.r
 // Grid: nx fastest, 2D grids have nz == 1.
 // ------------------------------------------------------------------------------------
 struct Grid {
-  int n[3];   // nodes along x, y, z
-  int N;      // total nodes
+  int n[3];        // nodes along x, y, z
+  int N;           // total nodes
+  double r0, r01;  // 1 / n[0] and 1 / (n[0] n[1]) (index decoding without integer division)
 };
 
+// Node index -> (x, y, z).  The quotients come from a double-precision multiply by the
+// reciprocal, then one exact correction step: for i < 2^30 the product is within 2^-22 of
+// the true quotient, so the truncated value is off by at most one.
 __device__ __forceinline__ void decode(const Grid &g, int i, int &x, int &y, int &z) {
-  int nxy = g.n[0] * g.n[1];
-  z = i / nxy;
-  int rem = i - z * nxy;
-  y = rem / g.n[0];
-  x = rem - y * g.n[0];
+  const int nxy = g.n[0] * g.n[1];
+  int q = (int)((double)i * g.r01);
+  int rem = i - q * nxy;
+  if (rem < 0) {
+    --q;
+    rem += nxy;
+  } else if (rem >= nxy) {
+    ++q;
+    rem -= nxy;
+  }
+  int q2 = (int)((double)rem * g.r0);
+  int r2 = rem - q2 * g.n[0];
+  if (r2 < 0) {
+    --q2;
+    r2 += g.n[0];
+  } else if (r2 >= g.n[0]) {
+    ++q2;
+    r2 -= g.n[0];
+  }
+  z = q;
+  y = q2;
+  x = r2;
 }
 
 // ------------------------------------------------------------------------------------

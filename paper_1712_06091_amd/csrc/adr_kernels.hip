@@ -243,16 +243,20 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_fine_apply(Grid G, FineCoef<T> C,
   for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
     int idx[3];
     decode(G, i, idx[0], idx[1], idx[2]);
+    // Gathers first, so that their latency overlaps the row computation.
+    int nb[1 + 4 * D];
+    fine_neighbours<D>(G, i, idx, nb);
+    cx<Tin> xv[1 + 4 * D];
+#pragma unroll
+    for (int p = 0; p < 1 + 4 * D; ++p) xv[p] = x[nb[p]];
     T gk[3], L;
     cx<T> c;
     load_fine_coef<T, D>(C, i, gk, L, c);
     cx<T> e[1 + 4 * D];
     fine_row<T, D>(G, P, idx, gk, L, c, e);
-    int nb[1 + 4 * D];
-    fine_neighbours<D>(G, i, idx, nb);
     cx<T> acc = mk<T>(T(0), T(0));
 #pragma unroll
-    for (int p = 0; p < 1 + 4 * D; ++p) acc = cfma(e[p], cvt<T, Tin>(x[nb[p]]), acc);
+    for (int p = 0; p < 1 + 4 * D; ++p) acc = cfma(e[p], cvt<T, Tin>(xv[p]), acc);
     cx<To> o = cvt<To, T>(acc);
     if (mode == 1) o = b[i] - o;
     y[i] = o;
@@ -325,21 +329,28 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_fine_jacobi(Grid G, FineCoef<T> C
   for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
     int idx[3];
     decode(G, i, idx[0], idx[1], idx[2]);
-    T gk[3], L;
-    cx<T> c;
-    load_fine_coef<T, D>(C, i, gk, L, c);
-    cx<T> e[1 + 4 * D];
-    fine_row<T, D>(G, P, idx, gk, L, c, e);
-    cx<T> r = b[i];
-    cx<T> x0 = mk<T>(T(0), T(0));
+    // Gathers first, so that their latency overlaps the row computation.
+    cx<T> xv[1 + 4 * D];
     if (xin) {
       int nb[1 + 4 * D];
       fine_neighbours<D>(G, i, idx, nb);
+#pragma unroll
+      for (int p = 0; p < 1 + 4 * D; ++p) xv[p] = xin[nb[p]];
+    }
+    T gk[3], L;
+    cx<T> c;
+    load_fine_coef<T, D>(C, i, gk, L, c);
+    const cx<T> bi = b[i];
+    cx<T> e[1 + 4 * D];
+    fine_row<T, D>(G, P, idx, gk, L, c, e);
+    cx<T> r = bi;
+    cx<T> x0 = mk<T>(T(0), T(0));
+    if (xin) {
       cx<T> acc = mk<T>(T(0), T(0));
 #pragma unroll
-      for (int p = 0; p < 1 + 4 * D; ++p) acc = cfma(e[p], xin[nb[p]], acc);
+      for (int p = 0; p < 1 + 4 * D; ++p) acc = cfma(e[p], xv[p], acc);
       r = r - acc;
-      x0 = xin[i];
+      x0 = xv[0];
     }
     xout[i] = cfma(weight * cinv(e[0]), r, x0);
   }
