@@ -104,6 +104,10 @@ typedef struct {
                         /* many nodes down to the coarsest in one single-workgroup       */
                         /* kernel.  Disabled: must be 0 (the default); any other value   */
                         /* makes adr_setup return ADR_ENOTSUP                            */
+  int full_cycles;      /* 1: every FGMRES restart cycle takes `restart` steps, the      */
+                        /* convergence test only at cycle ends (batched solves always    */
+                        /* run this way); default 0: stop inside a cycle once the        */
+                        /* residual estimate reaches tol                                 */
 } adr_options;
 
 typedef struct {
@@ -197,15 +201,20 @@ int adr_num_levels(const adr_ctx *ctx);
  * (may be NULL).  Entries that point outside the grid are zero. */
 adr_status adr_get_level_stencil(adr_ctx *ctx, int level, void *planes_c128, int *offsets);
 
-/* Batched shots: `count` independent problems (own source, tau and grid each) solved
- * together.  adr_setup_batch creates `nstreams` (1..64) non-blocking streams of default
- * priority and one context per shot on stream i % nstreams.  adr_solve_batch runs the
- * FGMRES of every shot in lockstep: each round enqueues the next step of every
- * unconverged shot, synchronizes the streams once and updates all shots on the host, so
- * shots on different streams overlap on the GPU; converged shots drop out (mask).
- * q[i], a[i]: per-shot c128 device arrays as in adr_solve (zero initial guess).  stats:
- * host array of count entries, or NULL.  Returns ADR_OK if every shot converged, else
- * the first non-convergence/error status; every a[i] holds its best iterate. */
+/* Batched shots: `count` independent problems (own source, medium, tau and omega each;
+ * any mix of grid sizes) solved together, the batched point sources of Sec. 4.2 (one
+ * solve per source).  adr_setup_batch groups the problems by grid shape; each group's
+ * contexts live in one device arena at a constant stride, so every kernel of a group
+ * runs once for all its problems (one launch per phase), on one of `nstreams` (1..64)
+ * non-blocking streams of default priority (group g on stream g % nstreams).
+ * adr_solve_batch runs one FGMRES per problem with full restart cycles (see
+ * adr_options.full_cycles; the options' own value is ignored) so that the problems of a
+ * group stay in lockstep; converged problems are masked off on the device, and groups
+ * advance independently.  Per problem the result equals adr_solve with full_cycles = 1
+ * bit for bit.  q[i], a[i]: per-problem c128 device arrays as in adr_solve (zero initial
+ * guess; a[i] is written when problem i finishes).  stats: host array of count entries,
+ * or NULL.  Returns ADR_OK if every problem converged, else the first
+ * non-convergence/error status; every a[i] holds its best iterate. */
 typedef struct adr_batch adr_batch;
 adr_status adr_setup_batch(int count, const adr_problem *probs, const adr_options *opt, int nstreams,
                            adr_batch **out);

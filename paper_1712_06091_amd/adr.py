@@ -50,6 +50,7 @@ class AdrOptions(ctypes.Structure):
         ("kcycle_threshold", ctypes.c_double),
         ("coarse_split", ctypes.c_int),
         ("tail_max_nodes", ctypes.c_int),
+        ("full_cycles", ctypes.c_int),
     ]
 
 

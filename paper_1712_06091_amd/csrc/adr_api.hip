@@ -114,6 +114,19 @@ struct adr_ctx {
   cx<double> *wo = nullptr, *ro = nullptr, *qh = nullptr;
   cx<float> *b32 = nullptr, *z32 = nullptr;   // mixed-mode V-cycle in/out staging
 
+  // Allocation: by default every device buffer is its own hipMalloc.  A context of a
+  // shot group carves its setup allocations, in a fixed order, from one slot of the
+  // group's arena [arena, arena + arena_cap), so that the buffers of problem s lie
+  // s * stride bytes after problem 0's.  alloc_need counts the bytes a slot needs.
+  char *arena = nullptr;
+  size_t arena_off = 0, arena_cap = 0;
+  const char *arena_lo = nullptr, *arena_hi = nullptr;
+  size_t alloc_need = 0;
+  bool group_member = false;
+  FineParams *Pdev = nullptr;     // device copies of the fine-operator parameters: [0] beta = 0, [1] A_beta
+  int *active = nullptr;          // shot-group flag: 1 while the problem is being solved
+  cx<double> *qin = nullptr, *xg = nullptr;   // shot-group copies of right-hand side and solution
+
   // Coarse tail: levels tail_level.. run in one single-workgroup kernel (-1: none); device
   // copies of its level table for the forward [0] and adjoint [1] hierarchies.
   int tail_level = -1;
@@ -126,6 +139,7 @@ struct adr_ctx {
     const void *in = nullptr;
     void *out = nullptr;
     bool adj = false;
+    int group = 1;             // problems per launch (shot group) when captured
     hipGraph_t g = nullptr;
     hipGraphExec_t e = nullptr;
     unsigned long long last_use = 0;
@@ -160,6 +174,17 @@ template <typename T>
 adr_status dalloc(adr_ctx *ctx, T **p, size_t count) {
   *p = nullptr;
   if (count == 0) return ADR_OK;
+  const size_t aligned = (count * sizeof(T) + 255) & ~(size_t)255;
+  ctx->alloc_need += aligned;
+  if (ctx->arena) {
+    if (ctx->arena_off + aligned > ctx->arena_cap) {
+      ctx->err = "shot-group arena slot exhausted";
+      return ADR_ENOMEM;
+    }
+    *p = (T *)(ctx->arena + ctx->arena_off);
+    ctx->arena_off += aligned;
+    return ADR_OK;
+  }
   hipError_t e = hipMalloc((void **)p, count * sizeof(T));
   if (e != hipSuccess) {
     *p = nullptr;
@@ -168,6 +193,14 @@ adr_status dalloc(adr_ctx *ctx, T **p, size_t count) {
   }
   return ADR_OK;
 }
+// Free a buffer from dalloc (arena slots are released with their group).
+void dfree(adr_ctx *ctx, void *p) {
+  if (!p) return;
+  const char *c = (const char *)p;
+  if (ctx->arena_lo && c >= ctx->arena_lo && c < ctx->arena_hi) return;
+  hipFree(p);
+}
+
 #define ADR_TRY(x)                   \
   do {                               \
     adr_status s_ = (x);             \
@@ -479,7 +512,7 @@ cx<T> *jacobi_sweeps(adr_ctx *ctx, int nu, const cx<T> *x_start, const cx<T> *b,
     out = (k % 2 == 0) ? first : second;
     int t0 = tbegin(ctx, ADR_TIMER_FINE_JACOBI, 0);
     if (ctx->adj) adrk::fine_jacobi_adj<T>(ctx->stream, G, ctx->D, C, P, in, b, out, ctx->opt.jacobi_weight);
-    else adrk::fine_jacobi<T>(ctx->stream, G, ctx->D, C, P, in, b, out, ctx->opt.jacobi_weight);
+    else adrk::fine_jacobi<T>(ctx->stream, G, ctx->D, C, P, in, b, out, ctx->opt.jacobi_weight, ctx->Pdev + 1);
     tend(ctx, t0, (double)G.N * (fine_coef_bytes<T>(ctx->D) + sizeof(cx<T>) * (in ? 3 : 2)));
     in = out;
   }
@@ -536,7 +569,7 @@ cx<T> *vcycle(adr_ctx *ctx, int l, const cx<T> *b, cx<T> *out0, ProIn bpin = Pro
                                     nullptr, false, nullptr);
     else
       adrk::fine_apply<T, T, T>(s, L.G, D, fine_coef<T>(ctx), fine_params(ctx, ctx->opt.beta), x, b, L.r, 1,
-                                nullptr, false, nullptr);
+                                nullptr, false, nullptr, ctx->Pdev + 1);
     tend(ctx, t0, (double)L.G.N * (fine_coef_bytes<T>(D) + 3 * cb));
   }
   // The coarse level (unless it is the coarsest) starts with a GMRES relaxation from
@@ -852,7 +885,7 @@ adr_status build_hierarchy(adr_ctx *ctx) {
     // The FP64 planes are the level stencil in FP64 mode; mixed mode keeps an FP32 copy
     // and frees the FP64 planes once the next level is built from them.
     lv[l].S = Sc;
-    if (l == 1 || ctx->opt.prec != ADR_PREC_FP64) hipFree(prev);
+    if (l == 1 || ctx->opt.prec != ADR_PREC_FP64) dfree(ctx, prev);
     prev = cur;
     if (ctx->opt.prec == ADR_PREC_FP64) {
       lv[l].planes = (cx<T> *)cur;
@@ -869,14 +902,14 @@ adr_status build_hierarchy(adr_ctx *ctx) {
     adrk::stencil_diag_inv<T>(s, lv[l].G.N, lv[l].planes + (size_t)centre * lv[l].G.N, lv[l].dinv);
   }
   for (int i = 0; i < 2; ++i) {
-    hipFree(tri_start[i]);
-    hipFree(tri_p[i]);
-    hipFree(tri_d[i]);
-    hipFree(tri_w[i]);
+    dfree(ctx, tri_start[i]);
+    dfree(ctx, tri_p[i]);
+    dfree(ctx, tri_d[i]);
+    dfree(ctx, tri_w[i]);
   }
   if (st != ADR_OK) {
     // In FP64 mode `prev` is owned by a level (or is the fine temporary on level 1).
-    if (ctx->opt.prec != ADR_PREC_FP64 || (prev && lv[1].planes != (cx<T> *)prev)) hipFree(prev);
+    if (ctx->opt.prec != ADR_PREC_FP64 || (prev && lv[1].planes != (cx<T> *)prev)) dfree(ctx, prev);
     return st;
   }
   // Coarsest: dense FP64 inverse.
@@ -893,7 +926,7 @@ adr_status build_hierarchy(adr_ctx *ctx) {
     std::vector<cx<double>> hp((size_t)Sf * n);
     ADR_HIP(hipMemcpyAsync(hp.data(), tmp, hp.size() * sizeof(cx<double>), hipMemcpyDeviceToHost, s));
     ADR_HIP(hipStreamSynchronize(s));
-    hipFree(tmp);
+    dfree(ctx, tmp);
     for (int i = 0; i < n; ++i) {
       int ix = i % Gc.n[0], iy = (i / Gc.n[0]) % Gc.n[1], iz = i / (Gc.n[0] * Gc.n[1]);
       for (int p = 0; p < Sf; ++p) {
@@ -916,7 +949,7 @@ adr_status build_hierarchy(adr_ctx *ctx) {
         A[(size_t)i * n + j] = std::complex<double>(hp[(size_t)p * n + i].re, hp[(size_t)p * n + i].im);
       }
     }
-    if (ctx->opt.prec != ADR_PREC_FP64) hipFree(prev);
+    if (ctx->opt.prec != ADR_PREC_FP64) dfree(ctx, prev);
   }
   if (!dense_inverse(n, A, inv)) {
     ctx->err = "coarsest operator is singular";
@@ -942,9 +975,7 @@ adr_status build_hierarchy(adr_ctx *ctx) {
 
 void free_ctx(adr_ctx *ctx) {
   if (!ctx) return;
-  auto F = [](void *p) {
-    if (p) hipFree(p);
-  };
+  auto F = [ctx](void *p) { dfree(ctx, p); };
   for (int k = 0; k < 3; ++k) {
     F(ctx->g64[k]);
     F(ctx->g32[k]);
@@ -983,6 +1014,10 @@ void free_ctx(adr_ctx *ctx) {
   F(ctx->z32);
   F(ctx->tail_args[0]);
   F(ctx->tail_args[1]);
+  F(ctx->Pdev);
+  F(ctx->active);
+  F(ctx->qin);
+  F(ctx->xg);
   for (auto &e : ctx->timer.ev) hipEventDestroy(e);
   for (auto &g : ctx->graphs) {
     hipGraphExecDestroy(g.e);
@@ -1015,6 +1050,22 @@ adr_status setup_impl(adr_ctx *ctx, const adr_problem *p) {
   ADR_TRY(dalloc(ctx, &ctx->osc, 64));
   ADR_HIP(hipMemsetAsync(ctx->osc, 0, sizeof(double) * 64, s));
   ADR_HIP(hipHostMalloc((void **)&ctx->hpin, kPin * sizeof(double), hipHostMallocDefault));
+  // Device copies of the fine-operator parameters (kernels of a shot group read their
+  // own problem's omega and source there) and the shot-group flag.
+  ADR_TRY(dalloc(ctx, &ctx->Pdev, 2));
+  {
+    const FineParams hpar[2] = {fine_params(ctx, 0.0), fine_params(ctx, ctx->opt.beta)};
+    ADR_HIP(hipMemcpy(ctx->Pdev, hpar, sizeof(hpar), hipMemcpyHostToDevice));
+  }
+  ADR_TRY(dalloc(ctx, &ctx->active, 1));
+  {
+    const int one = 1;
+    ADR_HIP(hipMemcpy(ctx->active, &one, sizeof(one), hipMemcpyHostToDevice));
+  }
+  if (ctx->group_member) {
+    ADR_TRY(dalloc(ctx, &ctx->qin, N));
+    ADR_TRY(dalloc(ctx, &ctx->xg, N));
+  }
   if (ctx->opt.prec == ADR_PREC_MIXED) {
     for (int k = 0; k < D; ++k) {
       ADR_TRY(dalloc(ctx, &ctx->g32[k], N));
@@ -1078,7 +1129,7 @@ adr_status precondition(adr_ctx *ctx, const cx<double> *v, void *z, bool z_is_c1
   }
   adr_ctx::GraphEntry *hit = nullptr;
   for (auto &g : ctx->graphs)
-    if (g.in == v && g.out == z && g.adj == ctx->adj) hit = &g;
+    if (g.in == v && g.out == z && g.adj == ctx->adj && g.group == adrk::g_shot.count) hit = &g;
   if (!hit) {
     if (!ctx->cap_stream) ADR_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
     if (ctx->graphs.size() >= 16) {   // evict the least recently used capture
@@ -1094,6 +1145,7 @@ adr_status precondition(adr_ctx *ctx, const cx<double> *v, void *z, bool z_is_c1
     ge.in = v;
     ge.out = z;
     ge.adj = ctx->adj;
+    ge.group = adrk::g_shot.count;
     hipStream_t user = ctx->stream;
     ctx->stream = ctx->cap_stream;
     hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed);
@@ -1112,6 +1164,66 @@ adr_status precondition(adr_ctx *ctx, const cx<double> *v, void *z, bool z_is_c1
   }
   hit->last_use = ++ctx->graph_clock;
   ADR_HIP(hipGraphLaunch(hit->e, ctx->stream));
+  return ADR_OK;
+}
+
+}  // namespace
+
+extern "C" void adr_default_options(adr_options *o);
+
+namespace {
+// Context setup.  With `slot`, every device allocation of the setup is carved, in a fixed
+// order, from [slot, slot + slot_cap) (one problem of a shot group); later allocations
+// (adjoint preparation) use hipMalloc.  `group_member` adds the group's right-hand-side
+// and solution buffers.
+adr_status setup_ctx(const adr_problem *prob, const adr_options *opt, hipStream_t stream, char *slot,
+                     size_t slot_cap, bool group_member, adr_ctx **out) {
+  if (!out) {
+    g_setup_error = "null output pointer";
+    return ADR_EINVAL;
+  }
+  *out = nullptr;
+  adr_options defaults;
+  adr_default_options(&defaults);
+  const adr_options *o = opt ? opt : &defaults;
+  std::string err;
+  adr_status st = validate(prob, o, err);
+  if (st != ADR_OK) {
+    g_setup_error = err;
+    return st;
+  }
+  const double t0 = now_ms();
+  adr_ctx *ctx = new adr_ctx();
+  ctx->opt = *o;
+  ctx->stream = stream;
+  ctx->group_member = group_member;
+  if (slot) {
+    ctx->arena = slot;
+    ctx->arena_cap = slot_cap;
+    ctx->arena_lo = slot;
+    ctx->arena_hi = slot + slot_cap;
+  }
+  ctx->D = prob->ndim;
+  ctx->G0 = make_grid(ctx->D, prob->n);
+  ctx->h = prob->h;
+  ctx->omega = prob->omega;
+  for (int k = 0; k < 3; ++k) ctx->src[k] = (prob->src[0] >= 0 && k < ctx->D) ? prob->src[k] : 0;
+  if (prob->src[0] < 0) ctx->src[0] = -1;
+  ctx->levels = o->levels > 0 ? o->levels : auto_levels(ctx->D, prob->n, o->coarsest_max > 0 ? o->coarsest_max : 729);
+  for (int l = 0; l < kMaxLevels; ++l) {
+    ctx->nu[l] = o->nu[l];
+    ctx->relax[l] = o->relax[l];
+  }
+  st = check_levels(ctx);
+  if (st == ADR_OK) st = setup_impl(ctx, prob);
+  if (st != ADR_OK) {
+    g_setup_error = ctx->err;
+    free_ctx(ctx);
+    return st;
+  }
+  (void)t0;
+  ctx->arena = nullptr;   // later allocations are ordinary ones
+  *out = ctx;
   return ADR_OK;
 }
 
@@ -1142,45 +1254,7 @@ void adr_default_options(adr_options *o) {
 }
 
 adr_status adr_setup(const adr_problem *prob, const adr_options *opt, void *stream, adr_ctx **out) {
-  if (!out) {
-    g_setup_error = "null output pointer";
-    return ADR_EINVAL;
-  }
-  *out = nullptr;
-  adr_options defaults;
-  adr_default_options(&defaults);
-  const adr_options *o = opt ? opt : &defaults;
-  std::string err;
-  adr_status st = validate(prob, o, err);
-  if (st != ADR_OK) {
-    g_setup_error = err;
-    return st;
-  }
-  const double t0 = now_ms();
-  adr_ctx *ctx = new adr_ctx();
-  ctx->opt = *o;
-  ctx->stream = (hipStream_t)stream;
-  ctx->D = prob->ndim;
-  ctx->G0 = make_grid(ctx->D, prob->n);
-  ctx->h = prob->h;
-  ctx->omega = prob->omega;
-  for (int k = 0; k < 3; ++k) ctx->src[k] = (prob->src[0] >= 0 && k < ctx->D) ? prob->src[k] : 0;
-  if (prob->src[0] < 0) ctx->src[0] = -1;
-  ctx->levels = o->levels > 0 ? o->levels : auto_levels(ctx->D, prob->n, o->coarsest_max > 0 ? o->coarsest_max : 729);
-  for (int l = 0; l < kMaxLevels; ++l) {
-    ctx->nu[l] = o->nu[l];
-    ctx->relax[l] = o->relax[l];
-  }
-  st = check_levels(ctx);
-  if (st == ADR_OK) st = setup_impl(ctx, prob);
-  if (st != ADR_OK) {
-    g_setup_error = ctx->err;
-    free_ctx(ctx);
-    return st;
-  }
-  (void)t0;
-  *out = ctx;
-  return ADR_OK;
+  return setup_ctx(prob, opt, (hipStream_t)stream, nullptr, 0, false, out);
 }
 
 void adr_destroy(adr_ctx *ctx) {
@@ -1262,7 +1336,7 @@ int fine_residual64(adr_ctx *ctx, const cx<double> *x, const cx<double> *rhs, cx
     return adrk::fine_apply_adj<double, double, double>(ctx->stream, ctx->G0, ctx->D, C, P0, x, rhs, r, 1, nullptr,
                                                         true, ctx->part[0]);
   return adrk::fine_apply<double, double, double>(ctx->stream, ctx->G0, ctx->D, C, P0, x, rhs, r, 1, nullptr, true,
-                                                  ctx->part[0]);
+                                                  ctx->part[0], ctx->Pdev);
 }
 
 // Conjugate-transposed hierarchy, built on the first adjoint solve.
@@ -1319,6 +1393,7 @@ struct Solver {
   int nb = 0;
   double bnorm = 0, rnorm = 0, relres = 0, t0 = 0;
   int iters = 0, restarts = 0, j = 0, k = 0;
+  bool full = false;     // restart cycles always take m steps (shot groups run in lockstep)
   adr_status result = ADR_OK;
   std::complex<double> Hh[kMaxRestart + 1][kMaxRestart], g[kMaxRestart + 1], sn[kMaxRestart];
   double cs[kMaxRestart];
@@ -1331,30 +1406,54 @@ void *zslot(adr_ctx *ctx, int j) {
 }
 
 // Enqueue the action S.next (the cycle's first step also scales V0 = r / ||r||).
-adr_status solver_enqueue(Solver &S) {
+// One FGMRES action in three parts, so that a shot group can run the kernels once for
+// all its problems: solver_pre moves a problem's host-side inputs to the device,
+// solver_device enqueues the kernels (on the lead problem's buffers, shifted per problem
+// inside a shot-group launch), solver_post starts the read-backs of a problem's scalars.
+adr_status solver_pre(Solver &S) {
+  if (S.next != Solver::CYCLE_END) return ADR_OK;
   adr_ctx *ctx = S.ctx;
+  double *hp = ctx->hpin;
+  // y = R^{-1} g for the host's rotated Hessenberg, then to the device.
+  const int k = S.k;
+  std::complex<double> y[kMaxRestart];
+  for (int i = k - 1; i >= 0; --i) {
+    std::complex<double> acc = S.g[i];
+    for (int jj = i + 1; jj < k; ++jj) acc -= S.Hh[i][jj] * y[jj];
+    y[i] = (S.Hh[i][i] == 0.0) ? 0.0 : acc / S.Hh[i][i];
+  }
+  for (int i = 0; i < k; ++i) {
+    hp[kPinY + 2 * i] = y[i].real();
+    hp[kPinY + 2 * i + 1] = y[i].imag();
+  }
+  ADR_HIP(hipMemcpyAsync(ctx->osc + 48, hp + kPinY, 2 * k * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  return ADR_OK;
+}
+
+// A = the action (next, j, k, nb, guess); ctx, q, x = the lead problem's buffers.
+adr_status solver_device(const Solver &A, adr_ctx *ctx, const cx<double> *q, cx<double> *x) {
   hipStream_t s = ctx->stream;
   const int N = ctx->G0.N, D = ctx->D;
   const bool mixed = ctx->opt.prec == ADR_PREC_MIXED;
-  double *hp = ctx->hpin;
   auto Vp = [&](int j) { return ctx->Vo + (size_t)j * N; };
-  switch (S.next) {
+  switch (A.next) {
     case Solver::START: {
-      adrk::phase(s, N, S.q, ctx->tau, ctx->omega, +1, ctx->qh);
-      S.nb = adrk::norm2<double>(s, N, ctx->qh, nullptr, nullptr, ctx->part[0]);
-      ADR_HIP(hipMemcpyAsync(hp + kPinA, ctx->part[0], S.nb * sizeof(double), hipMemcpyDeviceToHost, s));
-      if (S.guess) {
-        fine_residual64(ctx, S.x, ctx->qh, ctx->ro);   // partials in part[0] after the copy above
-        ADR_HIP(hipMemcpyAsync(hp + kPinB, ctx->part[0], S.nb * sizeof(double), hipMemcpyDeviceToHost, s));
+      adrk::phase(s, N, q, ctx->tau, ctx->omega, +1, ctx->qh, &ctx->Pdev[0].omega);
+      adrk::norm2<double>(s, N, ctx->qh, nullptr, nullptr, ctx->part[0]);
+      if (A.guess) {
+        // ||q_hat|| is read back before the residual overwrites the partials.
+        ADR_HIP(hipMemcpyAsync(ctx->hpin + kPinA, ctx->part[0], A.nb * sizeof(double), hipMemcpyDeviceToHost, s));
+        fine_residual64(ctx, x, ctx->qh, ctx->ro);
       } else {
-        ADR_HIP(hipMemsetAsync(S.x, 0, sizeof(cx<double>) * N, s));
-        ADR_HIP(hipMemcpyAsync(ctx->ro, ctx->qh, sizeof(cx<double>) * N, hipMemcpyDeviceToDevice, s));
+        adrk::zero(s, N, x);
+        adrk::copy(s, N, ctx->qh, ctx->ro);
       }
       return ADR_OK;
     }
     case Solver::STEP: {
-      const int j = S.j;
-      if (j == 0) adrk::scale(s, N, ctx->ro, S.rnorm > 0.0 ? 1.0 / S.rnorm : 0.0, Vp(0));
+      const int j = A.j;
+      // V_0 = r / ||r||, the norm from the partials of the residual just computed.
+      if (j == 0) adrk::normalize(s, N, ctx->ro, ProIn{ctx->part[0], A.nb, 1}, Vp(0));
       ADR_TRY(precondition(ctx, Vp(j), zslot(ctx, j), !mixed));
       VecSet<double> Vs{};
       Vs.count = j + 1;
@@ -1369,57 +1468,72 @@ adr_status solver_enqueue(Solver &S) {
                                                          nullptr, ctx->wo, 0, &Vs, false, ctx->part[0]);
       else if (mixed)
         nb = adrk::fine_apply<double, float, double>(s, ctx->G0, D, C, P0, (const cx<float> *)zslot(ctx, j),
-                                                     nullptr, ctx->wo, 0, &Vs, false, ctx->part[0]);
+                                                     nullptr, ctx->wo, 0, &Vs, false, ctx->part[0], ctx->Pdev);
       else if (ctx->adj)
         nb = adrk::fine_apply_adj<double, double, double>(s, ctx->G0, D, C, P0,
                                                           (const cx<double> *)zslot(ctx, j), nullptr, ctx->wo, 0,
                                                           &Vs, false, ctx->part[0]);
       else
         nb = adrk::fine_apply<double, double, double>(s, ctx->G0, D, C, P0, (const cx<double> *)zslot(ctx, j),
-                                                      nullptr, ctx->wo, 0, &Vs, false, ctx->part[0]);
+                                                      nullptr, ctx->wo, 0, &Vs, false, ctx->part[0], ctx->Pdev);
       tend(ctx, t0, (double)N * (fine_coef_bytes<double>(D) + (mixed ? 8.0 : 16.0) + 16.0 * (j + 2)));
       int t1 = tbegin(ctx, ADR_TIMER_OUTER_ORTH, 0);
       nb = adrk::outer_orth1(s, N, ctx->wo, Vs, ProIn{ctx->part[0], nb, 2 * (j + 1)}, red1, ctx->part[1]);
       adrk::outer_orth2(s, N, ctx->wo, Vs, ProIn{ctx->part[1], nb, 2 * (j + 1) + 1}, red2, Vp(j + 1));
       tend(ctx, t1, (double)N * 16.0 * (2 * (j + 1) + 4));
-      const int nred = 2 * (kMaxRestart + 1) * 2 + 1;
-      ADR_HIP(hipMemcpyAsync(hp + kPinRed, red1, nred * sizeof(double), hipMemcpyDeviceToHost, s));
       return ADR_OK;
     }
     case Solver::CYCLE_END: {
-      // y = R^{-1} g, x += Z y, then the true residual.
-      const int k = S.k;
-      std::complex<double> y[kMaxRestart];
-      for (int i = k - 1; i >= 0; --i) {
-        std::complex<double> acc = S.g[i];
-        for (int jj = i + 1; jj < k; ++jj) acc -= S.Hh[i][jj] * y[jj];
-        y[i] = (S.Hh[i][i] == 0.0) ? 0.0 : acc / S.Hh[i][i];
-      }
-      for (int i = 0; i < k; ++i) {
-        hp[kPinY + 2 * i] = y[i].real();
-        hp[kPinY + 2 * i + 1] = y[i].imag();
-      }
+      // x += Z y (y uploaded by solver_pre), then the true residual.
+      const int k = A.k;
       double *ydev = ctx->osc + 48;
-      ADR_HIP(hipMemcpyAsync(ydev, hp + kPinY, 2 * k * sizeof(double), hipMemcpyHostToDevice, s));
       if (mixed) {
         VecSet<float> Zs{};
         Zs.count = k;
         for (int i = 0; i < k; ++i) Zs.v[i] = (const cx<float> *)zslot(ctx, i);
-        adrk::multi_axpy<float>(s, N, S.x, Zs, ydev);
+        adrk::multi_axpy<float>(s, N, x, Zs, ydev);
       } else {
         VecSet<double> Zs{};
         Zs.count = k;
         for (int i = 0; i < k; ++i) Zs.v[i] = (const cx<double> *)zslot(ctx, i);
-        adrk::multi_axpy<double>(s, N, S.x, Zs, ydev);
+        adrk::multi_axpy<double>(s, N, x, Zs, ydev);
       }
-      S.nb = fine_residual64(ctx, S.x, ctx->qh, ctx->ro);
-      ADR_HIP(hipMemcpyAsync(hp + kPinA, ctx->part[0], S.nb * sizeof(double), hipMemcpyDeviceToHost, s));
+      fine_residual64(ctx, x, ctx->qh, ctx->ro);
       return ADR_OK;
     }
     case Solver::DONE:
       return ADR_OK;
   }
   return ADR_OK;
+}
+
+adr_status solver_post(Solver &S) {
+  adr_ctx *ctx = S.ctx;
+  hipStream_t s = ctx->stream;
+  double *hp = ctx->hpin;
+  switch (S.next) {
+    case Solver::START:
+      ADR_HIP(hipMemcpyAsync(hp + (S.guess ? kPinB : kPinA), ctx->part[0], S.nb * sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+      return ADR_OK;
+    case Solver::STEP: {
+      const int nred = 2 * (kMaxRestart + 1) * 2 + 1;
+      ADR_HIP(hipMemcpyAsync(hp + kPinRed, ctx->osc + 2, nred * sizeof(double), hipMemcpyDeviceToHost, s));
+      return ADR_OK;
+    }
+    case Solver::CYCLE_END:
+      ADR_HIP(hipMemcpyAsync(hp + kPinA, ctx->part[0], S.nb * sizeof(double), hipMemcpyDeviceToHost, s));
+      return ADR_OK;
+    case Solver::DONE:
+      return ADR_OK;
+  }
+  return ADR_OK;
+}
+
+adr_status solver_enqueue(Solver &S) {
+  ADR_TRY(solver_pre(S));
+  ADR_TRY(solver_device(S, S.ctx, S.q, S.x));
+  return solver_post(S);
 }
 
 // Consume the read-back of the last action (its stream has been synchronized) and set
@@ -1492,7 +1606,7 @@ void solver_finish(Solver &S) {
       if (!std::isfinite(est)) {
         S.result = ADR_ENUMERIC;
         S.next = Solver::DONE;
-      } else if (est <= S.tol || S.iters >= S.maxit || j == m - 1) {
+      } else if ((!S.full && (est <= S.tol || S.iters >= S.maxit)) || j == m - 1) {
         S.k = j + 1;
         S.next = Solver::CYCLE_END;
       } else {
@@ -1514,6 +1628,8 @@ void solver_finish(Solver &S) {
 
 void solver_init(Solver &S, adr_ctx *ctx, const void *q, void *a_out, double tol, int maxit, int guess) {
   S.ctx = ctx;
+  S.nb = launch_blocks_red(ctx->G0.N);   // block count of every norm reduction over the fine grid
+  S.full = ctx->opt.full_cycles != 0;
   S.q = (const cx<double> *)q;
   S.x = (cx<double> *)a_out;
   S.tol = tol;
@@ -1613,27 +1729,45 @@ adr_status adr_adjoint_source(adr_ctx *ctx, const int *idx, const void *r, int n
 }
 
 // ---------------------------------------------------------------------------------------
-// Batched shots: many independent problems.  Each shot has its own context; the contexts
-// are spread over `nstreams` streams (shots on one stream run one after another, shots
-// on different streams overlap on the GPU).  The host advances every shot on its own:
-// after enqueuing a shot's next FGMRES action it records an event, and whichever shot's
-// event has completed is finished (its read-back consumed) and re-enqueued, with no
-// barrier across shots; converged shots drop out.
+// Batched shots.  Problems with the same grid shape form a shot group: their contexts
+// are built in one arena, one slot per problem at a constant stride, so every kernel of
+// an FGMRES action runs once for the whole group (blockIdx.y = problem, see Shot) on the
+// group's stream, V-cycles included (captured per group).  The FGMRES state machines stay
+// per problem on the host; restart cycles always take m steps so that the problems of a
+// group stay in lockstep (same action, same Arnoldi index), and a converged problem is
+// switched off by its device flag.  Groups advance independently: the host finishes
+// whichever group's last action has completed and enqueues its next one.
 // ---------------------------------------------------------------------------------------
 }  // extern "C"
 
 struct adr_batch {
-  std::vector<adr_ctx *> ctx;
+  struct Group {
+    std::vector<int> members;   // batch indices, slot order
+    char *arena = nullptr;
+    size_t stride = 0;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr;
+  };
+  std::vector<adr_ctx *> ctx;   // per problem (contexts live in their group's arena)
+  std::vector<Group> groups;
   std::vector<hipStream_t> streams;
-  std::vector<hipEvent_t> events;   // one per shot: end of its last enqueued action
+  int *pin_flags = nullptr;     // pinned host ints {0, 1} for the device flags
   std::string err;
 };
 
-#define ADR_BATCH_TRY(expr)         \
-  do {                              \
-    adr_status st_ = (expr);        \
-    if (st_ != ADR_OK) return st_;  \
-  } while (0)
+namespace {
+void free_batch(adr_batch *b) {
+  if (!b) return;
+  for (adr_ctx *c : b->ctx) adr_destroy(c);
+  for (auto &g : b->groups) {
+    if (g.ev) hipEventDestroy(g.ev);
+    if (g.arena) hipFree(g.arena);
+  }
+  for (hipStream_t s : b->streams) hipStreamDestroy(s);
+  if (b->pin_flags) hipHostFree(b->pin_flags);
+  delete b;
+}
+}  // namespace
 
 extern "C" {
 
@@ -1646,24 +1780,55 @@ adr_status adr_setup_batch(int count, const adr_problem *probs, const adr_option
     return ADR_EINVAL;
   }
   adr_batch *b = new adr_batch();
+  auto fail = [&](adr_status st, const std::string &msg) {
+    g_setup_error = msg;
+    free_batch(b);
+    return st;
+  };
+  if (hipHostMalloc((void **)&b->pin_flags, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess)
+    return fail(ADR_ENOMEM, "hipHostMalloc failed");
+  b->pin_flags[0] = 0;
+  b->pin_flags[1] = 1;
   for (int i = 0; i < nstreams; ++i) {
     hipStream_t s;
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
-      g_setup_error = "hipStreamCreate failed";
-      adr_destroy_batch(b);
-      return ADR_EHIP;
-    }
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return fail(ADR_EHIP, "hipStreamCreate failed");
     b->streams.push_back(s);
   }
+  // Group by grid shape (first-appearance order).
+  std::map<std::array<int, 4>, int> key_to_group;
   for (int i = 0; i < count; ++i) {
-    adr_ctx *c = nullptr;
-    adr_status st = adr_setup(&probs[i], opt, b->streams[i % nstreams], &c);
-    if (st != ADR_OK) {
-      g_setup_error = "shot " + std::to_string(i) + ": " + g_setup_error;
-      adr_destroy_batch(b);
-      return st;
+    const adr_problem &p = probs[i];
+    const std::array<int, 4> key = {p.ndim, p.n[0], p.n[1], p.ndim == 3 ? p.n[2] : 1};
+    auto it = key_to_group.find(key);
+    if (it == key_to_group.end()) {
+      it = key_to_group.emplace(key, (int)b->groups.size()).first;
+      b->groups.emplace_back();
     }
-    b->ctx.push_back(c);
+    b->groups[it->second].members.push_back(i);
+  }
+  b->ctx.assign(count, nullptr);
+  for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+    auto &g = b->groups[gi];
+    g.stream = b->streams[gi % b->streams.size()];
+    if (hipEventCreateWithFlags(&g.ev, hipEventDisableTiming) != hipSuccess) return fail(ADR_EHIP, "hipEventCreate failed");
+    // Slot size: build the first problem once with ordinary allocations and count.
+    adr_ctx *m = nullptr;
+    adr_status st = setup_ctx(&probs[g.members[0]], opt, g.stream, nullptr, 0, true, &m);
+    if (st != ADR_OK) return fail(st, "shot " + std::to_string(g.members[0]) + ": " + g_setup_error);
+    const size_t need = m->alloc_need;
+    adr_destroy(m);
+    g.stride = (need + 65535) & ~(size_t)65535;
+    if (hipMalloc((void **)&g.arena, g.stride * g.members.size()) != hipSuccess)
+      return fail(ADR_ENOMEM, "shot-group arena of " + std::to_string(g.stride * g.members.size()) + " bytes");
+    for (size_t k = 0; k < g.members.size(); ++k) {
+      const int i = g.members[k];
+      adr_ctx *c = nullptr;
+      st = setup_ctx(&probs[i], opt, g.stream, g.arena + k * g.stride, g.stride, true, &c);
+      if (st != ADR_OK) return fail(st, "shot " + std::to_string(i) + ": " + g_setup_error);
+      b->ctx[i] = c;
+      if (c->arena_off != need)
+        return fail(ADR_EINVAL, "shot " + std::to_string(i) + ": layout differs from its group's first problem");
+    }
   }
   *out = b;
   return ADR_OK;
@@ -1683,54 +1848,92 @@ adr_status adr_solve_batch(adr_batch *b, const void *const *q, void *const *a, d
   for (int i = 0; i < n; ++i)
     if (!q[i] || !a[i]) return ADR_EINVAL;
   std::vector<Solver> S(n);
-  if (b->events.size() < (size_t)n) {
-    for (size_t i = b->events.size(); i < (size_t)n; ++i) {
-      hipEvent_t e;
-      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-        b->err = "hipEventCreate failed";
-        return ADR_EHIP;
-      }
-      b->events.push_back(e);
-    }
-  }
-  // Enqueue one action of shot i and mark its end; false on error.
-  auto launch = [&](int i) -> adr_status {
-    adr_status st = solver_enqueue(S[i]);
-    if (st != ADR_OK) {
-      b->err = "shot " + std::to_string(i) + ": " + b->ctx[i]->err;
-      return st;
-    }
-    if (hipEventRecord(b->events[i], b->ctx[i]->stream) != hipSuccess) {
-      b->err = "hipEventRecord failed";
-      return ADR_EHIP;
-    }
-    return ADR_OK;
+  const size_t vbytes = sizeof(cx<double>);
+  auto hip_fail = [&](const char *what, hipError_t e) {
+    b->err = std::string(what) + ": " + hipGetErrorString(e);
+    return ADR_EHIP;
   };
-  int active = 0;
-  for (int i = 0; i < n; ++i) {
-    b->ctx[i]->adj = false;
-    solver_init(S[i], b->ctx[i], q[i], a[i], tol, maxit, 0);
-    if (S[i].next != Solver::DONE) {
-      ADR_BATCH_TRY(launch(i));
-      ++active;
+  // Problem inputs into the arena, flags on, state machines at START.
+  for (auto &g : b->groups)
+    for (int i : g.members) {
+      adr_ctx *c = b->ctx[i];
+      c->adj = false;
+      hipError_t e = hipMemcpyAsync(c->qin, q[i], vbytes * c->G0.N, hipMemcpyDeviceToDevice, g.stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(c->active, b->pin_flags + 1, sizeof(int), hipMemcpyHostToDevice, g.stream);
+      if (e != hipSuccess) return hip_fail("batch input copy", e);
+      solver_init(S[i], c, c->qin, c->xg, tol, maxit, 0);
+      S[i].full = true;
     }
-  }
-  while (active > 0) {
-    bool progressed = false;
-    for (int i = 0; i < n; ++i) {
-      if (S[i].next == Solver::DONE) continue;
-      hipError_t e = hipEventQuery(b->events[i]);
-      if (e == hipErrorNotReady) continue;
-      if (e != hipSuccess) {
-        b->err = std::string("shot ") + std::to_string(i) + ": " + hipGetErrorString(e);
-        return ADR_EHIP;
+  // Enqueue the next action of group g for its live problems; false when none is left.
+  auto launch = [&](adr_batch::Group &g, adr_status &st) -> bool {
+    std::vector<int> live;
+    for (int i : g.members)
+      if (S[i].next != Solver::DONE) live.push_back(i);
+    if (live.empty()) return false;
+    const Solver &A = S[live[0]];
+    for (int i : live)
+      if (S[i].next != A.next || S[i].j != A.j || (A.next == Solver::CYCLE_END && S[i].k != A.k)) {
+        b->err = "shot group out of lockstep";
+        st = ADR_ENUMERIC;
+        return false;
       }
+    for (int i : live)
+      if ((st = solver_pre(S[i])) != ADR_OK) return false;
+    adr_ctx *lead = b->ctx[g.members[0]];
+    adrk::g_shot.count = (int)g.members.size();
+    adrk::g_shot.sh = Shot{(long long)g.stride, lead->active};
+    st = solver_device(A, lead, lead->qin, lead->xg);
+    adrk::g_shot = adrk::ShotLaunch{};
+    if (st != ADR_OK) {
+      b->err = lead->err;
+      return false;
+    }
+    for (int i : live)
+      if ((st = solver_post(S[i])) != ADR_OK) return false;
+    hipError_t e = hipEventRecord(g.ev, g.stream);
+    if (e != hipSuccess) {
+      st = hip_fail("hipEventRecord", e);
+      return false;
+    }
+    return true;
+  };
+  std::vector<char> busy(b->groups.size(), 0);
+  int running = 0;
+  for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+    adr_status st = ADR_OK;
+    busy[gi] = launch(b->groups[gi], st);
+    if (st != ADR_OK) return st;
+    running += busy[gi];
+  }
+  while (running > 0) {
+    bool progressed = false;
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+      if (!busy[gi]) continue;
+      auto &g = b->groups[gi];
+      hipError_t e = hipEventQuery(g.ev);
+      if (e == hipErrorNotReady) continue;
+      if (e != hipSuccess) return hip_fail("batch", e);
       progressed = true;
-      solver_finish(S[i]);
-      if (S[i].next == Solver::DONE) --active;
-      else ADR_BATCH_TRY(launch(i));
+      for (int i : g.members) {
+        if (S[i].next == Solver::DONE) continue;
+        solver_finish(S[i]);
+        if (S[i].next == Solver::DONE) {
+          adr_ctx *c = b->ctx[i];
+          e = hipMemcpyAsync(c->active, b->pin_flags, sizeof(int), hipMemcpyHostToDevice, g.stream);
+          if (e == hipSuccess) e = hipMemcpyAsync(a[i], c->xg, vbytes * c->G0.N, hipMemcpyDeviceToDevice, g.stream);
+          if (e != hipSuccess) return hip_fail("batch result copy", e);
+        }
+      }
+      adr_status st = ADR_OK;
+      busy[gi] = launch(g, st);
+      if (st != ADR_OK) return st;
+      if (!busy[gi]) --running;
     }
     if (!progressed) std::this_thread::yield();
+  }
+  for (auto &g : b->groups) {
+    hipError_t e = hipStreamSynchronize(g.stream);
+    if (e != hipSuccess) return hip_fail("batch synchronization", e);
   }
   adr_status worst = ADR_OK;
   for (int i = 0; i < n; ++i) {
@@ -1740,13 +1943,7 @@ adr_status adr_solve_batch(adr_batch *b, const void *const *q, void *const *a, d
   return worst;
 }
 
-void adr_destroy_batch(adr_batch *b) {
-  if (!b) return;
-  for (adr_ctx *c : b->ctx) adr_destroy(c);
-  for (hipEvent_t e : b->events) hipEventDestroy(e);
-  for (hipStream_t s : b->streams) hipStreamDestroy(s);
-  delete b;
-}
+void adr_destroy_batch(adr_batch *b) { free_batch(b); }
 
 adr_status adr_timer_start(adr_ctx *ctx, int kind, int level) {
   if (!ctx || kind < 0 || kind > ADR_TIMER_COARSE_TAIL) return ADR_EINVAL;

@@ -138,6 +138,27 @@ inline int launch_blocks_red(long long N) {
   return (int)b;
 }
 
+// ------------------------------------------------------------------------------------
+// Shot groups.  One launch can serve `count` problems whose device data are laid out at a
+// constant byte stride (one arena slot per problem): blockIdx.y is the problem, every
+// pointer argument refers to problem 0 and is shifted by blockIdx.y * stride, and a
+// problem whose flag (an int at `active` + blockIdx.y * stride) is 0 exits at once.
+// stride = 0, active = NULL is an ordinary single-problem launch.
+// ------------------------------------------------------------------------------------
+struct Shot {
+  long long stride;
+  const int *active;
+};
+template <typename P>
+__device__ __forceinline__ P *shot_ptr(P *p, long long off) {
+  return p ? (P *)((char *)p + off) : p;
+}
+// Declares shot_off_ and returns from inactive problems (uniform per block).
+#define ADR_SHOT_ENTER(sh)                                                                \
+  const long long shot_off_ = (long long)blockIdx.y * (sh).stride;                      \
+  if ((sh).active && !*(const int *)((const char *)(sh).active + shot_off_)) return
+#define ADR_SHIFT(p) ((p) = shot_ptr((p), shot_off_))
+
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
   return v;

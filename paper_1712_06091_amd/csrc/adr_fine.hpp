@@ -31,6 +31,15 @@ struct FineParams {
   int src[3];      // source node; src[0] < 0: no near-source rule
 };
 
+// Shift the coefficient planes to problem blockIdx.y of a shot group (see Shot).
+template <typename T>
+__device__ __forceinline__ void shift_fine_coef(FineCoef<T> &C, long long off) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) C.g[k] = shot_ptr(C.g[k], off);
+  C.L = shot_ptr(C.L, off);
+  C.c = shot_ptr(C.c, off);
+}
+
 template <typename T, int D>
 __device__ __forceinline__ void fine_row(const Grid &G, const FineParams &P, int idx[3], const T gk[3],
                                          T L, cx<T> c, cx<T> (&e)[1 + 4 * D]) {

@@ -10,8 +10,13 @@
 
 namespace adrk {
 
+thread_local ShotLaunch g_shot;
+
 #define ADR_LAUNCH(kernel, nblocks, stream, ...) \
   hipLaunchKernelGGL(kernel, dim3(nblocks), dim3(ADR_BLOCK), 0, stream, __VA_ARGS__)
+// Group-capable kernels: one y-slice of blocks per problem of the current shot group.
+#define ADR_LAUNCH_S(kernel, nblocks, stream, ...) \
+  hipLaunchKernelGGL(kernel, dim3(nblocks, g_shot.count), dim3(ADR_BLOCK), 0, stream, __VA_ARGS__, g_shot.sh)
 
 // =====================================================================================
 // Setup: coefficients from tau (Sec. 2.1, eq. travel_time_coeff)
@@ -202,13 +207,16 @@ template void stencil_diag_inv<double>(hipStream_t, int, const cx<double> *, cx<
 template void stencil_diag_inv<float>(hipStream_t, int, const cx<float> *, cx<float> *);
 
 template <typename To, typename Ti>
-__global__ __launch_bounds__(ADR_BLOCK) void k_convert(long long n, const cx<Ti> *in, cx<To> *out) {
+__global__ __launch_bounds__(ADR_BLOCK) void k_convert(long long n, const cx<Ti> *in, cx<To> *out, Shot sh) {
+  ADR_SHOT_ENTER(sh);
+  ADR_SHIFT(in);
+  ADR_SHIFT(out);
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     out[i] = cvt<To, Ti>(in[i]);
 }
 template <typename To, typename Ti>
 void convert(hipStream_t s, long long n, const cx<Ti> *in, cx<To> *out) {
-  ADR_LAUNCH((k_convert<To, Ti>), launch_blocks(n), s, n, in, out);
+  ADR_LAUNCH_S((k_convert<To, Ti>), launch_blocks(n), s, n, in, out);
 }
 template void convert<float, double>(hipStream_t, long long, const cx<double> *, cx<float> *);
 template void convert<double, float>(hipStream_t, long long, const cx<float> *, cx<double> *);
@@ -232,7 +240,16 @@ template <typename T, typename Tin, typename To, int D, int NV, bool NORM>
 __global__ __launch_bounds__(ADR_BLOCK) void k_fine_apply(Grid G, FineCoef<T> C, FineParams P,
                                                           const cx<Tin> *__restrict__ x,
                                                           const cx<To> *__restrict__ b, cx<To> *__restrict__ y,
-                                                          int mode, VecSet<To> V, double *pout) {
+                                                          int mode, VecSet<To> V, double *pout,
+                                                          const FineParams *Pd, Shot sh) {
+  ADR_SHOT_ENTER(sh);
+  shift_fine_coef(C, shot_off_);
+  if (Pd) P = *shot_ptr(Pd, shot_off_);
+  ADR_SHIFT(x);
+  ADR_SHIFT(b);
+  ADR_SHIFT(y);
+  shift_set<NV>(V, shot_off_);
+  ADR_SHIFT(pout);
   constexpr int K = 2 * NV + (NORM ? 1 : 0);
   constexpr int KA = K > 0 ? K : 1;
   double red[KA];
@@ -275,17 +292,17 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_fine_apply(Grid G, FineCoef<T> C,
 template <typename T, typename Tin, typename To, int D, int NV, bool NORM>
 static void launch_fine_apply(hipStream_t s, int nb, const Grid &G, const FineCoef<T> &C, const FineParams &P,
                               const cx<Tin> *x, const cx<To> *b, cx<To> *y, int mode, const VecSet<To> &V,
-                              double *pout) {
-  ADR_LAUNCH((k_fine_apply<T, Tin, To, D, NV, NORM>), nb, s, G, C, P, x, b, y, mode, V, pout);
+                              double *pout, const FineParams *Pd) {
+  ADR_LAUNCH_S((k_fine_apply<T, Tin, To, D, NV, NORM>), nb, s, G, C, P, x, b, y, mode, V, pout, Pd);
 }
 
 template <typename T, typename Tin, typename To, int D, bool NORM>
 static void dispatch_fine_apply_nv(hipStream_t s, int nb, const Grid &G, const FineCoef<T> &C,
                                    const FineParams &P, const cx<Tin> *x, const cx<To> *b, cx<To> *y, int mode,
-                                   const VecSet<To> &V, double *pout) {
+                                   const VecSet<To> &V, double *pout, const FineParams *Pd) {
   switch (V.count) {
 #define ADR_NV_CASE(n) \
-  case n: launch_fine_apply<T, Tin, To, D, n, NORM>(s, nb, G, C, P, x, b, y, mode, V, pout); break;
+  case n: launch_fine_apply<T, Tin, To, D, n, NORM>(s, nb, G, C, P, x, b, y, mode, V, pout, Pd); break;
     ADR_NV_CASE(0) ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6)
     ADR_NV_CASE(7) ADR_NV_CASE(8)
 #undef ADR_NV_CASE
@@ -295,35 +312,45 @@ static void dispatch_fine_apply_nv(hipStream_t s, int nb, const Grid &G, const F
 
 template <typename T, typename Tin, typename To>
 int fine_apply(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P, const cx<Tin> *x,
-               const cx<To> *b, cx<To> *y, int mode, const VecSet<To> *dots, bool want_norm, double *pout) {
+               const cx<To> *b, cx<To> *y, int mode, const VecSet<To> *dots, bool want_norm, double *pout,
+               const FineParams *Pd) {
   VecSet<To> V{};
   if (dots) V = *dots;
   const bool red = want_norm || V.count > 0;
   const int nb = red ? launch_blocks_red(G.N) : launch_blocks(G.N);
   if (D == 2) {
-    if (want_norm) dispatch_fine_apply_nv<T, Tin, To, 2, true>(s, nb, G, C, P, x, b, y, mode, V, pout);
-    else dispatch_fine_apply_nv<T, Tin, To, 2, false>(s, nb, G, C, P, x, b, y, mode, V, pout);
+    if (want_norm) dispatch_fine_apply_nv<T, Tin, To, 2, true>(s, nb, G, C, P, x, b, y, mode, V, pout, Pd);
+    else dispatch_fine_apply_nv<T, Tin, To, 2, false>(s, nb, G, C, P, x, b, y, mode, V, pout, Pd);
   } else {
-    if (want_norm) dispatch_fine_apply_nv<T, Tin, To, 3, true>(s, nb, G, C, P, x, b, y, mode, V, pout);
-    else dispatch_fine_apply_nv<T, Tin, To, 3, false>(s, nb, G, C, P, x, b, y, mode, V, pout);
+    if (want_norm) dispatch_fine_apply_nv<T, Tin, To, 3, true>(s, nb, G, C, P, x, b, y, mode, V, pout, Pd);
+    else dispatch_fine_apply_nv<T, Tin, To, 3, false>(s, nb, G, C, P, x, b, y, mode, V, pout, Pd);
   }
   return nb;
 }
 template int fine_apply<double, double, double>(hipStream_t, const Grid &, int, const FineCoef<double> &,
                                                 const FineParams &, const cx<double> *, const cx<double> *,
-                                                cx<double> *, int, const VecSet<double> *, bool, double *);
+                                                cx<double> *, int, const VecSet<double> *, bool, double *,
+                                                const FineParams *);
 template int fine_apply<double, float, double>(hipStream_t, const Grid &, int, const FineCoef<double> &,
                                                const FineParams &, const cx<float> *, const cx<double> *,
-                                               cx<double> *, int, const VecSet<double> *, bool, double *);
+                                               cx<double> *, int, const VecSet<double> *, bool, double *,
+                                               const FineParams *);
 template int fine_apply<float, float, float>(hipStream_t, const Grid &, int, const FineCoef<float> &,
                                              const FineParams &, const cx<float> *, const cx<float> *,
-                                             cx<float> *, int, const VecSet<float> *, bool, double *);
+                                             cx<float> *, int, const VecSet<float> *, bool, double *,
+                                             const FineParams *);
 
 template <typename T, int D>
 __global__ __launch_bounds__(ADR_BLOCK) void k_fine_jacobi(Grid G, FineCoef<T> C, FineParams P,
                                                            const cx<T> *__restrict__ xin,
                                                            const cx<T> *__restrict__ b, cx<T> *__restrict__ xout,
-                                                           T weight) {
+                                                           T weight, const FineParams *Pd, Shot sh) {
+  ADR_SHOT_ENTER(sh);
+  shift_fine_coef(C, shot_off_);
+  if (Pd) P = *shot_ptr(Pd, shot_off_);
+  ADR_SHIFT(xin);
+  ADR_SHIFT(b);
+  ADR_SHIFT(xout);
   int beg, end;
   chunk_range(G.N, beg, end);
   for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
@@ -358,15 +385,15 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_fine_jacobi(Grid G, FineCoef<T> C
 
 template <typename T>
 void fine_jacobi(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P, const cx<T> *x_in,
-                 const cx<T> *b, cx<T> *x_out, double weight) {
+                 const cx<T> *b, cx<T> *x_out, double weight, const FineParams *Pd) {
   int nb = launch_blocks(G.N);
-  if (D == 2) ADR_LAUNCH((k_fine_jacobi<T, 2>), nb, s, G, C, P, x_in, b, x_out, (T)weight);
-  else ADR_LAUNCH((k_fine_jacobi<T, 3>), nb, s, G, C, P, x_in, b, x_out, (T)weight);
+  if (D == 2) ADR_LAUNCH_S((k_fine_jacobi<T, 2>), nb, s, G, C, P, x_in, b, x_out, (T)weight, Pd);
+  else ADR_LAUNCH_S((k_fine_jacobi<T, 3>), nb, s, G, C, P, x_in, b, x_out, (T)weight, Pd);
 }
 template void fine_jacobi<double>(hipStream_t, const Grid &, int, const FineCoef<double> &, const FineParams &,
-                                  const cx<double> *, const cx<double> *, cx<double> *, double);
+                                  const cx<double> *, const cx<double> *, cx<double> *, double, const FineParams *);
 template void fine_jacobi<float>(hipStream_t, const Grid &, int, const FineCoef<float> &, const FineParams &,
-                                 const cx<float> *, const cx<float> *, cx<float> *, double);
+                                 const cx<float> *, const cx<float> *, cx<float> *, double, const FineParams *);
 
 // The coarse stencil set: offsets with |d_k| <= 2 and at most one |d_k| == 2, ordered
 // dz-major then dy then dx (81 points in 3D, 21 in 2D).  Compile-time table so that the
@@ -615,7 +642,9 @@ void receiver_residual(hipStream_t s, int nrec, const int *idx, const cx<double>
   hipLaunchKernelGGL(k_receiver_residual, dim3((nrec + ADR_BLOCK - 1) / ADR_BLOCK), dim3(ADR_BLOCK), 0, s, nrec, idx,
                      u, d, r);
 }
-__global__ __launch_bounds__(ADR_BLOCK) void k_zero(long long n, cx<double> *x) {
+__global__ __launch_bounds__(ADR_BLOCK) void k_zero(long long n, cx<double> *x, Shot sh) {
+  ADR_SHOT_ENTER(sh);
+  ADR_SHIFT(x);
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     x[i] = mk<double>(0.0, 0.0);
 }
@@ -626,10 +655,20 @@ __global__ void k_scatter_add(int nrec, const int *__restrict__ idx, const cx<do
     for (int k = 0; k < nrec; ++k) s[idx[k]] = s[idx[k]] + r[k];
 }
 void adjoint_source(hipStream_t s, int N, int nrec, const int *idx, const cx<double> *r, cx<double> *src) {
-  ADR_LAUNCH(k_zero, launch_blocks(N), s, (long long)N, src);
+  ADR_LAUNCH_S(k_zero, launch_blocks(N), s, (long long)N, src);
   hipLaunchKernelGGL(k_scatter_add, dim3(1), dim3(64), 0, s, nrec, idx, r, src);
 }
-void zero(hipStream_t s, long long n, cx<double> *x) { ADR_LAUNCH(k_zero, launch_blocks(n), s, n, x); }
+void zero(hipStream_t s, long long n, cx<double> *x) { ADR_LAUNCH_S(k_zero, launch_blocks(n), s, n, x); }
+__global__ __launch_bounds__(ADR_BLOCK) void k_copy(long long n, const cx<double> *in, cx<double> *out, Shot sh) {
+  ADR_SHOT_ENTER(sh);
+  ADR_SHIFT(in);
+  ADR_SHIFT(out);
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    out[i] = in[i];
+}
+void copy(hipStream_t s, long long n, const cx<double> *in, cx<double> *out) {
+  ADR_LAUNCH_S(k_copy, launch_blocks(n), s, n, in, out);
+}
 
 // =====================================================================================
 // Coarse levels: stored Galerkin stencils (SoA planes)
@@ -713,7 +752,20 @@ __global__ __launch_bounds__(ADR_BLOCK) __attribute__((amdgpu_waves_per_eu(1, 4)
                                                             double *norm_out, int norm_cplx, double *inv_out,
                                                             const cx<T> *__restrict__ b, cx<T> *__restrict__ y,
                                                             const cx<T> *__restrict__ dinv, cx<T> *__restrict__ zout,
-                                                            int mode, VecSet<T> V, double *pout) {
+                                                            int mode, VecSet<T> V, double *pout, Shot sh) {
+  ADR_SHOT_ENTER(sh);
+  ADR_SHIFT(planes);
+  ADR_SHIFT(x);
+  ADR_SHIFT(pin.partials);
+  ADR_SHIFT(sdev);
+  ADR_SHIFT(norm_out);
+  ADR_SHIFT(inv_out);
+  ADR_SHIFT(b);
+  ADR_SHIFT(y);
+  ADR_SHIFT(dinv);
+  ADR_SHIFT(zout);
+  shift_set<NV>(V, shot_off_);
+  ADR_SHIFT(pout);
   constexpr int K = 2 * NV + (NORM ? 1 : 0);
   constexpr int KA = K > 0 ? K : 1;
   __shared__ double tot[1];
@@ -794,7 +846,7 @@ static void dispatch_coarse_nv(hipStream_t s, int nb, const CoarseArgs<T> &a, co
   switch (V.count) {
 #define ADR_NV_CASE(n)                                                                                              \
   case n:                                                                                                           \
-    ADR_LAUNCH((k_coarse_apply<T, D, n, NORM, SPLIT>), nb, s, a.G, a.planes, a.x, a.pin, a.sdev, a.norm_out,        \
+    ADR_LAUNCH_S((k_coarse_apply<T, D, n, NORM, SPLIT>), nb, s, a.G, a.planes, a.x, a.pin, a.sdev, a.norm_out,      \
                a.norm_cplx, a.inv_out, a.b, a.y, a.dinv, a.zout, a.mode, V, a.pout);                               \
     break;
     ADR_NV_CASE(0) ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6)
@@ -865,7 +917,13 @@ __device__ __forceinline__ cx<T> restrict_value(const Grid &Gf, const Grid &Gc, 
 template <typename T, int D>
 __global__ __launch_bounds__(ADR_BLOCK) void k_restrict(Grid Gf, Grid Gc, const cx<T> *__restrict__ rf,
                                                         cx<T> *__restrict__ rc, const cx<T> *__restrict__ dinv_c,
-                                                        cx<T> *__restrict__ z_c, double *pout) {
+                                                        cx<T> *__restrict__ z_c, double *pout, Shot sh) {
+  ADR_SHOT_ENTER(sh);
+  ADR_SHIFT(rf);
+  ADR_SHIFT(rc);
+  ADR_SHIFT(dinv_c);
+  ADR_SHIFT(z_c);
+  ADR_SHIFT(pout);
   double red[1] = {0.0};
   int beg, end;
   chunk_range(Gc.N, beg, end);
@@ -884,8 +942,8 @@ template <typename T>
 int restrict_full(hipStream_t s, const Grid &Gf, const Grid &Gc, int D, const cx<T> *rf, cx<T> *rc,
                   const cx<T> *dinv_c, cx<T> *z_c, double *pout) {
   int nb = pout ? launch_blocks_red(Gc.N) : launch_blocks(Gc.N);
-  if (D == 2) ADR_LAUNCH((k_restrict<T, 2>), nb, s, Gf, Gc, rf, rc, dinv_c, z_c, pout);
-  else ADR_LAUNCH((k_restrict<T, 3>), nb, s, Gf, Gc, rf, rc, dinv_c, z_c, pout);
+  if (D == 2) ADR_LAUNCH_S((k_restrict<T, 2>), nb, s, Gf, Gc, rf, rc, dinv_c, z_c, pout);
+  else ADR_LAUNCH_S((k_restrict<T, 3>), nb, s, Gf, Gc, rf, rc, dinv_c, z_c, pout);
   return nb;
 }
 template int restrict_full<double>(hipStream_t, const Grid &, const Grid &, int, const cx<double> *, cx<double> *,
@@ -914,7 +972,10 @@ __device__ __forceinline__ cx<T> prolong_value(const Grid &Gf, const Grid &Gc, c
 
 template <typename T, int D>
 __global__ __launch_bounds__(ADR_BLOCK) void k_prolong_add(Grid Gf, Grid Gc, const cx<T> *__restrict__ ec,
-                                                           cx<T> *__restrict__ xf) {
+                                                           cx<T> *__restrict__ xf, Shot sh) {
+  ADR_SHOT_ENTER(sh);
+  ADR_SHIFT(ec);
+  ADR_SHIFT(xf);
   int beg, end;
   chunk_range(Gf.N, beg, end);
   for (int f = beg + threadIdx.x; f < end; f += blockDim.x) xf[f] = xf[f] + prolong_value<T, D>(Gf, Gc, ec, f);
@@ -923,8 +984,8 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_prolong_add(Grid Gf, Grid Gc, con
 template <typename T>
 void prolong_add(hipStream_t s, const Grid &Gf, const Grid &Gc, int D, const cx<T> *ec, cx<T> *xf) {
   int nb = launch_blocks(Gf.N);
-  if (D == 2) ADR_LAUNCH((k_prolong_add<T, 2>), nb, s, Gf, Gc, ec, xf);
-  else ADR_LAUNCH((k_prolong_add<T, 3>), nb, s, Gf, Gc, ec, xf);
+  if (D == 2) ADR_LAUNCH_S((k_prolong_add<T, 2>), nb, s, Gf, Gc, ec, xf);
+  else ADR_LAUNCH_S((k_prolong_add<T, 3>), nb, s, Gf, Gc, ec, xf);
 }
 template void prolong_add<double>(hipStream_t, const Grid &, const Grid &, int, const cx<double> *, cx<double> *);
 template void prolong_add<float>(hipStream_t, const Grid &, const Grid &, int, const cx<float> *, cx<float> *);
@@ -939,7 +1000,17 @@ template <typename T, int NV>
 __global__ __launch_bounds__(ADR_BLOCK) void k_orth_step(int N, const cx<T> *__restrict__ w, VecSet<T> V, ProIn pin,
                                                          const double *scales, double *hcol,
                                                          const cx<T> *__restrict__ dinv, cx<T> *__restrict__ vnew,
-                                                         cx<T> *__restrict__ znew, double *pout) {
+                                                         cx<T> *__restrict__ znew, double *pout, Shot sh) {
+  ADR_SHOT_ENTER(sh);
+  ADR_SHIFT(w);
+  shift_set<NV>(V, shot_off_);
+  ADR_SHIFT(pin.partials);
+  ADR_SHIFT(scales);
+  ADR_SHIFT(hcol);
+  ADR_SHIFT(dinv);
+  ADR_SHIFT(vnew);
+  ADR_SHIFT(znew);
+  ADR_SHIFT(pout);
   __shared__ double tot[2 * NV];
   reduce_partials(pin.partials, pin.nb, 2 * NV, tot);
   cx<T> coef[NV];
@@ -973,7 +1044,7 @@ int orth_step(hipStream_t s, int N, const cx<T> *w, const VecSet<T> &V, ProIn pi
   const int nb = launch_blocks_red(N);
   switch (V.count) {
 #define ADR_NV_CASE(n) \
-  case n: ADR_LAUNCH((k_orth_step<T, n>), nb, s, N, w, V, pin, scales, hcol, dinv, vnew, znew, pout); break;
+  case n: ADR_LAUNCH_S((k_orth_step<T, n>), nb, s, N, w, V, pin, scales, hcol, dinv, vnew, znew, pout); break;
     ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6) ADR_NV_CASE(7)
     ADR_NV_CASE(8)
 #undef ADR_NV_CASE
@@ -989,7 +1060,12 @@ template int orth_step<float>(hipStream_t, int, const cx<float> *, const VecSet<
 // partial ||x||^2; z = dinv o x if z is given.
 template <typename T>
 __global__ __launch_bounds__(ADR_BLOCK) void k_norm2(int N, const cx<T> *__restrict__ x, const cx<T> *__restrict__ dinv,
-                                                     cx<T> *__restrict__ z, double *pout) {
+                                                     cx<T> *__restrict__ z, double *pout, Shot sh) {
+  ADR_SHOT_ENTER(sh);
+  ADR_SHIFT(x);
+  ADR_SHIFT(dinv);
+  ADR_SHIFT(z);
+  ADR_SHIFT(pout);
   double red[1] = {0.0};
   int beg, end;
   chunk_range(N, beg, end);
@@ -1003,7 +1079,7 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_norm2(int N, const cx<T> *__restr
 template <typename T>
 int norm2(hipStream_t s, int N, const cx<T> *x, const cx<T> *dinv, cx<T> *z, double *pout) {
   const int nb = launch_blocks_red(N);
-  ADR_LAUNCH(k_norm2<T>, nb, s, N, x, dinv, z, pout);
+  ADR_LAUNCH_S(k_norm2<T>, nb, s, N, x, dinv, z, pout);
   return nb;
 }
 template int norm2<double>(hipStream_t, int, const cx<double> *, const cx<double> *, cx<double> *, double *);
@@ -1065,7 +1141,17 @@ template <typename T, int NV>
 __global__ __launch_bounds__(ADR_BLOCK) void k_gmres_update(int N, const cx<T> *__restrict__ x0, VecSet<T> Z,
                                                             ProIn pin, const double *H, int ldh, const double *beta,
                                                             const double *scales, cx<T> *__restrict__ xout,
-                                                            VecSet<T> Vr, cx<T> *__restrict__ rout) {
+                                                            VecSet<T> Vr, cx<T> *__restrict__ rout, Shot sh) {
+  ADR_SHOT_ENTER(sh);
+  ADR_SHIFT(x0);
+  shift_set<NV>(Z, shot_off_);
+  ADR_SHIFT(pin.partials);
+  ADR_SHIFT(H);
+  ADR_SHIFT(beta);
+  ADR_SHIFT(scales);
+  ADR_SHIFT(xout);
+  shift_set<NV + 1>(Vr, shot_off_);
+  ADR_SHIFT(rout);
   __shared__ double tot[1];
   __shared__ double cs[2 * NV];
   __shared__ double rs[2 * (NV + 1)];
@@ -1135,7 +1221,7 @@ void gmres_update(hipStream_t s, int N, const cx<T> *x0, const VecSet<T> &Z, Pro
   if (r_out && V.count != Z.count + 1) return;
   switch (Z.count) {
 #define ADR_NV_CASE(n) \
-  case n: ADR_LAUNCH((k_gmres_update<T, n>), nb, s, N, x0, Z, pin, H, ldh, beta, scales, x_out, V, r_out); break;
+  case n: ADR_LAUNCH_S((k_gmres_update<T, n>), nb, s, N, x0, Z, pin, H, ldh, beta, scales, x_out, V, r_out); break;
     ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6) ADR_NV_CASE(7)
     ADR_NV_CASE(8)
 #undef ADR_NV_CASE
@@ -1153,7 +1239,11 @@ template void gmres_update<float>(hipStream_t, int, const cx<float> *, const Vec
 // Krylov cycle: flexible GMRES(2) on a coarse level
 // =====================================================================================
 __global__ __launch_bounds__(ADR_BLOCK) void k_reduce_norm(ProIn pin, double *norm_out, int norm_cplx,
-                                                           double *inv_out) {
+                                                           double *inv_out, Shot sh) {
+  ADR_SHOT_ENTER(sh);
+  ADR_SHIFT(pin.partials);
+  ADR_SHIFT(norm_out);
+  ADR_SHIFT(inv_out);
   __shared__ double tot[1];
   reduce_partials(pin.partials, pin.nb, 1, tot);
   if (threadIdx.x == 0) {
@@ -1164,7 +1254,7 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_reduce_norm(ProIn pin, double *no
   }
 }
 void reduce_norm(hipStream_t s, ProIn pin, double *norm_out, int norm_cplx, double *inv_out) {
-  hipLaunchKernelGGL(k_reduce_norm, dim3(1), dim3(ADR_BLOCK), 0, s, pin, norm_out, norm_cplx, inv_out);
+  ADR_LAUNCH_S(k_reduce_norm, 1, s, pin, norm_out, norm_cplx, inv_out);
 }
 
 // Thread 0 of every block solves the 1- or 2-column least squares (the same in every
@@ -1174,7 +1264,15 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_fgmres2_update(int N, const cx<T>
                                                               const cx<T> *__restrict__ Z1, ProIn pin,
                                                               const double *H, const double *beta,
                                                               const double *scales, double threshold,
-                                                              cx<T> *__restrict__ e) {
+                                                              cx<T> *__restrict__ e, Shot sh) {
+  ADR_SHOT_ENTER(sh);
+  ADR_SHIFT(Z0);
+  ADR_SHIFT(Z1);
+  ADR_SHIFT(pin.partials);
+  ADR_SHIFT(H);
+  ADR_SHIFT(beta);
+  ADR_SHIFT(scales);
+  ADR_SHIFT(e);
   __shared__ double tot[1];
   __shared__ double cs[4];
   reduce_partials(pin.partials, pin.nb, 1, tot);
@@ -1217,7 +1315,7 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_fgmres2_update(int N, const cx<T>
 template <typename T>
 void fgmres2_update(hipStream_t s, int N, const cx<T> *Z0, const cx<T> *Z1, ProIn pin, const double *H,
                     const double *beta, const double *scales, double threshold, cx<T> *e) {
-  ADR_LAUNCH(k_fgmres2_update<T>, launch_blocks(N), s, N, Z0, Z1, pin, H, beta, scales, threshold, e);
+  ADR_LAUNCH_S(k_fgmres2_update<T>, launch_blocks(N), s, N, Z0, Z1, pin, H, beta, scales, threshold, e);
 }
 template void fgmres2_update<double>(hipStream_t, int, const cx<double> *, const cx<double> *, ProIn,
                                      const double *, const double *, const double *, double, cx<double> *);
@@ -1230,7 +1328,13 @@ template void fgmres2_update<float>(hipStream_t, int, const cx<float> *, const c
 // Prologue: h = sums of the matvec's dot partials (block 0 stores them in h_out).
 template <int NV>
 __global__ __launch_bounds__(ADR_BLOCK) void k_outer_orth1(int N, cx<double> *__restrict__ w, VecSet<double> V,
-                                                           ProIn pin, double *h_out, double *pout) {
+                                                           ProIn pin, double *h_out, double *pout, Shot sh) {
+  ADR_SHOT_ENTER(sh);
+  ADR_SHIFT(w);
+  shift_set<NV>(V, shot_off_);
+  ADR_SHIFT(pin.partials);
+  ADR_SHIFT(h_out);
+  ADR_SHIFT(pout);
   constexpr int K = 2 * NV + 1;
   __shared__ double tot[2 * NV];
   reduce_partials(pin.partials, pin.nb, 2 * NV, tot);
@@ -1272,7 +1376,7 @@ int outer_orth1(hipStream_t s, int N, cx<double> *w, const VecSet<double> &V, Pr
   const int nb = launch_blocks_red(N);
   switch (V.count) {
 #define ADR_NV_CASE(n) \
-  case n: ADR_LAUNCH((k_outer_orth1<n>), nb, s, N, w, V, pin, h_out, pout); break;
+  case n: ADR_LAUNCH_S((k_outer_orth1<n>), nb, s, N, w, V, pin, h_out, pout); break;
     ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6) ADR_NV_CASE(7)
     ADR_NV_CASE(8)
 #undef ADR_NV_CASE
@@ -1285,7 +1389,14 @@ int outer_orth1(hipStream_t s, int N, cx<double> *w, const VecSet<double> &V, Pr
 // red_out for the host).  V_new = (w - sum_i c_i V_i) / sqrt(||w||^2 - sum |c_i|^2).
 template <int NV>
 __global__ __launch_bounds__(ADR_BLOCK) void k_outer_orth2(int N, const cx<double> *__restrict__ w, VecSet<double> V,
-                                                           ProIn pin, double *red_out, cx<double> *__restrict__ vnew) {
+                                                           ProIn pin, double *red_out, cx<double> *__restrict__ vnew,
+                                                           Shot sh) {
+  ADR_SHOT_ENTER(sh);
+  ADR_SHIFT(w);
+  shift_set<NV>(V, shot_off_);
+  ADR_SHIFT(pin.partials);
+  ADR_SHIFT(red_out);
+  ADR_SHIFT(vnew);
   __shared__ double red[2 * NV + 1];
   reduce_partials(pin.partials, pin.nb, 2 * NV + 1, red);
   if (blockIdx.x == 0 && threadIdx.x == 0)
@@ -1313,7 +1424,7 @@ void outer_orth2(hipStream_t s, int N, const cx<double> *w, const VecSet<double>
   int nb = launch_blocks(N);
   switch (V.count) {
 #define ADR_NV_CASE(n) \
-  case n: ADR_LAUNCH((k_outer_orth2<n>), nb, s, N, w, V, pin, red_out, vnew); break;
+  case n: ADR_LAUNCH_S((k_outer_orth2<n>), nb, s, N, w, V, pin, red_out, vnew); break;
     ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6) ADR_NV_CASE(7)
     ADR_NV_CASE(8)
 #undef ADR_NV_CASE
@@ -1323,7 +1434,11 @@ void outer_orth2(hipStream_t s, int N, const cx<double> *w, const VecSet<double>
 
 template <typename Tz, int NV>
 __global__ __launch_bounds__(ADR_BLOCK) void k_multi_axpy(int N, cx<double> *__restrict__ x, VecSet<Tz> Z,
-                                                          const double *y) {
+                                                          const double *y, Shot sh) {
+  ADR_SHOT_ENTER(sh);
+  ADR_SHIFT(x);
+  shift_set<NV>(Z, shot_off_);
+  ADR_SHIFT(y);
   cx<double> c[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) c[v] = mk<double>(y[2 * v], y[2 * v + 1]);
@@ -1341,7 +1456,7 @@ void multi_axpy(hipStream_t s, int N, cx<double> *x, const VecSet<Tz> &Z, const 
   int nb = launch_blocks(N);
   switch (Z.count) {
 #define ADR_NV_CASE(n) \
-  case n: ADR_LAUNCH((k_multi_axpy<Tz, n>), nb, s, N, x, Z, y); break;
+  case n: ADR_LAUNCH_S((k_multi_axpy<Tz, n>), nb, s, N, x, Z, y); break;
     ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6) ADR_NV_CASE(7)
     ADR_NV_CASE(8)
 #undef ADR_NV_CASE
@@ -1351,25 +1466,41 @@ void multi_axpy(hipStream_t s, int N, cx<double> *x, const VecSet<Tz> &Z, const 
 template void multi_axpy<double>(hipStream_t, int, cx<double> *, const VecSet<double> &, const double *);
 template void multi_axpy<float>(hipStream_t, int, cx<double> *, const VecSet<float> &, const double *);
 
-__global__ __launch_bounds__(ADR_BLOCK) void k_scale(int N, const cx<double> *__restrict__ x, double a,
-                                                     cx<double> *__restrict__ y) {
+// y = x / ||x||, the norm from the predecessor's partials of ||x||^2 (K = 1); y = 0 for a
+// zero norm.
+__global__ __launch_bounds__(ADR_BLOCK) void k_normalize(int N, const cx<double> *__restrict__ x, ProIn pin,
+                                                         cx<double> *__restrict__ y, Shot sh) {
+  ADR_SHOT_ENTER(sh);
+  ADR_SHIFT(x);
+  ADR_SHIFT(pin.partials);
+  ADR_SHIFT(y);
+  __shared__ double tot[1];
+  reduce_partials(pin.partials, pin.nb, 1, tot);
+  const double nrm = sqrt(tot[0]);
+  const double a = nrm > 0.0 ? 1.0 / nrm : 0.0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) y[i] = a * x[i];
 }
-void scale(hipStream_t s, int N, const cx<double> *x, double a, cx<double> *y) {
-  ADR_LAUNCH(k_scale, launch_blocks(N), s, N, x, a, y);
+void normalize(hipStream_t s, int N, const cx<double> *x, ProIn pin, cx<double> *y) {
+  ADR_LAUNCH_S(k_normalize, launch_blocks(N), s, N, x, pin, y);
 }
 
 __global__ __launch_bounds__(ADR_BLOCK) void k_phase(int N, const cx<double> *__restrict__ in,
                                                      const double *__restrict__ tau, double omega, int sign,
-                                                     cx<double> *out) {
+                                                     cx<double> *out, const double *omega_dev, Shot sh) {
+  ADR_SHOT_ENTER(sh);
+  ADR_SHIFT(in);
+  ADR_SHIFT(tau);
+  ADR_SHIFT(out);
+  if (omega_dev) omega = *shot_ptr(omega_dev, shot_off_);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
     double sn, cs;
     sincos(omega * tau[i], &sn, &cs);
     out[i] = in[i] * mk<double>(cs, sign * sn);
   }
 }
-void phase(hipStream_t s, int N, const cx<double> *in, const double *tau, double omega, int sign, cx<double> *out) {
-  ADR_LAUNCH(k_phase, launch_blocks(N), s, N, in, tau, omega, sign, out);
+void phase(hipStream_t s, int N, const cx<double> *in, const double *tau, double omega, int sign, cx<double> *out,
+           const double *omega_dev) {
+  ADR_LAUNCH_S(k_phase, launch_blocks(N), s, N, in, tau, omega, sign, out, omega_dev);
 }
 
 // =====================================================================================
@@ -1378,7 +1509,12 @@ void phase(hipStream_t s, int N, const cx<double> *in, const double *tau, double
 // =====================================================================================
 template <typename T>
 __global__ __launch_bounds__(ADR_BLOCK) void k_dense_gemv(int N, const cx<double> *__restrict__ Ainv,
-                                                          const cx<T> *__restrict__ b, cx<T> *__restrict__ x) {
+                                                          const cx<T> *__restrict__ b, cx<T> *__restrict__ x,
+                                                          Shot sh) {
+  ADR_SHOT_ENTER(sh);
+  ADR_SHIFT(Ainv);
+  ADR_SHIFT(b);
+  ADR_SHIFT(x);
   const int row = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (row >= N) return;
@@ -1396,8 +1532,7 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_dense_gemv(int N, const cx<double
 template <typename T>
 void dense_gemv(hipStream_t s, int N, const cx<double> *Ainv, const cx<T> *b, cx<T> *x) {
   const int rows_per_block = ADR_BLOCK / 64;
-  hipLaunchKernelGGL(k_dense_gemv<T>, dim3((N + rows_per_block - 1) / rows_per_block), dim3(ADR_BLOCK), 0, s, N,
-                     Ainv, b, x);
+  ADR_LAUNCH_S(k_dense_gemv<T>, (N + rows_per_block - 1) / rows_per_block, s, N, Ainv, b, x);
 }
 template void dense_gemv<double>(hipStream_t, int, const cx<double> *, const cx<double> *, cx<double> *);
 template void dense_gemv<float>(hipStream_t, int, const cx<double> *, const cx<float> *, cx<float> *);

@@ -20,6 +20,13 @@ struct ProIn {
   int nb, K;
 };
 
+// Shift the first NV pointers of a set to problem blockIdx.y of a shot group.
+template <int NV, typename T>
+__device__ __forceinline__ void shift_set(VecSet<T> &V, long long off) {
+#pragma unroll
+  for (int i = 0; i < NV; ++i) V.v[i] = shot_ptr(V.v[i], off);
+}
+
 // Arguments of the Galerkin-stencil apply (see k_coarse_apply).
 template <typename T>
 struct CoarseArgs {
@@ -61,6 +68,15 @@ struct TailArgs {
 
 namespace adrk {
 
+// Launch configuration of the group-capable kernels: problems per launch and their
+// layout (see Shot).  Set by the batch driver while it enqueues a group's work on the
+// calling thread; {1, {0, NULL}} otherwise.
+struct ShotLaunch {
+  int count = 1;
+  Shot sh{0, nullptr};
+};
+extern thread_local ShotLaunch g_shot;
+
 // ---- setup (FP64) ----------------------------------------------------------------
 void coefficients(hipStream_t s, const Grid &G, int D, double h, double omega, const int src[3],
                   const double *kappa2, const double *tau, const double *gamma, double *g0, double *g1,
@@ -78,17 +94,19 @@ template <typename To, typename Ti>
 void convert_real(hipStream_t s, long long n, const Ti *in, To *out);
 
 // ---- fine level (matrix-free) ------------------------------------------------------
-// y = A x (mode 0), r = b - A x (mode 1); optional fused reductions into `out`:
-// dots scale_i * conj(V_i) . y for the basis in `dots` (2 doubles each, first), then
-// ||y|| (the norm, not its square) if want_norm.  Output precision To, compute T, input Tin.
-// Partials go to pout; returns the number of blocks launched.
+// y = A x (mode 0), r = b - A x (mode 1); optional fused reductions: dots conj(V_i) . y
+// for the basis in `dots` (2 doubles each, first), then ||y||^2 if want_norm, as
+// per-block partials in pout.  Output precision To, compute T, input Tin.  The operator
+// parameters are P, or *Pd when Pd is given (a device copy, per problem in a shot
+// group).  Returns the number of blocks launched.
 template <typename T, typename Tin, typename To>
 int fine_apply(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P, const cx<Tin> *x,
-               const cx<To> *b, cx<To> *y, int mode, const VecSet<To> *dots, bool want_norm, double *pout);
-// x_out = x_in + w D^{-1} (b - A x_in); x_in NULL means zero.
+               const cx<To> *b, cx<To> *y, int mode, const VecSet<To> *dots, bool want_norm, double *pout,
+               const FineParams *Pd = nullptr);
+// x_out = x_in + w D^{-1} (b - A x_in); x_in NULL means zero.  Parameters as fine_apply.
 template <typename T>
 void fine_jacobi(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P, const cx<T> *x_in,
-                 const cx<T> *b, cx<T> *x_out, double weight);
+                 const cx<T> *b, cx<T> *x_out, double weight, const FineParams *Pd = nullptr);
 
 // A^H x on the fine level (conjugate transpose, matrix-free), same conventions.
 template <typename T, typename Tin, typename To>
@@ -110,6 +128,8 @@ void receiver_residual(hipStream_t s, int nrec, const int *idx, const cx<double>
 // src = 0, then src[idx_k] += r_k in receiver order
 void adjoint_source(hipStream_t s, int N, int nrec, const int *idx, const cx<double> *r, cx<double> *src);
 void zero(hipStream_t s, long long n, cx<double> *x);
+// out = in
+void copy(hipStream_t s, long long n, const cx<double> *in, cx<double> *out);
 
 // ---- coarse levels (stored stencils) ----------------------------------------------
 // Galerkin-stencil apply (see CoarseArgs); fused dot/norm partials; returns the block
@@ -167,10 +187,12 @@ void outer_orth2(hipStream_t s, int N, const cx<double> *w, const VecSet<double>
 // x += sum_j y_j Z_j (y host-provided via device array of complex doubles)
 template <typename Tz>
 void multi_axpy(hipStream_t s, int N, cx<double> *x, const VecSet<Tz> &Z, const double *y);
-// y = a x
-void scale(hipStream_t s, int N, const cx<double> *x, double a, cx<double> *y);
-// q_hat = q exp(+i w tau)  (sign = +1) or u = a exp(-i w tau) (sign = -1)
-void phase(hipStream_t s, int N, const cx<double> *in, const double *tau, double omega, int sign, cx<double> *out);
+// y = x / ||x|| with ||x||^2 from the predecessor's partials (pin, K = 1)
+void normalize(hipStream_t s, int N, const cx<double> *x, ProIn pin, cx<double> *y);
+// q_hat = q exp(+i w tau)  (sign = +1) or u = a exp(-i w tau) (sign = -1); w = *omega_dev
+// when given (device copy, per problem in a shot group), else omega.
+void phase(hipStream_t s, int N, const cx<double> *in, const double *tau, double omega, int sign, cx<double> *out,
+           const double *omega_dev = nullptr);
 
 // ---- coarse tail ---------------------------------------------------------------------
 // The V-cycle on levels first..last (coarsest) from a zero guess on level `first` with

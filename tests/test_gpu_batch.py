@@ -1,4 +1,5 @@
-"""GPU batched shots: lockstep solves over several streams equal individual solves."""
+"""GPU batched shots: shot groups (one launch per phase for all problems of a grid
+shape) give, per problem, the single solve with full restart cycles bit for bit."""
 import numpy as np
 import pytest
 
@@ -30,9 +31,11 @@ def test_batch_matches_individual_solves(prec):
     b = adr.Batch(shots, options=opts, nstreams=3)
     st, stats = b.solve(qs, outs, tol=1e-8, maxit=400)
     assert st == adr.ADR_OK
+    single = adr.default_options(prec=prec, full_cycles=1)
     for i, w in enumerate(wls):
-        c = adr.Context(shots[i]["kappa2"], shots[i]["tau"], shots[i]["gamma"], w.h, w.omega, w.src, options=opts)
+        c = adr.Context(shots[i]["kappa2"], shots[i]["tau"], shots[i]["gamma"], w.h, w.omega, w.src, options=single)
         a, s1 = c.solve(qs[i], tol=1e-8, maxit=400)
+        assert s1["outer_iters"] % 5 == 0 or s1["outer_iters"] >= 400, i
         assert s1["outer_iters"] == stats[i]["outer_iters"], i
         assert torch.equal(a, outs[i]), i
         c.close()
@@ -43,4 +46,35 @@ def test_batch_matches_individual_solves(prec):
         ref = osolve.direct_solve(p.H2up, osolve.rhs_hat(w.rhs(), w.tau, w.omega))
         got = outs[i].cpu().numpy().ravel()
         assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-6
+    b.close()
+
+
+def test_batch_repeated_solves_and_masking():
+    """Two batch solves in a row with different right-hand sides (the device flags are
+    re-armed), shots of one group converging at different iterations, and a zero
+    right-hand side (finished at START) inside a group."""
+    from paper_1712_06091_amd import adr
+    wls = [W.random_medium(65, 2, seed=s) for s in (31, 32, 33)] + [W.constant_medium(65, 2)]
+    print(f"[batch-repeat] {len(wls)} shots", flush=True)
+    opts = adr.default_options(prec="mixed")
+    shots = [_shot(w) for w in wls]
+    b = adr.Batch(shots, options=opts, nstreams=2)
+    single = adr.default_options(prec="mixed", full_cycles=1)
+    ctxs = [adr.Context(sh["kappa2"], sh["tau"], sh["gamma"], w.h, w.omega, w.src, options=single)
+            for sh, w in zip(shots, wls)]
+    for rnd in range(2):
+        qs = [_t(W.random_vector(w.shape, 100 * rnd + i), torch.complex128) for i, w in enumerate(wls)]
+        if rnd == 1:
+            qs[2] = torch.zeros_like(qs[2])
+        outs = [torch.full(w.shape, 7.0 + 0j, dtype=torch.complex128, device="cuda") for w in wls]
+        st, stats = b.solve(qs, outs, tol=1e-9, maxit=300)
+        assert st == adr.ADR_OK
+        for i in range(len(wls)):
+            a, s1 = ctxs[i].solve(qs[i], tol=1e-9, maxit=300)
+            assert s1["outer_iters"] == stats[i]["outer_iters"], (rnd, i)
+            assert torch.equal(a, outs[i]), (rnd, i)
+        if rnd == 1:
+            assert stats[2]["outer_iters"] == 0 and torch.count_nonzero(outs[2]) == 0
+    for c in ctxs:
+        c.close()
     b.close()
