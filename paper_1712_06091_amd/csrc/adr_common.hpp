@@ -153,11 +153,23 @@ template <typename P>
 __device__ __forceinline__ P *shot_ptr(P *p, long long off) {
   return p ? (P *)((char *)p + off) : p;
 }
-// Declares shot_off_ and returns from inactive problems (uniform per block).
-#define ADR_SHOT_ENTER(sh)                                                                \
-  const long long shot_off_ = (long long)blockIdx.y * (sh).stride;                      \
-  if ((sh).active && !*(const int *)((const char *)(sh).active + shot_off_)) return
-#define ADR_SHIFT(p) ((p) = shot_ptr((p), shot_off_))
+// Group-capable kernels carry a template flag GRP: the GRP = false instance (ordinary
+// launches) compiles to the plain kernel, the GRP = true instance (shot-group launches)
+// shifts its pointers and skips inactive problems.  ADR_SHOT_ENTER declares shot_off_;
+// ADR_SHOT_LIVE returns from an inactive problem (uniform per block).
+#define ADR_SHOT_ENTER(sh) const long long shot_off_ = GRP ? (long long)blockIdx.y * (sh).stride : 0LL
+#define ADR_SHOT_LIVE(sh)                                                                    \
+  do {                                                                                       \
+    if constexpr (GRP) {                                                                     \
+      if ((sh).active && !*(const int *)((const char *)(sh).active + shot_off_)) return;    \
+    }                                                                                        \
+  } while (0)
+#define ADR_SHIFT(p)                        \
+  do {                                      \
+    if constexpr (GRP) {                    \
+      (p) = shot_ptr((p), shot_off_);       \
+    }                                       \
+  } while (0)
 
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);

@@ -12,11 +12,18 @@ namespace adrk {
 
 thread_local ShotLaunch g_shot;
 
+// Launch of a group-capable kernel: the GRP = true instance with one y-slice of blocks per
+// problem of the current shot group, else the plain instance.
+template <typename F, typename... Args>
+inline void launch_g(F k_single, F k_group, int nblocks, hipStream_t s, Args... args) {
+  if (g_shot.count > 1)
+    hipLaunchKernelGGL(k_group, dim3(nblocks, g_shot.count), dim3(ADR_BLOCK), 0, s, args..., g_shot.sh);
+  else
+    hipLaunchKernelGGL(k_single, dim3(nblocks), dim3(ADR_BLOCK), 0, s, args..., Shot{0, nullptr});
+}
+
 #define ADR_LAUNCH(kernel, nblocks, stream, ...) \
   hipLaunchKernelGGL(kernel, dim3(nblocks), dim3(ADR_BLOCK), 0, stream, __VA_ARGS__)
-// Group-capable kernels: one y-slice of blocks per problem of the current shot group.
-#define ADR_LAUNCH_S(kernel, nblocks, stream, ...) \
-  hipLaunchKernelGGL(kernel, dim3(nblocks, g_shot.count), dim3(ADR_BLOCK), 0, stream, __VA_ARGS__, g_shot.sh)
 
 // =====================================================================================
 // Setup: coefficients from tau (Sec. 2.1, eq. travel_time_coeff)
@@ -206,17 +213,18 @@ void stencil_diag_inv(hipStream_t s, int N, const cx<T> *centre_plane, cx<T> *di
 template void stencil_diag_inv<double>(hipStream_t, int, const cx<double> *, cx<double> *);
 template void stencil_diag_inv<float>(hipStream_t, int, const cx<float> *, cx<float> *);
 
-template <typename To, typename Ti>
+template <typename To, typename Ti, bool GRP>
 __global__ __launch_bounds__(ADR_BLOCK) void k_convert(long long n, const cx<Ti> *in, cx<To> *out, Shot sh) {
   ADR_SHOT_ENTER(sh);
   ADR_SHIFT(in);
   ADR_SHIFT(out);
+  ADR_SHOT_LIVE(sh);
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     out[i] = cvt<To, Ti>(in[i]);
 }
 template <typename To, typename Ti>
 void convert(hipStream_t s, long long n, const cx<Ti> *in, cx<To> *out) {
-  ADR_LAUNCH_S((k_convert<To, Ti>), launch_blocks(n), s, n, in, out);
+  launch_g(k_convert<To, Ti, false>, k_convert<To, Ti, true>, launch_blocks(n), s, n, in, out);
 }
 template void convert<float, double>(hipStream_t, long long, const cx<double> *, cx<float> *);
 template void convert<double, float>(hipStream_t, long long, const cx<float> *, cx<double> *);
@@ -236,20 +244,23 @@ template void convert_real<float, double>(hipStream_t, long long, const double *
 // =====================================================================================
 // Fine level: matrix-free apply / residual with fused reductions, Jacobi sweep
 // =====================================================================================
-template <typename T, typename Tin, typename To, int D, int NV, bool NORM>
+template <typename T, typename Tin, typename To, int D, int NV, bool NORM, bool GRP>
 __global__ __launch_bounds__(ADR_BLOCK) void k_fine_apply(Grid G, FineCoef<T> C, FineParams P,
                                                           const cx<Tin> *__restrict__ x,
                                                           const cx<To> *__restrict__ b, cx<To> *__restrict__ y,
                                                           int mode, VecSet<To> V, double *pout,
                                                           const FineParams *Pd, Shot sh) {
   ADR_SHOT_ENTER(sh);
-  shift_fine_coef(C, shot_off_);
-  if (Pd) P = *shot_ptr(Pd, shot_off_);
+  if constexpr (GRP) shift_fine_coef(C, shot_off_);
+  if constexpr (GRP) {
+    if (Pd) P = *shot_ptr(Pd, shot_off_);
+  }
   ADR_SHIFT(x);
   ADR_SHIFT(b);
   ADR_SHIFT(y);
-  shift_set<NV>(V, shot_off_);
+  if constexpr (GRP) shift_set<NV>(V, shot_off_);
   ADR_SHIFT(pout);
+  ADR_SHOT_LIVE(sh);
   constexpr int K = 2 * NV + (NORM ? 1 : 0);
   constexpr int KA = K > 0 ? K : 1;
   double red[KA];
@@ -293,7 +304,7 @@ template <typename T, typename Tin, typename To, int D, int NV, bool NORM>
 static void launch_fine_apply(hipStream_t s, int nb, const Grid &G, const FineCoef<T> &C, const FineParams &P,
                               const cx<Tin> *x, const cx<To> *b, cx<To> *y, int mode, const VecSet<To> &V,
                               double *pout, const FineParams *Pd) {
-  ADR_LAUNCH_S((k_fine_apply<T, Tin, To, D, NV, NORM>), nb, s, G, C, P, x, b, y, mode, V, pout, Pd);
+  launch_g(k_fine_apply<T, Tin, To, D, NV, NORM, false>, k_fine_apply<T, Tin, To, D, NV, NORM, true>, nb, s, G, C, P, x, b, y, mode, V, pout, Pd);
 }
 
 template <typename T, typename Tin, typename To, int D, bool NORM>
@@ -340,17 +351,20 @@ template int fine_apply<float, float, float>(hipStream_t, const Grid &, int, con
                                              cx<float> *, int, const VecSet<float> *, bool, double *,
                                              const FineParams *);
 
-template <typename T, int D>
+template <typename T, int D, bool GRP>
 __global__ __launch_bounds__(ADR_BLOCK) void k_fine_jacobi(Grid G, FineCoef<T> C, FineParams P,
                                                            const cx<T> *__restrict__ xin,
                                                            const cx<T> *__restrict__ b, cx<T> *__restrict__ xout,
                                                            T weight, const FineParams *Pd, Shot sh) {
   ADR_SHOT_ENTER(sh);
-  shift_fine_coef(C, shot_off_);
-  if (Pd) P = *shot_ptr(Pd, shot_off_);
+  if constexpr (GRP) shift_fine_coef(C, shot_off_);
+  if constexpr (GRP) {
+    if (Pd) P = *shot_ptr(Pd, shot_off_);
+  }
   ADR_SHIFT(xin);
   ADR_SHIFT(b);
   ADR_SHIFT(xout);
+  ADR_SHOT_LIVE(sh);
   int beg, end;
   chunk_range(G.N, beg, end);
   for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
@@ -387,8 +401,8 @@ template <typename T>
 void fine_jacobi(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P, const cx<T> *x_in,
                  const cx<T> *b, cx<T> *x_out, double weight, const FineParams *Pd) {
   int nb = launch_blocks(G.N);
-  if (D == 2) ADR_LAUNCH_S((k_fine_jacobi<T, 2>), nb, s, G, C, P, x_in, b, x_out, (T)weight, Pd);
-  else ADR_LAUNCH_S((k_fine_jacobi<T, 3>), nb, s, G, C, P, x_in, b, x_out, (T)weight, Pd);
+  if (D == 2) launch_g(k_fine_jacobi<T, 2, false>, k_fine_jacobi<T, 2, true>, nb, s, G, C, P, x_in, b, x_out, (T)weight, Pd);
+  else launch_g(k_fine_jacobi<T, 3, false>, k_fine_jacobi<T, 3, true>, nb, s, G, C, P, x_in, b, x_out, (T)weight, Pd);
 }
 template void fine_jacobi<double>(hipStream_t, const Grid &, int, const FineCoef<double> &, const FineParams &,
                                   const cx<double> *, const cx<double> *, cx<double> *, double, const FineParams *);
@@ -642,9 +656,11 @@ void receiver_residual(hipStream_t s, int nrec, const int *idx, const cx<double>
   hipLaunchKernelGGL(k_receiver_residual, dim3((nrec + ADR_BLOCK - 1) / ADR_BLOCK), dim3(ADR_BLOCK), 0, s, nrec, idx,
                      u, d, r);
 }
+template <bool GRP>
 __global__ __launch_bounds__(ADR_BLOCK) void k_zero(long long n, cx<double> *x, Shot sh) {
   ADR_SHOT_ENTER(sh);
   ADR_SHIFT(x);
+  ADR_SHOT_LIVE(sh);
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     x[i] = mk<double>(0.0, 0.0);
 }
@@ -655,19 +671,21 @@ __global__ void k_scatter_add(int nrec, const int *__restrict__ idx, const cx<do
     for (int k = 0; k < nrec; ++k) s[idx[k]] = s[idx[k]] + r[k];
 }
 void adjoint_source(hipStream_t s, int N, int nrec, const int *idx, const cx<double> *r, cx<double> *src) {
-  ADR_LAUNCH_S(k_zero, launch_blocks(N), s, (long long)N, src);
+  launch_g(k_zero<false>, k_zero<true>, launch_blocks(N), s, (long long)N, src);
   hipLaunchKernelGGL(k_scatter_add, dim3(1), dim3(64), 0, s, nrec, idx, r, src);
 }
-void zero(hipStream_t s, long long n, cx<double> *x) { ADR_LAUNCH_S(k_zero, launch_blocks(n), s, n, x); }
+void zero(hipStream_t s, long long n, cx<double> *x) { launch_g(k_zero<false>, k_zero<true>, launch_blocks(n), s, n, x); }
+template <bool GRP>
 __global__ __launch_bounds__(ADR_BLOCK) void k_copy(long long n, const cx<double> *in, cx<double> *out, Shot sh) {
   ADR_SHOT_ENTER(sh);
   ADR_SHIFT(in);
   ADR_SHIFT(out);
+  ADR_SHOT_LIVE(sh);
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     out[i] = in[i];
 }
 void copy(hipStream_t s, long long n, const cx<double> *in, cx<double> *out) {
-  ADR_LAUNCH_S(k_copy, launch_blocks(n), s, n, in, out);
+  launch_g(k_copy<false>, k_copy<true>, launch_blocks(n), s, n, in, out);
 }
 
 // =====================================================================================
@@ -746,7 +764,7 @@ __device__ __forceinline__ cx<T> stencil_part_of(int w, const cx<T> *__restrict_
 // summing every SPLIT-th stencil entry; the parts are added in LDS in wave order (fewer
 // loads in flight per lane and SPLIT times more blocks, for the small coarse levels).
 // Partials: NV dots conj(V_v).y, then ||y||^2 if NORM.
-template <typename T, int D, int NV, bool NORM, int SPLIT>
+template <typename T, int D, int NV, bool NORM, int SPLIT, bool GRP>
 __global__ __launch_bounds__(ADR_BLOCK) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_coarse_apply(Grid G, const cx<T> *__restrict__ planes,
                                                             const cx<T> *__restrict__ x, ProIn pin, const double *sdev,
                                                             double *norm_out, int norm_cplx, double *inv_out,
@@ -764,8 +782,9 @@ __global__ __launch_bounds__(ADR_BLOCK) __attribute__((amdgpu_waves_per_eu(1, 4)
   ADR_SHIFT(y);
   ADR_SHIFT(dinv);
   ADR_SHIFT(zout);
-  shift_set<NV>(V, shot_off_);
+  if constexpr (GRP) shift_set<NV>(V, shot_off_);
   ADR_SHIFT(pout);
+  ADR_SHOT_LIVE(sh);
   constexpr int K = 2 * NV + (NORM ? 1 : 0);
   constexpr int KA = K > 0 ? K : 1;
   __shared__ double tot[1];
@@ -846,7 +865,7 @@ static void dispatch_coarse_nv(hipStream_t s, int nb, const CoarseArgs<T> &a, co
   switch (V.count) {
 #define ADR_NV_CASE(n)                                                                                              \
   case n:                                                                                                           \
-    ADR_LAUNCH_S((k_coarse_apply<T, D, n, NORM, SPLIT>), nb, s, a.G, a.planes, a.x, a.pin, a.sdev, a.norm_out,      \
+    launch_g(k_coarse_apply<T, D, n, NORM, SPLIT, false>, k_coarse_apply<T, D, n, NORM, SPLIT, true>, nb, s, a.G, a.planes, a.x, a.pin, a.sdev, a.norm_out,      \
                a.norm_cplx, a.inv_out, a.b, a.y, a.dinv, a.zout, a.mode, V, a.pout);                               \
     break;
     ADR_NV_CASE(0) ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6)
@@ -914,7 +933,7 @@ __device__ __forceinline__ cx<T> restrict_value(const Grid &Gf, const Grid &Gc, 
   return acc;
 }
 
-template <typename T, int D>
+template <typename T, int D, bool GRP>
 __global__ __launch_bounds__(ADR_BLOCK) void k_restrict(Grid Gf, Grid Gc, const cx<T> *__restrict__ rf,
                                                         cx<T> *__restrict__ rc, const cx<T> *__restrict__ dinv_c,
                                                         cx<T> *__restrict__ z_c, double *pout, Shot sh) {
@@ -924,6 +943,7 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_restrict(Grid Gf, Grid Gc, const 
   ADR_SHIFT(dinv_c);
   ADR_SHIFT(z_c);
   ADR_SHIFT(pout);
+  ADR_SHOT_LIVE(sh);
   double red[1] = {0.0};
   int beg, end;
   chunk_range(Gc.N, beg, end);
@@ -942,8 +962,8 @@ template <typename T>
 int restrict_full(hipStream_t s, const Grid &Gf, const Grid &Gc, int D, const cx<T> *rf, cx<T> *rc,
                   const cx<T> *dinv_c, cx<T> *z_c, double *pout) {
   int nb = pout ? launch_blocks_red(Gc.N) : launch_blocks(Gc.N);
-  if (D == 2) ADR_LAUNCH_S((k_restrict<T, 2>), nb, s, Gf, Gc, rf, rc, dinv_c, z_c, pout);
-  else ADR_LAUNCH_S((k_restrict<T, 3>), nb, s, Gf, Gc, rf, rc, dinv_c, z_c, pout);
+  if (D == 2) launch_g(k_restrict<T, 2, false>, k_restrict<T, 2, true>, nb, s, Gf, Gc, rf, rc, dinv_c, z_c, pout);
+  else launch_g(k_restrict<T, 3, false>, k_restrict<T, 3, true>, nb, s, Gf, Gc, rf, rc, dinv_c, z_c, pout);
   return nb;
 }
 template int restrict_full<double>(hipStream_t, const Grid &, const Grid &, int, const cx<double> *, cx<double> *,
@@ -970,12 +990,13 @@ __device__ __forceinline__ cx<T> prolong_value(const Grid &Gf, const Grid &Gc, c
   return acc;
 }
 
-template <typename T, int D>
+template <typename T, int D, bool GRP>
 __global__ __launch_bounds__(ADR_BLOCK) void k_prolong_add(Grid Gf, Grid Gc, const cx<T> *__restrict__ ec,
                                                            cx<T> *__restrict__ xf, Shot sh) {
   ADR_SHOT_ENTER(sh);
   ADR_SHIFT(ec);
   ADR_SHIFT(xf);
+  ADR_SHOT_LIVE(sh);
   int beg, end;
   chunk_range(Gf.N, beg, end);
   for (int f = beg + threadIdx.x; f < end; f += blockDim.x) xf[f] = xf[f] + prolong_value<T, D>(Gf, Gc, ec, f);
@@ -984,8 +1005,8 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_prolong_add(Grid Gf, Grid Gc, con
 template <typename T>
 void prolong_add(hipStream_t s, const Grid &Gf, const Grid &Gc, int D, const cx<T> *ec, cx<T> *xf) {
   int nb = launch_blocks(Gf.N);
-  if (D == 2) ADR_LAUNCH_S((k_prolong_add<T, 2>), nb, s, Gf, Gc, ec, xf);
-  else ADR_LAUNCH_S((k_prolong_add<T, 3>), nb, s, Gf, Gc, ec, xf);
+  if (D == 2) launch_g(k_prolong_add<T, 2, false>, k_prolong_add<T, 2, true>, nb, s, Gf, Gc, ec, xf);
+  else launch_g(k_prolong_add<T, 3, false>, k_prolong_add<T, 3, true>, nb, s, Gf, Gc, ec, xf);
 }
 template void prolong_add<double>(hipStream_t, const Grid &, const Grid &, int, const cx<double> *, cx<double> *);
 template void prolong_add<float>(hipStream_t, const Grid &, const Grid &, int, const cx<float> *, cx<float> *);
@@ -996,14 +1017,14 @@ template void prolong_add<float>(hipStream_t, const Grid &, const Grid &, int, c
 // Prologue: H[i][j] = s_i * (sum of the predecessor's dot partials), i < NV (block 0
 // stores them in hcol).  Then v_new = w - sum_i H[i][j] s_i V_i (the basis is kept
 // unnormalized, v_i = s_i V_i), z_new = dinv o v_new, partial ||v_new||^2.
-template <typename T, int NV>
+template <typename T, int NV, bool GRP>
 __global__ __launch_bounds__(ADR_BLOCK) void k_orth_step(int N, const cx<T> *__restrict__ w, VecSet<T> V, ProIn pin,
                                                          const double *scales, double *hcol,
                                                          const cx<T> *__restrict__ dinv, cx<T> *__restrict__ vnew,
                                                          cx<T> *__restrict__ znew, double *pout, Shot sh) {
   ADR_SHOT_ENTER(sh);
   ADR_SHIFT(w);
-  shift_set<NV>(V, shot_off_);
+  if constexpr (GRP) shift_set<NV>(V, shot_off_);
   ADR_SHIFT(pin.partials);
   ADR_SHIFT(scales);
   ADR_SHIFT(hcol);
@@ -1011,6 +1032,7 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_orth_step(int N, const cx<T> *__r
   ADR_SHIFT(vnew);
   ADR_SHIFT(znew);
   ADR_SHIFT(pout);
+  ADR_SHOT_LIVE(sh);
   __shared__ double tot[2 * NV];
   reduce_partials(pin.partials, pin.nb, 2 * NV, tot);
   cx<T> coef[NV];
@@ -1044,7 +1066,7 @@ int orth_step(hipStream_t s, int N, const cx<T> *w, const VecSet<T> &V, ProIn pi
   const int nb = launch_blocks_red(N);
   switch (V.count) {
 #define ADR_NV_CASE(n) \
-  case n: ADR_LAUNCH_S((k_orth_step<T, n>), nb, s, N, w, V, pin, scales, hcol, dinv, vnew, znew, pout); break;
+  case n: launch_g(k_orth_step<T, n, false>, k_orth_step<T, n, true>, nb, s, N, w, V, pin, scales, hcol, dinv, vnew, znew, pout); break;
     ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6) ADR_NV_CASE(7)
     ADR_NV_CASE(8)
 #undef ADR_NV_CASE
@@ -1058,7 +1080,7 @@ template int orth_step<float>(hipStream_t, int, const cx<float> *, const VecSet<
                               double *, const cx<float> *, cx<float> *, cx<float> *, double *);
 
 // partial ||x||^2; z = dinv o x if z is given.
-template <typename T>
+template <typename T, bool GRP>
 __global__ __launch_bounds__(ADR_BLOCK) void k_norm2(int N, const cx<T> *__restrict__ x, const cx<T> *__restrict__ dinv,
                                                      cx<T> *__restrict__ z, double *pout, Shot sh) {
   ADR_SHOT_ENTER(sh);
@@ -1066,6 +1088,7 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_norm2(int N, const cx<T> *__restr
   ADR_SHIFT(dinv);
   ADR_SHIFT(z);
   ADR_SHIFT(pout);
+  ADR_SHOT_LIVE(sh);
   double red[1] = {0.0};
   int beg, end;
   chunk_range(N, beg, end);
@@ -1079,7 +1102,7 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_norm2(int N, const cx<T> *__restr
 template <typename T>
 int norm2(hipStream_t s, int N, const cx<T> *x, const cx<T> *dinv, cx<T> *z, double *pout) {
   const int nb = launch_blocks_red(N);
-  ADR_LAUNCH_S(k_norm2<T>, nb, s, N, x, dinv, z, pout);
+  launch_g(k_norm2<T, false>, k_norm2<T, true>, nb, s, N, x, dinv, z, pout);
   return nb;
 }
 template int norm2<double>(hipStream_t, int, const cx<double> *, const cx<double> *, cx<double> *, double *);
@@ -1137,21 +1160,22 @@ __device__ void gmres_lsq(cx<double> (&R)[K + 1][K], double beta, cx<double> (&y
 // With rout, also the new residual from the Arnoldi relation A Z = V Hbar:
 // b - A x_out = (b - A x0) - V Hbar y = sum_{i <= NV} (beta e_1 - Hbar y)_i s_i V_i, where
 // V_NV is the last (unnormalized) Arnoldi vector, s_NV = 1/H[NV][NV-1].
-template <typename T, int NV>
+template <typename T, int NV, bool GRP>
 __global__ __launch_bounds__(ADR_BLOCK) void k_gmres_update(int N, const cx<T> *__restrict__ x0, VecSet<T> Z,
                                                             ProIn pin, const double *H, int ldh, const double *beta,
                                                             const double *scales, cx<T> *__restrict__ xout,
                                                             VecSet<T> Vr, cx<T> *__restrict__ rout, Shot sh) {
   ADR_SHOT_ENTER(sh);
   ADR_SHIFT(x0);
-  shift_set<NV>(Z, shot_off_);
+  if constexpr (GRP) shift_set<NV>(Z, shot_off_);
   ADR_SHIFT(pin.partials);
   ADR_SHIFT(H);
   ADR_SHIFT(beta);
   ADR_SHIFT(scales);
   ADR_SHIFT(xout);
-  shift_set<NV + 1>(Vr, shot_off_);
+  if constexpr (GRP) shift_set<NV + 1>(Vr, shot_off_);
   ADR_SHIFT(rout);
+  ADR_SHOT_LIVE(sh);
   __shared__ double tot[1];
   __shared__ double cs[2 * NV];
   __shared__ double rs[2 * (NV + 1)];
@@ -1221,7 +1245,7 @@ void gmres_update(hipStream_t s, int N, const cx<T> *x0, const VecSet<T> &Z, Pro
   if (r_out && V.count != Z.count + 1) return;
   switch (Z.count) {
 #define ADR_NV_CASE(n) \
-  case n: ADR_LAUNCH_S((k_gmres_update<T, n>), nb, s, N, x0, Z, pin, H, ldh, beta, scales, x_out, V, r_out); break;
+  case n: launch_g(k_gmres_update<T, n, false>, k_gmres_update<T, n, true>, nb, s, N, x0, Z, pin, H, ldh, beta, scales, x_out, V, r_out); break;
     ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6) ADR_NV_CASE(7)
     ADR_NV_CASE(8)
 #undef ADR_NV_CASE
@@ -1238,12 +1262,14 @@ template void gmres_update<float>(hipStream_t, int, const cx<float> *, const Vec
 // =====================================================================================
 // Krylov cycle: flexible GMRES(2) on a coarse level
 // =====================================================================================
+template <bool GRP>
 __global__ __launch_bounds__(ADR_BLOCK) void k_reduce_norm(ProIn pin, double *norm_out, int norm_cplx,
                                                            double *inv_out, Shot sh) {
   ADR_SHOT_ENTER(sh);
   ADR_SHIFT(pin.partials);
   ADR_SHIFT(norm_out);
   ADR_SHIFT(inv_out);
+  ADR_SHOT_LIVE(sh);
   __shared__ double tot[1];
   reduce_partials(pin.partials, pin.nb, 1, tot);
   if (threadIdx.x == 0) {
@@ -1254,12 +1280,12 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_reduce_norm(ProIn pin, double *no
   }
 }
 void reduce_norm(hipStream_t s, ProIn pin, double *norm_out, int norm_cplx, double *inv_out) {
-  ADR_LAUNCH_S(k_reduce_norm, 1, s, pin, norm_out, norm_cplx, inv_out);
+  launch_g(k_reduce_norm<false>, k_reduce_norm<true>, 1, s, pin, norm_out, norm_cplx, inv_out);
 }
 
 // Thread 0 of every block solves the 1- or 2-column least squares (the same in every
 // block, from the same device scalars and partials), then e = c_0 Z0 + c_1 Z1.
-template <typename T>
+template <typename T, bool GRP>
 __global__ __launch_bounds__(ADR_BLOCK) void k_fgmres2_update(int N, const cx<T> *__restrict__ Z0,
                                                               const cx<T> *__restrict__ Z1, ProIn pin,
                                                               const double *H, const double *beta,
@@ -1273,6 +1299,7 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_fgmres2_update(int N, const cx<T>
   ADR_SHIFT(beta);
   ADR_SHIFT(scales);
   ADR_SHIFT(e);
+  ADR_SHOT_LIVE(sh);
   __shared__ double tot[1];
   __shared__ double cs[4];
   reduce_partials(pin.partials, pin.nb, 1, tot);
@@ -1315,7 +1342,7 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_fgmres2_update(int N, const cx<T>
 template <typename T>
 void fgmres2_update(hipStream_t s, int N, const cx<T> *Z0, const cx<T> *Z1, ProIn pin, const double *H,
                     const double *beta, const double *scales, double threshold, cx<T> *e) {
-  ADR_LAUNCH_S(k_fgmres2_update<T>, launch_blocks(N), s, N, Z0, Z1, pin, H, beta, scales, threshold, e);
+  launch_g(k_fgmres2_update<T, false>, k_fgmres2_update<T, true>, launch_blocks(N), s, N, Z0, Z1, pin, H, beta, scales, threshold, e);
 }
 template void fgmres2_update<double>(hipStream_t, int, const cx<double> *, const cx<double> *, ProIn,
                                      const double *, const double *, const double *, double, cx<double> *);
@@ -1326,15 +1353,16 @@ template void fgmres2_update<float>(hipStream_t, int, const cx<float> *, const c
 // Outer FGMRES (FP64) Arnoldi: classical Gram-Schmidt with one re-orthogonalization
 // =====================================================================================
 // Prologue: h = sums of the matvec's dot partials (block 0 stores them in h_out).
-template <int NV>
+template <int NV, bool GRP>
 __global__ __launch_bounds__(ADR_BLOCK) void k_outer_orth1(int N, cx<double> *__restrict__ w, VecSet<double> V,
                                                            ProIn pin, double *h_out, double *pout, Shot sh) {
   ADR_SHOT_ENTER(sh);
   ADR_SHIFT(w);
-  shift_set<NV>(V, shot_off_);
+  if constexpr (GRP) shift_set<NV>(V, shot_off_);
   ADR_SHIFT(pin.partials);
   ADR_SHIFT(h_out);
   ADR_SHIFT(pout);
+  ADR_SHOT_LIVE(sh);
   constexpr int K = 2 * NV + 1;
   __shared__ double tot[2 * NV];
   reduce_partials(pin.partials, pin.nb, 2 * NV, tot);
@@ -1376,7 +1404,7 @@ int outer_orth1(hipStream_t s, int N, cx<double> *w, const VecSet<double> &V, Pr
   const int nb = launch_blocks_red(N);
   switch (V.count) {
 #define ADR_NV_CASE(n) \
-  case n: ADR_LAUNCH_S((k_outer_orth1<n>), nb, s, N, w, V, pin, h_out, pout); break;
+  case n: launch_g(k_outer_orth1<n, false>, k_outer_orth1<n, true>, nb, s, N, w, V, pin, h_out, pout); break;
     ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6) ADR_NV_CASE(7)
     ADR_NV_CASE(8)
 #undef ADR_NV_CASE
@@ -1387,16 +1415,17 @@ int outer_orth1(hipStream_t s, int N, cx<double> *w, const VecSet<double> &V, Pr
 
 // Prologue: c_i and ||w||^2 from the first pass's partials (block 0 stores them in
 // red_out for the host).  V_new = (w - sum_i c_i V_i) / sqrt(||w||^2 - sum |c_i|^2).
-template <int NV>
+template <int NV, bool GRP>
 __global__ __launch_bounds__(ADR_BLOCK) void k_outer_orth2(int N, const cx<double> *__restrict__ w, VecSet<double> V,
                                                            ProIn pin, double *red_out, cx<double> *__restrict__ vnew,
                                                            Shot sh) {
   ADR_SHOT_ENTER(sh);
   ADR_SHIFT(w);
-  shift_set<NV>(V, shot_off_);
+  if constexpr (GRP) shift_set<NV>(V, shot_off_);
   ADR_SHIFT(pin.partials);
   ADR_SHIFT(red_out);
   ADR_SHIFT(vnew);
+  ADR_SHOT_LIVE(sh);
   __shared__ double red[2 * NV + 1];
   reduce_partials(pin.partials, pin.nb, 2 * NV + 1, red);
   if (blockIdx.x == 0 && threadIdx.x == 0)
@@ -1424,7 +1453,7 @@ void outer_orth2(hipStream_t s, int N, const cx<double> *w, const VecSet<double>
   int nb = launch_blocks(N);
   switch (V.count) {
 #define ADR_NV_CASE(n) \
-  case n: ADR_LAUNCH_S((k_outer_orth2<n>), nb, s, N, w, V, pin, red_out, vnew); break;
+  case n: launch_g(k_outer_orth2<n, false>, k_outer_orth2<n, true>, nb, s, N, w, V, pin, red_out, vnew); break;
     ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6) ADR_NV_CASE(7)
     ADR_NV_CASE(8)
 #undef ADR_NV_CASE
@@ -1432,13 +1461,14 @@ void outer_orth2(hipStream_t s, int N, const cx<double> *w, const VecSet<double>
   }
 }
 
-template <typename Tz, int NV>
+template <typename Tz, int NV, bool GRP>
 __global__ __launch_bounds__(ADR_BLOCK) void k_multi_axpy(int N, cx<double> *__restrict__ x, VecSet<Tz> Z,
                                                           const double *y, Shot sh) {
   ADR_SHOT_ENTER(sh);
   ADR_SHIFT(x);
-  shift_set<NV>(Z, shot_off_);
+  if constexpr (GRP) shift_set<NV>(Z, shot_off_);
   ADR_SHIFT(y);
+  ADR_SHOT_LIVE(sh);
   cx<double> c[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) c[v] = mk<double>(y[2 * v], y[2 * v + 1]);
@@ -1456,7 +1486,7 @@ void multi_axpy(hipStream_t s, int N, cx<double> *x, const VecSet<Tz> &Z, const 
   int nb = launch_blocks(N);
   switch (Z.count) {
 #define ADR_NV_CASE(n) \
-  case n: ADR_LAUNCH_S((k_multi_axpy<Tz, n>), nb, s, N, x, Z, y); break;
+  case n: launch_g(k_multi_axpy<Tz, n, false>, k_multi_axpy<Tz, n, true>, nb, s, N, x, Z, y); break;
     ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6) ADR_NV_CASE(7)
     ADR_NV_CASE(8)
 #undef ADR_NV_CASE
@@ -1468,12 +1498,14 @@ template void multi_axpy<float>(hipStream_t, int, cx<double> *, const VecSet<flo
 
 // y = x / ||x||, the norm from the predecessor's partials of ||x||^2 (K = 1); y = 0 for a
 // zero norm.
+template <bool GRP>
 __global__ __launch_bounds__(ADR_BLOCK) void k_normalize(int N, const cx<double> *__restrict__ x, ProIn pin,
                                                          cx<double> *__restrict__ y, Shot sh) {
   ADR_SHOT_ENTER(sh);
   ADR_SHIFT(x);
   ADR_SHIFT(pin.partials);
   ADR_SHIFT(y);
+  ADR_SHOT_LIVE(sh);
   __shared__ double tot[1];
   reduce_partials(pin.partials, pin.nb, 1, tot);
   const double nrm = sqrt(tot[0]);
@@ -1481,9 +1513,10 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_normalize(int N, const cx<double>
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) y[i] = a * x[i];
 }
 void normalize(hipStream_t s, int N, const cx<double> *x, ProIn pin, cx<double> *y) {
-  ADR_LAUNCH_S(k_normalize, launch_blocks(N), s, N, x, pin, y);
+  launch_g(k_normalize<false>, k_normalize<true>, launch_blocks(N), s, N, x, pin, y);
 }
 
+template <bool GRP>
 __global__ __launch_bounds__(ADR_BLOCK) void k_phase(int N, const cx<double> *__restrict__ in,
                                                      const double *__restrict__ tau, double omega, int sign,
                                                      cx<double> *out, const double *omega_dev, Shot sh) {
@@ -1491,7 +1524,10 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_phase(int N, const cx<double> *__
   ADR_SHIFT(in);
   ADR_SHIFT(tau);
   ADR_SHIFT(out);
-  if (omega_dev) omega = *shot_ptr(omega_dev, shot_off_);
+  if constexpr (GRP) {
+    if (omega_dev) omega = *shot_ptr(omega_dev, shot_off_);
+  }
+  ADR_SHOT_LIVE(sh);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
     double sn, cs;
     sincos(omega * tau[i], &sn, &cs);
@@ -1500,14 +1536,14 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_phase(int N, const cx<double> *__
 }
 void phase(hipStream_t s, int N, const cx<double> *in, const double *tau, double omega, int sign, cx<double> *out,
            const double *omega_dev) {
-  ADR_LAUNCH_S(k_phase, launch_blocks(N), s, N, in, tau, omega, sign, out, omega_dev);
+  launch_g(k_phase<false>, k_phase<true>, launch_blocks(N), s, N, in, tau, omega, sign, out, omega_dev);
 }
 
 // =====================================================================================
 // Coarsest level: x = A_L^{-1} b with the dense FP64 inverse (row-major), one
 // wavefront per row, lanes striding over the columns.
 // =====================================================================================
-template <typename T>
+template <typename T, bool GRP>
 __global__ __launch_bounds__(ADR_BLOCK) void k_dense_gemv(int N, const cx<double> *__restrict__ Ainv,
                                                           const cx<T> *__restrict__ b, cx<T> *__restrict__ x,
                                                           Shot sh) {
@@ -1515,6 +1551,7 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_dense_gemv(int N, const cx<double
   ADR_SHIFT(Ainv);
   ADR_SHIFT(b);
   ADR_SHIFT(x);
+  ADR_SHOT_LIVE(sh);
   const int row = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (row >= N) return;
@@ -1532,7 +1569,7 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_dense_gemv(int N, const cx<double
 template <typename T>
 void dense_gemv(hipStream_t s, int N, const cx<double> *Ainv, const cx<T> *b, cx<T> *x) {
   const int rows_per_block = ADR_BLOCK / 64;
-  ADR_LAUNCH_S(k_dense_gemv<T>, (N + rows_per_block - 1) / rows_per_block, s, N, Ainv, b, x);
+  launch_g(k_dense_gemv<T, false>, k_dense_gemv<T, true>, (N + rows_per_block - 1) / rows_per_block, s, N, Ainv, b, x);
 }
 template void dense_gemv<double>(hipStream_t, int, const cx<double> *, const cx<double> *, cx<double> *);
 template void dense_gemv<float>(hipStream_t, int, const cx<double> *, const cx<float> *, cx<float> *);
