@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-looped", action="store_true", help="batch: skip the one-shot-at-a-time comparison")
     ap.add_argument("--mixed-only", action="store_true", help="with --profile-only: skip the FP64 solves")
     ap.add_argument("--no-graph", action="store_true", help="launch the cycles eagerly (no hipGraph)")
+    ap.add_argument("--coarse-split", type=int, default=0, choices=[0, 1, 4],
+                    help="Galerkin-apply variant on every coarse level (0 = timed at setup)")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -361,7 +363,8 @@ def main():
         s0 = time.perf_counter()
         ctxs[prec] = adr.Context(k2, tau, gam, wl.h, wl.omega, wl.src,
                                  options=adr.default_options(prec=prec, cycle=args.cycle,
-                                                             use_graph=0 if args.no_graph else 1))
+                                                             use_graph=0 if args.no_graph else 1,
+                                                             coarse_split=args.coarse_split))
         torch.cuda.synchronize()
         setup_ms[prec] = (time.perf_counter() - s0) * 1e3
         log(f"setup {prec}: {setup_ms[prec]:.0f} ms, {ctxs[prec].num_levels} levels")
@@ -453,7 +456,8 @@ def main():
         "dtype": "c64 V-cycle / c128 FGMRES",
         "data": "synthetic",
         "config": {"workload": wl.name, "grid": list(wl.shape), "nodes": N, "omega": wl.omega,
-                   "tol": TOL, "restart": 5, "levels": ctx.num_levels, "precision": "mixed"},
+                   "tol": TOL, "restart": 5, "levels": ctx.num_levels, "precision": "mixed",
+                   "coarse_splits": [ctx.level_split(l) for l in range(1, ctx.num_levels - 1)]},
         "fp64": {"value": fp64_value, "ms_per_step": ms_fp64, "outer_iters": iters_d},
         "mixed_over_fp64": value / fp64_value,
         "outer_iters": iters_m,

@@ -193,6 +193,13 @@ adr_status adr_get_coefficients(adr_ctx *ctx, double *g, double *L, void *c_c128
  * size along axis k; *stencil_points = stored stencil size (0 for the matrix-free fine
  * level, 21 in 2D / 81 in 3D on Galerkin levels). */
 adr_status adr_level_info(adr_ctx *ctx, int level, int *nodes, int *stencil_points);
+
+/* Galerkin-apply variant in use on coarse level `level`, 1 <= level <= levels - 2 (host
+ * out-param): 1 = one lane per node, 4 = four wavefronts per 64 nodes
+ * (adr_options.coarse_split, or the setup-time timing when that is 0).  ADR_EINVAL for
+ * the fine level, the coarsest level (solved by its dense inverse), a level out of range
+ * or a NULL pointer. */
+adr_status adr_level_split(adr_ctx *ctx, int level, int *split);
 int adr_num_levels(const adr_ctx *ctx);
 
 /* Copy a Galerkin level's stencil (level >= 1) out as c128: stencil_points planes of

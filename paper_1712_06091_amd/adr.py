@@ -96,6 +96,7 @@ def load_library(path=LIB_PATH):
         "adr_wavefield": (I, [P, P, P]),
         "adr_get_coefficients": (I, [P, P, P, P]),
         "adr_level_info": (I, [P, I, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+        "adr_level_split": (I, [P, I, ctypes.POINTER(ctypes.c_int)]),
         "adr_num_levels": (I, [P]),
         "adr_get_level_stencil": (I, [P, I, P, ctypes.POINTER(ctypes.c_int)]),
         "adr_solve_adjoint": (I, [P, P, P, D, I, I, ctypes.POINTER(AdrStats)]),
@@ -345,6 +346,12 @@ class Context:
         d = len(self.shape)
         shape = tuple(nodes[d - 1 - k] for k in range(d))
         return shape, sp.value
+
+    def level_split(self, level):
+        """Galerkin-apply variant of coarse level ``level`` >= 1 (1 or 4)."""
+        sp = ctypes.c_int()
+        _check(self._lib.adr_level_split(self._ptr, level, ctypes.byref(sp)), self._ptr)
+        return sp.value
 
     def level_stencil(self, level):
         """(planes complex128 [S, *shape_l], offsets int list of (dx, dy, dz))."""

@@ -731,10 +731,11 @@ int auto_levels(int D, const int n[3], int coarsest_max) {
 }
 
 // Galerkin-apply variant per coarse level (one lane per node, or four wavefronts per
-// 64 nodes): adr_options.coarse_split if set, else the faster of the two in a short
-// timing on this level (mode 0 with one fused dot, as in the GMRES relaxation).  The
-// choice is cached per grid shape and precision for the life of the process, so every
-// context on a given shape launches the same kernels and sums in the same order.
+// 64 nodes): adr_options.coarse_split if set, else a short timing on this level (mode 0
+// with one fused dot, as in the GMRES relaxation) in which the four-wavefront variant
+// has to beat the one-lane variant by 5%, so that near ties do not flip from run to run.
+// The choice is cached per grid shape and precision for the life of the process, so
+// every context on a given shape launches the same kernels and sums in the same order.
 template <typename T>
 adr_status tune_split(adr_ctx *ctx, int l) {
   LevelT<T> &L = levels_of<T>(ctx)[l];
@@ -786,7 +787,7 @@ adr_status tune_split(adr_ctx *ctx, int l) {
       ctx->err = std::string("split tuning: ") + hipGetErrorString(e);
       return ADR_EHIP;
     }
-    if (split == 1 || ms < best_ms) {
+    if (split == 1 || ms < 0.95f * best_ms) {
       best_ms = ms;
       best = split;
     }
@@ -1271,6 +1272,12 @@ adr_status adr_level_info(adr_ctx *ctx, int level, int *nodes, int *stencil_poin
   if (nodes)
     for (int k = 0; k < 3; ++k) nodes[k] = G.n[k];
   if (stencil_points) *stencil_points = level == 0 ? 0 : ctx->S_coarse;
+  return ADR_OK;
+}
+
+adr_status adr_level_split(adr_ctx *ctx, int level, int *split) {
+  if (!ctx || !split || level < 1 || level >= ctx->levels - 1) return ADR_EINVAL;
+  *split = ctx->opt.prec == ADR_PREC_MIXED ? ctx->lv32[level].split : ctx->lv64[level].split;
   return ADR_OK;
 }
 

@@ -92,6 +92,8 @@ def test_null_context_calls(lib):
     assert lib.adr_solve(None, None, None, 1e-6, 10, 0, None) == adr.ADR_EINVAL
     assert lib.adr_wavefield(None, None, None) == adr.ADR_EINVAL
     assert lib.adr_num_levels(None) == 0
+    sp = ctypes.c_int()
+    assert lib.adr_level_split(None, 1, ctypes.byref(sp)) == adr.ADR_EINVAL
     lib.adr_destroy(None)
     assert lib.adr_strerror(adr.ADR_ENOCONV) == b"not converged"
 

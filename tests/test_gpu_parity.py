@@ -259,6 +259,8 @@ def test_split_variants_agree_on_solve(prec):
     out = {}
     for split in (1, 4, 0):
         ctx = _ctx(wl, prec=prec, coarse_split=split)
+        used = [ctx.level_split(l) for l in range(1, ctx.num_levels - 1)]
+        assert all(u == split for u in used) if split else all(u in (1, 4) for u in used)
         a, st = ctx.solve(_t(wl.rhs()), tol=1e-10, maxit=300)
         assert st["relres"] <= 1e-10
         out[split] = a.cpu().numpy()
