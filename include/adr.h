@@ -59,7 +59,10 @@ typedef enum {
  * doubles each; gamma may be NULL (no absorption).  src[k] is the source node index
  * along axis k; it must be at least 2 nodes from every face.  With src[0] < 0 the
  * travel-time derivatives are plain differences of tau (no factoring, no near-source
- * rule).  Requires ndim in {2,3}, n[k] >= 5, h > 0, omega > 0. */
+ * rule).  tau may be NULL: tau = 0 everywhere, src is ignored, and the operator is the
+ * standard second-order Helmholtz matrix H of eq. HelmholtzLinSystem (with the
+ * absorbing term of Sec. 1); u = a.  Requires ndim in {2,3}, n[k] >= 5, h > 0,
+ * omega > 0. */
 typedef struct {
   int ndim;
   int n[3];
@@ -108,6 +111,10 @@ typedef struct {
                         /* convergence test only at cycle ends (batched solves always    */
                         /* run this way); default 0: stop inside a cycle once the        */
                         /* residual estimate reaches tol                                 */
+  double shift_alpha;   /* alpha >= 0: the multigrid cycle works on the shifted operator */
+                        /* A_beta - i alpha w^2 diag(kappa^2) (Sec. 3.1, eq. shift; the  */
+                        /* paper's Helmholtz runs use 0.2 with tau = NULL) while FGMRES  */
+                        /* solves the unshifted system; default 0 (no shift)             */
 } adr_options;
 
 typedef struct {

@@ -51,6 +51,7 @@ class AdrOptions(ctypes.Structure):
         ("coarse_split", ctypes.c_int),
         ("tail_max_nodes", ctypes.c_int),
         ("full_cycles", ctypes.c_int),
+        ("shift_alpha", ctypes.c_double),
     ]
 
 
@@ -167,9 +168,10 @@ def _dev(t, dtype):
 
 
 def make_problem(kappa2, tau, gamma, h, omega, src, factored=True):
-    """adr_problem for device tensors (NumPy axis order; reversed for the ABI)."""
+    """adr_problem for device tensors (NumPy axis order; reversed for the ABI).  tau=None:
+    the standard Helmholtz operator (tau = 0, no factoring)."""
     import torch
-    shape = tuple(tau.shape)
+    shape = tuple(kappa2.shape)
     d = len(shape)
     prob = AdrProblem()
     prob.ndim = d
@@ -178,7 +180,7 @@ def make_problem(kappa2, tau, gamma, h, omega, src, factored=True):
     prob.h = float(h)
     prob.omega = float(omega)
     prob.kappa2 = _dev(kappa2, torch.float64)
-    prob.tau = _dev(tau, torch.float64)
+    prob.tau = _dev(tau, torch.float64) if tau is not None else None
     prob.gamma = _dev(gamma, torch.float64) if gamma is not None else None
     if factored and src is not None:
         for k in range(3):
@@ -194,8 +196,9 @@ class Context:
     def __init__(self, kappa2, tau, gamma, h, omega, src, options=None, stream=None, factored=True, _borrowed=None):
         lib = load_library()
         self._lib = lib
-        self.shape = tuple(tau.shape)
-        self.device = tau.device
+        ref = tau if tau is not None else kappa2
+        self.shape = tuple(ref.shape)
+        self.device = ref.device
         if _borrowed is not None:   # a context owned by a Batch
             self._ptr = _borrowed
             self._owned = False
@@ -373,15 +376,15 @@ class Batch:
         self.options = options if options is not None else default_options()
         probs = (AdrProblem * len(shots))()
         for i, s in enumerate(shots):
-            probs[i] = make_problem(s["kappa2"], s["tau"], s.get("gamma"), s["h"], s["omega"], s["src"])
-        self.shapes = [tuple(s["tau"].shape) for s in shots]
-        self.device = shots[0]["tau"].device
+            probs[i] = make_problem(s["kappa2"], s.get("tau"), s.get("gamma"), s["h"], s["omega"], s["src"])
+        self.shapes = [tuple(s["kappa2"].shape) for s in shots]
+        self.device = shots[0]["kappa2"].device
         ptr = ctypes.c_void_p()
         st = lib.adr_setup_batch(len(shots), probs, ctypes.byref(self.options), int(nstreams), ctypes.byref(ptr))
         if st != ADR_OK:
             raise AdrError(st, (lib.adr_last_error(None) or b"").decode())
         self._ptr = ptr
-        self.contexts = [Context(None, s["tau"], None, s["h"], s["omega"], s["src"], options=self.options,
+        self.contexts = [Context(s["kappa2"], s.get("tau"), None, s["h"], s["omega"], s["src"], options=self.options,
                                  _borrowed=ctypes.c_void_p(lib.adr_batch_context(ptr, i)))
                          for i, s in enumerate(shots)]
 

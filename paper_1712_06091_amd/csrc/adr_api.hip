@@ -85,6 +85,7 @@ struct adr_ctx {
   float *g32[3] = {nullptr, nullptr, nullptr};
   float *L32 = nullptr;
   cx<float> *c32 = nullptr;
+  cx<double> *cM64 = nullptr;  // reaction plane of the shifted preconditioner (shift_alpha > 0)
   double *tau = nullptr;
 
   // hierarchy (one of the two, by precision)
@@ -341,6 +342,20 @@ FineCoef<float> fine_coef<float>(adr_ctx *ctx) {
   return FineCoef<float>{{ctx->g32[0], ctx->g32[1], ctx->g32[2]}, ctx->L32, ctx->c32};
 }
 
+// Coefficients of the operator the multigrid cycle works on: A_beta's, with the reaction
+// plane of the shifted operator when shift_alpha > 0 (in mixed mode the FP32 copy was
+// made from that plane).  The outer FGMRES matvec always uses fine_coef<double>.
+template <typename T>
+FineCoef<T> prec_coef(adr_ctx *ctx);
+template <>
+FineCoef<double> prec_coef<double>(adr_ctx *ctx) {
+  FineCoef<double> C = fine_coef<double>(ctx);
+  if (ctx->cM64) C.c = ctx->cM64;
+  return C;
+}
+template <>
+FineCoef<float> prec_coef<float>(adr_ctx *ctx) { return fine_coef<float>(ctx); }
+
 FineParams fine_params(adr_ctx *ctx, double beta) {
   FineParams P;
   P.h = ctx->h;
@@ -504,7 +519,7 @@ void gmres_relax(adr_ctx *ctx, int l, const cx<T> *x0, const cx<T> *b, cx<T> *x_
 template <typename T>
 cx<T> *jacobi_sweeps(adr_ctx *ctx, int nu, const cx<T> *x_start, const cx<T> *b, cx<T> *first, cx<T> *second) {
   const Grid &G = levels_of<T>(ctx)[0].G;
-  FineCoef<T> C = fine_coef<T>(ctx);
+  FineCoef<T> C = prec_coef<T>(ctx);
   FineParams P = fine_params(ctx, ctx->opt.beta);
   const cx<T> *in = x_start;
   cx<T> *out = first;
@@ -565,10 +580,10 @@ cx<T> *vcycle(adr_ctx *ctx, int l, const cx<T> *b, cx<T> *out0, ProIn bpin = Pro
   if (l == 0) {
     int t0 = tbegin(ctx, ADR_TIMER_FINE_RESIDUAL, 0);
     if (ctx->adj)
-      adrk::fine_apply_adj<T, T, T>(s, L.G, D, fine_coef<T>(ctx), fine_params(ctx, ctx->opt.beta), x, b, L.r, 1,
+      adrk::fine_apply_adj<T, T, T>(s, L.G, D, prec_coef<T>(ctx), fine_params(ctx, ctx->opt.beta), x, b, L.r, 1,
                                     nullptr, false, nullptr);
     else
-      adrk::fine_apply<T, T, T>(s, L.G, D, fine_coef<T>(ctx), fine_params(ctx, ctx->opt.beta), x, b, L.r, 1,
+      adrk::fine_apply<T, T, T>(s, L.G, D, prec_coef<T>(ctx), fine_params(ctx, ctx->opt.beta), x, b, L.r, 1,
                                 nullptr, false, nullptr, ctx->Pdev + 1);
     tend(ctx, t0, (double)L.G.N * (fine_coef_bytes<T>(D) + 3 * cb));
   }
@@ -684,8 +699,8 @@ adr_status validate(const adr_problem *p, const adr_options *o, std::string &err
   for (int k = 0; k < p->ndim; ++k) N *= p->n[k];
   if (N > (1LL << 30)) { err = "grid too large (more than 2^30 nodes)"; return ADR_EINVAL; }
   if (!(p->h > 0) || !(p->omega > 0)) { err = "h and omega must be > 0"; return ADR_EINVAL; }
-  if (!p->kappa2 || !p->tau) { err = "kappa2 and tau are required"; return ADR_EINVAL; }
-  if (p->src[0] >= 0) {
+  if (!p->kappa2) { err = "kappa2 is required"; return ADR_EINVAL; }
+  if (p->tau && p->src[0] >= 0) {
     for (int k = 0; k < p->ndim; ++k)
       if (p->src[k] < 2 || p->src[k] > p->n[k] - 3) {
         err = "source must be at least 2 nodes from every face";
@@ -712,6 +727,10 @@ adr_status validate(const adr_problem *p, const adr_options *o, std::string &err
     return ADR_EINVAL;
   }
   if (!(o->kcycle_threshold >= 0.0)) { err = "kcycle_threshold must be >= 0"; return ADR_EINVAL; }
+  if (!(o->shift_alpha >= 0.0 && o->shift_alpha < 1e300)) {
+    err = "shift_alpha must be finite and >= 0";
+    return ADR_EINVAL;
+  }
   return ADR_OK;
 }
 
@@ -872,7 +891,7 @@ adr_status build_hierarchy(adr_ctx *ctx) {
   if (ctx->levels > 1) {
     st = dalloc(ctx, &prev, (size_t)Sf * ctx->G0.N);
     if (st == ADR_OK) {
-      FineCoef<double> C = fine_coef<double>(ctx);
+      FineCoef<double> C = prec_coef<double>(ctx);
       adrk::fine_stencil(s, ctx->G0, D, C, fine_params(ctx, ctx->opt.beta), prev);
     }
   }
@@ -923,7 +942,7 @@ adr_status build_hierarchy(adr_ctx *ctx) {
     // Single level: materialize the fine stencil of A_beta directly.
     cx<double> *tmp = nullptr;
     ADR_TRY(dalloc(ctx, &tmp, (size_t)Sf * n));
-    adrk::fine_stencil(s, ctx->G0, D, fine_coef<double>(ctx), fine_params(ctx, ctx->opt.beta), tmp);
+    adrk::fine_stencil(s, ctx->G0, D, prec_coef<double>(ctx), fine_params(ctx, ctx->opt.beta), tmp);
     std::vector<cx<double>> hp((size_t)Sf * n);
     ADR_HIP(hipMemcpyAsync(hp.data(), tmp, hp.size() * sizeof(cx<double>), hipMemcpyDeviceToHost, s));
     ADR_HIP(hipStreamSynchronize(s));
@@ -985,6 +1004,7 @@ void free_ctx(adr_ctx *ctx) {
   F(ctx->L32);
   F(ctx->c64);
   F(ctx->c32);
+  F(ctx->cM64);
   F(ctx->tau);
   F(ctx->gamma);
   F(ctx->Ainv_adj);
@@ -1036,13 +1056,20 @@ adr_status setup_impl(adr_ctx *ctx, const adr_problem *p) {
   ADR_TRY(dalloc(ctx, &ctx->L64, N));
   ADR_TRY(dalloc(ctx, &ctx->c64, N));
   ADR_TRY(dalloc(ctx, &ctx->tau, N));
-  ADR_HIP(hipMemcpyAsync(ctx->tau, p->tau, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+  if (p->tau)
+    ADR_HIP(hipMemcpyAsync(ctx->tau, p->tau, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+  else
+    ADR_HIP(hipMemsetAsync(ctx->tau, 0, sizeof(double) * N, s));
   if (p->gamma) {
     ADR_TRY(dalloc(ctx, &ctx->gamma, N));
     ADR_HIP(hipMemcpyAsync(ctx->gamma, p->gamma, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
   }
-  adrk::coefficients(s, ctx->G0, D, ctx->h, ctx->omega, ctx->src, p->kappa2, p->tau, p->gamma, ctx->g64[0],
+  adrk::coefficients(s, ctx->G0, D, ctx->h, ctx->omega, ctx->src, p->kappa2, ctx->tau, p->gamma, ctx->g64[0],
                      ctx->g64[1], D == 3 ? ctx->g64[2] : nullptr, ctx->L64, ctx->c64);
+  if (ctx->opt.shift_alpha > 0.0) {
+    ADR_TRY(dalloc(ctx, &ctx->cM64, N));
+    adrk::shift_reaction(s, N, ctx->c64, p->kappa2, ctx->opt.shift_alpha * ctx->omega * ctx->omega, ctx->cM64);
+  }
   ADR_HIP(hipGetLastError());
   // Reduction scratch and scalars.
   for (int i = 0; i < 2; ++i) ADR_TRY(dalloc(ctx, &ctx->part[i], (size_t)ADR_MAX_RED_BLOCKS * ADR_MAX_RED));
@@ -1075,7 +1102,7 @@ adr_status setup_impl(adr_ctx *ctx, const adr_problem *p) {
     ADR_TRY(dalloc(ctx, &ctx->L32, N));
     adrk::convert_real<float, double>(s, N, ctx->L64, ctx->L32);
     ADR_TRY(dalloc(ctx, &ctx->c32, N));
-    adrk::convert<float, double>(s, N, ctx->c64, ctx->c32);
+    adrk::convert<float, double>(s, N, ctx->cM64 ? ctx->cM64 : ctx->c64, ctx->c32);
     ADR_TRY(build_hierarchy<float>(ctx));
     ADR_TRY(dalloc(ctx, &ctx->b32, N));
     ADR_TRY(dalloc(ctx, &ctx->z32, N));
@@ -1208,8 +1235,10 @@ adr_status setup_ctx(const adr_problem *prob, const adr_options *opt, hipStream_
   ctx->G0 = make_grid(ctx->D, prob->n);
   ctx->h = prob->h;
   ctx->omega = prob->omega;
-  for (int k = 0; k < 3; ++k) ctx->src[k] = (prob->src[0] >= 0 && k < ctx->D) ? prob->src[k] : 0;
-  if (prob->src[0] < 0) ctx->src[0] = -1;
+  // Without tau (standard Helmholtz) there is no factoring and no near-source rule.
+  const bool has_src = prob->tau && prob->src[0] >= 0;
+  for (int k = 0; k < 3; ++k) ctx->src[k] = (has_src && k < ctx->D) ? prob->src[k] : 0;
+  if (!has_src) ctx->src[0] = -1;
   ctx->levels = o->levels > 0 ? o->levels : auto_levels(ctx->D, prob->n, o->coarsest_max > 0 ? o->coarsest_max : 729);
   for (int l = 0; l < kMaxLevels; ++l) {
     ctx->nu[l] = o->nu[l];
@@ -1252,6 +1281,7 @@ void adr_default_options(adr_options *o) {
   o->cycle = ADR_CYCLE_V;
   o->kcycle_threshold = 0.1;
   o->tail_max_nodes = 0;
+  o->shift_alpha = 0.0;
 }
 
 adr_status adr_setup(const adr_problem *prob, const adr_options *opt, void *stream, adr_ctx **out) {

@@ -1539,6 +1539,19 @@ void phase(hipStream_t s, int N, const cx<double> *in, const double *tau, double
   launch_g(k_phase<false>, k_phase<true>, launch_blocks(N), s, N, in, tau, omega, sign, out, omega_dev);
 }
 
+// Reaction plane of the shifted operator H_s = H - i alpha w^2 diag(kappa^2) (Sec. 3.1,
+// eq. shift): out = c - i s kappa2 with s = alpha w^2.  Setup only.
+__global__ __launch_bounds__(ADR_BLOCK) void k_shift_reaction(long long n, const cx<double> *__restrict__ c,
+                                                              const double *__restrict__ kappa2, double s,
+                                                              cx<double> *__restrict__ out) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    out[i] = mk<double>(c[i].re, c[i].im - s * kappa2[i]);
+}
+void shift_reaction(hipStream_t s, long long n, const cx<double> *c, const double *kappa2, double shift,
+                    cx<double> *out) {
+  hipLaunchKernelGGL(k_shift_reaction, dim3(launch_blocks(n)), dim3(ADR_BLOCK), 0, s, n, c, kappa2, shift, out);
+}
+
 // =====================================================================================
 // Coarsest level: x = A_L^{-1} b with the dense FP64 inverse (row-major), one
 // wavefront per row, lanes striding over the columns.

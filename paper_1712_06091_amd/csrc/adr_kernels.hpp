@@ -193,6 +193,9 @@ void normalize(hipStream_t s, int N, const cx<double> *x, ProIn pin, cx<double> 
 // when given (device copy, per problem in a shot group), else omega.
 void phase(hipStream_t s, int N, const cx<double> *in, const double *tau, double omega, int sign, cx<double> *out,
            const double *omega_dev = nullptr);
+// out = c - i shift kappa2 (reaction plane of the shifted preconditioner).
+void shift_reaction(hipStream_t s, long long n, const cx<double> *c, const double *kappa2, double shift,
+                    cx<double> *out);
 
 // ---- coarse tail ---------------------------------------------------------------------
 // The V-cycle on levels first..last (coarsest) from a zero guess on level `first` with

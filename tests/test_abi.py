@@ -38,7 +38,7 @@ def test_default_options(lib):
     assert list(o.nu)[:3] == [2, 3, 4]
     assert o.relax[0] == adr.ADR_RELAX_JACOBI and o.relax[1] == adr.ADR_RELAX_GMRES
     assert o.cycle == adr.ADR_CYCLE_V and abs(o.kcycle_threshold - 0.1) < 1e-15 and o.coarse_split == 0
-    assert o.tail_max_nodes == 0
+    assert o.tail_max_nodes == 0 and o.shift_alpha == 0.0
     assert adr.default_options(cycle="k").cycle == adr.ADR_CYCLE_K
 
 
@@ -76,7 +76,8 @@ def test_setup_rejects_bad_problem(lib, bad):
 
 
 @pytest.mark.parametrize("bad", [dict(restart=0), dict(restart=9), dict(levels=9), dict(beta=1.5), dict(prec=7),
-                                 dict(cycle=2), dict(kcycle_threshold=-0.5), dict(coarse_split=2)])
+                                 dict(cycle=2), dict(kcycle_threshold=-0.5), dict(coarse_split=2),
+                                 dict(shift_alpha=-0.1), dict(shift_alpha=float("nan"))])
 def test_setup_rejects_bad_options(lib, bad):
     from paper_1712_06091_amd import adr
     p = _problem()
