@@ -21,6 +21,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 TOL = 1e-6
+TIMER_LAUNCHES = 65536   # launches one adr_timer_start can time
 
 
 def log(msg):
@@ -526,6 +527,8 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(args.workload),
                      "avg_launch_ms": avg_ms, "launches": dm_n, "algorithmic_bytes_per_launch": avg_bytes},
         "breakdown_ms": {c: round(v["ms"], 4) for c, v in breakdown.items()},
+        "breakdown_launches": {c: v["launches"] for c, v in breakdown.items()},
+        "breakdown_truncated": [c for c, v in breakdown.items() if v["launches"] >= TIMER_LAUNCHES],
     }
     log(f"breakdown done; level-1 apply {avg_ms * 1e3:.1f} us/launch; V-cycle {vc_ms:.3f} ms")
     if not args.no_cpu_baseline:

@@ -252,7 +252,7 @@ typedef enum {
 
 /* Benchmark instrumentation.  adr_timer_start(ctx, kind, level) makes every later launch
  * of that kernel class (on `level`, or on any level if level < 0) record a pair of HIP
- * events on the context stream, up to 8192 launches.  adr_timer_stop synchronizes the
+ * events on the context stream, up to 65536 launches (later ones go untimed).  adr_timer_stop synchronizes the
  * stream and returns (host out-params, any may be NULL) the summed kernel time in ms,
  * the number of timed launches and their algorithmic bytes: every array the kernel reads
  * or writes counted once per node (stencil neighbours of a vector count once).  Timing

@@ -1982,11 +1982,13 @@ adr_status adr_solve_batch(adr_batch *b, const void *const *q, void *const *a, d
 
 void adr_destroy_batch(adr_batch *b) { free_batch(b); }
 
+constexpr int kTimerLaunches = 65536;   // launches one adr_timer_start can time
+
 adr_status adr_timer_start(adr_ctx *ctx, int kind, int level) {
   if (!ctx || kind < 0 || kind > ADR_TIMER_COARSE_TAIL) return ADR_EINVAL;
   auto &T = ctx->timer;
   if (T.ev.empty()) {
-    T.ev.resize(2 * 8192);
+    T.ev.resize(2 * (size_t)kTimerLaunches);
     for (auto &e : T.ev) ADR_HIP(hipEventCreate(&e));
   }
   T.kind = kind;

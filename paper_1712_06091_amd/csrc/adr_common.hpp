@@ -129,7 +129,9 @@ __device__ __forceinline__ void chunk_range(int N, int &beg, int &end) {
 // own.  (Device-scope fences and atomics would serialize through memory across the 8
 // XCDs; a separate one-block finish kernel costs a launch per reduction.)
 // ------------------------------------------------------------------------------------
+#ifndef ADR_MAX_RED_BLOCKS
 #define ADR_MAX_RED_BLOCKS 512
+#endif
 
 inline int launch_blocks_red(long long N) {
   long long b = (N + ADR_BLOCK - 1) / ADR_BLOCK;

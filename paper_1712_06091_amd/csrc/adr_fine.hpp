@@ -55,7 +55,7 @@ __device__ __forceinline__ void fine_row(const Grid &G, const FineParams &P, int
   }
   T cre = c.re, cim = c.im;
   // Mass term: on faces it multiplies a_j, inside the neighbours' mean.
-  const T mass_nb = on_face ? T(0) : -w * L / T(2 * D);
+  const T mass_nb = on_face ? T(0) : -w * L * (T(1) / T(2 * D));
   if (on_face) cim += -w * L;
 #pragma unroll
   for (int k = 0; k < D; ++k) {
@@ -178,6 +178,6 @@ __device__ __forceinline__ cx<T> fine_offdiag(const Grid &G, const FineParams &P
     }
   }
   T im = T(-2) * w * g * d;
-  if (!on_face && (o == -1 || o == 1)) im += -w * L / T(2 * D);
+  if (!on_face && (o == -1 || o == 1)) im += -w * L * (T(1) / T(2 * D));
   return mk<T>(lap, im);
 }

@@ -351,7 +351,10 @@ template int fine_apply<float, float, float>(hipStream_t, const Grid &, int, con
                                              cx<float> *, int, const VecSet<float> *, bool, double *,
                                              const FineParams *);
 
-template <typename T, int D, bool GRP>
+// HASX = false: the sweep starts from x = 0 (no gathers).  A compile-time flag, because a
+// run-time test around the gathers makes the compiler wait for all of them at the join
+// before it issues the coefficient loads.
+template <typename T, int D, bool HASX, bool GRP>
 __global__ __launch_bounds__(ADR_BLOCK) void k_fine_jacobi(Grid G, FineCoef<T> C, FineParams P,
                                                            const cx<T> *__restrict__ xin,
                                                            const cx<T> *__restrict__ b, cx<T> *__restrict__ xout,
@@ -368,25 +371,24 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_fine_jacobi(Grid G, FineCoef<T> C
   int beg, end;
   chunk_range(G.N, beg, end);
   for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    T gk[3], L;
+    cx<T> c;
+    load_fine_coef<T, D>(C, i, gk, L, c);
+    const cx<T> bi = b[i];
     int idx[3];
     decode(G, i, idx[0], idx[1], idx[2]);
-    // Gathers first, so that their latency overlaps the row computation.
     cx<T> xv[1 + 4 * D];
-    if (xin) {
+    if constexpr (HASX) {
       int nb[1 + 4 * D];
       fine_neighbours<D>(G, i, idx, nb);
 #pragma unroll
       for (int p = 0; p < 1 + 4 * D; ++p) xv[p] = xin[nb[p]];
     }
-    T gk[3], L;
-    cx<T> c;
-    load_fine_coef<T, D>(C, i, gk, L, c);
-    const cx<T> bi = b[i];
     cx<T> e[1 + 4 * D];
     fine_row<T, D>(G, P, idx, gk, L, c, e);
     cx<T> r = bi;
     cx<T> x0 = mk<T>(T(0), T(0));
-    if (xin) {
+    if constexpr (HASX) {
       cx<T> acc = mk<T>(T(0), T(0));
 #pragma unroll
       for (int p = 0; p < 1 + 4 * D; ++p) acc = cfma(e[p], xv[p], acc);
@@ -401,8 +403,21 @@ template <typename T>
 void fine_jacobi(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P, const cx<T> *x_in,
                  const cx<T> *b, cx<T> *x_out, double weight, const FineParams *Pd) {
   int nb = launch_blocks(G.N);
-  if (D == 2) launch_g(k_fine_jacobi<T, 2, false>, k_fine_jacobi<T, 2, true>, nb, s, G, C, P, x_in, b, x_out, (T)weight, Pd);
-  else launch_g(k_fine_jacobi<T, 3, false>, k_fine_jacobi<T, 3, true>, nb, s, G, C, P, x_in, b, x_out, (T)weight, Pd);
+  if (x_in) {
+    if (D == 2)
+      launch_g(k_fine_jacobi<T, 2, true, false>, k_fine_jacobi<T, 2, true, true>, nb, s, G, C, P, x_in, b, x_out,
+               (T)weight, Pd);
+    else
+      launch_g(k_fine_jacobi<T, 3, true, false>, k_fine_jacobi<T, 3, true, true>, nb, s, G, C, P, x_in, b, x_out,
+               (T)weight, Pd);
+  } else {
+    if (D == 2)
+      launch_g(k_fine_jacobi<T, 2, false, false>, k_fine_jacobi<T, 2, false, true>, nb, s, G, C, P, x_in, b, x_out,
+               (T)weight, Pd);
+    else
+      launch_g(k_fine_jacobi<T, 3, false, false>, k_fine_jacobi<T, 3, false, true>, nb, s, G, C, P, x_in, b, x_out,
+               (T)weight, Pd);
+  }
 }
 template void fine_jacobi<double>(hipStream_t, const Grid &, int, const FineCoef<double> &, const FineParams &,
                                   const cx<double> *, const cx<double> *, cx<double> *, double, const FineParams *);
