@@ -12,6 +12,10 @@ Row j of A_beta (eq. ADR discretized as in Sec. 2.2-2.3, blended as in eq. precA
   for g_k < 0 the forward mirror images.  H_2up = A_0, H_1up = A_1.
 * Near the source (Chebyshev distance <= 1 node from it) every D_k is the central
   difference of eq. londDiff, whatever beta (Sec. 2.2).
+* central=True gives H_cen (eq. ADRLinSystemCentral): D_k is the central difference of
+  eq. londDiff at every node that has both neighbours along axis k; on the two face
+  nodes of the axis, where it would need a node outside, the upwind operators (and
+  their fallbacks, below) replace it, as Sec. 2.2.1 prescribes.
 * Where an upwind stencil would leave the grid (Sec. 2.2.1 says it should not for an
   interior source; this fixes what happens when it does): one node short -> both
   orders use the first-order upwind formula; two nodes short (face node, g pointing
@@ -61,7 +65,7 @@ def _advection_weights(mode, beta, h):
     raise ValueError(mode)
 
 
-def advection_modes(g_axis, axis, shape, src):
+def advection_modes(g_axis, axis, shape, src, central=False):
     """Per-node stencil choice along one axis: array of mode strings."""
     idx = _node_indices(shape)
     i = idx[axis]
@@ -75,13 +79,15 @@ def advection_modes(g_axis, axis, shape, src):
     mode[fwd & (i <= n - 3)] = "F2"
     mode[fwd & (i == n - 2)] = "F1"
     mode[fwd & (i == n - 1)] = "B2"
+    if central:
+        mode[(i >= 1) & (i <= n - 2)] = "C"
     if src is not None:
         cheb = np.max(np.stack([np.abs(idx[a] - src[a]) for a in range(len(shape))]), axis=0)
         mode[cheb <= 1] = "C"
     return mode
 
 
-def adr_stencil(g, L, c, h, omega, beta, src=None):
+def adr_stencil(g, L, c, h, omega, beta, src=None, central=False):
     """Per-node stencil of A_beta as a dict {offset tuple: complex array}.
 
     Offsets are NumPy-axis-ordered tuples; entries that would reach outside the grid are
@@ -121,7 +127,7 @@ def adr_stencil(g, L, c, h, omega, beta, src=None):
         acc(off(a, +1), np.where(inner, 1.0 / h**2, 0.0) + np.where(low, 2.0 / h**2, 0.0))
         acc(zero, -2.0 / h**2 + np.where(low, -2.0 * iw * ga / h, 0.0) + np.where(high, 2.0 * iw * ga / h, 0.0))
         # Advection -2 i w g_k D_k^beta.
-        modes = advection_modes(ga, a, shape, src)
+        modes = advection_modes(ga, a, shape, src, central)
         for m in ("B2", "B1", "F2", "F1", "C"):
             sel = modes == m
             if not np.any(sel):
@@ -170,9 +176,10 @@ def stencil_to_csr(st, shape):
     return A
 
 
-def assemble_adr(g, L, c, h, omega, beta, src=None):
-    """A_beta as a CSR matrix (complex128)."""
-    st = adr_stencil(g, L, c, h, omega, beta, src)
+def assemble_adr(g, L, c, h, omega, beta, src=None, central=False):
+    """A_beta (or, with central=True, H_cen; beta then only matters on face nodes) as a
+    CSR matrix (complex128)."""
+    st = adr_stencil(g, L, c, h, omega, beta, src, central)
     return stencil_to_csr(st, np.asarray(L).shape)
 
 
