@@ -82,6 +82,14 @@ typedef enum {
                      /* zero, preconditioned by the cycle one level down                 */
 } adr_cycle;
 
+/* Advection scheme of the ADR operator (Sec. 2.2). */
+typedef enum {
+  ADR_ADV_UPWIND = 0,   /* second-order upwind, eq. londUpwindDiff (H_2up; blended with   */
+                        /* first-order upwind by beta in the preconditioner)              */
+  ADR_ADV_CENTRAL = 1   /* central, eq. londDiff (H_cen of eq. ADRLinSystemCentral); face */
+                        /* nodes of an axis use the upwind operators there (Sec. 2.2.1)   */
+} adr_advection;
+
 /* Solver options; adr_default_options() fills the defaults named below. */
 typedef struct {
   adr_precision prec;   /* default ADR_PREC_MIXED                                        */
@@ -115,6 +123,16 @@ typedef struct {
                         /* A_beta - i alpha w^2 diag(kappa^2) (Sec. 3.1, eq. shift; the  */
                         /* paper's Helmholtz runs use 0.2 with tau = NULL) while FGMRES  */
                         /* solves the unshifted system; default 0 (no shift)             */
+  adr_advection advection; /* default ADR_ADV_UPWIND; applies to the solved operator and */
+                        /* to the preconditioner                                          */
+  double outer_beta;    /* blend of the operator FGMRES solves: 0 (default) = H_2up,      */
+                        /* 1 = H_1up (eq. 1up, the first stage of Alg. ADRlong)          */
+  int rescaled;         /* 1: the cycle preconditions M A M^{-1} (M = diag(exp(-i w tau)), */
+                        /* eq. ADRcenRescaled): its fine level is the phase-rescaled      */
+                        /* operator and its coarse levels the Galerkin products of that   */
+                        /* (the second stage of Alg. ADRlong); the solve stays in a, which */
+                        /* gives the same iterates since M is unitary.  Not with the      */
+                        /* adjoint or batch calls (ADR_ENOTSUP).  Default 0               */
 } adr_options;
 
 typedef struct {
@@ -259,6 +277,19 @@ typedef enum {
  * adds an event record before and after each timed launch and nothing else. */
 adr_status adr_timer_start(adr_ctx *ctx, int kind, int level);
 adr_status adr_timer_stop(adr_ctx *ctx, double *ms, int *launches, double *bytes);
+
+/* Two-stage solve of H_cen a = q_hat (Sec. 3.2, Alg. ADRlong).  `first` and `second`
+ * are contexts on the same problem: adr_two_stage_options fills their options as in
+ * Sec. 4.2 (first: H_1up solved and preconditioned, beta = outer_beta = 1, Krylov
+ * cycle; second: central advection, beta = 0, shift_alpha = 0.2, rescaled, Krylov
+ * cycle), starting from the defaults and keeping `prec` of *first on entry.
+ * adr_solve_two_stage runs the first stage from zero to tol_first or maxit_first
+ * iterations (5 and 1e-2 in the paper; not converging there is not an error), then the
+ * second from that iterate to tol.  q, a as in adr_solve; st_first/st_second may be
+ * NULL.  Returns the second stage's status (the first stage's on a failure there). */
+void adr_two_stage_options(adr_options *first, adr_options *second);
+adr_status adr_solve_two_stage(adr_ctx *first, adr_ctx *second, const void *q_c128, void *a_c128, double tol_first,
+                               int maxit_first, double tol, int maxit, adr_stats *st_first, adr_stats *st_second);
 
 const char *adr_strerror(adr_status s);
 const char *adr_last_error(const adr_ctx *ctx);   /* NULL ctx: last setup error */

@@ -18,6 +18,7 @@ ADR_OK, ADR_EINVAL, ADR_ENOMEM, ADR_EHIP, ADR_ENOCONV, ADR_ENUMERIC, ADR_ENOTSUP
 ADR_PREC_FP64, ADR_PREC_MIXED = 0, 1
 ADR_RELAX_JACOBI, ADR_RELAX_GMRES = 0, 1
 ADR_CYCLE_V, ADR_CYCLE_K = 0, 1
+ADR_ADV_UPWIND, ADR_ADV_CENTRAL = 0, 1
 TIMER_KINDS = {"fine_jacobi": 0, "fine_residual": 1, "coarse_apply": 2, "coarse_orth": 3, "transfer": 4,
                "outer_matvec": 5, "outer_orth": 6, "coarse_tail": 7}
 
@@ -52,6 +53,9 @@ class AdrOptions(ctypes.Structure):
         ("tail_max_nodes", ctypes.c_int),
         ("full_cycles", ctypes.c_int),
         ("shift_alpha", ctypes.c_double),
+        ("advection", ctypes.c_int),
+        ("outer_beta", ctypes.c_double),
+        ("rescaled", ctypes.c_int),
     ]
 
 
@@ -94,6 +98,8 @@ def load_library(path=LIB_PATH):
         "adr_apply": (I, [P, D, P, P]),
         "adr_vcycle": (I, [P, P, P]),
         "adr_solve": (I, [P, P, P, D, I, I, ctypes.POINTER(AdrStats)]),
+        "adr_two_stage_options": (None, [ctypes.POINTER(AdrOptions), ctypes.POINTER(AdrOptions)]),
+        "adr_solve_two_stage": (I, [P, P, P, P, D, I, D, I, ctypes.POINTER(AdrStats), ctypes.POINTER(AdrStats)]),
         "adr_wavefield": (I, [P, P, P]),
         "adr_get_coefficients": (I, [P, P, P, P]),
         "adr_level_info": (I, [P, I, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
@@ -137,9 +143,34 @@ def default_options(**kw):
             o.prec = {"fp64": ADR_PREC_FP64, "mixed": ADR_PREC_MIXED}.get(v, v)
         elif k == "cycle":
             o.cycle = {"v": ADR_CYCLE_V, "k": ADR_CYCLE_K}.get(v, v)
+        elif k == "advection":
+            o.advection = {"upwind": ADR_ADV_UPWIND, "central": ADR_ADV_CENTRAL}.get(v, v)
         else:
             setattr(o, k, v)
     return o
+
+
+def two_stage_options(prec="mixed"):
+    """Options of the two contexts of the two-stage solve (adr_two_stage_options)."""
+    lib = load_library()
+    first, second = AdrOptions(), AdrOptions()
+    first.prec = {"fp64": ADR_PREC_FP64, "mixed": ADR_PREC_MIXED}.get(prec, prec)
+    lib.adr_two_stage_options(ctypes.byref(first), ctypes.byref(second))
+    return first, second
+
+
+def solve_two_stage(first, second, q, tol=1e-6, maxit=500, tol_first=1e-2, maxit_first=5, out=None):
+    """adr_solve_two_stage on two Contexts of one problem; returns (a, stats1, stats2)."""
+    import torch
+    a = first._new(torch.complex128) if out is None else out
+    s1, s2 = AdrStats(), AdrStats()
+    status = _check(first._lib.adr_solve_two_stage(first._ptr, second._ptr, _dev(q, torch.complex128),
+                                                   _dev(a, torch.complex128), float(tol_first), int(maxit_first),
+                                                   float(tol), int(maxit), ctypes.byref(s1), ctypes.byref(s2)),
+                    second._ptr)
+    d1, d2 = s1.as_dict(), s2.as_dict()
+    d2["status"] = status
+    return a, d1, d2
 
 
 def _check(status, ctx_ptr=None):

@@ -86,6 +86,9 @@ struct adr_ctx {
   float *L32 = nullptr;
   cx<float> *c32 = nullptr;
   cx<double> *cM64 = nullptr;  // reaction plane of the shifted preconditioner (shift_alpha > 0)
+  cx<double> *ph64 = nullptr;  // exp(i w tau) when the cycle works on the rescaled operator
+  cx<float> *ph32 = nullptr;   // its FP32 copy (mixed precision)
+  cx<double> *vtmp = nullptr;  // rescaled cycle input (FP64 mode)
   double *tau = nullptr;
 
   // hierarchy (one of the two, by precision)
@@ -356,12 +359,21 @@ FineCoef<double> prec_coef<double>(adr_ctx *ctx) {
 template <>
 FineCoef<float> prec_coef<float>(adr_ctx *ctx) { return fine_coef<float>(ctx); }
 
+// exp(i w tau) in the cycle's precision (rescaled cycles only).
+template <typename T>
+const cx<T> *phase_of(adr_ctx *ctx);
+template <>
+const cx<double> *phase_of<double>(adr_ctx *ctx) { return ctx->ph64; }
+template <>
+const cx<float> *phase_of<float>(adr_ctx *ctx) { return ctx->ph32; }
+
 FineParams fine_params(adr_ctx *ctx, double beta) {
   FineParams P;
   P.h = ctx->h;
   P.omega = ctx->omega;
   P.beta = beta;
   for (int k = 0; k < 3; ++k) P.src[k] = ctx->src[k];
+  P.central = ctx->opt.advection == ADR_ADV_CENTRAL ? 1 : 0;
   return P;
 }
 
@@ -527,6 +539,8 @@ cx<T> *jacobi_sweeps(adr_ctx *ctx, int nu, const cx<T> *x_start, const cx<T> *b,
     out = (k % 2 == 0) ? first : second;
     int t0 = tbegin(ctx, ADR_TIMER_FINE_JACOBI, 0);
     if (ctx->adj) adrk::fine_jacobi_adj<T>(ctx->stream, G, ctx->D, C, P, in, b, out, ctx->opt.jacobi_weight);
+    else if (ctx->ph64)
+      adrk::fine_jacobi_ph<T>(ctx->stream, G, ctx->D, C, P, phase_of<T>(ctx), in, b, out, ctx->opt.jacobi_weight);
     else adrk::fine_jacobi<T>(ctx->stream, G, ctx->D, C, P, in, b, out, ctx->opt.jacobi_weight, ctx->Pdev + 1);
     tend(ctx, t0, (double)G.N * (fine_coef_bytes<T>(ctx->D) + sizeof(cx<T>) * (in ? 3 : 2)));
     in = out;
@@ -582,6 +596,9 @@ cx<T> *vcycle(adr_ctx *ctx, int l, const cx<T> *b, cx<T> *out0, ProIn bpin = Pro
     if (ctx->adj)
       adrk::fine_apply_adj<T, T, T>(s, L.G, D, prec_coef<T>(ctx), fine_params(ctx, ctx->opt.beta), x, b, L.r, 1,
                                     nullptr, false, nullptr);
+    else if (ctx->ph64)
+      adrk::fine_residual_ph<T>(s, L.G, D, prec_coef<T>(ctx), fine_params(ctx, ctx->opt.beta), phase_of<T>(ctx), x,
+                                b, L.r);
     else
       adrk::fine_apply<T, T, T>(s, L.G, D, prec_coef<T>(ctx), fine_params(ctx, ctx->opt.beta), x, b, L.r, 1,
                                 nullptr, false, nullptr, ctx->Pdev + 1);
@@ -727,6 +744,9 @@ adr_status validate(const adr_problem *p, const adr_options *o, std::string &err
     return ADR_EINVAL;
   }
   if (!(o->kcycle_threshold >= 0.0)) { err = "kcycle_threshold must be >= 0"; return ADR_EINVAL; }
+  if (o->advection != ADR_ADV_UPWIND && o->advection != ADR_ADV_CENTRAL) { err = "bad advection"; return ADR_EINVAL; }
+  if (!(o->outer_beta >= 0.0 && o->outer_beta <= 1.0)) { err = "outer_beta must be in [0, 1]"; return ADR_EINVAL; }
+  if (o->rescaled != 0 && o->rescaled != 1) { err = "rescaled must be 0 or 1"; return ADR_EINVAL; }
   if (!(o->shift_alpha >= 0.0 && o->shift_alpha < 1e300)) {
     err = "shift_alpha must be finite and >= 0";
     return ADR_EINVAL;
@@ -893,6 +913,7 @@ adr_status build_hierarchy(adr_ctx *ctx) {
     if (st == ADR_OK) {
       FineCoef<double> C = prec_coef<double>(ctx);
       adrk::fine_stencil(s, ctx->G0, D, C, fine_params(ctx, ctx->opt.beta), prev);
+      if (ctx->ph64) adrk::stencil_rescale(s, ctx->G0, D, prev, ctx->ph64);
     }
   }
   for (int l = 1; l < ctx->levels && st == ADR_OK; ++l) {
@@ -943,6 +964,7 @@ adr_status build_hierarchy(adr_ctx *ctx) {
     cx<double> *tmp = nullptr;
     ADR_TRY(dalloc(ctx, &tmp, (size_t)Sf * n));
     adrk::fine_stencil(s, ctx->G0, D, prec_coef<double>(ctx), fine_params(ctx, ctx->opt.beta), tmp);
+    if (ctx->ph64) adrk::stencil_rescale(s, ctx->G0, D, tmp, ctx->ph64);
     std::vector<cx<double>> hp((size_t)Sf * n);
     ADR_HIP(hipMemcpyAsync(hp.data(), tmp, hp.size() * sizeof(cx<double>), hipMemcpyDeviceToHost, s));
     ADR_HIP(hipStreamSynchronize(s));
@@ -1005,6 +1027,9 @@ void free_ctx(adr_ctx *ctx) {
   F(ctx->c64);
   F(ctx->c32);
   F(ctx->cM64);
+  F(ctx->ph64);
+  F(ctx->ph32);
+  F(ctx->vtmp);
   F(ctx->tau);
   F(ctx->gamma);
   F(ctx->Ainv_adj);
@@ -1082,7 +1107,7 @@ adr_status setup_impl(adr_ctx *ctx, const adr_problem *p) {
   // own problem's omega and source there) and the shot-group flag.
   ADR_TRY(dalloc(ctx, &ctx->Pdev, 2));
   {
-    const FineParams hpar[2] = {fine_params(ctx, 0.0), fine_params(ctx, ctx->opt.beta)};
+    const FineParams hpar[2] = {fine_params(ctx, ctx->opt.outer_beta), fine_params(ctx, ctx->opt.beta)};
     ADR_HIP(hipMemcpy(ctx->Pdev, hpar, sizeof(hpar), hipMemcpyHostToDevice));
   }
   ADR_TRY(dalloc(ctx, &ctx->active, 1));
@@ -1093,6 +1118,16 @@ adr_status setup_impl(adr_ctx *ctx, const adr_problem *p) {
   if (ctx->group_member) {
     ADR_TRY(dalloc(ctx, &ctx->qin, N));
     ADR_TRY(dalloc(ctx, &ctx->xg, N));
+  }
+  if (ctx->opt.rescaled) {
+    ADR_TRY(dalloc(ctx, &ctx->ph64, N));
+    adrk::phase_plane(s, N, ctx->tau, ctx->omega, ctx->ph64);
+    if (ctx->opt.prec == ADR_PREC_MIXED) {
+      ADR_TRY(dalloc(ctx, &ctx->ph32, N));
+      adrk::convert<float, double>(s, N, ctx->ph64, ctx->ph32);
+    } else {
+      ADR_TRY(dalloc(ctx, &ctx->vtmp, N));
+    }
   }
   if (ctx->opt.prec == ADR_PREC_MIXED) {
     for (int k = 0; k < D; ++k) {
@@ -1135,6 +1170,24 @@ adr_status setup_impl(adr_ctx *ctx, const adr_problem *p) {
 void enqueue_vcycle(adr_ctx *ctx, const cx<double> *v, void *z, bool z_is_c128) {
   hipStream_t s = ctx->stream;
   const int N = ctx->G0.N;
+  if (ctx->ph64) {
+    // Rescaled cycle: z = M^{-1} K(M v) with M = diag(conj(ph)).
+    if (ctx->opt.prec == ADR_PREC_MIXED) {
+      adrk::mul_phase<double, float>(s, N, v, ctx->ph64, true, ctx->b32);
+      if (z_is_c128) {
+        vcycle<float>(ctx, 0, ctx->b32, ctx->z32);
+        adrk::mul_phase<float, double>(s, N, ctx->z32, ctx->ph64, false, (cx<double> *)z);
+      } else {
+        cx<float> *zf = vcycle<float>(ctx, 0, ctx->b32, (cx<float> *)z);
+        adrk::mul_phase<float, float>(s, N, zf, ctx->ph64, false, (cx<float> *)z);
+      }
+    } else {
+      adrk::mul_phase<double, double>(s, N, v, ctx->ph64, true, ctx->vtmp);
+      cx<double> *zd = vcycle<double>(ctx, 0, ctx->vtmp, (cx<double> *)z);
+      adrk::mul_phase<double, double>(s, N, zd, ctx->ph64, false, (cx<double> *)z);
+    }
+    return;
+  }
   if (ctx->opt.prec == ADR_PREC_MIXED) {
     adrk::convert<float, double>(s, N, v, ctx->b32);
     if (z_is_c128) {
@@ -1282,6 +1335,9 @@ void adr_default_options(adr_options *o) {
   o->kcycle_threshold = 0.1;
   o->tail_max_nodes = 0;
   o->shift_alpha = 0.0;
+  o->advection = ADR_ADV_UPWIND;
+  o->outer_beta = 0.0;
+  o->rescaled = 0;
 }
 
 adr_status adr_setup(const adr_problem *prob, const adr_options *opt, void *stream, adr_ctx **out) {
@@ -1368,7 +1424,7 @@ namespace {
 // r = rhs - (H or H^H) x in FP64 with the norm partials in part[0]; returns the block count.
 int fine_residual64(adr_ctx *ctx, const cx<double> *x, const cx<double> *rhs, cx<double> *r) {
   FineCoef<double> C = fine_coef<double>(ctx);
-  FineParams P0 = fine_params(ctx, 0.0);
+  FineParams P0 = fine_params(ctx, ctx->opt.outer_beta);
   if (ctx->adj)
     return adrk::fine_apply_adj<double, double, double>(ctx->stream, ctx->G0, ctx->D, C, P0, x, rhs, r, 1, nullptr,
                                                         true, ctx->part[0]);
@@ -1392,6 +1448,10 @@ adr_status prepare_adjoint_levels(adr_ctx *ctx) {
 }
 adr_status prepare_adjoint(adr_ctx *ctx) {
   if (ctx->adj_ready) return ADR_OK;
+  if (ctx->opt.rescaled) {
+    ctx->err = "adjoint solves with a rescaled cycle are not supported";
+    return ADR_ENOTSUP;
+  }
   if (ctx->opt.prec == ADR_PREC_MIXED) ADR_TRY(prepare_adjoint_levels<float>(ctx));
   else ADR_TRY(prepare_adjoint_levels<double>(ctx));
   const int n = ctx->Ncoarsest;
@@ -1497,7 +1557,7 @@ adr_status solver_device(const Solver &A, adr_ctx *ctx, const cx<double> *q, cx<
       for (int i = 0; i <= j; ++i) Vs.v[i] = Vp(i);
       double *red1 = ctx->osc + 2, *red2 = ctx->osc + 2 + 2 * (kMaxRestart + 1);
       FineCoef<double> C = fine_coef<double>(ctx);
-      FineParams P0 = fine_params(ctx, 0.0);
+      FineParams P0 = fine_params(ctx, ctx->opt.outer_beta);
       int t0 = tbegin(ctx, ADR_TIMER_OUTER_MATVEC, 0);
       int nb;
       if (mixed && ctx->adj)
@@ -1714,6 +1774,40 @@ adr_status adr_solve(adr_ctx *ctx, const void *q, void *a_out, double tol, int m
   return solve_impl(ctx, q, a_out, tol, maxit, use_initial_guess, stats);
 }
 
+void adr_two_stage_options(adr_options *first, adr_options *second) {
+  if (!first || !second) return;
+  const adr_precision prec = first->prec;
+  adr_default_options(first);
+  adr_default_options(second);
+  first->prec = second->prec = prec;
+  first->beta = 1.0;
+  first->outer_beta = 1.0;
+  first->cycle = ADR_CYCLE_K;
+  second->advection = ADR_ADV_CENTRAL;
+  second->beta = 0.0;
+  second->shift_alpha = 0.2;
+  second->rescaled = 1;
+  second->cycle = ADR_CYCLE_K;
+}
+
+adr_status adr_solve_two_stage(adr_ctx *first, adr_ctx *second, const void *q, void *a, double tol_first,
+                               int maxit_first, double tol, int maxit, adr_stats *st_first, adr_stats *st_second) {
+  if (!first || !second || first == second || !q || !a || maxit_first < 0 || maxit < 0 || !(tol_first >= 0) ||
+      !(tol >= 0))
+    return ADR_EINVAL;
+  if (first->D != second->D || first->G0.N != second->G0.N || first->G0.n[0] != second->G0.n[0] ||
+      first->G0.n[1] != second->G0.n[1] || first->G0.n[2] != second->G0.n[2]) {
+    second->err = "the two stages need contexts on the same grid";
+    return ADR_EINVAL;
+  }
+  first->adj = false;
+  adr_status st = solve_impl(first, q, a, tol_first, maxit_first, 0, st_first);
+  if (st != ADR_OK && st != ADR_ENOCONV) return st;
+  // adr_solve synchronizes its stream, so the second stage (on its own stream) sees a.
+  second->adj = false;
+  return solve_impl(second, q, a, tol, maxit, 1, st_second);
+}
+
 adr_status adr_solve_adjoint(adr_ctx *ctx, const void *s_c128, void *lam_c128, double tol, int maxit,
                              int use_initial_guess, adr_stats *stats) {
   if (!ctx || !s_c128 || !lam_c128 || maxit < 0 || !(tol >= 0)) return ADR_EINVAL;
@@ -1727,7 +1821,7 @@ adr_status adr_solve_adjoint(adr_ctx *ctx, const void *s_c128, void *lam_c128, d
 adr_status adr_apply_adjoint(adr_ctx *ctx, const void *x, void *y) {
   if (!ctx || !x || !y || x == y) return ADR_EINVAL;
   adrk::fine_apply_adj<double, double, double>(ctx->stream, ctx->G0, ctx->D, fine_coef<double>(ctx),
-                                               fine_params(ctx, 0.0), (const cx<double> *)x, nullptr,
+                                               fine_params(ctx, ctx->opt.outer_beta), (const cx<double> *)x, nullptr,
                                                (cx<double> *)y, 0, nullptr, false, nullptr);
   ADR_HIP(hipGetLastError());
   return ADR_OK;
@@ -1815,6 +1909,10 @@ adr_status adr_setup_batch(int count, const adr_problem *probs, const adr_option
   if (count <= 0 || !probs || nstreams <= 0 || nstreams > 64) {
     g_setup_error = "bad batch arguments";
     return ADR_EINVAL;
+  }
+  if (opt && opt->rescaled) {
+    g_setup_error = "batched solves with a rescaled cycle are not supported";
+    return ADR_ENOTSUP;
   }
   adr_batch *b = new adr_batch();
   auto fail = [&](adr_status st, const std::string &msg) {

@@ -29,6 +29,7 @@ struct FineCoef {
 struct FineParams {
   double h, omega, beta;
   int src[3];      // source node; src[0] < 0: no near-source rule
+  int central;     // 1: central advection (eq. londDiff) off the faces of each axis
 };
 
 // Shift the coefficient planes to problem blockIdx.y of a shot group (see Shot).
@@ -70,7 +71,7 @@ __device__ __forceinline__ void fine_row(const Grid &G, const FineParams &P, int
     if (high) cim += T(2) * w * g * ih;
     // Advection weights for offsets -2..+2 (real), scaled by -2 w g into the imaginary part.
     T d_m2 = 0, d_m1 = 0, d_0 = 0, d_p1 = 0, d_p2 = 0;
-    if (near) {
+    if (near || (P.central && !low && !high)) {
       d_m1 = T(-0.5) * ih;
       d_p1 = T(0.5) * ih;
     } else {
@@ -156,7 +157,7 @@ __device__ __forceinline__ cx<T> fine_offdiag(const Grid &G, const FineParams &P
   if (o == -1) lap = low ? T(0) : (high ? T(2) * ih2 : ih2);
   if (o == 1) lap = high ? T(0) : (low ? T(2) * ih2 : ih2);
   T d = 0;
-  if (near) {
+  if (near || (P.central && !low && !high)) {
     if (o == -1) d = T(-0.5) * ih;
     if (o == 1) d = T(0.5) * ih;
   } else {

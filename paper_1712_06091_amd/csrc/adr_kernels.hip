@@ -704,6 +704,176 @@ void copy(hipStream_t s, long long n, const cx<double> *in, cx<double> *out) {
 }
 
 // =====================================================================================
+// Rescaled fine operator B = M A M^{-1} with M = diag(exp(-i w tau)) (Sec. 3.2,
+// eq. ADRcenRescaled): with ph = exp(i w tau), row j of B is
+// conj(ph_j) sum_k A_jk ph_k x_k, and its diagonal is A's.  The multigrid cycle of the
+// second stage of Alg. ADRlong works on B (shifted), so that its coarse levels are
+// Galerkin products of B.
+// =====================================================================================
+__global__ __launch_bounds__(ADR_BLOCK) void k_phase_plane(long long n, const double *__restrict__ tau, double omega,
+                                                           cx<double> *__restrict__ ph) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    double sn, cs;
+    sincos(omega * tau[i], &sn, &cs);
+    ph[i] = mk<double>(cs, sn);
+  }
+}
+void phase_plane(hipStream_t s, long long n, const double *tau, double omega, cx<double> *ph) {
+  ADR_LAUNCH(k_phase_plane, launch_blocks(n), s, n, tau, omega, ph);
+}
+
+// out = conj(ph) in (conj != 0) or ph in; in and out may alias.
+template <typename Ti, typename To>
+__global__ __launch_bounds__(ADR_BLOCK) void k_mul_phase(long long n, const cx<Ti> *in, const cx<double> *__restrict__ ph,
+                                                         int conj, cx<To> *out) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const cx<double> p = ph[i];
+    const cx<double> v = cvt<double, Ti>(in[i]);
+    out[i] = cvt<To, double>(conj ? cdotc(p, v) : p * v);
+  }
+}
+template <typename Ti, typename To>
+void mul_phase(hipStream_t s, long long n, const cx<Ti> *in, const cx<double> *ph, bool conj, cx<To> *out) {
+  ADR_LAUNCH((k_mul_phase<Ti, To>), launch_blocks(n), s, n, in, ph, conj ? 1 : 0, out);
+}
+template void mul_phase<double, double>(hipStream_t, long long, const cx<double> *, const cx<double> *, bool,
+                                        cx<double> *);
+template void mul_phase<double, float>(hipStream_t, long long, const cx<double> *, const cx<double> *, bool,
+                                       cx<float> *);
+template void mul_phase<float, double>(hipStream_t, long long, const cx<float> *, const cx<double> *, bool,
+                                       cx<double> *);
+template void mul_phase<float, float>(hipStream_t, long long, const cx<float> *, const cx<double> *, bool,
+                                      cx<float> *);
+
+// planes[p][j] *= conj(ph_j) ph_{nb_p(j)} for the 1 + 4D planes of the fine stencil (the
+// entries towards neighbours outside the grid are zero and stay zero).
+template <int D>
+__global__ __launch_bounds__(ADR_BLOCK) void k_stencil_rescale(Grid G, cx<double> *planes,
+                                                               const cx<double> *__restrict__ ph) {
+  int beg, end;
+  chunk_range(G.N, beg, end);
+  for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    int idx[3];
+    decode(G, i, idx[0], idx[1], idx[2]);
+    int nb[1 + 4 * D];
+    fine_neighbours<D>(G, i, idx, nb);
+    const cx<double> pj = ph[i];
+#pragma unroll
+    for (int p = 1; p < 1 + 4 * D; ++p) {
+      cx<double> &e = planes[(size_t)p * G.N + i];
+      e = cdotc(pj, ph[nb[p]] * e);
+    }
+  }
+}
+void stencil_rescale(hipStream_t s, const Grid &G, int D, cx<double> *planes, const cx<double> *ph) {
+  int nb = launch_blocks(G.N);
+  if (D == 2) ADR_LAUNCH(k_stencil_rescale<2>, nb, s, G, planes, ph);
+  else ADR_LAUNCH(k_stencil_rescale<3>, nb, s, G, planes, ph);
+}
+
+// Damped Jacobi on B (x_in NULL: from zero), and the residual r = b - B x.
+template <typename T, int D, bool HASX>
+__global__ __launch_bounds__(ADR_BLOCK) void k_fine_jacobi_ph(Grid G, FineCoef<T> C, FineParams P,
+                                                              const cx<T> *__restrict__ ph,
+                                                              const cx<T> *__restrict__ xin,
+                                                              const cx<T> *__restrict__ b, cx<T> *__restrict__ xout,
+                                                              T weight) {
+  int beg, end;
+  chunk_range(G.N, beg, end);
+  for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    T gk[3], L;
+    cx<T> c;
+    load_fine_coef<T, D>(C, i, gk, L, c);
+    const cx<T> bi = b[i];
+    const cx<T> pi = ph[i];
+    int idx[3];
+    decode(G, i, idx[0], idx[1], idx[2]);
+    cx<T> xv[1 + 4 * D], pv[1 + 4 * D];
+    if constexpr (HASX) {
+      int nb[1 + 4 * D];
+      fine_neighbours<D>(G, i, idx, nb);
+#pragma unroll
+      for (int p = 0; p < 1 + 4 * D; ++p) {
+        xv[p] = xin[nb[p]];
+        pv[p] = ph[nb[p]];
+      }
+    }
+    cx<T> e[1 + 4 * D];
+    fine_row<T, D>(G, P, idx, gk, L, c, e);
+    cx<T> r = bi;
+    cx<T> x0 = mk<T>(T(0), T(0));
+    if constexpr (HASX) {
+      cx<T> acc = mk<T>(T(0), T(0));
+#pragma unroll
+      for (int p = 0; p < 1 + 4 * D; ++p) acc = cfma(e[p], pv[p] * xv[p], acc);
+      r = r - cdotc(pi, acc);
+      x0 = xv[0];
+    }
+    xout[i] = cfma(weight * cinv(e[0]), r, x0);
+  }
+}
+template <typename T, int D>
+__global__ __launch_bounds__(ADR_BLOCK) void k_fine_residual_ph(Grid G, FineCoef<T> C, FineParams P,
+                                                                const cx<T> *__restrict__ ph,
+                                                                const cx<T> *__restrict__ x,
+                                                                const cx<T> *__restrict__ b, cx<T> *__restrict__ r) {
+  int beg, end;
+  chunk_range(G.N, beg, end);
+  for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    T gk[3], L;
+    cx<T> c;
+    load_fine_coef<T, D>(C, i, gk, L, c);
+    const cx<T> bi = b[i];
+    const cx<T> pi = ph[i];
+    int idx[3];
+    decode(G, i, idx[0], idx[1], idx[2]);
+    int nb[1 + 4 * D];
+    fine_neighbours<D>(G, i, idx, nb);
+    cx<T> xv[1 + 4 * D], pv[1 + 4 * D];
+#pragma unroll
+    for (int p = 0; p < 1 + 4 * D; ++p) {
+      xv[p] = x[nb[p]];
+      pv[p] = ph[nb[p]];
+    }
+    cx<T> e[1 + 4 * D];
+    fine_row<T, D>(G, P, idx, gk, L, c, e);
+    cx<T> acc = mk<T>(T(0), T(0));
+#pragma unroll
+    for (int p = 0; p < 1 + 4 * D; ++p) acc = cfma(e[p], pv[p] * xv[p], acc);
+    r[i] = bi - cdotc(pi, acc);
+  }
+}
+template <typename T>
+void fine_jacobi_ph(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P, const cx<T> *ph,
+                    const cx<T> *x_in, const cx<T> *b, cx<T> *x_out, double weight) {
+  int nb = launch_blocks(G.N);
+  if (x_in) {
+    if (D == 2) ADR_LAUNCH((k_fine_jacobi_ph<T, 2, true>), nb, s, G, C, P, ph, x_in, b, x_out, (T)weight);
+    else ADR_LAUNCH((k_fine_jacobi_ph<T, 3, true>), nb, s, G, C, P, ph, x_in, b, x_out, (T)weight);
+  } else {
+    if (D == 2) ADR_LAUNCH((k_fine_jacobi_ph<T, 2, false>), nb, s, G, C, P, ph, x_in, b, x_out, (T)weight);
+    else ADR_LAUNCH((k_fine_jacobi_ph<T, 3, false>), nb, s, G, C, P, ph, x_in, b, x_out, (T)weight);
+  }
+}
+template <typename T>
+void fine_residual_ph(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P,
+                      const cx<T> *ph, const cx<T> *x, const cx<T> *b, cx<T> *r) {
+  int nb = launch_blocks(G.N);
+  if (D == 2) ADR_LAUNCH((k_fine_residual_ph<T, 2>), nb, s, G, C, P, ph, x, b, r);
+  else ADR_LAUNCH((k_fine_residual_ph<T, 3>), nb, s, G, C, P, ph, x, b, r);
+}
+template void fine_jacobi_ph<double>(hipStream_t, const Grid &, int, const FineCoef<double> &, const FineParams &,
+                                     const cx<double> *, const cx<double> *, const cx<double> *, cx<double> *,
+                                     double);
+template void fine_jacobi_ph<float>(hipStream_t, const Grid &, int, const FineCoef<float> &, const FineParams &,
+                                    const cx<float> *, const cx<float> *, const cx<float> *, cx<float> *, double);
+template void fine_residual_ph<double>(hipStream_t, const Grid &, int, const FineCoef<double> &,
+                                       const FineParams &, const cx<double> *, const cx<double> *,
+                                       const cx<double> *, cx<double> *);
+template void fine_residual_ph<float>(hipStream_t, const Grid &, int, const FineCoef<float> &, const FineParams &,
+                                      const cx<float> *, const cx<float> *, const cx<float> *, cx<float> *);
+
+// =====================================================================================
 // Coarse levels: stored Galerkin stencils (SoA planes)
 // =====================================================================================
 // Clamped neighbour index tables of node i along each axis (offsets -2..2), as linear

@@ -108,6 +108,20 @@ template <typename T>
 void fine_jacobi(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P, const cx<T> *x_in,
                  const cx<T> *b, cx<T> *x_out, double weight, const FineParams *Pd = nullptr);
 
+// Rescaled fine operator B = M A M^{-1}, M = diag(conj(ph)), ph = exp(i w tau):
+// ph = exp(i w tau); out = conj(ph) in or ph in (in, out may alias); the fine stencil
+// planes of A turned into B's; Jacobi on B and r = b - B x.
+void phase_plane(hipStream_t s, long long n, const double *tau, double omega, cx<double> *ph);
+template <typename Ti, typename To>
+void mul_phase(hipStream_t s, long long n, const cx<Ti> *in, const cx<double> *ph, bool conj, cx<To> *out);
+void stencil_rescale(hipStream_t s, const Grid &G, int D, cx<double> *planes, const cx<double> *ph);
+template <typename T>
+void fine_jacobi_ph(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P, const cx<T> *ph,
+                    const cx<T> *x_in, const cx<T> *b, cx<T> *x_out, double weight);
+template <typename T>
+void fine_residual_ph(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P,
+                      const cx<T> *ph, const cx<T> *x, const cx<T> *b, cx<T> *r);
+
 // A^H x on the fine level (conjugate transpose, matrix-free), same conventions.
 template <typename T, typename Tin, typename To>
 int fine_apply_adj(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P, const cx<Tin> *x,

@@ -39,6 +39,12 @@ def test_default_options(lib):
     assert o.relax[0] == adr.ADR_RELAX_JACOBI and o.relax[1] == adr.ADR_RELAX_GMRES
     assert o.cycle == adr.ADR_CYCLE_V and abs(o.kcycle_threshold - 0.1) < 1e-15 and o.coarse_split == 0
     assert o.tail_max_nodes == 0 and o.shift_alpha == 0.0
+    assert o.advection == adr.ADR_ADV_UPWIND and o.outer_beta == 0.0 and o.rescaled == 0
+    first, second = adr.two_stage_options("fp64")
+    assert first.prec == second.prec == adr.ADR_PREC_FP64
+    assert first.beta == first.outer_beta == 1.0 and first.cycle == adr.ADR_CYCLE_K
+    assert second.advection == adr.ADR_ADV_CENTRAL and second.rescaled == 1 and second.beta == 0.0
+    assert abs(second.shift_alpha - 0.2) < 1e-15 and second.cycle == adr.ADR_CYCLE_K
     assert adr.default_options(cycle="k").cycle == adr.ADR_CYCLE_K
 
 
@@ -77,7 +83,8 @@ def test_setup_rejects_bad_problem(lib, bad):
 
 @pytest.mark.parametrize("bad", [dict(restart=0), dict(restart=9), dict(levels=9), dict(beta=1.5), dict(prec=7),
                                  dict(cycle=2), dict(kcycle_threshold=-0.5), dict(coarse_split=2),
-                                 dict(shift_alpha=-0.1), dict(shift_alpha=float("nan"))])
+                                 dict(shift_alpha=-0.1), dict(shift_alpha=float("nan")), dict(advection=2),
+                                 dict(outer_beta=1.5), dict(rescaled=2)])
 def test_setup_rejects_bad_options(lib, bad):
     from paper_1712_06091_amd import adr
     p = _problem()
@@ -95,6 +102,7 @@ def test_null_context_calls(lib):
     assert lib.adr_num_levels(None) == 0
     sp = ctypes.c_int()
     assert lib.adr_level_split(None, 1, ctypes.byref(sp)) == adr.ADR_EINVAL
+    assert lib.adr_solve_two_stage(None, None, None, None, 1e-2, 5, 1e-6, 10, None, None) == adr.ADR_EINVAL
     lib.adr_destroy(None)
     assert lib.adr_strerror(adr.ADR_ENOCONV) == b"not converged"
 
