@@ -34,7 +34,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="3d_129",
-                    choices=["3d_129", "2d_129", "3d_65", "3d_257", "batch_2d", "adjoint_3d_193", "helmholtz_3d_129"])
+                    choices=["3d_129", "2d_129", "3d_65", "3d_257", "batch_2d", "adjoint_3d_193", "compare_3d_129"])
     ap.add_argument("--adjoint-n", type=int, default=193, help="grid size of the adjoint workload")
     ap.add_argument("--fm-workers", type=int, default=8, help="CPU processes for fast marching")
     ap.add_argument("--streams", type=int, default=4, help="streams of the batched-shot solve")
@@ -42,7 +42,7 @@ def parse():
                     help="GPU_MAX_HW_QUEUES for this process (set before the GPU is initialized; <= 32)")
     ap.add_argument("--cycle", default="v", choices=["v", "k"], help="V-cycle or Krylov cycle preconditioner")
     ap.add_argument("--shift", type=float, default=0.2,
-                    help="helmholtz_3d_129: shifted-Laplacian alpha of the preconditioner")
+                    help="compare_3d_129: shifted-Laplacian alpha of the preconditioner")
     ap.add_argument("--batch-maxit", type=int, default=3000, help="FGMRES iteration cap per shot (batch)")
     ap.add_argument("--no-looped", action="store_true", help="batch: skip the one-shot-at-a-time comparison")
     ap.add_argument("--mixed-only", action="store_true", help="with --profile-only: skip the FP64 solves")
@@ -321,10 +321,11 @@ def run_batch(args):
     print(json.dumps(out))
 
 
-def run_helmholtz(args):
-    """Standard Helmholtz (tau = NULL) on the 3D 129^3 linear-gradient medium, FGMRES(5)
-    with the shifted-Laplacian multigrid preconditioner (alpha = --shift), beside the ADR
-    solve of the same medium and source."""
+def run_compare(args):
+    """The three discretizations of the paper's performance tables (Sec. 4.2) on the 3D
+    129^3 linear-gradient medium and source: standard Helmholtz with the shifted-Laplacian
+    preconditioner (alpha = --shift), the ADR-central system by the two-stage solve, and
+    the ADR-upwind system; FGMRES(5), the --cycle preconditioner, to 1e-6."""
     import numpy as np
     import torch
 
@@ -339,37 +340,56 @@ def run_helmholtz(args):
     out = torch.empty(wl.shape, dtype=torch.complex128, device=dev)
     maxit = 2000
 
-    def timed(ctx):
+    def timed(solve_once):
         for _ in range(args.warmup):
-            ctx.solve(q, tol=TOL, maxit=maxit, out=out)
+            solve_once()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            _, st = ctx.solve(q, tol=TOL, maxit=maxit, out=out)
+            its, st = solve_once()
             if st["status"] != adr.ADR_OK or not st["relres"] <= TOL:
                 raise RuntimeError(f"solve did not converge: {st}")
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) * 1e3 / args.steps, st["outer_iters"]
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        return {"value": N / (ms * 1e-3) / 1e6, "ms_per_step": ms, "outer_iters": its}
 
     res = {}
     for name, tau_arg, alpha in (("standard", None, args.shift), ("adr_upwind", tau, 0.0)):
-        opts = adr.default_options(prec="mixed", cycle=args.cycle, shift_alpha=alpha)
-        ctx = adr.Context(k2, tau_arg, gam, wl.h, wl.omega, wl.src, options=opts)
-        ms, its = timed(ctx)
-        res[name] = {"value": N / (ms * 1e-3) / 1e6, "ms_per_step": ms, "outer_iters": its}
-        log(f"{name}: {ms:.1f} ms/solve, {its} iterations")
+        ctx = adr.Context(k2, tau_arg, gam, wl.h, wl.omega, wl.src,
+                          options=adr.default_options(prec="mixed", cycle=args.cycle, shift_alpha=alpha))
+
+        def once(ctx=ctx):
+            _, st = ctx.solve(q, tol=TOL, maxit=maxit, out=out)
+            return st["outer_iters"], st
+        res[name] = timed(once)
+        log(f"{name}: {res[name]['ms_per_step']:.1f} ms/solve, {res[name]['outer_iters']} iterations")
         ctx.close()
-    std = res["standard"]
+    o1, o2 = adr.two_stage_options("mixed")
+    o1.cycle = o2.cycle = adr.ADR_CYCLE_K if args.cycle == "k" else adr.ADR_CYCLE_V
+    o2.shift_alpha = args.shift
+    c1 = adr.Context(k2, tau, gam, wl.h, wl.omega, wl.src, options=o1)
+    c2 = adr.Context(k2, tau, gam, wl.h, wl.omega, wl.src, options=o2)
+
+    def once2():
+        _, s1, s2 = adr.solve_two_stage(c1, c2, q, tol=TOL, maxit=maxit, out=out)
+        return [s1["outer_iters"], s2["outer_iters"]], s2
+    res["adr_central_two_stage"] = timed(once2)
+    log(f"adr_central_two_stage: {res['adr_central_two_stage']['ms_per_step']:.1f} ms/solve, "
+        f"{res['adr_central_two_stage']['outer_iters']} iterations (stage 1, stage 2)")
+    c1.close()
+    c2.close()
+    up = res["adr_upwind"]
     print(json.dumps({
-        "metric": "Standard Helmholtz solves (shifted-Laplacian multigrid): Mpoints/s to 1e-6 residual",
-        "value": std["value"], "unit": "Mpoints/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": std["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "c64 V-cycle / c128 FGMRES", "data": "synthetic",
-        "config": {"workload": "helmholtz_3d_129_linear_gradient", "grid": list(wl.shape), "nodes": N,
+        "metric": "Discretization comparison, Mpoints/s to 1e-6 residual (value: ADR upwind)",
+        "value": up["value"], "unit": "Mpoints/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": up["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64 cycle / c128 FGMRES", "data": "synthetic",
+        "config": {"workload": "compare_3d_129_linear_gradient", "grid": list(wl.shape), "nodes": N,
                    "omega": wl.omega, "tol": TOL, "restart": 5, "shift_alpha": args.shift, "cycle": args.cycle},
-        "outer_iters": std["outer_iters"],
-        "adr_same_medium": res["adr_upwind"],
-        "adr_over_standard": res["adr_upwind"]["value"] / std["value"],
+        "outer_iters": up["outer_iters"],
+        "standard_shifted_laplacian": res["standard"],
+        "adr_central_two_stage": res["adr_central_two_stage"],
+        "adr_upwind": up,
     }))
 
 
@@ -396,8 +416,8 @@ def main():
     if args.workload == "adjoint_3d_193":
         run_adjoint(args)
         return
-    if args.workload == "helmholtz_3d_129":
-        run_helmholtz(args)
+    if args.workload == "compare_3d_129":
+        run_compare(args)
         return
 
     import numpy as np
