@@ -1090,28 +1090,47 @@ template int coarse_apply<float>(hipStream_t, int, const CoarseArgs<float> &, co
 // =====================================================================================
 // With pout: also z_c = dinv_c o r_c and the partials of ||r_c||^2 (the coarse
 // relaxation's first Krylov vector and its norm).
+// Full weighting with fixed trip counts: neighbours outside the fine grid are clamped to
+// it and weighted 0, so all loads of a node can be issued together (the sum is the same
+// as skipping them).
 template <typename T, int D>
 __device__ __forceinline__ cx<T> restrict_value(const Grid &Gf, const Grid &Gc, const cx<T> *__restrict__ rf, int J) {
   int jx, jy, jz;
   decode(Gc, J, jx, jy, jz);
   const int fx = 2 * jx, fy = 2 * jy, fz = 2 * jz;
+  constexpr int NZ = (D == 3) ? 3 : 1;
+  int xo[3], yo[3], zo[3];
+  T wx[3], wy[3], wz[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int x = fx + q - 1, y = fy + q - 1, z = fz + q - 1;
+    xo[q] = min(max(x, 0), Gf.n[0] - 1);
+    yo[q] = Gf.n[0] * min(max(y, 0), Gf.n[1] - 1);
+    zo[q] = (D == 3) ? Gf.n[0] * Gf.n[1] * min(max(z, 0), Gf.n[2] - 1) : 0;
+    const T w = q == 1 ? T(1) : T(0.5);
+    wx[q] = (x >= 0 && x < Gf.n[0]) ? w : T(0);
+    wy[q] = (y >= 0 && y < Gf.n[1]) ? w : T(0);
+    wz[q] = (D == 2) ? T(1) : ((z >= 0 && z < Gf.n[2]) ? w : T(0));
+  }
+  cx<T> v[NZ][3][3];
+#pragma unroll
+  for (int c = 0; c < NZ; ++c)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) v[c][b][a] = rf[xo[a] + yo[b] + zo[D == 3 ? c : 1]];
   cx<T> acc = mk<T>(T(0), T(0));
-  const int zlo = (D == 3) ? -1 : 0, zhi = (D == 3) ? 1 : 0;
-  for (int pz = zlo; pz <= zhi; ++pz) {
-    const int z = fz + pz;
-    if (z < 0 || z >= Gf.n[2]) continue;
-    const T wz = pz == 0 ? T(1) : T(0.5);
-    for (int py = -1; py <= 1; ++py) {
-      const int y = fy + py;
-      if (y < 0 || y >= Gf.n[1]) continue;
-      const T wy = wz * (py == 0 ? T(1) : T(0.5));
-      for (int px = -1; px <= 1; ++px) {
-        const int x = fx + px;
-        if (x < 0 || x >= Gf.n[0]) continue;
-        const T w = wy * (px == 0 ? T(1) : T(0.5));
-        const cx<T> v = rf[x + Gf.n[0] * (y + Gf.n[1] * z)];
-        acc.re += w * v.re;
-        acc.im += w * v.im;
+#pragma unroll
+  for (int c = 0; c < NZ; ++c) {
+    const T w2 = (D == 3) ? wz[c] : T(1);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const T w1 = w2 * wy[b];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const T w = w1 * wx[a];
+        acc.re += w * v[c][b][a].re;
+        acc.im += w * v[c][b][a].im;
       }
     }
   }
@@ -1143,10 +1162,15 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_restrict(Grid Gf, Grid Gc, const 
   if (pout) block_partials<1>(red, 1, pout);
 }
 
+constexpr int kRestrictMaxBlocks = 4096;
+static_assert(kRestrictMaxBlocks <= ADR_MAX_RED_BLOCKS * ADR_MAX_RED, "restriction partials must fit");
 template <typename T>
 int restrict_full(hipStream_t s, const Grid &Gf, const Grid &Gc, int D, const cx<T> *rf, cx<T> *rc,
                   const cx<T> *dinv_c, cx<T> *z_c, double *pout) {
-  int nb = pout ? launch_blocks_red(Gc.N) : launch_blocks(Gc.N);
+  // One partial per block: more blocks than the usual reduction cap cost the consumer
+  // little (its prologue sums nb doubles) and give the gathers more parallelism.
+  int nb = launch_blocks(Gc.N);
+  if (pout && nb > kRestrictMaxBlocks) nb = kRestrictMaxBlocks;
   if (D == 2) launch_g(k_restrict<T, 2, false>, k_restrict<T, 2, true>, nb, s, Gf, Gc, rf, rc, dinv_c, z_c, pout);
   else launch_g(k_restrict<T, 3, false>, k_restrict<T, 3, true>, nb, s, Gf, Gc, rf, rc, dinv_c, z_c, pout);
   return nb;
@@ -1156,21 +1180,37 @@ template int restrict_full<double>(hipStream_t, const Grid &, const Grid &, int,
 template int restrict_full<float>(hipStream_t, const Grid &, const Grid &, int, const cx<float> *, cx<float> *,
                                   const cx<float> *, cx<float> *, double *);
 
+// Multilinear interpolation with fixed trip counts: the second coarse node along an axis
+// gets weight 0 when the fine node sits on a coarse node (clamped into the grid).
 template <typename T, int D>
 __device__ __forceinline__ cx<T> prolong_value(const Grid &Gf, const Grid &Gc, const cx<T> *__restrict__ ec, int f) {
   int fx, fy, fz;
   decode(Gf, f, fx, fy, fz);
   const int x0 = fx >> 1, y0 = fy >> 1, z0 = fz >> 1;
-  const int nxs = (fx & 1) ? 2 : 1, nys = (fy & 1) ? 2 : 1, nzs = (D == 3 && (fz & 1)) ? 2 : 1;
-  const T wx = (fx & 1) ? T(0.5) : T(1), wy = (fy & 1) ? T(0.5) : T(1), wz = (D == 3 && (fz & 1)) ? T(0.5) : T(1);
+  constexpr int NZ = (D == 3) ? 2 : 1;
+  const int xs[2] = {x0, min(x0 + 1, Gc.n[0] - 1)};
+  const int ys[2] = {Gc.n[0] * y0, Gc.n[0] * min(y0 + 1, Gc.n[1] - 1)};
+  const int zs[2] = {Gc.n[0] * Gc.n[1] * z0, (D == 3) ? Gc.n[0] * Gc.n[1] * min(z0 + 1, Gc.n[2] - 1) : 0};
+  const T wx[2] = {(fx & 1) ? T(0.5) : T(1), (fx & 1) ? T(0.5) : T(0)};
+  const T wy[2] = {(fy & 1) ? T(0.5) : T(1), (fy & 1) ? T(0.5) : T(0)};
+  const T wz[2] = {(D == 3 && (fz & 1)) ? T(0.5) : T(1), (D == 3 && (fz & 1)) ? T(0.5) : T(0)};
+  cx<T> v[NZ][2][2];
+#pragma unroll
+  for (int c = 0; c < NZ; ++c)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) v[c][b][a] = ec[xs[a] + ys[b] + zs[c]];
   cx<T> acc = mk<T>(T(0), T(0));
-  for (int cz = 0; cz < nzs; ++cz)
-    for (int cy = 0; cy < nys; ++cy)
-      for (int cxx = 0; cxx < nxs; ++cxx) {
-        const cx<T> v = ec[(x0 + cxx) + Gc.n[0] * ((y0 + cy) + Gc.n[1] * (z0 + cz))];
-        const T w = wx * wy * wz;
-        acc.re += w * v.re;
-        acc.im += w * v.im;
+#pragma unroll
+  for (int c = 0; c < NZ; ++c)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const T w = wx[a] * wy[b] * wz[c];
+        acc.re += w * v[c][b][a].re;
+        acc.im += w * v[c][b][a].im;
       }
   return acc;
 }
