@@ -159,6 +159,27 @@ def test_two_stage_solve(name, prec):
         assert _rel(a1.cpu().numpy(), o_a1.reshape(wl.shape)) <= 1e-9
 
 
+def test_two_stage_without_first_stage_and_bad_pairs():
+    """maxit_first = 0 leaves a = 0 after stage 1, so the result is stage 2's solve from
+    zero; contexts on different grids are refused."""
+    from paper_1712_06091_amd import adr
+    wl = W.constant_medium(65, 2)
+    print("[two-stage-edge] 2d 65", flush=True)
+    o1, o2 = adr.two_stage_options("fp64")
+    c1, c2 = _ctx(wl, o1), _ctx(wl, o2)
+    q = _t(wl.rhs())
+    a, s1, s2 = adr.solve_two_stage(c1, c2, q, tol=1e-10, maxit=400, maxit_first=0)
+    assert s1["outer_iters"] == 0 and s2["relres"] <= 1e-10
+    b, st = c2.solve(q, tol=1e-10, maxit=400)
+    assert st["outer_iters"] == s2["outer_iters"]
+    assert _rel(a.cpu().numpy(), b.cpu().numpy()) <= 1e-12
+    other = W.constant_medium(33, 2)
+    c3 = _ctx(other, o2)
+    with pytest.raises(adr.AdrError) as e:
+        adr.solve_two_stage(c1, c3, q, tol=1e-10, maxit=10)
+    assert e.value.status == adr.ADR_EINVAL
+
+
 def test_rescaled_refuses_adjoint_and_batch():
     from paper_1712_06091_amd import adr
     wl = W.constant_medium(33, 2)
