@@ -59,7 +59,6 @@ def parse():
     return ap.parse_args()
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_coarse_apply_level1_3d_129.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1712_06091_amd", "csrc", f)
                   for f in ("adr_kernels.hip", "adr_kernels.hpp", "adr_common.hpp")]
 
@@ -74,20 +73,22 @@ def kernel_source_hash():
 
 
 def measured_traffic(workload):
-    """HBM bytes per launch of the level-1 Galerkin apply from the committed counter
-    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when there is no
-    summary for this workload or the kernel sources changed since it was taken."""
-    if workload != "3d_129" or not os.path.exists(TRAFFIC_FILE):
+    """HBM bytes from the committed counter summary of this workload (FETCH_SIZE +
+    WRITE_SIZE, scaled by a plain copy): {"level1": per level-1 Galerkin apply, "vcycle":
+    per V-cycle}, or None when there is no summary or the kernel sources changed since
+    it was taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
+    if not os.path.exists(path):
         return None
     vals = {}
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if ":" in line and line.strip().startswith("- `"):
                 k, v = line.strip()[3:].split("`", 1)
                 vals[k] = v.split(":", 1)[1].strip().strip("`")
     if vals.get("kernel_sources_sha256") != kernel_source_hash():
         return None
-    return float(vals["traffic_bytes_per_launch"])
+    return {"level1": float(vals["level1_traffic_bytes_per_launch"]), "vcycle": float(vals["vcycle_traffic_bytes"])}
 
 
 def make_workload(name):
@@ -516,6 +517,7 @@ def main():
     torch.cuda.synchronize()
     vc_ms = e0.elapsed_time(e1) / reps
 
+    traffic = measured_traffic(args.workload)
     iters_m = st_mixed[-1]["outer_iters"]
     iters_d = st_fp64[-1]["outer_iters"]
     value = N / (ms_mixed * 1e-3) / 1e6
@@ -542,9 +544,10 @@ def main():
         "final_relres": st_mixed[-1]["relres"],
         "setup_ms": setup_ms,
         "vcycle": {"ms": vc_ms, "algorithmic_bytes": vc_bytes, "GBps": vc_bytes / (vc_ms * 1e-3) / 1e9,
-                   "frac": vc_bytes / (vc_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS},
+                   "frac": vc_bytes / (vc_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                   "traffic": traffic["vcycle"] if traffic else None},
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(args.workload),
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic["level1"] if traffic else None,
                      "avg_launch_ms": avg_ms, "launches": dm_n, "algorithmic_bytes_per_launch": avg_bytes},
         "breakdown_ms": {c: round(v["ms"], 4) for c, v in breakdown.items()},
         "breakdown_launches": {c: v["launches"] for c, v in breakdown.items()},
