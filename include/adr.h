@@ -138,8 +138,9 @@ typedef struct {
 typedef struct {
   int outer_iters;      /* FGMRES iterations (= preconditioner applications)             */
   int restarts;
-  double relres;        /* final true relative residual ||q_hat - H_2up a|| / ||q_hat||  */
-  double setup_ms;      /* adr_setup wall time                                           */
+  double relres;        /* final true relative residual ||q_hat - A a|| / ||q_hat||, A    */
+                        /* the solved operator (H_2up, or as set by outer_beta/advection) */
+  double setup_ms;      /* wall time of the setup that built the context                 */
   double solve_ms;      /* adr_solve wall time                                           */
 } adr_stats;
 

@@ -89,6 +89,7 @@ struct adr_ctx {
   cx<double> *ph64 = nullptr;  // exp(i w tau) when the cycle works on the rescaled operator
   cx<float> *ph32 = nullptr;   // its FP32 copy (mixed precision)
   cx<double> *vtmp = nullptr;  // rescaled cycle input (FP64 mode)
+  double setup_ms = 0.0;       // wall time of the setup that built this context
   double *tau = nullptr;
 
   // hierarchy (one of the two, by precision)
@@ -1304,7 +1305,7 @@ adr_status setup_ctx(const adr_problem *prob, const adr_options *opt, hipStream_
     free_ctx(ctx);
     return st;
   }
-  (void)t0;
+  ctx->setup_ms = now_ms() - t0;
   ctx->arena = nullptr;   // later allocations are ordinary ones
   *out = ctx;
   return ADR_OK;
@@ -1744,6 +1745,7 @@ adr_status solver_result(Solver &S, adr_stats *stats) {
     st.outer_iters = S.iters;
     st.restarts = S.restarts;
     st.relres = S.relres;
+    st.setup_ms = S.ctx->setup_ms;
     st.solve_ms = now_ms() - S.t0;
     *stats = st;
   }

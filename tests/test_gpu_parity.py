@@ -185,6 +185,7 @@ def test_solve_initial_guess_and_zero_rhs():
     print("[solve-edge] 2d 33", flush=True)
     ctx = _ctx(wl, prec="fp64")
     a, st = ctx.solve(_t(wl.rhs()), tol=1e-10, maxit=200)
+    assert st["setup_ms"] > 0 and st["solve_ms"] > 0
     a2, st2 = ctx.solve(_t(wl.rhs()), tol=1e-10, maxit=200, x0=a)
     assert st2["outer_iters"] == 0 and st2["relres"] <= 1e-10
     z, st3 = ctx.solve(_t(np.zeros(wl.shape, complex)), tol=1e-10, maxit=10)
