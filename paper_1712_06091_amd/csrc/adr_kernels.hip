@@ -950,12 +950,12 @@ __device__ __forceinline__ cx<T> stencil_part_of(int w, const cx<T> *__restrict_
 // loads in flight per lane and SPLIT times more blocks, for the small coarse levels).
 // Partials: NV dots conj(V_v).y, then ||y||^2 if NORM.
 template <typename T, int D, int NV, bool NORM, int SPLIT, bool GRP>
-__global__ __launch_bounds__(ADR_BLOCK) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_coarse_apply(Grid G, const cx<T> *__restrict__ planes,
-                                                            const cx<T> *__restrict__ x, ProIn pin, const double *sdev,
-                                                            double *norm_out, int norm_cplx, double *inv_out,
-                                                            const cx<T> *__restrict__ b, cx<T> *__restrict__ y,
-                                                            const cx<T> *__restrict__ dinv, cx<T> *__restrict__ zout,
-                                                            int mode, VecSet<T> V, double *pout, Shot sh) {
+__device__ __forceinline__ void coarse_apply_body(Grid G, const cx<T> *__restrict__ planes,
+                                                  const cx<T> *__restrict__ x, ProIn pin, const double *sdev,
+                                                  double *norm_out, int norm_cplx, double *inv_out,
+                                                  const cx<T> *__restrict__ b, cx<T> *__restrict__ y,
+                                                  const cx<T> *__restrict__ dinv, cx<T> *__restrict__ zout, int mode,
+                                                  VecSet<T> V, double *pout, Shot sh) {
   ADR_SHOT_ENTER(sh);
   ADR_SHIFT(planes);
   ADR_SHIFT(x);
@@ -1045,13 +1045,39 @@ __global__ __launch_bounds__(ADR_BLOCK) __attribute__((amdgpu_waves_per_eu(1, 4)
   if (K > 0) block_partials<KA>(red, K, pout);
 }
 
+// The kernel, in two register budgets: the FP32 instances fit 4 waves per SIMD; the FP64
+// ones (twice the registers for a batch of 27 plane loads and gathers) are given room
+// for 2, which measured faster for them.
+template <typename T, int D, int NV, bool NORM, int SPLIT, bool GRP>
+__global__ __launch_bounds__(ADR_BLOCK) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_coarse_apply(
+    Grid G, const cx<T> *__restrict__ planes, const cx<T> *__restrict__ x, ProIn pin, const double *sdev,
+    double *norm_out, int norm_cplx, double *inv_out, const cx<T> *__restrict__ b, cx<T> *__restrict__ y,
+    const cx<T> *__restrict__ dinv, cx<T> *__restrict__ zout, int mode, VecSet<T> V, double *pout, Shot sh) {
+  coarse_apply_body<T, D, NV, NORM, SPLIT, GRP>(G, planes, x, pin, sdev, norm_out, norm_cplx, inv_out, b, y, dinv,
+                                                zout, mode, V, pout, sh);
+}
+template <typename T, int D, int NV, bool NORM, int SPLIT, bool GRP>
+__global__ __launch_bounds__(ADR_BLOCK) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_coarse_apply_w2(
+    Grid G, const cx<T> *__restrict__ planes, const cx<T> *__restrict__ x, ProIn pin, const double *sdev,
+    double *norm_out, int norm_cplx, double *inv_out, const cx<T> *__restrict__ b, cx<T> *__restrict__ y,
+    const cx<T> *__restrict__ dinv, cx<T> *__restrict__ zout, int mode, VecSet<T> V, double *pout, Shot sh) {
+  coarse_apply_body<T, D, NV, NORM, SPLIT, GRP>(G, planes, x, pin, sdev, norm_out, norm_cplx, inv_out, b, y, dinv,
+                                                zout, mode, V, pout, sh);
+}
+
 template <typename T, int D, bool NORM, int SPLIT>
 static void dispatch_coarse_nv(hipStream_t s, int nb, const CoarseArgs<T> &a, const VecSet<T> &V) {
   switch (V.count) {
 #define ADR_NV_CASE(n)                                                                                              \
   case n:                                                                                                           \
-    launch_g(k_coarse_apply<T, D, n, NORM, SPLIT, false>, k_coarse_apply<T, D, n, NORM, SPLIT, true>, nb, s, a.G, a.planes, a.x, a.pin, a.sdev, a.norm_out,      \
-               a.norm_cplx, a.inv_out, a.b, a.y, a.dinv, a.zout, a.mode, V, a.pout);                               \
+    if constexpr (sizeof(T) == 8)                                                                                   \
+      launch_g(k_coarse_apply_w2<T, D, n, NORM, SPLIT, false>, k_coarse_apply_w2<T, D, n, NORM, SPLIT, true>, nb, s, \
+               a.G, a.planes, a.x, a.pin, a.sdev, a.norm_out, a.norm_cplx, a.inv_out, a.b, a.y, a.dinv, a.zout,     \
+               a.mode, V, a.pout);                                                                                   \
+    else                                                                                                            \
+      launch_g(k_coarse_apply<T, D, n, NORM, SPLIT, false>, k_coarse_apply<T, D, n, NORM, SPLIT, true>, nb, s, a.G,  \
+               a.planes, a.x, a.pin, a.sdev, a.norm_out, a.norm_cplx, a.inv_out, a.b, a.y, a.dinv, a.zout, a.mode,   \
+               V, a.pout);                                                                                           \
     break;
     ADR_NV_CASE(0) ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6)
     ADR_NV_CASE(7) ADR_NV_CASE(8)
