@@ -78,3 +78,29 @@ def test_batch_repeated_solves_and_masking():
     for c in ctxs:
         c.close()
     b.close()
+
+
+@pytest.mark.parametrize("variant", ["kcycle", "central", "h1up", "shift"])
+def test_batch_option_variants(variant):
+    """The per-problem operator parameters of a shot group (advection scheme, the blend of
+    the solved operator, the shift, the cycle) reach every problem: each equals its single
+    solve with full restart cycles bit for bit."""
+    from paper_1712_06091_amd import adr
+    kw = {"kcycle": dict(cycle="k"), "central": dict(advection="central", beta=0.0),
+          "h1up": dict(beta=1.0, outer_beta=1.0, cycle="k"), "shift": dict(shift_alpha=0.3)}[variant]
+    wls = [W.random_medium(65, 2, seed=s) for s in (41, 42)] + [W.constant_medium(65, 2)]
+    print(f"[batch-variant] {variant} shots={len(wls)} omegas={[round(w.omega, 2) for w in wls]}", flush=True)
+    shots = [_shot(w) for w in wls]
+    qs = [_t(w.rhs(), torch.complex128) for w in wls]
+    outs = [torch.empty(w.shape, dtype=torch.complex128, device="cuda") for w in wls]
+    b = adr.Batch(shots, options=adr.default_options(prec="mixed", **kw), nstreams=2)
+    st, stats = b.solve(qs, outs, tol=1e-8, maxit=400)
+    assert st == adr.ADR_OK
+    single = adr.default_options(prec="mixed", full_cycles=1, **kw)
+    for i, w in enumerate(wls):
+        c = adr.Context(shots[i]["kappa2"], shots[i]["tau"], shots[i]["gamma"], w.h, w.omega, w.src, options=single)
+        a, s1 = c.solve(qs[i], tol=1e-8, maxit=400)
+        assert s1["outer_iters"] == stats[i]["outer_iters"], i
+        assert torch.equal(a, outs[i]), i
+        c.close()
+    b.close()
