@@ -773,7 +773,7 @@ int auto_levels(int D, const int n[3], int coarsest_max) {
 // Galerkin-apply variant per coarse level (one lane per node, or four wavefronts per
 // 64 nodes): adr_options.coarse_split if set, else a short timing on this level (mode 0
 // with one fused dot, as in the GMRES relaxation) in which the four-wavefront variant
-// has to beat the one-lane variant by 5%, so that near ties do not flip from run to run.
+// has to beat the one-lane variant by 10%, so that near ties do not flip from run to run.
 // The choice is cached per grid shape and precision for the life of the process, so
 // every context on a given shape launches the same kernels and sums in the same order.
 template <typename T>
@@ -827,7 +827,7 @@ adr_status tune_split(adr_ctx *ctx, int l) {
       ctx->err = std::string("split tuning: ") + hipGetErrorString(e);
       return ADR_EHIP;
     }
-    if (split == 1 || ms < 0.95f * best_ms) {
+    if (split == 1 || ms < 0.90f * best_ms) {
       best_ms = ms;
       best = split;
     }
