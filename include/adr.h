@@ -12,7 +12,10 @@
  * the averaging mass for the Lap(tau) term (Sec. 2.3) and the boundary condition
  * eq. BCADR, and solved by flexible GMRES(m) (Sec. 4.2) preconditioned by a multigrid
  * V-cycle on (1-beta) H_2up + beta H_1up (eq. precADRup) with Galerkin coarse
- * operators (eq. coarseGridMatrix).
+ * operators (eq. coarseGridMatrix).  Options select the paper's other systems on the same
+ * kernels: the Krylov cycle (Alg. KrylovCycle), the central-advection system H_cen and
+ * its two-stage solve (Alg. ADRlong), and the standard Helmholtz system (tau = NULL) with
+ * the shifted-Laplacian preconditioner (eq. shift).
  *
  * Conventions (every entry point):
  *  - Grids are nodal with n[k] nodes along axis k (k = 0 is x, the fastest-varying
@@ -158,18 +161,23 @@ adr_status adr_setup(const adr_problem *prob, const adr_options *opt, void *stre
 /* Free everything the context owns.  NULL is a no-op. */
 void adr_destroy(adr_ctx *ctx);
 
-/* y = A_beta x on the fine grid in FP64 (beta as given, e.g. 0 for H_2up), x and y c128
- * of n nodes, distinct buffers.  Enqueued on the context stream. */
+/* y = A_beta x on the fine grid in FP64: the context's ADR operator with advection blend
+ * beta (0 = H_2up, 1 = H_1up; with central advection H_cen, beta only acting on face
+ * nodes; the Helmholtz H when tau was NULL), never shifted.  x and y c128 of n nodes,
+ * distinct buffers.  Enqueued on the context stream. */
 adr_status adr_apply(adr_ctx *ctx, double beta, const void *x_c128, void *y_c128);
 
 /* One preconditioner application z = M^{-1} r: the configured cycle (a V-cycle, Alg.
- * TwoCycle applied recursively, or a Krylov cycle, Alg. KrylovCycle) on A_beta from a
- * zero guess, in the context's precision; r and z c128, distinct.  The Krylov cycle is
+ * TwoCycle applied recursively, or a Krylov cycle, Alg. KrylovCycle) on A_beta (shifted
+ * when shift_alpha > 0, on the rescaled operator when `rescaled`) from a zero guess, in
+ * the context's precision; r and z c128, distinct.  The Krylov cycle is
  * not linear in r (it is homogeneous: scaling r scales z).
  * Enqueued on the context stream; no host synchronization. */
 adr_status adr_vcycle(adr_ctx *ctx, const void *r_c128, void *z_c128);
 
-/* Solve H_2up a = q exp(i w tau) by FGMRES(m) + V-cycle (Sec. 4.2).  q: c128 right-hand
+/* Solve A a = q exp(i w tau) by FGMRES(m) preconditioned by the configured cycle
+ * (Sec. 4.2); A = H_2up by default, H_1up with outer_beta = 1, H_cen with central
+ * advection, the Helmholtz H (and a = u) when tau was NULL.  q: c128 right-hand
  * side of the Helmholtz equation (a point source is e_src / h^ndim).  a: c128, in =
  * initial guess when use_initial_guess != 0 (else ignored and zero is used), out =
  * amplitude.  Stops when the true relative residual is <= tol or after maxit FGMRES
@@ -187,8 +195,8 @@ adr_status adr_solve(adr_ctx *ctx, const void *q_c128, void *a_c128, double tol,
 adr_status adr_solve_adjoint(adr_ctx *ctx, const void *s_c128, void *lam_c128, double tol, int maxit,
                              int use_initial_guess, adr_stats *stats);
 
-/* y = H_2up^H x in FP64 (conjugate transpose of adr_apply with beta = 0); x, y c128,
- * distinct.  Enqueued. */
+/* y = A^H x in FP64, A the operator adr_solve solves (conjugate transpose of adr_apply
+ * with beta = outer_beta); x, y c128, distinct.  Enqueued. */
 adr_status adr_apply_adjoint(adr_ctx *ctx, const void *x_c128, void *y_c128);
 
 /* grad[i] += -Re(conj(lam_i) (w^2 - i w gamma_i) a_i): the kappa^2 derivative of the misfit
