@@ -187,7 +187,8 @@ adr_status adr_solve(adr_ctx *ctx, const void *q_c128, void *a_c128, double tol,
                      int use_initial_guess, adr_stats *stats);
 
 /* Adjoint solve (not in the paper; the gradient of a receiver misfit needs it):
- * H_2up^H lam = s exp(i w tau), with the conjugate-transposed fine operator and the
+ * A^H lam = s exp(i w tau), A the operator adr_solve solves (H_2up by default; not with a
+ * rescaled cycle: ADR_ENOTSUP), with the conjugate-transposed fine operator and the
  * conjugate-transposed multigrid hierarchy ((P^T A P)^H = P^T A^H P, P real), built on
  * the first call.  For J = 1/2 ||R u - d||^2, u = a exp(-i w tau), the right-hand side is
  * s = R^T (R u - d) (see adr_adjoint_source); then dJ/dkappa2 = adr_grad_kappa2(a, lam).
