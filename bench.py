@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--no-looped", action="store_true", help="batch: skip the one-shot-at-a-time comparison")
     ap.add_argument("--mixed-only", action="store_true", help="with --profile-only: skip the FP64 solves")
     ap.add_argument("--no-graph", action="store_true", help="launch the cycles eagerly (no hipGraph)")
+    ap.add_argument("--pipeline-max-nodes", type=int, default=None,
+                    help="coarse levels up to this many nodes use the pipelined relaxation "
+                         "(0 = off; default: the library's, every coarse level)")
     ap.add_argument("--coarse-split", type=int, default=0, choices=[0, 1, 4],
                     help="Galerkin-apply variant on every coarse level (0 = timed at setup)")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MIB",
@@ -70,6 +73,11 @@ def kernel_source_hash():
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def pipe_opt(args):
+    """Option override for --pipeline-max-nodes (none: the library default)."""
+    return {} if args.pipeline_max_nodes is None else {"pipeline_max_nodes": args.pipeline_max_nodes}
 
 
 def measured_traffic(workload):
@@ -273,7 +281,7 @@ def run_batch(args):
     qs = [t(w.rhs(), torch.complex128) for w in wls]
     outs = [torch.empty(w.shape, dtype=torch.complex128, device=dev) for w in wls]
     nodes = sum(w.nodes for w in wls)
-    opts = adr.default_options(prec="mixed", cycle=args.cycle)
+    opts = adr.default_options(prec="mixed", cycle=args.cycle, **pipe_opt(args))
     maxit = args.batch_maxit
     torch.cuda.synchronize()
     s0 = time.perf_counter()
@@ -443,7 +451,8 @@ def main():
         ctxs[prec] = adr.Context(k2, tau, gam, wl.h, wl.omega, wl.src,
                                  options=adr.default_options(prec=prec, cycle=args.cycle,
                                                              use_graph=0 if args.no_graph else 1,
-                                                             coarse_split=args.coarse_split))
+                                                             coarse_split=args.coarse_split,
+                                                             **pipe_opt(args)))
         torch.cuda.synchronize()
         setup_ms[prec] = (time.perf_counter() - s0) * 1e3
         log(f"setup {prec}: {setup_ms[prec]:.0f} ms, {ctxs[prec].num_levels} levels")
@@ -486,7 +495,8 @@ def main():
         ms, n, by = ctx.timer_stop()
         breakdown[cls] = {"ms": ms, "launches": n, "bytes": by}
     # Dominant kernel: the Galerkin 81-point stencil apply on level 1 (the first coarse
-    # grid), the largest single contributor to the solve.
+    # grid), the largest single contributor to the solve: its plain launches and the
+    # pipelined relaxation steps that carry it.
     ctx.timer_start("coarse_apply", 1)
     step(ctx)
     dm_ms, dm_n, dm_bytes = ctx.timer_stop()
@@ -494,7 +504,8 @@ def main():
     avg_bytes = dm_bytes / max(dm_n, 1)
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
     lvl1_shape, lvl1_S = ctx.level_info(1)
-    dominant = f"k_coarse_apply (level 1, {'x'.join(map(str, lvl1_shape))}, {lvl1_S}-point Galerkin stencil, c64)"
+    dominant = (f"k_coarse_apply + k_pipe_step (level 1, {'x'.join(map(str, lvl1_shape))}, {lvl1_S}-point "
+                "Galerkin stencil, c64)")
 
     # V-cycle alone: algorithmic bytes summed over its kernel classes, time by events.
     r = torch.randn(wl.shape, dtype=torch.complex128, device=dev)

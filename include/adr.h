@@ -136,6 +136,12 @@ typedef struct {
                         /* (the second stage of Alg. ADRlong); the solve stays in a, which */
                         /* gives the same iterates since M is unitary.  Not with the      */
                         /* adjoint or batch calls (ADR_ENOTSUP).  Default 0               */
+  int pipeline_max_nodes; /* coarse levels with at most this many nodes relax by the    */
+                        /* pipelined GMRES step (one launch per Arnoldi step: the        */
+                        /* orthogonalization of step k-1 and the apply of step k share   */
+                        /* it, the apply formed by linearity from stored products).  Same */
+                        /* result up to rounding.  Default 2^31 - 1 (every coarse        */
+                        /* level); 0 = the two-launch steps everywhere                   */
 } adr_options;
 
 typedef struct {

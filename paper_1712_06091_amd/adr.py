@@ -56,6 +56,7 @@ class AdrOptions(ctypes.Structure):
         ("advection", ctypes.c_int),
         ("outer_beta", ctypes.c_double),
         ("rescaled", ctypes.c_int),
+        ("pipeline_max_nodes", ctypes.c_int),
     ]
 
 

@@ -61,6 +61,8 @@ struct LevelT {
   cx<T> *ku = nullptr;       // Krylov cycle: second coarse basis vector u_1
   cx<T> *kz = nullptr;       // Krylov cycle: first preconditioned direction K(u_0)
   int split = 1;             // Galerkin-apply variant (wavefronts per node), tuned at setup
+  cx<T> *Gs = nullptr;       // pipelined relaxation: kMaxNu x N stored A D^{-1} u_i (see k_pipe_step)
+  cx<T> *Yp = nullptr;       // pipelined relaxation: 2 x N, D^{-1} Gs_{k-1} (ping-pong)
   cx<T> *planes_adj = nullptr;   // conjugate-transposed stencil (adjoint solves)
   cx<T> *dinv_adj = nullptr;
 };
@@ -410,6 +412,13 @@ template <typename T>
 double fine_coef_bytes(int D) { return (double)(D + 3) * sizeof(T); }
 
 // Allocate the per-level vectors and convert/store the stencil in precision T.
+// Coarse levels relaxed by the pipelined GMRES steps: those with at most
+// pipeline_max_nodes nodes that relax by GMRES.
+bool pipelined_level(const adr_ctx *ctx, int l, size_t N) {
+  return ctx->opt.pipeline_max_nodes > 0 && l >= 1 && l < ctx->levels - 1 && N <= (size_t)ctx->opt.pipeline_max_nodes &&
+         ctx->relax[l] == ADR_RELAX_GMRES && ctx->nu[l] >= 1 && ctx->nu[l] <= 8;
+}
+
 template <typename T>
 adr_status alloc_level_vectors(adr_ctx *ctx, LevelT<T> &L, int l) {
   const size_t N = L.G.N;
@@ -424,6 +433,10 @@ adr_status alloc_level_vectors(adr_ctx *ctx, LevelT<T> &L, int l) {
     if (ctx->opt.cycle == ADR_CYCLE_K && l < ctx->levels - 1) {
       ADR_TRY(dalloc(ctx, &L.ku, N));
       ADR_TRY(dalloc(ctx, &L.kz, N));
+    }
+    if (pipelined_level(ctx, l, N)) {
+      ADR_TRY(dalloc(ctx, &L.Gs, N * kMaxNu));
+      ADR_TRY(dalloc(ctx, &L.Yp, N * 2));
     }
   }
   return ADR_OK;
@@ -486,6 +499,61 @@ void gmres_relax(adr_ctx *ctx, int l, const cx<T> *x0, const cx<T> *b, cx<T> *x_
     nb = adrk::coarse_apply<T>(s, D, a, nullptr, true);
     tend(ctx, t0, (double)N * cb * (L.S + 5));
   }
+  if (L.Gs) {
+    // Pipelined steps: the first apply, nu - 1 fused orthogonalization + apply steps and
+    // the last orthogonalization (see k_pipe_step).
+    cx<T> *Gp[kMaxNu], *Yb[2] = {L.Yp, L.Yp + N};
+    for (int i = 0; i < nu; ++i) Gp[i] = L.Gs + (size_t)i * N;
+    {
+      VecSet<T> V0{};
+      V0.count = 1;
+      V0.v[0] = Vp[0];
+      CoarseArgs<T> a{};
+      a.split = L.split;
+      a.G = L.G;
+      a.planes = planes;
+      a.x = Zp[0];
+      a.pin = ProIn{ctx->part[cur], nb, 1};
+      a.norm_out = sc + kBeta;
+      a.norm_cplx = 0;
+      a.inv_out = sc + kS + 0;
+      a.y = Gp[0];
+      a.dinv = dinv;
+      a.zout = Yb[0];
+      a.mode = 0;
+      a.pout = ctx->part[cur ^ 1];
+      int t0 = tbegin(ctx, ADR_TIMER_COARSE_APPLY, l);
+      nb = adrk::coarse_apply<T>(s, D, a, &V0, false);
+      tend(ctx, t0, (double)N * cb * (L.S + 4));
+      cur ^= 1;
+    }
+    for (int k = 1; k <= nu; ++k) {
+      VecSet<T> U{}, Gv{};
+      U.count = k;
+      Gv.count = k;
+      for (int i = 0; i < k; ++i) {
+        U.v[i] = Vp[i];
+        Gv.v[i] = Gp[i];
+      }
+      double *hcol = sc + kH + 2 * ((k - 1) * kLdH);
+      double *hsub = k >= 2 ? sc + kH + 2 * ((k - 2) * kLdH + (k - 1)) : nullptr;
+      double *sout = k >= 2 ? sc + kS + (k - 1) : nullptr;
+      const ProIn pin{ctx->part[cur], nb, 2 * k + (k >= 2 ? 1 : 0)};
+      if (k < nu) {
+        int t0 = tbegin(ctx, ADR_TIMER_COARSE_APPLY, l);
+        nb = adrk::pipe_step<T>(s, D, L.split, L.G, planes, Yb[(k - 1) & 1], pin, sc + kS, hcol, hsub, sout, U, Gv,
+                                dinv, L.V + (size_t)k * N, Zp[k], Gp[k], Yb[k & 1], ctx->part[cur ^ 1]);
+        // planes, the gathered D^{-1} Gs_{k-1}, U and Gs (k each), dinv; u, z, G, D^{-1} G written
+        tend(ctx, t0, (double)N * cb * (L.S + 6 + 2 * k));
+      } else {
+        int t1 = tbegin(ctx, ADR_TIMER_COARSE_ORTH, l);
+        nb = adrk::pipe_final<T>(s, N, pin, sc + kS, hcol, hsub, sout, U, Gv, L.V + (size_t)k * N,
+                                 ctx->part[cur ^ 1]);
+        tend(ctx, t1, (double)N * cb * (2 + k));
+      }
+      cur ^= 1;
+    }
+  } else
   for (int j = 0; j < nu; ++j) {
     VecSet<T> Vs{};
     Vs.count = j + 1;
@@ -745,6 +813,7 @@ adr_status validate(const adr_problem *p, const adr_options *o, std::string &err
     return ADR_EINVAL;
   }
   if (!(o->kcycle_threshold >= 0.0)) { err = "kcycle_threshold must be >= 0"; return ADR_EINVAL; }
+  if (o->pipeline_max_nodes < 0) { err = "pipeline_max_nodes must be >= 0"; return ADR_EINVAL; }
   if (o->advection != ADR_ADV_UPWIND && o->advection != ADR_ADV_CENTRAL) { err = "bad advection"; return ADR_EINVAL; }
   if (!(o->outer_beta >= 0.0 && o->outer_beta <= 1.0)) { err = "outer_beta must be in [0, 1]"; return ADR_EINVAL; }
   if (o->rescaled != 0 && o->rescaled != 1) { err = "rescaled must be 0 or 1"; return ADR_EINVAL; }
@@ -1038,7 +1107,8 @@ void free_ctx(adr_ctx *ctx) {
     LevelT<double> &a = ctx->lv64[l];
     LevelT<float> &b = ctx->lv32[l];
     for (void *p : {(void *)a.planes, (void *)a.dinv, (void *)a.x, (void *)a.xt, (void *)a.b, (void *)a.r,
-                    (void *)a.w, (void *)a.V, (void *)a.Z, (void *)a.ku, (void *)a.kz, (void *)a.planes_adj,
+                    (void *)a.w, (void *)a.V, (void *)a.Z, (void *)a.ku, (void *)a.kz, (void *)a.Gs, (void *)a.Yp,
+                    (void *)b.Gs, (void *)b.Yp, (void *)a.planes_adj,
                     (void *)a.dinv_adj, (void *)b.planes, (void *)b.dinv, (void *)b.x, (void *)b.xt, (void *)b.b,
                     (void *)b.r, (void *)b.w, (void *)b.V, (void *)b.Z, (void *)b.ku, (void *)b.kz,
                     (void *)b.planes_adj, (void *)b.dinv_adj})
@@ -1339,6 +1409,7 @@ void adr_default_options(adr_options *o) {
   o->advection = ADR_ADV_UPWIND;
   o->outer_beta = 0.0;
   o->rescaled = 0;
+  o->pipeline_max_nodes = 0x7fffffff;   // every coarse level
 }
 
 adr_status adr_setup(const adr_problem *prob, const adr_options *opt, void *stream, adr_ctx **out) {

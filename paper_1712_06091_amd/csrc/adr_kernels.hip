@@ -998,6 +998,7 @@ __device__ __forceinline__ void coarse_apply_body(Grid G, const cx<T> *__restric
     cx<T> o;
     if (mode == 0) {
       o = xs * sum;
+      if (zout) zout[i] = o * dinv[i];
     } else {
       o = b[i] - sum;
       if (zout) zout[i] = o * dinv[i];
@@ -1064,6 +1065,244 @@ __global__ __launch_bounds__(ADR_BLOCK) __attribute__((amdgpu_waves_per_eu(1, 2)
   coarse_apply_body<T, D, NV, NORM, SPLIT, GRP>(G, planes, x, pin, sdev, norm_out, norm_cplx, inv_out, b, y, dinv,
                                                 zout, mode, V, pout, sh);
 }
+
+// =====================================================================================
+// Pipelined GMRES relaxation (one launch per Arnoldi step).  With the unnormalized
+// basis u_i (v_i = s_i u_i, s_i = 1/||u_i||) and G_i = A D^{-1} u_i, the step that forms
+// u_k = w_{k-1} - sum_i H[i][k-1] v_i (w_{k-1} = A D^{-1} v_{k-1}) also forms, by
+// linearity, G_k = A D^{-1} w_{k-1} - sum_i H[i][k-1] A D^{-1} v_i, the first term a
+// stencil apply to D^{-1} w_{k-1}, the others the stored G_i.  So the orthogonalization
+// of step k-1 and the operator apply of step k share one launch.
+// Storage: Gs_0 = w_0 (normalized by the first apply), Gs_i = G_i (i >= 1, unnormalized),
+// so w_i = phi_i Gs_i and A D^{-1} u_i = psi_i Gs_i with phi_0 = 1, psi_0 = 1/s_0 and
+// phi_i = s_i, psi_i = 1 for i >= 1.  Y = D^{-1} Gs_{k-1}.
+// Prologue: the predecessor's partials hold conj(u_i).Gs_{k-1} for i < NK (= k) and,
+// when NK >= 2, ||u_{k-1}||^2 (then s_{k-1} and H[k-1][k-2] are stored here).
+// =====================================================================================
+template <typename T, int NK>
+struct PipeCoef {
+  cx<T> cu[NK];   // coefficients of u_i in u_k
+  cx<T> cg[NK];   // coefficients of Gs_i in G_k
+  T phi;          // w_{k-1} = phi Gs_{k-1}
+};
+template <typename T, int NK>
+__device__ __forceinline__ PipeCoef<T, NK> pipe_prologue(ProIn pin, const double *scales, double *hcol, double *hsub,
+                                                         double *sout) {
+  constexpr int KP = 2 * NK + (NK >= 2 ? 1 : 0);
+  __shared__ double tot[KP];
+  reduce_partials(pin.partials, pin.nb, KP, tot);
+  double slast;
+  if constexpr (NK >= 2) {
+    const double n = sqrt(tot[2 * NK]);
+    slast = n > 0.0 ? 1.0 / n : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      *sout = slast;
+      hsub[0] = n;
+      hsub[1] = 0.0;
+    }
+  } else {
+    slast = scales[0];
+  }
+  const double phi = NK == 1 ? 1.0 : slast;
+  PipeCoef<T, NK> pc;
+  pc.phi = (T)phi;
+#pragma unroll
+  for (int i = 0; i < NK; ++i) {
+    const double si = (i == NK - 1) ? slast : scales[i];
+    const double hre = si * phi * tot[2 * i], him = si * phi * tot[2 * i + 1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      hcol[2 * i] = hre;
+      hcol[2 * i + 1] = him;
+    }
+    pc.cu[i] = mk<T>((T)(hre * si), (T)(him * si));
+    const double psi = (i == 0) ? (scales[0] > 0.0 ? 1.0 / scales[0] : 0.0) : 1.0;
+    pc.cg[i] = mk<T>((T)(hre * si * psi), (T)(him * si * psi));
+  }
+  return pc;
+}
+
+template <typename T, int D, int NK, int SPLIT, bool GRP>
+__global__ __launch_bounds__(ADR_BLOCK) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_pipe_step(
+    Grid G, const cx<T> *__restrict__ planes, const cx<T> *__restrict__ yin, ProIn pin, const double *scales,
+    double *hcol, double *hsub, double *sout, VecSet<T> U, VecSet<T> Gs, const cx<T> *__restrict__ dinv,
+    cx<T> *__restrict__ uo, cx<T> *__restrict__ zo, cx<T> *__restrict__ go, cx<T> *__restrict__ yo, double *pout,
+    Shot sh) {
+  ADR_SHOT_ENTER(sh);
+  ADR_SHIFT(planes);
+  ADR_SHIFT(yin);
+  ADR_SHIFT(pin.partials);
+  ADR_SHIFT(scales);
+  ADR_SHIFT(hcol);
+  ADR_SHIFT(hsub);
+  ADR_SHIFT(sout);
+  if constexpr (GRP) {
+    shift_set<NK>(U, shot_off_);
+    shift_set<NK>(Gs, shot_off_);
+  }
+  ADR_SHIFT(dinv);
+  ADR_SHIFT(uo);
+  ADR_SHIFT(zo);
+  ADR_SHIFT(go);
+  ADR_SHIFT(yo);
+  ADR_SHIFT(pout);
+  ADR_SHOT_LIVE(sh);
+  const PipeCoef<T, NK> pc = pipe_prologue<T, NK>(pin, scales, hcol, hsub, sout);
+  constexpr int K = 2 * (NK + 1) + 1;
+  double red[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) red[k] = 0.0;
+  int beg, end;
+  chunk_range(G.N, beg, end);
+  const int N = G.N;
+  auto finish = [&](int i, const cx<T> &t) {
+    cx<T> u = pc.phi * Gs.v[NK - 1][i];
+    cx<T> g = pc.phi * t;
+#pragma unroll
+    for (int v = 0; v < NK; ++v) {
+      const cx<T> ui = U.v[v][i];
+      u = u - pc.cu[v] * ui;
+      g = g - pc.cg[v] * Gs.v[v][i];
+    }
+    const cx<T> di = dinv[i];
+    uo[i] = u;
+    zo[i] = u * di;
+    go[i] = g;
+    yo[i] = g * di;
+    const cx<double> gd = cvt<double, T>(g);
+#pragma unroll
+    for (int v = 0; v < NK; ++v) {
+      const cx<double> d = cdotc(cvt<double, T>(U.v[v][i]), gd);
+      red[2 * v] += d.re;
+      red[2 * v + 1] += d.im;
+    }
+    const cx<double> ud = cvt<double, T>(u);
+    const cx<double> d = cdotc(ud, gd);
+    red[2 * NK] += d.re;
+    red[2 * NK + 1] += d.im;
+    red[K - 1] += ud.re * ud.re + ud.im * ud.im;
+  };
+  if constexpr (SPLIT == 1) {
+    for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+      int X[5], Y[5], Z[5];
+      coarse_neighbours<D>(G, i, X, Y, Z);
+      finish(i, stencil_part<T, D, 0, 1>(planes + i, N, yin, X, Y, Z));
+    }
+  } else {
+    constexpr int GROUPS = ADR_BLOCK / 64 / SPLIT;
+    __shared__ cx<T> part[GROUPS][SPLIT - 1][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int grp = wave / SPLIT, sub = wave % SPLIT;
+    for (int base = beg; base < end; base += GROUPS * 64) {
+      const int i = base + grp * 64 + lane;
+      const bool act = i < end;
+      cx<T> sum = mk<T>(T(0), T(0));
+      if (act) {
+        int X[5], Y[5], Z[5];
+        coarse_neighbours<D>(G, i, X, Y, Z);
+        sum = stencil_part_of<T, D, SPLIT>(sub, planes + i, N, yin, X, Y, Z);
+        if (sub > 0) part[grp][sub - 1][lane] = sum;
+      }
+      __syncthreads();
+      if (act && sub == 0) {
+#pragma unroll
+        for (int w = 1; w < SPLIT; ++w) sum = sum + part[grp][w - 1][lane];
+        finish(i, sum);
+      }
+      __syncthreads();
+    }
+  }
+  block_partials<K>(red, K, pout);
+}
+
+// Last step: u_nu only (no operator apply), and the partials of ||u_nu||^2.
+template <typename T, int NK, bool GRP>
+__global__ __launch_bounds__(ADR_BLOCK) void k_pipe_final(int N, ProIn pin, const double *scales, double *hcol,
+                                                          double *hsub, double *sout, VecSet<T> U, VecSet<T> Gs,
+                                                          cx<T> *__restrict__ uo, double *pout, Shot sh) {
+  ADR_SHOT_ENTER(sh);
+  ADR_SHIFT(pin.partials);
+  ADR_SHIFT(scales);
+  ADR_SHIFT(hcol);
+  ADR_SHIFT(hsub);
+  ADR_SHIFT(sout);
+  if constexpr (GRP) {
+    shift_set<NK>(U, shot_off_);
+    shift_set<NK>(Gs, shot_off_);
+  }
+  ADR_SHIFT(uo);
+  ADR_SHIFT(pout);
+  ADR_SHOT_LIVE(sh);
+  const PipeCoef<T, NK> pc = pipe_prologue<T, NK>(pin, scales, hcol, hsub, sout);
+  double red[1] = {0.0};
+  int beg, end;
+  chunk_range(N, beg, end);
+  for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    cx<T> u = pc.phi * Gs.v[NK - 1][i];
+#pragma unroll
+    for (int v = 0; v < NK; ++v) u = u - pc.cu[v] * U.v[v][i];
+    uo[i] = u;
+    red[0] += (double)u.re * u.re + (double)u.im * u.im;
+  }
+  block_partials<1>(red, 1, pout);
+}
+
+template <typename T>
+int pipe_step(hipStream_t s, int D, int split, const Grid &G, const cx<T> *planes, const cx<T> *yin, ProIn pin,
+              const double *scales, double *hcol, double *hsub, double *sout, const VecSet<T> &U,
+              const VecSet<T> &Gs, const cx<T> *dinv, cx<T> *uo, cx<T> *zo, cx<T> *go, cx<T> *yo, double *pout) {
+  const int nb = split == 4 ? launch_blocks_red(4LL * G.N) : launch_blocks_red(G.N);
+#define ADR_PIPE_CASE(n)                                                                                        \
+  case n:                                                                                                       \
+    if (D == 2) {                                                                                               \
+      if (split == 4)                                                                                           \
+        launch_g(k_pipe_step<T, 2, n, 4, false>, k_pipe_step<T, 2, n, 4, true>, nb, s, G, planes, yin, pin, scales, \
+                 hcol, hsub, sout, U, Gs, dinv, uo, zo, go, yo, pout);                                           \
+      else                                                                                                      \
+        launch_g(k_pipe_step<T, 2, n, 1, false>, k_pipe_step<T, 2, n, 1, true>, nb, s, G, planes, yin, pin, scales, \
+                 hcol, hsub, sout, U, Gs, dinv, uo, zo, go, yo, pout);                                           \
+    } else {                                                                                                    \
+      if (split == 4)                                                                                           \
+        launch_g(k_pipe_step<T, 3, n, 4, false>, k_pipe_step<T, 3, n, 4, true>, nb, s, G, planes, yin, pin, scales, \
+                 hcol, hsub, sout, U, Gs, dinv, uo, zo, go, yo, pout);                                           \
+      else                                                                                                      \
+        launch_g(k_pipe_step<T, 3, n, 1, false>, k_pipe_step<T, 3, n, 1, true>, nb, s, G, planes, yin, pin, scales, \
+                 hcol, hsub, sout, U, Gs, dinv, uo, zo, go, yo, pout);                                           \
+    }                                                                                                           \
+    break;
+  switch (U.count) {
+    ADR_PIPE_CASE(1) ADR_PIPE_CASE(2) ADR_PIPE_CASE(3) ADR_PIPE_CASE(4) ADR_PIPE_CASE(5) ADR_PIPE_CASE(6)
+    ADR_PIPE_CASE(7)
+    default: break;
+  }
+#undef ADR_PIPE_CASE
+  return nb;
+}
+template <typename T>
+int pipe_final(hipStream_t s, int N, ProIn pin, const double *scales, double *hcol, double *hsub, double *sout,
+               const VecSet<T> &U, const VecSet<T> &Gs, cx<T> *uo, double *pout) {
+  const int nb = launch_blocks_red(N);
+  switch (U.count) {
+#define ADR_PF_CASE(n) \
+  case n: launch_g(k_pipe_final<T, n, false>, k_pipe_final<T, n, true>, nb, s, N, pin, scales, hcol, hsub, sout, U, Gs, uo, pout); break;
+    ADR_PF_CASE(1) ADR_PF_CASE(2) ADR_PF_CASE(3) ADR_PF_CASE(4) ADR_PF_CASE(5) ADR_PF_CASE(6) ADR_PF_CASE(7)
+    ADR_PF_CASE(8)
+#undef ADR_PF_CASE
+    default: break;
+  }
+  return nb;
+}
+template int pipe_step<float>(hipStream_t, int, int, const Grid &, const cx<float> *, const cx<float> *, ProIn,
+                              const double *, double *, double *, double *, const VecSet<float> &,
+                              const VecSet<float> &, const cx<float> *, cx<float> *, cx<float> *, cx<float> *,
+                              cx<float> *, double *);
+template int pipe_step<double>(hipStream_t, int, int, const Grid &, const cx<double> *, const cx<double> *, ProIn,
+                               const double *, double *, double *, double *, const VecSet<double> &,
+                               const VecSet<double> &, const cx<double> *, cx<double> *, cx<double> *,
+                               cx<double> *, cx<double> *, double *);
+template int pipe_final<float>(hipStream_t, int, ProIn, const double *, double *, double *, double *,
+                               const VecSet<float> &, const VecSet<float> &, cx<float> *, double *);
+template int pipe_final<double>(hipStream_t, int, ProIn, const double *, double *, double *, double *,
+                                const VecSet<double> &, const VecSet<double> &, cx<double> *, double *);
 
 template <typename T, int D, bool NORM, int SPLIT>
 static void dispatch_coarse_nv(hipStream_t s, int nb, const CoarseArgs<T> &a, const VecSet<T> &V) {

@@ -108,6 +108,16 @@ template <typename T>
 void fine_jacobi(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P, const cx<T> *x_in,
                  const cx<T> *b, cx<T> *x_out, double weight, const FineParams *Pd = nullptr);
 
+// Pipelined GMRES relaxation steps (see k_pipe_step): one fused orthogonalization and
+// apply, and the last orthogonalization; return the block count of their partials.
+template <typename T>
+int pipe_step(hipStream_t s, int D, int split, const Grid &G, const cx<T> *planes, const cx<T> *yin, ProIn pin,
+              const double *scales, double *hcol, double *hsub, double *sout, const VecSet<T> &U,
+              const VecSet<T> &Gs, const cx<T> *dinv, cx<T> *uo, cx<T> *zo, cx<T> *go, cx<T> *yo, double *pout);
+template <typename T>
+int pipe_final(hipStream_t s, int N, ProIn pin, const double *scales, double *hcol, double *hsub, double *sout,
+               const VecSet<T> &U, const VecSet<T> &Gs, cx<T> *uo, double *pout);
+
 // Rescaled fine operator B = M A M^{-1}, M = diag(conj(ph)), ph = exp(i w tau):
 // ph = exp(i w tau); out = conj(ph) in or ph in (in, out may alias); the fine stencil
 // planes of A turned into B's; Jacobi on B and r = b - B x.

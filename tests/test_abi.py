@@ -40,6 +40,7 @@ def test_default_options(lib):
     assert o.cycle == adr.ADR_CYCLE_V and abs(o.kcycle_threshold - 0.1) < 1e-15 and o.coarse_split == 0
     assert o.tail_max_nodes == 0 and o.shift_alpha == 0.0
     assert o.advection == adr.ADR_ADV_UPWIND and o.outer_beta == 0.0 and o.rescaled == 0
+    assert o.pipeline_max_nodes == 2 ** 31 - 1
     first, second = adr.two_stage_options("fp64")
     assert first.prec == second.prec == adr.ADR_PREC_FP64
     assert first.beta == first.outer_beta == 1.0 and first.cycle == adr.ADR_CYCLE_K
@@ -84,7 +85,7 @@ def test_setup_rejects_bad_problem(lib, bad):
 @pytest.mark.parametrize("bad", [dict(restart=0), dict(restart=9), dict(levels=9), dict(beta=1.5), dict(prec=7),
                                  dict(cycle=2), dict(kcycle_threshold=-0.5), dict(coarse_split=2),
                                  dict(shift_alpha=-0.1), dict(shift_alpha=float("nan")), dict(advection=2),
-                                 dict(outer_beta=1.5), dict(rescaled=2)])
+                                 dict(outer_beta=1.5), dict(rescaled=2), dict(pipeline_max_nodes=-1)])
 def test_setup_rejects_bad_options(lib, bad):
     from paper_1712_06091_amd import adr
     p = _problem()
