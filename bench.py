@@ -169,7 +169,7 @@ def copy_probe(args):
 
 def run_adjoint(args):
     """Misfit gradient: 16 sources on an n^3 smooth random medium, a 64 x 64 receiver plane
-    on the top face, data from a seeded 2% kappa^2 perturbation; one step = J and
+    on the top face, data from a seeded 5% kappa^2 perturbation; one step = J and
     dJ/dkappa^2 through the autograd Function (16 forward + 16 adjoint solves to 1e-6,
     context setup included, since tau differs per source)."""
     import numpy as np

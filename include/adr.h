@@ -85,6 +85,18 @@ typedef enum {
                      /* zero, preconditioned by the cycle one level down                 */
 } adr_cycle;
 
+/* Reaction term of the ADR operator.  Sec. 1 notes that a travel time solving the
+ * eikonal equation |grad tau|^2 = kappa^2 removes -w^2 (|grad tau|^2 - kappa^2) a from
+ * eq. ADR; a numerical tau satisfies it only approximately (and not across the kinks of
+ * a first-arrival tau).  Both add the absorbing term -i w gamma kappa^2 of Sec. 1. */
+typedef enum {
+  ADR_REACTION_NUMERICAL = 0,  /* c = w^2 (kappa^2 - |g|^2) - i w gamma kappa^2 with the     */
+                               /* numerical g = grad tau: kappa^2 enters the operator here   */
+  ADR_REACTION_EIKONAL = 1     /* c = -i w gamma kappa^2: the term is dropped, as Sec. 1     */
+                               /* does; requires tau (ADR_EINVAL with tau = NULL, where the  */
+                               /* w^2 kappa^2 term is the Helmholtz operator's own)          */
+} adr_reaction;
+
 /* Advection scheme of the ADR operator (Sec. 2.2). */
 typedef enum {
   ADR_ADV_UPWIND = 0,   /* second-order upwind, eq. londUpwindDiff (H_2up; blended with   */
@@ -142,6 +154,7 @@ typedef struct {
                         /* it, the apply formed by linearity from stored products).  Same */
                         /* result up to rounding.  Default 2^31 - 1 (every coarse        */
                         /* level); 0 = the two-launch steps everywhere                   */
+  adr_reaction reaction; /* default ADR_REACTION_NUMERICAL                                */
 } adr_options;
 
 typedef struct {
@@ -206,10 +219,10 @@ adr_status adr_solve_adjoint(adr_ctx *ctx, const void *s_c128, void *lam_c128, d
  * with beta = outer_beta); x, y c128, distinct.  Enqueued. */
 adr_status adr_apply_adjoint(adr_ctx *ctx, const void *x_c128, void *y_c128);
 
-/* grad[i] += -Re(conj(lam_i) (w^2 - i w gamma_i) a_i): the kappa^2 derivative of the misfit
- * at fixed travel time (dH_2up/dkappa2_i = (w^2 - i w gamma_i) e_i e_i^T through the
- * reaction term).  a, lam c128; grad FP64 device array of n nodes, accumulated into.
- * Enqueued. */
+/* grad[i] += -Re(conj(lam_i) c'_i a_i): the kappa^2 derivative of the misfit at fixed
+ * travel time, dH_2up/dkappa2_i = c'_i e_i e_i^T through the reaction term, with
+ * c'_i = w^2 - i w gamma_i (ADR_REACTION_NUMERICAL) or -i w gamma_i (ADR_REACTION_EIKONAL).
+ * a, lam c128; grad FP64 device array of n nodes, accumulated into.  Enqueued. */
 adr_status adr_grad_kappa2(adr_ctx *ctx, const void *a_c128, const void *lam_c128, double *grad);
 
 /* Receivers: r_k = u[idx_k] - d_k for k < nrec (idx: device int32 linear node indices;

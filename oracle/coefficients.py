@@ -14,10 +14,20 @@ one-sided on the domain boundary) and lap tau1 the central second difference
 Readings where the paper is silent (listed in the design notes):
 * at the source node tau0 = 0 and grad tau0 is undefined: grad tau := 0 there and
   lap tau := the 2d-neighbour discrete Laplacian of tau at the source;
-* tau1 at the source is the limit tau/|x-x0| -> kappa(x0) = sqrt(kappa2[src]);
-* the reaction keeps -w^2(|grad tau|^2 - kappa^2) with the numerical grad tau, and adds
-  the absorbing-layer term -i w gamma kappa^2 of Sec. 1:
-      c = w^2 (kappa^2 - |g|^2) - i w gamma kappa^2.
+* tau1 = tau/tau0 is 0/0 at the source; there it is the mean of tau/tau0 over the
+  source's 2d axis neighbours (tau0 = h there).  For tau = kappa(x0) r + O(r^2) this is
+  kappa(x0) + O(h^2) (the first-order terms of opposite neighbours cancel), exact for a
+  constant medium, and it is a function of tau alone: at fixed tau the operator depends
+  on kappa^2 only through the reaction term below, which is what the kappa^2 gradient at
+  fixed tau differentiates;
+* the reaction: Sec. 1 notes that a travel time solving the eikonal equation removes
+  the term -w^2(|grad tau|^2 - kappa^2) from eq. ADR.  Two forms are offered:
+  "numerical" keeps it with the numerical grad tau (the discrete system stays a diagonal
+  rescaling of the Helmholtz one up to the eikonal residual, and kappa^2 enters the
+  operator there), "eikonal" drops it as Sec. 1 does.  Both add the absorbing-layer
+  term -i w gamma kappa^2 of Sec. 1:
+      numerical: c = w^2 (kappa^2 - |g|^2) - i w gamma kappa^2
+      eikonal:   c = -i w gamma kappa^2.
 """
 import numpy as np
 
@@ -46,7 +56,7 @@ def second_difference(f, axis, h):
     return np.moveaxis(out, 0, axis)
 
 
-def travel_time_derivatives(tau, h, src=None, kappa2=None):
+def travel_time_derivatives(tau, h, src=None):
     """Return (g, L): g is a list with one array per NumPy axis (g[a] = d tau / d x_a),
     L = lap tau.
 
@@ -60,8 +70,6 @@ def travel_time_derivatives(tau, h, src=None, kappa2=None):
         return g, L
 
     src = tuple(int(s) for s in src)
-    if kappa2 is None:
-        raise ValueError("factored derivatives need kappa2 (for tau1 at the source)")
     grids = np.meshgrid(*[np.arange(n, dtype=np.float64) for n in tau.shape], indexing="ij")
     dx = [(grids[a] - src[a]) * h for a in range(d)]
     r = np.sqrt(sum(x * x for x in dx))
@@ -73,7 +81,13 @@ def travel_time_derivatives(tau, h, src=None, kappa2=None):
     lap_tau0 = np.where(at_src, 0.0, (d - 1) / r_safe)
 
     tau1 = np.where(at_src, 0.0, tau / r_safe)
-    tau1[src] = np.sqrt(np.asarray(kappa2, dtype=np.float64)[src])
+    nbrs = []
+    for a in range(d):
+        for o in (-1, 1):
+            j = list(src)
+            j[a] += o
+            nbrs.append(tau1[tuple(j)])
+    tau1[src] = np.mean(nbrs)
 
     grad_tau1 = [first_difference(tau1, a, h) for a in range(d)]
     lap_tau1 = sum(second_difference(tau1, a, h) for a in range(d))
@@ -95,16 +109,30 @@ def travel_time_derivatives(tau, h, src=None, kappa2=None):
     return g, L
 
 
-def reaction(g, kappa2, gamma, omega):
-    """c = w^2 (kappa^2 - |g|^2) - i w gamma kappa^2 (eq. ADR plus the absorbing term)."""
+def reaction(g, kappa2, gamma, omega, form="numerical"):
+    """The reaction coefficient of eq. ADR plus the absorbing term:
+    "numerical": c = w^2 (kappa^2 - |g|^2) - i w gamma kappa^2;
+    "eikonal":   c = -i w gamma kappa^2 (the eikonal equation removes the w^2 term)."""
     kappa2 = np.asarray(kappa2, dtype=np.float64)
-    gg = sum(ga * ga for ga in g)
     gam = np.zeros_like(kappa2) if gamma is None else np.asarray(gamma, dtype=np.float64)
-    return omega * omega * (kappa2 - gg) - 1j * omega * gam * kappa2
+    absorb = -1j * omega * gam * kappa2
+    if form == "eikonal":
+        return absorb + 0.0
+    if form != "numerical":
+        raise ValueError(form)
+    gg = sum(ga * ga for ga in g)
+    return omega * omega * (kappa2 - gg) + absorb
 
 
-def adr_coefficients(tau, kappa2, gamma, h, omega, src=None):
+def reaction_derivative(gamma, omega, shape, form="numerical"):
+    """d c / d kappa^2 at fixed tau, per node: w^2 - i w gamma ("numerical") or
+    -i w gamma ("eikonal")."""
+    gam = np.zeros(shape) if gamma is None else np.asarray(gamma, dtype=np.float64)
+    return (0.0 if form == "eikonal" else omega * omega) - 1j * omega * gam
+
+
+def adr_coefficients(tau, kappa2, gamma, h, omega, src=None, form="numerical"):
     """All per-node coefficients of the ADR operator: (g list, L, c complex)."""
-    g, L = travel_time_derivatives(tau, h, src=src, kappa2=kappa2)
-    c = reaction(g, kappa2, gamma, omega)
+    g, L = travel_time_derivatives(tau, h, src=src)
+    c = reaction(g, kappa2, gamma, omega, form)
     return g, L, c

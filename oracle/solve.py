@@ -6,9 +6,10 @@ TEST INFRASTRUCTURE ONLY.
 * Outer solve: flexible GMRES(m) on H_2up, preconditioned by a V-cycle on
   A_beta = (1-beta) H_2up + beta H_1up, beta = 0.25 (eq. precADRup, Sec. 4.2).
 * Adjoint (not in the paper): for J = 1/2 sum_s ||R u_s - d_s||^2 at fixed tau,
-  dH_2up/dkappa2_j = (w^2 - i w gamma_j) e_j e_j^T, so with
+  dH_2up/dkappa2_j = c'_j e_j e_j^T with c'_j = w^2 - i w gamma_j (numerical reaction)
+  or -i w gamma_j (eikonal reaction), so with
   lambda = H_2up^{-H} M^H R^T (R M a - d), M = diag(exp(-i w tau)),
-  dJ/dkappa2_j = -Re(conj(lambda_j) (w^2 - i w gamma_j) a_j).
+  dJ/dkappa2_j = -Re(conj(lambda_j) c'_j a_j).
 """
 import numpy as np
 import scipy.linalg as sla
@@ -34,15 +35,16 @@ def wavefield(a, tau, omega):
 class Problem:
     """The discrete ADR problem for one source: coefficients and the two operators."""
 
-    def __init__(self, kappa2, tau, gamma, h, omega, src, beta=0.25, factored=True):
+    def __init__(self, kappa2, tau, gamma, h, omega, src, beta=0.25, factored=True, reaction="numerical"):
         self.shape = np.asarray(tau).shape
         self.h, self.omega, self.src, self.beta = h, omega, tuple(src), beta
+        self.reaction = reaction
         self.kappa2 = np.asarray(kappa2, dtype=np.float64)
         self.tau = np.asarray(tau, dtype=np.float64)
         self.gamma = None if gamma is None else np.asarray(gamma, dtype=np.float64)
         fsrc = self.src if factored else None
         self.g, self.L, self.c = coefficients.adr_coefficients(
-            self.tau, self.kappa2, self.gamma, h, omega, src=fsrc)
+            self.tau, self.kappa2, self.gamma, h, omega, src=fsrc, form=reaction)
         self.H2up = operators.assemble_adr(self.g, self.L, self.c, h, omega, 0.0, src=self.src)
         self.Abeta = operators.assemble_adr(self.g, self.L, self.c, h, omega, beta, src=self.src)
 
@@ -101,6 +103,6 @@ def adjoint_gradient(prob, a, receivers, d_obs, solve=direct_solve):
     np.add.at(rhs, receivers, res)
     rhs = np.conj(np.exp(-1j * prob.omega * prob.tau)) * rhs   # M^H R^T r
     lam = solve(prob.H2up.conj().T.tocsr(), rhs.ravel()).reshape(prob.shape)
-    gam = np.zeros(prob.shape) if prob.gamma is None else prob.gamma
-    grad = -np.real(np.conj(lam) * (prob.omega ** 2 - 1j * prob.omega * gam) * a)
+    dc = coefficients.reaction_derivative(prob.gamma, prob.omega, prob.shape, prob.reaction)
+    grad = -np.real(np.conj(lam) * dc * a)
     return J, grad, lam

@@ -19,6 +19,7 @@ ADR_PREC_FP64, ADR_PREC_MIXED = 0, 1
 ADR_RELAX_JACOBI, ADR_RELAX_GMRES = 0, 1
 ADR_CYCLE_V, ADR_CYCLE_K = 0, 1
 ADR_ADV_UPWIND, ADR_ADV_CENTRAL = 0, 1
+ADR_REACTION_NUMERICAL, ADR_REACTION_EIKONAL = 0, 1
 TIMER_KINDS = {"fine_jacobi": 0, "fine_residual": 1, "coarse_apply": 2, "coarse_orth": 3, "transfer": 4,
                "outer_matvec": 5, "outer_orth": 6, "coarse_tail": 7}
 
@@ -57,6 +58,7 @@ class AdrOptions(ctypes.Structure):
         ("outer_beta", ctypes.c_double),
         ("rescaled", ctypes.c_int),
         ("pipeline_max_nodes", ctypes.c_int),
+        ("reaction", ctypes.c_int),
     ]
 
 
@@ -146,6 +148,8 @@ def default_options(**kw):
             o.cycle = {"v": ADR_CYCLE_V, "k": ADR_CYCLE_K}.get(v, v)
         elif k == "advection":
             o.advection = {"upwind": ADR_ADV_UPWIND, "central": ADR_ADV_CENTRAL}.get(v, v)
+        elif k == "reaction":
+            o.reaction = {"numerical": ADR_REACTION_NUMERICAL, "eikonal": ADR_REACTION_EIKONAL}.get(v, v)
         else:
             setattr(o, k, v)
     return o

@@ -817,6 +817,14 @@ adr_status validate(const adr_problem *p, const adr_options *o, std::string &err
   if (o->advection != ADR_ADV_UPWIND && o->advection != ADR_ADV_CENTRAL) { err = "bad advection"; return ADR_EINVAL; }
   if (!(o->outer_beta >= 0.0 && o->outer_beta <= 1.0)) { err = "outer_beta must be in [0, 1]"; return ADR_EINVAL; }
   if (o->rescaled != 0 && o->rescaled != 1) { err = "rescaled must be 0 or 1"; return ADR_EINVAL; }
+  if (o->reaction != ADR_REACTION_NUMERICAL && o->reaction != ADR_REACTION_EIKONAL) {
+    err = "bad reaction";
+    return ADR_EINVAL;
+  }
+  if (o->reaction == ADR_REACTION_EIKONAL && !p->tau) {
+    err = "the eikonal reaction needs a travel time (tau = NULL is the Helmholtz operator)";
+    return ADR_EINVAL;
+  }
   if (!(o->shift_alpha >= 0.0 && o->shift_alpha < 1e300)) {
     err = "shift_alpha must be finite and >= 0";
     return ADR_EINVAL;
@@ -1160,8 +1168,9 @@ adr_status setup_impl(adr_ctx *ctx, const adr_problem *p) {
     ADR_TRY(dalloc(ctx, &ctx->gamma, N));
     ADR_HIP(hipMemcpyAsync(ctx->gamma, p->gamma, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
   }
-  adrk::coefficients(s, ctx->G0, D, ctx->h, ctx->omega, ctx->src, p->kappa2, ctx->tau, p->gamma, ctx->g64[0],
-                     ctx->g64[1], D == 3 ? ctx->g64[2] : nullptr, ctx->L64, ctx->c64);
+  adrk::coefficients(s, ctx->G0, D, ctx->h, ctx->omega, ctx->src, ctx->opt.reaction == ADR_REACTION_NUMERICAL,
+                     p->kappa2, ctx->tau, p->gamma, ctx->g64[0], ctx->g64[1], D == 3 ? ctx->g64[2] : nullptr,
+                     ctx->L64, ctx->c64);
   if (ctx->opt.shift_alpha > 0.0) {
     ADR_TRY(dalloc(ctx, &ctx->cM64, N));
     adrk::shift_reaction(s, N, ctx->c64, p->kappa2, ctx->opt.shift_alpha * ctx->omega * ctx->omega, ctx->cM64);
@@ -1902,8 +1911,8 @@ adr_status adr_apply_adjoint(adr_ctx *ctx, const void *x, void *y) {
 
 adr_status adr_grad_kappa2(adr_ctx *ctx, const void *a, const void *lam, double *grad) {
   if (!ctx || !a || !lam || !grad) return ADR_EINVAL;
-  adrk::grad_kappa2(ctx->stream, ctx->G0.N, ctx->omega, ctx->gamma, (const cx<double> *)a,
-                    (const cx<double> *)lam, grad);
+  adrk::grad_kappa2(ctx->stream, ctx->G0.N, ctx->omega, ctx->opt.reaction == ADR_REACTION_NUMERICAL, ctx->gamma,
+                    (const cx<double> *)a, (const cx<double> *)lam, grad);
   ADR_HIP(hipGetLastError());
   return ADR_OK;
 }

@@ -30,7 +30,7 @@ inline void launch_g(F k_single, F k_group, int nblocks, hipStream_t s, Args... 
 // =====================================================================================
 template <int D>
 __global__ __launch_bounds__(ADR_BLOCK) void k_coefficients(Grid G, double h, double omega, int sx, int sy, int sz,
-                                                            const double *__restrict__ kappa2,
+                                                            double w2r, const double *__restrict__ kappa2,
                                                             const double *__restrict__ tau,
                                                             const double *__restrict__ gamma, double *g0,
                                                             double *g1, double *g2, double *Lout,
@@ -41,7 +41,13 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_coefficients(Grid G, double h, do
   const bool fact = sx >= 0;
   const int stride[3] = {1, G.n[0], G.n[0] * G.n[1]};
   const int srcidx = fact ? sx + G.n[0] * (sy + G.n[1] * sz) : -1;
-  const double ksrc = fact ? sqrt(kappa2[srcidx]) : 0.0;
+  // tau1 at the source (0/0 there): the mean of tau / h over its 2D axis neighbours, a
+  // function of tau alone, so kappa2 enters the operator only through the reaction.
+  double ksrc = 0.0;
+  if (fact) {
+    for (int k = 0; k < D; ++k) ksrc += tau[srcidx - stride[k]] / h + tau[srcidx + stride[k]] / h;
+    ksrc /= (double)(2 * D);
+  }
   for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
     int idx[3];
     decode(G, i, idx[0], idx[1], idx[2]);
@@ -112,18 +118,21 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_coefficients(Grid G, double h, do
     g1[i] = g[1];
     if (D == 3) g2[i] = g[2];
     Lout[i] = L;
-    cout[i] = mk<double>(omega * omega * (k2 - gg), -omega * gam * k2);
+    cout[i] = mk<double>(w2r * (k2 - gg), -omega * gam * k2);
   }
 }
 
 void coefficients(hipStream_t s, const Grid &G, int D, double h, double omega, const int src[3],
-                  const double *kappa2, const double *tau, const double *gamma, double *g0, double *g1,
-                  double *g2, double *L, cx<double> *c) {
+                  bool numerical_reaction, const double *kappa2, const double *tau, const double *gamma, double *g0,
+                  double *g1, double *g2, double *L, cx<double> *c) {
   int nb = launch_blocks(G.N);
+  const double w2r = numerical_reaction ? omega * omega : 0.0;
   if (D == 2)
-    ADR_LAUNCH(k_coefficients<2>, nb, s, G, h, omega, src[0], src[1], src[2], kappa2, tau, gamma, g0, g1, g2, L, c);
+    ADR_LAUNCH(k_coefficients<2>, nb, s, G, h, omega, src[0], src[1], src[2], w2r, kappa2, tau, gamma, g0, g1, g2, L,
+               c);
   else
-    ADR_LAUNCH(k_coefficients<3>, nb, s, G, h, omega, src[0], src[1], src[2], kappa2, tau, gamma, g0, g1, g2, L, c);
+    ADR_LAUNCH(k_coefficients<3>, nb, s, G, h, omega, src[0], src[1], src[2], w2r, kappa2, tau, gamma, g0, g1, g2, L,
+               c);
 }
 
 // =====================================================================================
@@ -639,21 +648,24 @@ void adjoint_planes(hipStream_t s, const Grid &G, int D, const cx<T> *A, cx<T> *
 template void adjoint_planes<double>(hipStream_t, const Grid &, int, const cx<double> *, cx<double> *);
 template void adjoint_planes<float>(hipStream_t, const Grid &, int, const cx<float> *, cx<float> *);
 
-// grad[i] += -Re(conj(lam_i) (w^2 - i w gamma_i) a_i): the derivative of a receiver misfit
-// with respect to kappa^2_i at fixed travel time, given the forward amplitude a and the
-// adjoint state lam (dH_2up / dkappa2_i = (w^2 - i w gamma_i) e_i e_i^T).
-__global__ __launch_bounds__(ADR_BLOCK) void k_grad_kappa2(int N, double omega, const double *__restrict__ gamma,
+// grad[i] += -Re(conj(lam_i) c'_i a_i): the derivative of a receiver misfit with respect to
+// kappa^2_i at fixed travel time, given the forward amplitude a and the adjoint state lam
+// (dH_2up / dkappa2_i = c'_i e_i e_i^T, c'_i = w2r - i w gamma_i with w2r = w^2 when the
+// reaction keeps w^2 kappa^2, 0 when the eikonal equation removed it).
+__global__ __launch_bounds__(ADR_BLOCK) void k_grad_kappa2(int N, double omega, double w2r,
+                                                           const double *__restrict__ gamma,
                                                            const cx<double> *__restrict__ a,
                                                            const cx<double> *__restrict__ lam, double *grad) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
     const double gm = gamma ? gamma[i] : 0.0;
-    const cx<double> t = cdotc(lam[i], mk<double>(omega * omega, -omega * gm) * a[i]);
+    const cx<double> t = cdotc(lam[i], mk<double>(w2r, -omega * gm) * a[i]);
     grad[i] -= t.re;
   }
 }
-void grad_kappa2(hipStream_t s, int N, double omega, const double *gamma, const cx<double> *a, const cx<double> *lam,
-                 double *grad) {
-  ADR_LAUNCH(k_grad_kappa2, launch_blocks(N), s, N, omega, gamma, a, lam, grad);
+void grad_kappa2(hipStream_t s, int N, double omega, bool numerical_reaction, const double *gamma,
+                 const cx<double> *a, const cx<double> *lam, double *grad) {
+  const double w2r = numerical_reaction ? omega * omega : 0.0;
+  ADR_LAUNCH(k_grad_kappa2, launch_blocks(N), s, N, omega, w2r, gamma, a, lam, grad);
 }
 
 // Receivers: r_k = u[idx_k] - d_k; adjoint source s = sum_k e_{idx_k} r_k (s is zeroed

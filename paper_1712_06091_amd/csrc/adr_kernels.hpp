@@ -78,9 +78,10 @@ struct ShotLaunch {
 extern thread_local ShotLaunch g_shot;
 
 // ---- setup (FP64) ----------------------------------------------------------------
+// numerical_reaction: c = w^2 (kappa2 - |g|^2) - i w gamma kappa2, else c = -i w gamma kappa2
 void coefficients(hipStream_t s, const Grid &G, int D, double h, double omega, const int src[3],
-                  const double *kappa2, const double *tau, const double *gamma, double *g0, double *g1,
-                  double *g2, double *L, cx<double> *c);
+                  bool numerical_reaction, const double *kappa2, const double *tau, const double *gamma, double *g0,
+                  double *g1, double *g2, double *L, cx<double> *c);
 void fine_stencil(hipStream_t s, const Grid &G, int D, const FineCoef<double> &C, const FineParams &P,
                   cx<double> *planes /* (1+4D) x N */);
 void galerkin(hipStream_t s, const Grid &Gf, const Grid &Gc, const cx<double> *in_planes, const int *in_off_xyz,
@@ -144,8 +145,8 @@ void fine_jacobi_adj(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, 
 template <typename T>
 void adjoint_planes(hipStream_t s, const Grid &G, int D, const cx<T> *A, cx<T> *AH);
 // grad[i] += -Re(conj(lam_i) (w^2 - i w gamma_i) a_i)  (gamma may be NULL)
-void grad_kappa2(hipStream_t s, int N, double omega, const double *gamma, const cx<double> *a, const cx<double> *lam,
-                 double *grad);
+void grad_kappa2(hipStream_t s, int N, double omega, bool numerical_reaction, const double *gamma,
+                 const cx<double> *a, const cx<double> *lam, double *grad);
 // r_k = u[idx_k] - d_k
 void receiver_residual(hipStream_t s, int nrec, const int *idx, const cx<double> *u, const cx<double> *d,
                        cx<double> *r);

@@ -7,10 +7,9 @@ H_2up(kappa^2) a_s = q_s exp(i w tau_s) (adr_solve), forms u_s = a_s exp(-i w ta
 pass solves H_2up^H lam_s = exp(i w tau_s) R^T r_s (adr_adjoint_source, adr_solve_adjoint)
 and accumulates dJ/dkappa2 = -sum_s Re(conj(lam_s) (w^2 - i w gamma) a_s) (adr_grad_kappa2).
 
-kappa^2 enters the operator through the reaction term w^2 (kappa^2 - |grad tau|^2)
-- i w gamma kappa^2; the travel-time derivatives are taken from tau and do not move with
-kappa^2 (the gradient is at fixed tau), except that the factored form reads
-kappa(source) for tau/|x - x0| at the source node, a dependence this gradient leaves out.
+kappa^2 enters the operator only through the reaction term w^2 (kappa^2 - |grad tau|^2)
+- i w gamma kappa^2: the travel-time derivatives are functions of tau alone (the factored
+tau/|x - x0| at the source node included), so at fixed tau this gradient is complete.
 """
 import torch
 

@@ -265,23 +265,28 @@ class AdjointWorkload:
     receivers: np.ndarray       # int32 linear node indices
 
 
-def adjoint_3d(n=193, seed=5, nsrc_axis=4, nrec_axis=64, pert=0.02, workers=8, name=None):
+def adjoint_3d(n=193, seed=5, nsrc_axis=4, nrec_axis=64, pert=0.05, eta_seed=55, rec_first=2, rec_step=3,
+               workers=8, name=None):
     """3D n^3 unit cube, v = 2 (1 + 0.2 eta) km/s (seed), nsrc_axis^2 sources on a regular
     grid at depth 0.1 km (x, y in {1, ..., nsrc_axis} / (nsrc_axis + 1) km), an
-    nrec_axis^2 receiver plane on the top face (z = 0, evenly spaced in x and y), observed
-    data from kappa2_true = kappa2 (1 + pert * eta2) with eta2 seeded by seed + 1, tau by
-    factored fast marching in kappa2, 10 points per wavelength."""
+    nrec_axis^2 receiver plane on the top face (z = 0) at nodes i, j = rec_first + rec_step k,
+    k = 0 .. nrec_axis - 1, observed data from kappa2_true = kappa2 (1 + pert * eta2) with
+    eta2 a smooth field seeded by eta_seed, tau by factored fast marching in kappa2, 10
+    points per wavelength."""
     shape = (n,) * 3
     h = 1.0 / (n - 1)
+    last = rec_first + rec_step * (nrec_axis - 1)
+    if last >= n:
+        raise ValueError(f"receiver line {rec_first} + {rec_step} k, k < {nrec_axis}, leaves a grid of {n} nodes")
     v = smooth_random_velocity(shape, h, seed)
     kappa2 = 1.0 / v ** 2
-    kappa2_true = kappa2 * (1.0 + pert * smooth_random_field(shape, h, seed + 1))
+    kappa2_true = kappa2 * (1.0 + pert * smooth_random_field(shape, h, eta_seed))
     omega = omega_for_ppw(float(v.min()), h)
     gamma = absorbing_layer(shape, h, omega, 10 * h)
     fr = [(k + 1) / (nsrc_axis + 1) for k in range(nsrc_axis)]
     sources = [(int(round(0.1 / h)), int(round(y / h)), int(round(x / h))) for y in fr for x in fr]
     taus = factored_traveltimes(kappa2, h, sources, workers)
-    line = np.round(np.linspace(0, n - 1, nrec_axis)).astype(np.int64)
+    line = rec_first + rec_step * np.arange(nrec_axis, dtype=np.int64)
     yy, xx = np.meshgrid(line, line, indexing="ij")
     receivers = np.ravel_multi_index((np.zeros(yy.size, dtype=np.int64), yy.ravel(), xx.ravel()), shape)
     return AdjointWorkload(name or f"adjoint_3d_{n}", shape, h, omega, kappa2, kappa2_true, gamma, sources, taus,

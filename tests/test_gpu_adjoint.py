@@ -93,8 +93,9 @@ def _receivers(shape):
 
 def test_gradient_finite_differences_and_oracle():
     """dJ/dkappa^2 from the adjoint against central finite differences of GPU solves
-    (FP64, tol 1e-12, direction zero at the source node) and against the oracle's
-    adjoint gradient."""
+    (FP64, tol 1e-12; a smooth direction and the unit vector at the source node, where
+    kappa^2 must not reach the operator except through the reaction term) and against the
+    oracle's adjoint gradient."""
     from paper_1712_06091_amd import adr, misfit
     wl = W.linear_gradient(17, 3)
     print("[gradient] 3d 17", flush=True)
@@ -114,16 +115,20 @@ def test_gradient_finite_differences_and_oracle():
     Jo, go, _ = osolve.adjoint_gradient(p, a, np.unravel_index(rec, wl.shape), d_obs)
     assert abs(J.item() - Jo) <= 1e-8 * Jo
     assert _rel(g, go) <= 1e-6
-    # finite differences along a smooth direction that vanishes at the source node
+    # finite differences along a smooth direction (nonzero at the source node) and along
+    # the source node's unit vector
     xs = W.node_coordinates(wl.shape, wl.h)
-    dk = np.sin(3 * xs[0]) * np.cos(2 * xs[1] + xs[2])
-    dk[wl.src] = 0.0
+    smooth = np.sin(3 * xs[0]) * np.cos(2 * xs[1] + xs[2]) + 0.5
+    e_src = np.zeros(wl.shape)
+    e_src[wl.src] = 1.0
+    assert abs(smooth[wl.src]) > 0.1
     eps = 1e-4 * np.abs(wl.kappa2).max()
-    vals = []
-    for sgn in (+1, -1):
-        kk = _t(wl.kappa2 + sgn * eps * dk, torch.float64)
-        vals.append(misfit.receiver_misfit(kk, gam, [tau], [wl.src], wl.h, wl.omega, recs, [dd],
-                                           options=opts, tol=1e-12).item())
-    fd = (vals[0] - vals[1]) / (2 * eps)
-    an = float(np.sum(g * dk))
-    assert abs(fd - an) <= 1e-5 * abs(an), (fd, an)
+    for dk in (smooth, e_src):
+        vals = []
+        for sgn in (+1, -1):
+            kk = _t(wl.kappa2 + sgn * eps * dk, torch.float64)
+            vals.append(misfit.receiver_misfit(kk, gam, [tau], [wl.src], wl.h, wl.omega, recs, [dd],
+                                               options=opts, tol=1e-12).item())
+        fd = (vals[0] - vals[1]) / (2 * eps)
+        an = float(np.sum(g * dk))
+        assert abs(fd - an) <= 1e-5 * abs(an), (fd, an)

@@ -84,7 +84,7 @@ def test_coefficients_linear_gradient_second_order():
     errs_e, errs_l = [], []
     for n in (33, 65):
         wl = W.linear_gradient(n, ndim=2, absorb=False)
-        g, L = coefficients.travel_time_derivatives(wl.tau, wl.h, src=wl.src, kappa2=wl.kappa2)
+        g, L = coefficients.travel_time_derivatives(wl.tau, wl.h, src=wl.src)
         xs = W.node_coordinates(wl.shape, wl.h)
         r = W.distance(wl.shape, wl.h, wl.src)
         mask = (r >= 0.2) & ~boundary_mask(wl.shape)
@@ -172,6 +172,49 @@ def test_operator_on_quadratics(d, beta):
     np.testing.assert_allclose(got[inner], expect[inner], rtol=1e-11, atol=1e-8)
 
 
+@pytest.mark.parametrize("d,beta", [(2, 0.0), (2, 0.25), (3, 0.25), (3, 1.0)])
+def test_operator_rows_one_node_from_faces(d, beta):
+    """Rows one node inside a face whose upwind stencil would need the node beyond the
+    face (g_k > 0 at i_k = 1, g_k < 0 at i_k = n-2): both upwind orders fall back to the
+    first-order upwind difference, whose value on a quadratic is a' -+ (h/2) a''
+    whatever beta.  Every row off the faces is checked, on every axis, with random
+    coefficient signs; rows that do not fall back follow the interior rules."""
+    n = 9 if d == 3 else 15
+    shape = (n,) * d
+    h = 1.0 / (n - 1)
+    omega = 6.0
+    rng = np.random.default_rng(12)
+    g = [rng.standard_normal(shape) for _ in range(d)]
+    L = rng.standard_normal(shape)
+    c = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    src = (n // 2,) * d
+    A = operators.assemble_adr(g, L, c, h, omega, beta, src=src)
+    a, grad, second = _quadratic(shape, h, 13)
+    got = (A @ a.ravel()).reshape(shape)
+    idx = np.meshgrid(*[np.arange(k) for k in shape], indexing="ij")
+    cheb = np.max(np.stack([np.abs(idx[k] - src[k]) for k in range(d)]), axis=0)
+    off_faces = np.ones(shape, dtype=bool)
+    for k in range(d):
+        off_faces &= (idx[k] >= 1) & (idx[k] <= n - 2)
+    lap = sum(second)
+    adv = 0.0
+    short = np.zeros(shape, dtype=bool)
+    for k in range(d):
+        back = g[k] >= 0
+        one_short_b = back & (idx[k] == 1)
+        one_short_f = ~back & (idx[k] == n - 2)
+        short |= (one_short_b | one_short_f) & (cheb > 1)
+        sign = np.where(back, 1.0, -1.0)
+        first_order = grad[k] - sign * 0.5 * h * second[k]
+        blended = grad[k] - beta * sign * 0.5 * h * second[k]
+        dk = np.where(one_short_b | one_short_f, first_order, blended)
+        dk = np.where(cheb <= 1, grad[k], dk)
+        adv = adv + g[k] * dk
+    expect = lap - 2j * omega * adv - 1j * omega * L * (a + h * h / (2 * d) * lap) + c * a
+    assert short[off_faces].sum() > 10
+    np.testing.assert_allclose(got[off_faces], expect[off_faces], rtol=1e-11, atol=1e-8)
+
+
 @pytest.mark.parametrize("g0", [0.7, -0.7])
 def test_operator_face_rows(g0):
     """Face rows: a(x) = 1 + i w g0 s + c2 s^2 (s = distance into the domain along x)
@@ -204,7 +247,7 @@ def test_operator_face_rows(g0):
         np.testing.assert_allclose(got[rows, col], expect, rtol=1e-12, atol=1e-9)
 
 
-def _manufactured_error(n, beta, omega=20.0, gam=2.0, x0=(-0.3, -0.2)):
+def _manufactured_error(n, beta, omega=20.0, gam=2.0, x0=(-0.3, -0.2), form="numerical"):
     shape = (n, n)
     h = 1.0 / (n - 1)
     Y, X = W.node_coordinates(shape, h)
@@ -219,17 +262,20 @@ def _manufactured_error(n, beta, omega=20.0, gam=2.0, x0=(-0.3, -0.2)):
     lap = -np.pi ** 2 * s1 * s2 * p + 1j * np.pi * c1 * s2 - 4 * np.pi ** 2 * s1 * s2 * p
     # eq. ADR with tau = |x - x0| (|grad tau| = kappa = 1, lap tau = 1/r) and absorption.
     f = lap - 2j * omega * (dx / r * ax + dy / r * ay) - 1j * omega / r * a - 1j * omega * gam * a
-    g, L, c = coefficients.adr_coefficients(r, np.ones(shape), np.full(shape, gam), h, omega, src=None)
+    g, L, c = coefficients.adr_coefficients(r, np.ones(shape), np.full(shape, gam), h, omega, src=None, form=form)
     A = operators.assemble_adr(g, L, c, h, omega, beta, src=None)
     ah = solve_dirichlet(A, shape, f, a)
     return np.linalg.norm(ah - a) / np.linalg.norm(a)
 
 
-def test_manufactured_solution_orders():
-    """Smooth manufactured amplitude, smooth tau (source outside the domain): H_2up
-    converges at second order (Sec. 2.2 claims a second-order scheme), H_1up at first."""
-    e2 = [_manufactured_error(n, 0.0) for n in (65, 129, 257)]
-    e1 = [_manufactured_error(n, 1.0) for n in (65, 129)]
+@pytest.mark.parametrize("form", ["numerical", "eikonal"])
+def test_manufactured_solution_orders(form):
+    """Smooth manufactured amplitude, smooth tau solving the eikonal equation (source
+    outside the domain, kappa = 1), so eq. ADR has no w^2 reaction term: H_2up converges at
+    second order (Sec. 2.2 claims a second-order scheme), H_1up at first, with the
+    reaction kept as the numerical eikonal residual or dropped (Sec. 1)."""
+    e2 = [_manufactured_error(n, 0.0, form=form) for n in (65, 129, 257)]
+    e1 = [_manufactured_error(n, 1.0, form=form) for n in (65, 129)]
     o2 = np.log2(e2[1] / e2[2])
     assert np.log2(e2[0] / e2[1]) > 1.7 and o2 > 1.8
     assert 0.75 < np.log2(e1[0] / e1[1]) < 1.2
@@ -411,6 +457,55 @@ def test_gmres_relaxation_is_residual_minimizer():
     assert np.linalg.norm(b - A @ x1) < np.linalg.norm(b - A @ x0)
 
 
+def _dense_prolongation(shape):
+    """Nodal (bi/tri)linear interpolation as a dense matrix, built from its definition:
+    the fine node x takes the coarse values at the corners of its coarse cell, each
+    weighted by the product over axes of (1 - |x_k - 2 X_k| / 2)."""
+    cs = tuple((n - 1) // 2 + 1 for n in shape)
+    fine = np.array(np.unravel_index(np.arange(int(np.prod(shape))), shape)).T
+    coarse = np.array(np.unravel_index(np.arange(int(np.prod(cs))), cs)).T
+    P = np.ones((len(fine), len(coarse)))
+    for k in range(len(shape)):
+        dist = np.abs(fine[:, k][:, None] - 2 * coarse[:, k][None, :]) / 2.0
+        P *= np.clip(1.0 - dist, 0.0, None)
+    return P, cs
+
+
+@pytest.mark.parametrize("levels", [2, 3])
+def test_vcycle_is_the_two_grid_recursion(levels):
+    """With damped Jacobi on every level the V-cycle from a zero guess is a linear map
+    B, and Alg. TwoCycle fixes it: the error propagation of the cycle on level l is
+    E_l = S_l^nu (I - P B_{l+1} P^T A_l) S_l^nu with S_l = I - w D_l^-1 A_l, the coarse
+    operator P^T A_l P, B_L = A_L^-1 on the coarsest level and B_l = (I - E_l) A_l^-1.
+    Built here with dense matrices and an independently written interpolation; the
+    oracle's V-cycle must reproduce B_0 b.  Dropping a relaxation, the coarse
+    correction, or transposing P changes the result."""
+    wl = W.linear_gradient(17, ndim=2)
+    p = solve.Problem(wl.kappa2, wl.tau, wl.gamma, wl.h, wl.omega, wl.src)
+    nu = [2, 3, 4][:levels]
+    w = 0.8
+    hier = p.hierarchy(levels, nu=nu, jacobi_weight=w, smoothers=["jacobi"] * levels)
+    A = [p.Abeta.toarray()]
+    Ps = []
+    shape = wl.shape
+    for _ in range(levels - 1):
+        P, shape = _dense_prolongation(shape)
+        Ps.append(P)
+        A.append(P.T @ A[-1] @ P)
+    B = np.linalg.inv(A[-1])
+    for l in range(levels - 2, -1, -1):
+        I = np.eye(A[l].shape[0])
+        S = I - w * np.diag(1.0 / np.diag(A[l])) @ A[l]
+        Sn = np.linalg.matrix_power(S, nu[l])
+        E = Sn @ (I - Ps[l] @ B @ Ps[l].T @ A[l]) @ Sn
+        B = (I - E) @ np.linalg.inv(A[l])
+    rng = np.random.default_rng(21)
+    b = rng.standard_normal(A[0].shape[0]) + 1j * rng.standard_normal(A[0].shape[0])
+    x = hier.vcycle(b)
+    ref = B @ b
+    assert np.linalg.norm(x - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
 def test_jacobi_fixed_point():
     wl, p = _small_problem(17)
     hier = p.hierarchy(2)
@@ -457,33 +552,35 @@ def test_vcycle_preconditioner_converges_2d_129():
 # Adjoint (gradient of a receiver misfit w.r.t. kappa^2 at fixed tau)
 # ----------------------------------------------------------------------------------
 
-def test_adjoint_gradient_finite_differences():
+@pytest.mark.parametrize("form", ["numerical", "eikonal"])
+def test_adjoint_gradient_finite_differences(form):
+    """The adjoint gradient equals central finite differences of the whole forward map
+    kappa^2 -> J at fixed tau (coefficients rebuilt from the perturbed kappa^2), in a
+    direction that is nonzero everywhere, the source node included: at fixed tau the
+    operator may depend on kappa^2 only through its reaction term (with the eikonal form,
+    only through the absorbing term)."""
     wl = W.linear_gradient(17, ndim=2)
     rec = (np.full(8, 1), np.arange(1, 17, 2))
     rng = np.random.default_rng(7)
     d_obs = rng.standard_normal(len(rec[0])) * 0.01 + 0j
 
-    def misfit(k2):
-        p = solve.Problem(k2, wl.tau, wl.gamma, wl.h, wl.omega, wl.src)
+    def solve_for(k2):
+        p = solve.Problem(k2, wl.tau, wl.gamma, wl.h, wl.omega, wl.src, reaction=form)
         a = solve.direct_solve(p.H2up, solve.rhs_hat(wl.rhs(), wl.tau, wl.omega)).reshape(wl.shape)
         return p, a
 
-    p, a = misfit(wl.kappa2)
+    p, a = solve_for(wl.kappa2)
     J, grad, _ = solve.adjoint_gradient(p, a, rec, d_obs)
-    # At fixed tau only the reaction depends on kappa^2, so the FD must hold g, L fixed:
-    # perturb kappa^2 inside c only, through a Problem whose tau derivatives are reused.
     dk = rng.standard_normal(wl.shape)
-    eps = 1e-6
-    vals = []
-    for s in (+1, -1):
-        k2 = wl.kappa2 + s * eps * dk
-        pp = solve.Problem(wl.kappa2, wl.tau, wl.gamma, wl.h, wl.omega, wl.src)
-        gam = np.zeros(wl.shape) if wl.gamma is None else wl.gamma
-        c = coefficients.reaction(pp.g, k2, gam, wl.omega)
-        H = operators.assemble_adr(pp.g, pp.L, c, wl.h, wl.omega, 0.0, src=wl.src)
-        aa = solve.direct_solve(H, solve.rhs_hat(wl.rhs(), wl.tau, wl.omega)).reshape(wl.shape)
-        u = solve.wavefield(aa, wl.tau, wl.omega)
-        vals.append(0.5 * np.sum(np.abs(u[rec] - d_obs) ** 2))
-    fd = (vals[0] - vals[1]) / (2 * eps)
-    an = float(np.sum(grad * dk))
-    assert abs(fd - an) <= 1e-6 * abs(an)
+    assert abs(dk[wl.src]) > 0.1
+    for direction in (dk, np.where(np.arange(dk.size).reshape(wl.shape) == np.ravel_multi_index(wl.src, wl.shape),
+                                   1.0, 0.0)):
+        eps = 1e-6
+        vals = []
+        for s in (+1, -1):
+            _, aa = solve_for(wl.kappa2 + s * eps * direction)
+            u = solve.wavefield(aa, wl.tau, wl.omega)
+            vals.append(0.5 * np.sum(np.abs(u[rec] - d_obs) ** 2))
+        fd = (vals[0] - vals[1]) / (2 * eps)
+        an = float(np.sum(grad * direction))
+        assert abs(fd - an) <= 1e-6 * abs(an) + 1e-14 * abs(J)
