@@ -231,6 +231,21 @@ adr_status adr_grad_kappa2(adr_ctx *ctx, const void *a_c128, const void *lam_c12
 adr_status adr_receiver_residual(adr_ctx *ctx, const void *u_c128, const int *idx, const void *d_c128, int nrec,
                                  void *r_c128, double *misfit);
 
+/* For callers that cannot allocate device memory (code under stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc): adr_receiver_residual without a
+ * context.  r_k = u[idx_k] - d_k for k < nrec, enqueued on `stream` (a hipStream_t; NULL =
+ * the default stream).  If misfit != NULL (host), *misfit = 1/2 sum |r_k|^2, summed in the
+ * same order as adr_receiver_residual (same value bit for bit), and the stream is
+ * synchronized.  The misfit's partial sums live in a fixed device array inside the
+ * library (512 doubles, 4 KiB, one copy per GPU, held until the process ends); nothing
+ * is allocated.  Every call on a GPU shares that array, which keeps the last call's
+ * partials: calls that overlap on one GPU (other threads, other streams) race.
+ * ADR_EINVAL for a NULL array pointer or nrec outside [1, ADR_NOALLOC_MAX_REC];
+ * adr_last_error(NULL) gives the message. */
+#define ADR_NOALLOC_MAX_REC (1 << 26)
+adr_status adr_receiver_residual_noalloc(const void *u_c128, const int *idx, const void *d_c128, int nrec,
+                                         void *r_c128, double *misfit, void *stream);
+
 /* Adjoint source s = R^T r: s = 0, then s[idx_k] += r_k for k in order (repeated indices
  * accumulate).  s: c128 of n nodes.  Enqueued. */
 adr_status adr_adjoint_source(adr_ctx *ctx, const int *idx, const void *r_c128, int nrec, void *s_c128);

@@ -20,6 +20,7 @@ ADR_RELAX_JACOBI, ADR_RELAX_GMRES = 0, 1
 ADR_CYCLE_V, ADR_CYCLE_K = 0, 1
 ADR_ADV_UPWIND, ADR_ADV_CENTRAL = 0, 1
 ADR_REACTION_NUMERICAL, ADR_REACTION_EIKONAL = 0, 1
+ADR_NOALLOC_MAX_REC = 1 << 26
 TIMER_KINDS = {"fine_jacobi": 0, "fine_residual": 1, "coarse_apply": 2, "coarse_orth": 3, "transfer": 4,
                "outer_matvec": 5, "outer_orth": 6, "coarse_tail": 7}
 
@@ -113,6 +114,7 @@ def load_library(path=LIB_PATH):
         "adr_apply_adjoint": (I, [P, P, P]),
         "adr_grad_kappa2": (I, [P, P, P, P]),
         "adr_receiver_residual": (I, [P, P, P, P, I, P, ctypes.POINTER(ctypes.c_double)]),
+        "adr_receiver_residual_noalloc": (I, [P, P, P, I, P, ctypes.POINTER(ctypes.c_double), P]),
         "adr_adjoint_source": (I, [P, P, P, I, P]),
         "adr_setup_batch": (I, [I, ctypes.POINTER(AdrProblem), ctypes.POINTER(AdrOptions), I, ctypes.POINTER(P)]),
         "adr_solve_batch": (I, [P, ctypes.POINTER(P), ctypes.POINTER(P), D, I, ctypes.POINTER(AdrStats)]),
@@ -176,6 +178,18 @@ def solve_two_stage(first, second, q, tol=1e-6, maxit=500, tol_first=1e-2, maxit
     d1, d2 = s1.as_dict(), s2.as_dict()
     d2["status"] = status
     return a, d1, d2
+
+
+def receiver_residual_noalloc(u, idx, d, out, stream=None):
+    """adr_receiver_residual_noalloc: (r, misfit) with r_k = u[idx_k] - d_k, no context and
+    no allocation by the library; ``out`` (complex128, idx.numel() entries) is the caller's."""
+    import torch
+    lib = load_library()
+    J = ctypes.c_double()
+    _check(lib.adr_receiver_residual_noalloc(_dev(u, torch.complex128), _dev(idx, torch.int32),
+                                             _dev(d, torch.complex128), int(idx.numel()),
+                                             _dev(out, torch.complex128), ctypes.byref(J), _stream_ptr(stream)))
+    return out, J.value
 
 
 def _check(status, ctx_ptr=None):

@@ -1934,6 +1934,93 @@ adr_status adr_receiver_residual(adr_ctx *ctx, const void *u, const int *idx, co
   return ADR_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// Device scratch of adr_receiver_residual_noalloc: the per-block partial sums of the misfit
+// (one per reduction block, at most ADR_MAX_RED_BLOCKS).  Every GPU holds its own copy; host
+// code uses the address hipGetSymbolAddress returns for the current device, never the name.
+constexpr int kNoAllocPartials = ADR_MAX_RED_BLOCKS;
+static __device__ __align__(256) double scratch[kNoAllocPartials];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of `scratch`, looked up on the first call on that device.
+adr_status noalloc_scratch(double **out, std::string &err) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    err = std::string("hipGetDevice failed: ") + hipGetErrorString(e);
+    return ADR_EHIP;
+  }
+  if (dev < 0 || dev >= kMaxDevices) {
+    err = "device index out of range for the no-allocation scratch";
+    return ADR_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      err = std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e);
+      return ADR_EHIP;
+    }
+    g_scratch_ptr[dev] = (double *)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return ADR_OK;
+}
+}  // namespace
+
+extern "C" {
+
+adr_status adr_receiver_residual_noalloc(const void *u, const int *idx, const void *d, int nrec, void *r,
+                                         double *misfit, void *stream) {
+  if (!u || !idx || !d || !r) {
+    g_setup_error = "null pointer argument";
+    return ADR_EINVAL;
+  }
+  if (nrec <= 0 || nrec > ADR_NOALLOC_MAX_REC) {
+    g_setup_error = "nrec must be in [1, ADR_NOALLOC_MAX_REC = " + std::to_string(ADR_NOALLOC_MAX_REC) + "]";
+    return ADR_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  adrk::receiver_residual(s, nrec, idx, (const cx<double> *)u, (const cx<double> *)d, (cx<double> *)r);
+  if (misfit) {
+    double *part = nullptr;
+    std::string err;
+    adr_status st = noalloc_scratch(&part, err);
+    if (st != ADR_OK) {
+      g_setup_error = err;
+      return st;
+    }
+    const int nb = adrk::norm2<double>(s, nrec, (const cx<double> *)r, nullptr, nullptr, part);
+    if (nb > kNoAllocPartials) {
+      g_setup_error = "reduction wider than the no-allocation scratch";
+      return ADR_EINVAL;
+    }
+    // Same summation order as adr_receiver_residual: the partials in block order on the host.
+    double host[kNoAllocPartials];
+    hipError_t e = hipMemcpyAsync(host, part, nb * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      g_setup_error = std::string("HIP error: ") + hipGetErrorString(e);
+      return ADR_EHIP;
+    }
+    double acc = 0.0;
+    for (int b = 0; b < nb; ++b) acc += host[b];
+    *misfit = 0.5 * acc;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    g_setup_error = std::string("HIP error: ") + hipGetErrorString(e);
+    return ADR_EHIP;
+  }
+  return ADR_OK;
+}
+
 adr_status adr_adjoint_source(adr_ctx *ctx, const int *idx, const void *r, int nrec, void *src) {
   if (!ctx || !idx || !r || !src || nrec <= 0) return ADR_EINVAL;
   adrk::adjoint_source(ctx->stream, ctx->G0.N, nrec, idx, (const cx<double> *)r, (cx<double> *)src);
