@@ -11,6 +11,14 @@
 // root (each used axis' derivative points away from its neighbour and tau does not
 // decrease), the smallest such root among sets of that size; a trial value computed
 // from more axes replaces one from fewer.  The source node has tau1 = kappa(x0).
+//
+// Safeguard: a first arrival is Lipschitz, tau_i <= tau_j + h max(kappa_i, kappa_j) for
+// every grid neighbour j.  Where the factored update has no causal root, or its root
+// exceeds that bound by more than 10% for an accepted neighbour (near caustics, where the
+// factored one-sided differences straddle a kink), the node takes the first-order
+// Godunov update of the unfactored equation, sum_k (tau - t_k)^2 = (h kappa_i)^2 over
+// the smallest accepted neighbour values t_k for which the root stays above them.
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -152,6 +160,49 @@ extern "C" int fm_factored(int ndim, const int *n /* n[0] = x fastest */, double
     return bestT;
   };
 
+  // Unfactored first-order Godunov update of node i from its accepted neighbours, and the
+  // Lipschitz bound min_j (tau_j + 1.1 h max(kappa_i, kappa_j)) over them.
+  auto godunov = [&](int64_t i, double &bound) -> double {
+    int c[3];
+    coords(i, c);
+    double tk[3];
+    int m = 0;
+    bound = INFINITY;
+    const double ki = std::sqrt(kappa2[i]);
+    for (int k = 0; k < D; ++k) {
+      double best = INFINITY;
+      for (int sgn = -1; sgn <= 1; sgn += 2) {
+        const int q = c[k] + sgn;
+        if (q < 0 || q >= n[k]) continue;
+        const int64_t j = i + sgn * stride[k];
+        if (state[j] != 2) continue;
+        int cj[3] = {c[0], c[1], c[2]};
+        cj[k] = q;
+        const double tj = (j == s) ? 0.0 : tau0(cj) * t1[j];
+        best = std::fmin(best, tj);
+        bound = std::fmin(bound, tj + 1.1 * h * std::fmax(ki, std::sqrt(kappa2[j])));
+      }
+      if (best < INFINITY) tk[m++] = best;
+    }
+    if (m == 0) return INFINITY;
+    std::sort(tk, tk + m);
+    const double f = h * ki;
+    double T = tk[0] + f;
+    for (int u = 2; u <= m; ++u) {
+      if (T <= tk[u - 1]) break;
+      // sum_{k<u} (T - t_k)^2 = f^2
+      double a = u, b = 0, cc = -f * f;
+      for (int k = 0; k < u; ++k) {
+        b -= 2 * tk[k];
+        cc += tk[k] * tk[k];
+      }
+      const double disc = b * b - 4 * a * cc;
+      if (disc < 0) break;
+      T = (-b + std::sqrt(disc)) / (2 * a);
+    }
+    return T;
+  };
+
   auto push_neighbours = [&](int64_t i) {
     int c[3];
     coords(i, c);
@@ -161,16 +212,34 @@ extern "C" int fm_factored(int ndim, const int *n /* n[0] = x fastest */, double
         if (q < 0 || q >= n[k]) continue;
         const int64_t j = i + sgn * stride[k];
         if (state[j] == 2) continue;
-        const double T = update(j);
+        int cj[3] = {c[0], c[1], c[2]};
+        cj[k] = q;
+        const double rj = tau0(cj);
+        double T = update(j);
+        double bound;
+        const double tg = godunov(j, bound);
+        if (!(T < INFINITY) || rj * T > bound) {
+          T = tg / rj;
+          used_axes = D;
+        }
         // A value from more axes replaces one from fewer (a one-axis factored update can
-        // under-estimate); among equal axis counts the smaller value wins.
+        // under-estimate); among equal axis counts the smaller value wins.  Whatever stays
+        // must respect the bound from the neighbours accepted so far, so every node
+        // ends within it of each neighbour accepted before it.
+        bool changed = false;
         if (T < INFINITY && (used_axes > axes[j] || (used_axes == axes[j] && T < t1[j]))) {
           t1[j] = T;
           axes[j] = (uint8_t)used_axes;
+          changed = true;
+        }
+        if (rj * t1[j] > bound) {
+          t1[j] = tg / rj;
+          axes[j] = (uint8_t)D;
+          changed = true;
+        }
+        if (changed) {
           state[j] = 1;
-          int cj[3] = {c[0], c[1], c[2]};
-          cj[k] = q;
-          heap.push(Item{tau0(cj) * T, j});
+          heap.push(Item{rj * t1[j], j});
         }
       }
   };

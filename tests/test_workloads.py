@@ -47,3 +47,22 @@ def test_random_medium_workload():
     assert wl.tau[wl.src] == 0.0 and np.all(wl.tau >= 0)
     v_min = np.sqrt(1.0 / wl.kappa2.max())
     assert abs(wl.omega - 2 * np.pi * v_min / (10 * wl.h)) < 1e-9
+
+
+@pytest.mark.parametrize("n,d,seed", [(129, 3, 3), (65, 3, 7), (257, 2, 4003), (513, 2, 4001)])
+def test_fast_marching_random_medium_is_a_first_arrival(n, d, seed):
+    """In the smooth random media every node is reached (finite tau), tau >= 0 = tau(source),
+    and neighbouring values differ by at most 1.1 h max(kappa_i, kappa_j): a
+    first arrival is Lipschitz with the local slowness, so a larger jump is a marching
+    error (before the fast marching bounded its factored update this way, 129^3 seed 3
+    left 404 nodes unreached and 257^3 seed 3 had jumps of 10 h kappa)."""
+    wl = W.random_medium(n, d, seed=seed)
+    tau = wl.tau
+    assert np.all(np.isfinite(tau))
+    assert tau[wl.src] == 0.0 and np.all(tau >= 0)
+    kap = np.sqrt(wl.kappa2)
+    for ax in range(d):
+        t0 = np.take(tau, np.arange(n - 1), axis=ax)
+        t1 = np.take(tau, np.arange(1, n), axis=ax)
+        k = np.maximum(np.take(kap, np.arange(n - 1), axis=ax), np.take(kap, np.arange(1, n), axis=ax))
+        assert np.max(np.abs(t1 - t0) / (wl.h * k)) <= 1.1 * (1 + 1e-12)
