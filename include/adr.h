@@ -113,7 +113,9 @@ typedef struct {
   int coarsest_max;     /* default 729                                                    */
   int nu[8];            /* relaxations per level (pre = post); default l+2 for 0-based    */
                         /* level l, i.e. 2 on the finest, 3 on the next (Sec. 4.2)        */
-  adr_relax relax[8];   /* default JACOBI on level 0, GMRES on coarser levels            */
+  adr_relax relax[8];   /* default JACOBI on level 0, GMRES on coarser levels (which    */
+                        /* must relax by GMRES); GMRES on level 0 is the paper's choice  */
+                        /* (Sec. 4.2), not with adjoint solves or rescaled cycles        */
   double jacobi_weight; /* default 0.8                                                    */
   double beta;          /* preconditioner blend of eq. precADRup; default 0.25 (Sec. 4.2) */
   int restart;          /* FGMRES restart length m; default 5 (Sec. 4.2); max 8           */
@@ -309,7 +311,8 @@ typedef enum {
   ADR_TIMER_TRANSFER = 4,       /* restriction and prolongation                           */
   ADR_TIMER_OUTER_MATVEC = 5,   /* FP64 H_2up apply with fused Arnoldi dots (FGMRES)      */
   ADR_TIMER_OUTER_ORTH = 6,     /* FP64 Gram-Schmidt passes of the outer FGMRES           */
-  ADR_TIMER_COARSE_TAIL = 7     /* single-workgroup coarse tail of the V-cycle            */
+  ADR_TIMER_COARSE_TAIL = 7,    /* single-workgroup coarse tail of the V-cycle            */
+  ADR_TIMER_FINE_GMRES = 8      /* matrix-free apply of the finest level's GMRES relaxation */
 } adr_timer_kind;
 
 /* Benchmark instrumentation.  adr_timer_start(ctx, kind, level) makes every later launch

@@ -22,7 +22,7 @@ ADR_ADV_UPWIND, ADR_ADV_CENTRAL = 0, 1
 ADR_REACTION_NUMERICAL, ADR_REACTION_EIKONAL = 0, 1
 ADR_NOALLOC_MAX_REC = 1 << 26
 TIMER_KINDS = {"fine_jacobi": 0, "fine_residual": 1, "coarse_apply": 2, "coarse_orth": 3, "transfer": 4,
-               "outer_matvec": 5, "outer_orth": 6, "coarse_tail": 7}
+               "outer_matvec": 5, "outer_orth": 6, "coarse_tail": 7, "fine_gmres": 8}
 
 
 class AdrProblem(ctypes.Structure):

@@ -419,6 +419,9 @@ bool pipelined_level(const adr_ctx *ctx, int l, size_t N) {
          ctx->relax[l] == ADR_RELAX_GMRES && ctx->nu[l] >= 1 && ctx->nu[l] <= 8;
 }
 
+// The finest level relaxes by GMRES (Sec. 4.2) instead of damped Jacobi.
+bool fine_gmres(const adr_ctx *ctx) { return ctx->levels > 1 && ctx->relax[0] == ADR_RELAX_GMRES; }
+
 template <typename T>
 adr_status alloc_level_vectors(adr_ctx *ctx, LevelT<T> &L, int l) {
   const size_t N = L.G.N;
@@ -426,6 +429,13 @@ adr_status alloc_level_vectors(adr_ctx *ctx, LevelT<T> &L, int l) {
   ADR_TRY(dalloc(ctx, &L.xt, N));
   ADR_TRY(dalloc(ctx, &L.b, N));
   ADR_TRY(dalloc(ctx, &L.r, N));
+  if (l == 0 && fine_gmres(ctx)) {
+    ADR_TRY(dalloc(ctx, &L.w, N));
+    ADR_TRY(dalloc(ctx, &L.V, N * (kMaxNu + 1)));
+    ADR_TRY(dalloc(ctx, &L.Z, N * (kMaxNu + 1)));
+    ADR_TRY(dalloc(ctx, &L.dinv, N));
+    adrk::fine_dinv<T>(ctx->stream, L.G, ctx->D, prec_coef<double>(ctx), fine_params(ctx, ctx->opt.beta), L.dinv);
+  }
   if (l > 0) {
     ADR_TRY(dalloc(ctx, &L.w, N));
     ADR_TRY(dalloc(ctx, &L.V, N * (kMaxNu + 1)));
@@ -477,6 +487,15 @@ void gmres_relax(adr_ctx *ctx, int l, const cx<T> *x0, const cx<T> *b, cx<T> *x_
     Zp[j] = L.Z + (size_t)j * N;
   }
   const cx<T> *planes = lvl_planes(ctx, L), *dinv = lvl_dinv(ctx, L);
+  // The operator: stored Galerkin planes on coarse levels, rows recomputed from the
+  // coefficient planes on the finest (its bytes per node: planes or coefficients).
+  const double opb = l == 0 ? fine_coef_bytes<T>(D) : cb * L.S;
+  auto level_apply = [&](const CoarseArgs<T> &a, const VecSet<T> *dots, bool want_norm) {
+    if (l == 0)
+      return adrk::fine_gapply<T>(s, D, prec_coef<T>(ctx), fine_params(ctx, ctx->opt.beta), a, dots, want_norm,
+                                  ctx->Pdev + 1);
+    return adrk::coarse_apply<T>(s, D, a, dots, want_norm);
+  };
   int cur = 0, nb;
   if (!x0) {
     Vp[0] = b;
@@ -495,9 +514,9 @@ void gmres_relax(adr_ctx *ctx, int l, const cx<T> *x0, const cx<T> *b, cx<T> *x_
     a.zout = Zp[0];
     a.mode = 1;
     a.pout = ctx->part[cur];
-    int t0 = tbegin(ctx, ADR_TIMER_COARSE_APPLY, l);
-    nb = adrk::coarse_apply<T>(s, D, a, nullptr, true);
-    tend(ctx, t0, (double)N * cb * (L.S + 5));
+    int t0 = tbegin(ctx, l == 0 ? ADR_TIMER_FINE_GMRES : ADR_TIMER_COARSE_APPLY, l);
+    nb = level_apply(a, nullptr, true);
+    tend(ctx, t0, (double)N * (opb + cb * 5));
   }
   if (L.Gs) {
     // Pipelined steps: the first apply, nu - 1 fused orthogonalization + apply steps and
@@ -572,9 +591,9 @@ void gmres_relax(adr_ctx *ctx, int l, const cx<T> *x0, const cx<T> *b, cx<T> *x_
     a.y = L.w;
     a.mode = 0;
     a.pout = ctx->part[cur ^ 1];
-    int t0 = tbegin(ctx, ADR_TIMER_COARSE_APPLY, l);
-    nb = adrk::coarse_apply<T>(s, D, a, &Vs, false);
-    tend(ctx, t0, (double)N * cb * (L.S + 2 + (j + 1)));
+    int t0 = tbegin(ctx, l == 0 ? ADR_TIMER_FINE_GMRES : ADR_TIMER_COARSE_APPLY, l);
+    nb = level_apply(a, &Vs, false);
+    tend(ctx, t0, (double)N * (opb + cb * (2 + (j + 1))));
     cur ^= 1;
     int t1 = tbegin(ctx, ADR_TIMER_COARSE_ORTH, l);
     nb = adrk::orth_step<T>(s, N, L.w, Vs, ProIn{ctx->part[cur], nb, 2 * (j + 1)}, sc + kS, hcol, dinv,
@@ -652,7 +671,8 @@ cx<T> *vcycle(adr_ctx *ctx, int l, const cx<T> *b, cx<T> *out0, ProIn bpin = Pro
   // iterate, ends in xa) and computes its residual with one more matrix-free apply; the
   // coarse levels' GMRES pre-relaxation also returns the residual in L.r.
   // (check_levels enforces this split.)
-  if (l == 0) {
+  const bool jacobi = l == 0 && !fine_gmres(ctx);
+  if (jacobi) {
     x = jacobi_sweeps<T>(ctx, ctx->nu[l], nullptr, b, L.xt, xa);
   } else {
     gmres_relax<T>(ctx, l, nullptr, b, xa, bpin, L.r);
@@ -660,7 +680,7 @@ cx<T> *vcycle(adr_ctx *ctx, int l, const cx<T> *b, cx<T> *out0, ProIn bpin = Pro
   }
   LevelT<T> &C = lv[l + 1];
   const double cb = sizeof(cx<T>);
-  if (l == 0) {
+  if (jacobi) {
     int t0 = tbegin(ctx, ADR_TIMER_FINE_RESIDUAL, 0);
     if (ctx->adj)
       adrk::fine_apply_adj<T, T, T>(s, L.G, D, prec_coef<T>(ctx), fine_params(ctx, ctx->opt.beta), x, b, L.r, 1,
@@ -687,7 +707,7 @@ cx<T> *vcycle(adr_ctx *ctx, int l, const cx<T> *b, cx<T> *out0, ProIn bpin = Pro
   adrk::prolong_add<T>(s, L.G, C.G, D, ec, x);
   tend(ctx, t2, cb * ((double)C.G.N + 2.0 * L.G.N));
   // post-relaxation
-  if (l == 0) {
+  if (jacobi) {
     cx<T> *other = (x == xa) ? L.xt : xa;
     return jacobi_sweeps<T>(ctx, ctx->nu[l], x, b, other, x);
   }
@@ -766,8 +786,8 @@ adr_status check_levels(adr_ctx *ctx) {
       ctx->err = "nu must be in [1, 8]";
       return ADR_EINVAL;
     }
-  if (ctx->levels > 1 && ctx->relax[0] == ADR_RELAX_GMRES) {
-    ctx->err = "GMRES relaxation on the matrix-free finest level is not implemented";
+  if (ctx->levels > 1 && ctx->relax[0] == ADR_RELAX_GMRES && ctx->opt.rescaled) {
+    ctx->err = "GMRES relaxation on the finest level of a rescaled cycle is not supported";
     return ADR_ENOTSUP;
   }
   return ADR_OK;
@@ -1533,6 +1553,10 @@ adr_status prepare_adjoint(adr_ctx *ctx) {
     ctx->err = "adjoint solves with a rescaled cycle are not supported";
     return ADR_ENOTSUP;
   }
+  if (ctx->levels > 1 && ctx->relax[0] == ADR_RELAX_GMRES) {
+    ctx->err = "adjoint solves with GMRES relaxation on the finest level are not supported";
+    return ADR_ENOTSUP;
+  }
   if (ctx->opt.prec == ADR_PREC_MIXED) ADR_TRY(prepare_adjoint_levels<float>(ctx));
   else ADR_TRY(prepare_adjoint_levels<double>(ctx));
   const int n = ctx->Ncoarsest;
@@ -2252,7 +2276,7 @@ void adr_destroy_batch(adr_batch *b) { free_batch(b); }
 constexpr int kTimerLaunches = 65536;   // launches one adr_timer_start can time
 
 adr_status adr_timer_start(adr_ctx *ctx, int kind, int level) {
-  if (!ctx || kind < 0 || kind > ADR_TIMER_COARSE_TAIL) return ADR_EINVAL;
+  if (!ctx || kind < 0 || kind > ADR_TIMER_FINE_GMRES) return ADR_EINVAL;
   auto &T = ctx->timer;
   if (T.ev.empty()) {
     T.ev.resize(2 * (size_t)kTimerLaunches);

@@ -1363,6 +1363,154 @@ template int coarse_apply<double>(hipStream_t, int, const CoarseArgs<double> &, 
 template int coarse_apply<float>(hipStream_t, int, const CoarseArgs<float> &, const VecSet<float> *, bool);
 
 // =====================================================================================
+// GMRES relaxation on the matrix-free finest level (Sec. 4.2: Jacobi-preconditioned GMRES
+// on every level).  The same contract as coarse_apply with the row recomputed from the
+// coefficient planes instead of read from stored Galerkin planes:
+// mode 0: y = s * (A x), s = 1/||.|| of the predecessor's partials (`pin`; block 0 stores
+//         the norm and the scale), or s = 1 without them;
+// mode 1: y = b - A x;
+// z = dinv o y when zout is given; partials: NV dots conj(V_v).y, then ||y||^2 if NORM.
+// =====================================================================================
+template <typename T, int D, int NV, bool NORM, bool GRP>
+__global__ __launch_bounds__(ADR_BLOCK) void k_fine_gapply(Grid G, FineCoef<T> C, FineParams P,
+                                                           const cx<T> *__restrict__ x, ProIn pin, double *norm_out,
+                                                           int norm_cplx, double *inv_out,
+                                                           const cx<T> *__restrict__ b, cx<T> *__restrict__ y,
+                                                           const cx<T> *__restrict__ dinv, cx<T> *__restrict__ zout,
+                                                           int mode, VecSet<T> V, double *pout, const FineParams *Pd,
+                                                           Shot sh) {
+  ADR_SHOT_ENTER(sh);
+  if constexpr (GRP) shift_fine_coef(C, shot_off_);
+  if constexpr (GRP) {
+    if (Pd) P = *shot_ptr(Pd, shot_off_);
+  }
+  ADR_SHIFT(x);
+  ADR_SHIFT(pin.partials);
+  ADR_SHIFT(norm_out);
+  ADR_SHIFT(inv_out);
+  ADR_SHIFT(b);
+  ADR_SHIFT(y);
+  ADR_SHIFT(dinv);
+  ADR_SHIFT(zout);
+  if constexpr (GRP) shift_set<NV>(V, shot_off_);
+  ADR_SHIFT(pout);
+  ADR_SHOT_LIVE(sh);
+  constexpr int K = 2 * NV + (NORM ? 1 : 0);
+  constexpr int KA = K > 0 ? K : 1;
+  __shared__ double tot[1];
+  T xs = T(1);
+  if (pin.partials) {
+    reduce_partials(pin.partials, pin.nb, 1, tot);
+    const double nrm = sqrt(tot[0]);
+    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    xs = (T)inv;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      norm_out[0] = nrm;
+      if (norm_cplx) norm_out[1] = 0.0;
+      *inv_out = inv;
+    }
+  }
+  double red[KA];
+#pragma unroll
+  for (int k = 0; k < KA; ++k) red[k] = 0.0;
+  int beg, end;
+  chunk_range(G.N, beg, end);
+  for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    int idx[3];
+    decode(G, i, idx[0], idx[1], idx[2]);
+    int nb[1 + 4 * D];
+    fine_neighbours<D>(G, i, idx, nb);
+    cx<T> xv[1 + 4 * D];
+#pragma unroll
+    for (int p = 0; p < 1 + 4 * D; ++p) xv[p] = x[nb[p]];
+    T gk[3], L;
+    cx<T> c;
+    load_fine_coef<T, D>(C, i, gk, L, c);
+    cx<T> e[1 + 4 * D];
+    fine_row<T, D>(G, P, idx, gk, L, c, e);
+    cx<T> acc = mk<T>(T(0), T(0));
+#pragma unroll
+    for (int p = 0; p < 1 + 4 * D; ++p) acc = cfma(e[p], xv[p], acc);
+    const cx<T> o = (mode == 0) ? xs * acc : b[i] - acc;
+    if (zout) zout[i] = o * dinv[i];
+    y[i] = o;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const cx<double> d = cdotc(cvt<double, T>(V.v[v][i]), cvt<double, T>(o));
+      red[2 * v] += d.re;
+      red[2 * v + 1] += d.im;
+    }
+    if (NORM) red[K - 1] += (double)o.re * o.re + (double)o.im * o.im;
+  }
+  if (K > 0) block_partials<KA>(red, K, pout);
+}
+
+template <typename T, int D, bool NORM>
+static void dispatch_fine_gapply(hipStream_t s, int nb, const FineCoef<T> &C, const FineParams &P,
+                                 const CoarseArgs<T> &a, const VecSet<T> &V, const FineParams *Pd) {
+  switch (V.count) {
+#define ADR_NV_CASE(n)                                                                                          \
+  case n:                                                                                                       \
+    launch_g(k_fine_gapply<T, D, n, NORM, false>, k_fine_gapply<T, D, n, NORM, true>, nb, s, a.G, C, P, a.x,    \
+             a.pin, a.norm_out, a.norm_cplx, a.inv_out, a.b, a.y, a.dinv, a.zout, a.mode, V, a.pout, Pd);       \
+    break;
+    ADR_NV_CASE(0) ADR_NV_CASE(1) ADR_NV_CASE(2) ADR_NV_CASE(3) ADR_NV_CASE(4) ADR_NV_CASE(5) ADR_NV_CASE(6)
+    ADR_NV_CASE(7) ADR_NV_CASE(8)
+#undef ADR_NV_CASE
+    default: break;
+  }
+}
+
+template <typename T>
+int fine_gapply(hipStream_t s, int D, const FineCoef<T> &C, const FineParams &P, const CoarseArgs<T> &a,
+                const VecSet<T> *dots, bool want_norm, const FineParams *Pd) {
+  VecSet<T> V{};
+  if (dots) V = *dots;
+  const bool red = want_norm || V.count > 0;
+  const int nb = red ? launch_blocks_red(a.G.N) : launch_blocks(a.G.N);
+  if (D == 2) {
+    if (want_norm) dispatch_fine_gapply<T, 2, true>(s, nb, C, P, a, V, Pd);
+    else dispatch_fine_gapply<T, 2, false>(s, nb, C, P, a, V, Pd);
+  } else {
+    if (want_norm) dispatch_fine_gapply<T, 3, true>(s, nb, C, P, a, V, Pd);
+    else dispatch_fine_gapply<T, 3, false>(s, nb, C, P, a, V, Pd);
+  }
+  return nb;
+}
+template int fine_gapply<double>(hipStream_t, int, const FineCoef<double> &, const FineParams &,
+                                 const CoarseArgs<double> &, const VecSet<double> *, bool, const FineParams *);
+template int fine_gapply<float>(hipStream_t, int, const FineCoef<float> &, const FineParams &,
+                                const CoarseArgs<float> &, const VecSet<float> *, bool, const FineParams *);
+
+// dinv = 1 / (diagonal entry of the fine row), from the FP64 coefficients (setup).
+template <typename T, int D>
+__global__ __launch_bounds__(ADR_BLOCK) void k_fine_dinv(Grid G, FineCoef<double> C, FineParams P,
+                                                         cx<T> *__restrict__ dinv) {
+  int beg, end;
+  chunk_range(G.N, beg, end);
+  for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
+    int idx[3];
+    decode(G, i, idx[0], idx[1], idx[2]);
+    double gk[3], L;
+    cx<double> c;
+    load_fine_coef<double, D>(C, i, gk, L, c);
+    cx<double> e[1 + 4 * D];
+    fine_row<double, D>(G, P, idx, gk, L, c, e);
+    const double den = e[0].re * e[0].re + e[0].im * e[0].im;
+    dinv[i] = cvt<T, double>(mk<double>(e[0].re / den, -e[0].im / den));
+  }
+}
+template <typename T>
+void fine_dinv(hipStream_t s, const Grid &G, int D, const FineCoef<double> &C, const FineParams &P, cx<T> *dinv) {
+  if (D == 2) ADR_LAUNCH((k_fine_dinv<T, 2>), launch_blocks(G.N), s, G, C, P, dinv);
+  else ADR_LAUNCH((k_fine_dinv<T, 3>), launch_blocks(G.N), s, G, C, P, dinv);
+}
+template void fine_dinv<double>(hipStream_t, const Grid &, int, const FineCoef<double> &, const FineParams &,
+                                cx<double> *);
+template void fine_dinv<float>(hipStream_t, const Grid &, int, const FineCoef<double> &, const FineParams &,
+                               cx<float> *);
+
+// =====================================================================================
 // Transfers: r_c = P^T r_f (nodal full weighting x 2^d), x_f += P e_c (bi/trilinear)
 // =====================================================================================
 // With pout: also z_c = dinv_c o r_c and the partials of ||r_c||^2 (the coarse

@@ -161,6 +161,14 @@ void copy(hipStream_t s, long long n, const cx<double> *in, cx<double> *out);
 // count.
 template <typename T>
 int coarse_apply(hipStream_t s, int D, const CoarseArgs<T> &a, const VecSet<T> *dots, bool want_norm);
+// The coarse_apply contract on the matrix-free finest level (a.planes and a.split unused):
+// GMRES relaxation there.  Pd: per-problem fine parameters of a shot group.
+template <typename T>
+int fine_gapply(hipStream_t s, int D, const FineCoef<T> &C, const FineParams &P, const CoarseArgs<T> &a,
+                const VecSet<T> *dots, bool want_norm, const FineParams *Pd);
+// dinv = 1 / diag(A_beta) of the fine operator, from the FP64 coefficients.
+template <typename T>
+void fine_dinv(hipStream_t s, const Grid &G, int D, const FineCoef<double> &C, const FineParams &P, cx<T> *dinv);
 
 // ---- transfers ---------------------------------------------------------------------
 // With pout (else NULL): also z_c = dinv_c o r_c and the partials of ||r_c||^2; returns
