@@ -55,7 +55,10 @@ def parse():
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-iters", type=int, default=8)
+    ap.add_argument("--no-257", action="store_true",
+                    help="default workload: skip the 3D 257^3 leg that carries the HBM roofline")
+    ap.add_argument("--cpu-sample-iters", type=int, default=60,
+                    help="iteration cap of the CPU oracle solve (default: enough for the 129^3 workload)")
     ap.add_argument("--cpu-sample-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--profile-only", action="store_true",
                     help="setup + warmup + timed steps only (for rocprofv3 runs)")
@@ -114,7 +117,9 @@ def make_workload(name):
 # CPU baseline: the FP64 oracle (NumPy/SciPy, one thread) on a bounded sample
 # --------------------------------------------------------------------------------------
 def cpu_sample_child(args):
-    """Runs in a child process with every BLAS/OpenMP pool limited to one thread."""
+    """Runs in a child process with every BLAS/OpenMP pool limited to one thread: the FP64
+    oracle's own FGMRES(5) + V-cycle on the full workload, from zero until the true relative
+    residual reaches the benchmark tolerance (or --cpu-sample-iters iterations)."""
     from oracle import krylov
     from oracle import solve as osolve
     wl = make_workload(args.workload)
@@ -138,17 +143,19 @@ def cpu_baseline(args, nodes, iters_needed):
            "--cpu-sample-iters", str(args.cpu_sample_iters)]
     out = subprocess.run(cmd, env=env, stdout=subprocess.PIPE, stderr=subprocess.PIPE, check=True, cwd=ROOT)
     r = json.loads(out.stdout.decode().strip().splitlines()[-1])
+    done = r["relres"] <= TOL
     per_iter = r["solve_s"] / max(r["iters"], 1)
-    est = per_iter * iters_needed
-    return {
-        "value": nodes / est / 1e6,
-        "unit": "Mpoints/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": (f"FP64 oracle FGMRES(5)+V-cycle on the full workload, {r['iters']} outer iterations in "
-                   f"{r['solve_s']:.1f} s ({per_iter:.2f} s/iteration, setup {r['setup_s']:.1f} s not counted), "
-                   f"scaled to the {iters_needed} iterations the FP64 solve needs to reach {TOL:g}"),
-    }
+    t = r["solve_s"] if done else per_iter * iters_needed
+    if done:
+        sample = (f"FP64 oracle FGMRES(5) + V-cycle (NumPy/SciPy, one thread) on the full workload: a whole solve "
+                  f"from zero to true relative residual {r['relres']:.2e} <= {TOL:g} in {r['iters']} iterations, "
+                  f"{r['solve_s']:.1f} s (setup {r['setup_s']:.1f} s not counted)")
+    else:
+        sample = (f"FP64 oracle FGMRES(5) + V-cycle (NumPy/SciPy, one thread) on the full workload: {r['iters']} "
+                  f"iterations in {r['solve_s']:.1f} s ({per_iter:.2f} s/iteration, setup {r['setup_s']:.1f} s not "
+                  f"counted), scaled to the {iters_needed} iterations the FP64 GPU solve needs to reach {TOL:g}")
+    return {"value": nodes / t / 1e6, "unit": "Mpoints/s", "cores": 1, "kind": "oracle", "sample": sample,
+            "whole_solve": done, **host_cpu()}
 
 
 # --------------------------------------------------------------------------------------
@@ -240,7 +247,8 @@ def run_adjoint(args):
 
 
 def looped_batch(shots, qs, outs, opts, maxit):
-    """The same shots one after another through adr_solve on the default stream."""
+    """The same shots one after another through adr_solve on the default stream; returns
+    (ms, total iterations, largest final true relative residual)."""
     import torch
 
     from paper_1712_06091_amd import adr
@@ -251,21 +259,48 @@ def looped_batch(shots, qs, outs, opts, maxit):
     torch.cuda.synchronize()
     log("looped warm-up done")
     t0 = time.perf_counter()
-    iters = 0
+    iters, worst = 0, 0.0
     for c, q, a in zip(ctxs, qs, outs):
         _, s1 = c.solve(q, tol=TOL, maxit=maxit, out=a)
         iters += s1["outer_iters"]
+        worst = max(worst, s1["relres"])
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3
     for c in ctxs:
         c.close()
-    return ms, iters
+    return ms, iters, worst
+
+
+def batched(shots, qs, outs, opts, args, maxit):
+    """One lockstep batched solve of every shot; returns (ms per batch, stats, setup s)."""
+    import torch
+
+    from paper_1712_06091_amd import adr
+    torch.cuda.synchronize()
+    s0 = time.perf_counter()
+    b = adr.Batch(shots, options=opts, nstreams=args.streams)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - s0
+    for _ in range(args.warmup):
+        b.solve(qs, outs, tol=TOL, maxit=maxit)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st, stats = b.solve(qs, outs, tol=TOL, maxit=maxit)
+        if st != adr.ADR_OK:
+            bad = [(i, s["outer_iters"], s["relres"]) for i, s in enumerate(stats) if not s["relres"] <= TOL]
+            raise RuntimeError(f"batched solve did not converge within {maxit} iterations: {bad[:8]}")
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    b.close()
+    return ms, stats, setup_s
 
 
 def run_batch(args):
     """64 2D shots (sizes from {257^2, 513^2, 1025^2}, random media, fast-marching tau):
-    one lockstep batched solve over several streams vs. the same shots solved one after
-    another; mixed precision, tol 1e-6."""
+    lockstep batched solves over several streams in mixed precision (the value) and in
+    FP64, against the same shots solved one after another in FP64 (adr_solve), all to the
+    same true relative residual 1e-6."""
     import numpy as np
     import torch
 
@@ -281,51 +316,39 @@ def run_batch(args):
     qs = [t(w.rhs(), torch.complex128) for w in wls]
     outs = [torch.empty(w.shape, dtype=torch.complex128, device=dev) for w in wls]
     nodes = sum(w.nodes for w in wls)
-    opts = adr.default_options(prec="mixed", cycle=args.cycle, **pipe_opt(args))
     maxit = args.batch_maxit
-    torch.cuda.synchronize()
-    s0 = time.perf_counter()
-    b = adr.Batch(shots, options=opts, nstreams=args.streams)
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - s0
-    log(f"batch setup {setup_s:.1f} s")
-    for _ in range(args.warmup):
-        b.solve(qs, outs, tol=TOL, maxit=maxit)
-    torch.cuda.synchronize()
-    log("batch warm-up done")
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        st, stats = b.solve(qs, outs, tol=TOL, maxit=maxit)
-        if st != adr.ADR_OK:
-            bad = [(i, s["outer_iters"], s["relres"]) for i, s in enumerate(stats) if not s["relres"] <= TOL]
-            raise RuntimeError(f"batched solve did not converge within {maxit} iterations: {bad[:8]}")
-        log("batch step done")
-    torch.cuda.synchronize()
-    ms_batch = (time.perf_counter() - t0) * 1e3 / args.steps
-    its = sorted(s["outer_iters"] for s in stats)
-    log(f"batched: {ms_batch:.1f} ms per batch; iterations min {its[0]} median {its[len(its) // 2]} max {its[-1]}")
-    b.close()
-    if args.no_looped:
-        ms_loop, iters_loop = float("nan"), 0
-    else:
-        ms_loop, iters_loop = looped_batch(shots, qs, outs, opts, maxit)
-    value = nodes / (ms_batch * 1e-3) / 1e6
-
+    legs = {}
+    for prec in ("mixed", "fp64"):
+        opts = adr.default_options(prec=prec, cycle=args.cycle, **pipe_opt(args))
+        ms, stats, setup_s = batched(shots, qs, outs, opts, args, maxit)
+        its = sorted(s["outer_iters"] for s in stats)
+        legs[prec] = {"value": nodes / (ms * 1e-3) / 1e6, "ms_per_step": ms, "setup_s": setup_s,
+                      "outer_iters": sum(its),
+                      "outer_iters_per_shot": {"min": its[0], "median": its[len(its) // 2], "max": its[-1]},
+                      "final_relres_max": max(s["relres"] for s in stats)}
+        log(f"batched {prec}: {ms:.1f} ms per batch; iterations min {its[0]} median {its[len(its) // 2]} "
+            f"max {its[-1]}")
+    looped = None
+    if not args.no_looped:
+        opts = adr.default_options(prec="fp64", cycle=args.cycle, **pipe_opt(args))
+        ms_loop, iters_loop, worst = looped_batch(shots, qs, outs, opts, maxit)
+        looped = {"precision": "fp64", "value": nodes / (ms_loop * 1e-3) / 1e6, "ms": ms_loop,
+                  "outer_iters": iters_loop, "final_relres_max": worst}
+        log(f"looped fp64: {ms_loop:.1f} ms")
+    m = legs["mixed"]
     out = {
         "metric": "ADR amplitude solves: Mpoints/s to 1e-6 residual (batched shots)",
-        "value": value, "unit": "Mpoints/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_batch, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "value": m["value"], "unit": "Mpoints/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": m["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "c64 V-cycle / c128 FGMRES", "data": "synthetic",
         "config": {"workload": "batch_2d_64_shots", "shots": len(wls), "nodes": nodes,
                    "sizes": sorted({w.shape[0] for w in wls}), "streams": args.streams, "tol": TOL,
                    "cycle": args.cycle, "maxit": maxit,
                    "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "0")) or None},
-        "looped": None if args.no_looped else {"value": nodes / (ms_loop * 1e-3) / 1e6, "ms": ms_loop,
-                                               "outer_iters": iters_loop},
-        "batched_over_looped": None if args.no_looped else ms_loop / ms_batch,
-        "outer_iters": sum(its),
-        "outer_iters_per_shot": {"min": its[0], "median": its[len(its) // 2], "max": its[-1]},
-        "setup_s": setup_s,
+        "batched_mixed": m, "batched_fp64": legs["fp64"], "looped_fp64": looped,
+        "batched_mixed_over_looped_fp64": None if looped is None else looped["ms"] / m["ms_per_step"],
+        "batched_fp64_over_looped_fp64": None if looped is None else looped["ms"] / legs["fp64"]["ms_per_step"],
+        "outer_iters": m["outer_iters"],
     }
     print(json.dumps(out))
 
@@ -402,6 +425,171 @@ def run_compare(args):
     }))
 
 
+def host_cpu():
+    """Host cores and model (the GPU machine's host, read at run time)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"host_cores": os.cpu_count(), "host_cpu": model}
+
+
+def gpu_tensors(wl):
+    import numpy as np
+    import torch
+    dev = torch.device("cuda:0")
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    return (t(wl.kappa2, torch.float64), t(wl.tau, torch.float64), t(wl.gamma, torch.float64),
+            t(wl.rhs(), torch.complex128))
+
+
+def make_ctx(wl, tensors, prec, args):
+    from paper_1712_06091_amd import adr
+    k2, tau, gam, _ = tensors
+    return adr.Context(k2, tau, gam, wl.h, wl.omega, wl.src,
+                       options=adr.default_options(prec=prec, cycle=args.cycle, use_graph=0 if args.no_graph else 1,
+                                                   coarse_split=args.coarse_split, **pipe_opt(args)))
+
+
+def solve_step(ctx, q, a, u, tol=TOL, maxit=3000):
+    """One benchmark step: a whole solve from zero to tol, then the wavefield."""
+    from paper_1712_06091_amd import adr
+    _, st = ctx.solve(q, tol=tol, maxit=maxit, out=a)
+    ctx.wavefield(a, out=u)
+    if st["status"] != adr.ADR_OK or not st["relres"] <= tol:
+        raise RuntimeError(f"solve did not converge: {st}")
+    return st
+
+
+def timed_solves(ctx, q, a, u, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        solve_step(ctx, q, a, u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sts = [solve_step(ctx, q, a, u) for _ in range(steps)]
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps, sts
+
+
+def level1_roofline(ctx, q, a, u, workload, cache_note=None):
+    """The dominant kernel, the 81/21-point Galerkin apply on level 1 (plain launches and
+    the pipelined relaxation steps that carry it), timed by the library's HIP events on the
+    context stream over one whole mixed solve."""
+    ctx.timer_start("coarse_apply", 1)
+    solve_step(ctx, q, a, u)
+    ms, n, by = ctx.timer_stop()
+    avg_ms = ms / max(n, 1)
+    avg_bytes = by / max(n, 1)
+    achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
+    shape, S = ctx.level_info(1)
+    traffic = measured_traffic(workload)
+    out = {"bound": "hbm", "workload": workload,
+           "kernel": (f"k_coarse_apply + k_pipe_step (level 1, {'x'.join(map(str, shape))}, {S}-point Galerkin "
+                      "stencil, c64)"),
+           "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+           "traffic": traffic["level1"] if traffic else None, "avg_launch_ms": avg_ms, "launches": n,
+           "algorithmic_bytes_per_launch": avg_bytes}
+    if cache_note:
+        out["note"] = cache_note
+    return out
+
+
+def vcycle_figures(ctx, shape, workload, reps=20):
+    """One V-cycle: algorithmic bytes summed over its kernel classes (library HIP events),
+    time by torch events around `reps` cycles on the current stream (the context's)."""
+    import torch
+    from paper_1712_06091_amd import adr
+    classes = list(adr.TIMER_KINDS)
+    r = torch.randn(shape, dtype=torch.complex128, device="cuda:0")
+    z = torch.empty_like(r)
+    vc_bytes = 0.0
+    for cls in classes[:5]:
+        ctx.timer_start(cls)
+        ctx.vcycle(r, out=z)
+        _, _, by = ctx.timer_stop()
+        vc_bytes += by
+    for _ in range(3):
+        ctx.vcycle(r, out=z)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        ctx.vcycle(r, out=z)
+    e1.record()
+    torch.cuda.synchronize()
+    vc_ms = e0.elapsed_time(e1) / reps
+    traffic = measured_traffic(workload)
+    gbps = vc_bytes / (vc_ms * 1e-3) / 1e9
+    return {"ms": vc_ms, "algorithmic_bytes": vc_bytes, "GBps": gbps, "frac": gbps / HBM_PEAK_GBPS,
+            "traffic": traffic["vcycle"] if traffic else None}
+
+
+def accuracy(ctx64, q, a_mixed, a_fp64):
+    """Errors of the benchmark results against an FP64 solve to 1e-10 (whose true residual
+    the GPU tests check with the oracle's matrix)."""
+    import torch
+    ref, st = ctx64.solve(q, tol=1e-10, maxit=5000)
+    nr = torch.linalg.vector_norm(ref).item()
+    return {"reference": "FP64 GPU solve to true relative residual 1e-10", "reference_relres": st["relres"],
+            "mixed_rel_l2": torch.linalg.vector_norm(a_mixed - ref).item() / nr,
+            "fp64_rel_l2": torch.linalg.vector_norm(a_fp64 - ref).item() / nr}
+
+
+def hbm_leg(args):
+    """3D 257^3 random medium (fast-marching tau): where the working set exceeds the
+    256 MB Infinity Cache, so the level-1 apply and the V-cycle are HBM-bound.  A few whole
+    solves in each precision, the level-1 roofline, the V-cycle fraction."""
+    import torch
+    wl = make_workload("3d_257")
+    tens = gpu_tensors(wl)
+    q = tens[3]
+    a = torch.empty(wl.shape, dtype=torch.complex128, device="cuda:0")
+    u = torch.empty_like(a)
+    a64 = torch.empty_like(a)
+    s0 = time.perf_counter()
+    ctx = make_ctx(wl, tens, "mixed", args)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - s0) * 1e3
+    ms_m, st_m = timed_solves(ctx, q, a, u, 2, 1)
+    log(f"3d_257 mixed: {ms_m:.1f} ms/solve, {st_m[-1]['outer_iters']} iterations")
+    levels = ctx.num_levels
+    splits = [ctx.level_split(l) for l in range(1, levels - 1)]
+    roof = level1_roofline(ctx, q, a, u, "3d_257")
+    vc = vcycle_figures(ctx, wl.shape, "3d_257")
+    log(f"3d_257 level-1 apply {roof['avg_launch_ms'] * 1e3:.1f} us/launch ({roof['frac']:.3f}); "
+        f"V-cycle {vc['ms']:.3f} ms ({vc['frac']:.3f})")
+    ctx.close()
+    kc = None
+    if args.cycle == "v":
+        # The Krylov cycle on the same problem (fewer iterations at this size).
+        ka = argparse.Namespace(**{**vars(args), "cycle": "k"})
+        ck = make_ctx(wl, tens, "mixed", ka)
+        ms_k, st_k = timed_solves(ck, q, a, u, 1, 1)
+        ck.close()
+        kc = {"value": wl.nodes / (ms_k * 1e-3) / 1e6, "ms_per_step": ms_k, "outer_iters": st_k[-1]["outer_iters"],
+              "final_relres": st_k[-1]["relres"]}
+        log(f"3d_257 mixed Krylov cycle: {ms_k:.1f} ms/solve, {st_k[-1]['outer_iters']} iterations")
+    c64 = make_ctx(wl, tens, "fp64", args)
+    ms_d, st_d = timed_solves(c64, q, a64, u, 1, 0)
+    log(f"3d_257 fp64: {ms_d:.1f} ms/solve, {st_d[-1]['outer_iters']} iterations")
+    acc = accuracy(c64, q, a, a64)
+    c64.close()
+    N = wl.nodes
+    return {"workload": wl.name, "grid": list(wl.shape), "nodes": N, "omega": wl.omega, "levels": levels,
+            "coarse_splits": splits,
+            "value": N / (ms_m * 1e-3) / 1e6, "ms_per_step": ms_m, "outer_iters": st_m[-1]["outer_iters"],
+            "final_relres": st_m[-1]["relres"],
+            "fp64": {"value": N / (ms_d * 1e-3) / 1e6, "ms_per_step": ms_d, "outer_iters": st_d[-1]["outer_iters"]},
+            "mixed_over_fp64": ms_d / ms_m, "accuracy": acc, "setup_ms": setup_ms, "vcycle": vc,
+            "roofline": roof, "kcycle_mixed": kc}
+
+
 def main():
     args = parse()
     if args.hw_queues:
@@ -429,18 +617,16 @@ def main():
         run_compare(args)
         return
 
-    import numpy as np
     import torch
 
     from paper_1712_06091_amd import adr
 
-    dev = torch.device("cuda:0")
     wl = make_workload(args.workload)
     N = wl.nodes
-    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
-    k2, tau, gam = t(wl.kappa2, torch.float64), t(wl.tau, torch.float64), t(wl.gamma, torch.float64)
-    q = t(wl.rhs(), torch.complex128)
-    a = torch.empty(wl.shape, dtype=torch.complex128, device=dev)
+    tens = gpu_tensors(wl)
+    q = tens[3]
+    a = torch.empty(wl.shape, dtype=torch.complex128, device="cuda:0")
+    a64 = torch.empty_like(a)
     u = torch.empty_like(a)
     torch.cuda.synchronize()
 
@@ -448,87 +634,42 @@ def main():
     for prec in (("mixed",) if args.mixed_only else ("mixed", "fp64")):
         torch.cuda.synchronize()
         s0 = time.perf_counter()
-        ctxs[prec] = adr.Context(k2, tau, gam, wl.h, wl.omega, wl.src,
-                                 options=adr.default_options(prec=prec, cycle=args.cycle,
-                                                             use_graph=0 if args.no_graph else 1,
-                                                             coarse_split=args.coarse_split,
-                                                             **pipe_opt(args)))
+        ctxs[prec] = make_ctx(wl, tens, prec, args)
         torch.cuda.synchronize()
         setup_ms[prec] = (time.perf_counter() - s0) * 1e3
         log(f"setup {prec}: {setup_ms[prec]:.0f} ms, {ctxs[prec].num_levels} levels")
 
-    def step(ctx):
-        _, st = ctx.solve(q, tol=TOL, maxit=500, out=a)
-        ctx.wavefield(a, out=u)
-        if st["status"] != adr.ADR_OK or not st["relres"] <= TOL:
-            raise RuntimeError(f"solve did not converge: {st}")
-        return st
-
-    def timed(ctx, steps, warmup):
-        for _ in range(warmup):
-            step(ctx)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sts = [step(ctx) for _ in range(steps)]
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) * 1e3 / steps, sts
-
-    ms_mixed, st_mixed = timed(ctxs["mixed"], args.steps, args.warmup)
+    ms_mixed, st_mixed = timed_solves(ctxs["mixed"], q, a, u, args.steps, args.warmup)
     log(f"mixed: {ms_mixed:.2f} ms/solve, {st_mixed[-1]['outer_iters']} iterations")
     if args.profile_only and args.mixed_only:
         print(json.dumps({"ms_mixed": ms_mixed}))
         return
-    ms_fp64, st_fp64 = timed(ctxs["fp64"], max(1, min(args.steps, 3)), 1)
+    ms_fp64, st_fp64 = timed_solves(ctxs["fp64"], q, a64, u, max(1, min(args.steps, 3)), 1)
     log(f"fp64: {ms_fp64:.2f} ms/solve, {st_fp64[-1]['outer_iters']} iterations")
     if args.profile_only:
         print(json.dumps({"ms_mixed": ms_mixed, "ms_fp64": ms_fp64}))
         return
 
     # Kernel-class breakdown of one mixed solve (HIP events around each launch of a class,
-    # on the context stream), then the V-cycle alone.
-    classes = list(adr.TIMER_KINDS)
-    breakdown = {}
+    # on the context stream).
     ctx = ctxs["mixed"]
-    for cls in classes:
+    breakdown = {}
+    for cls in adr.TIMER_KINDS:
         ctx.timer_start(cls)
-        step(ctx)
+        solve_step(ctx, q, a, u)
         ms, n, by = ctx.timer_stop()
         breakdown[cls] = {"ms": ms, "launches": n, "bytes": by}
-    # Dominant kernel: the Galerkin 81-point stencil apply on level 1 (the first coarse
-    # grid), the largest single contributor to the solve: its plain launches and the
-    # pipelined relaxation steps that carry it.
-    ctx.timer_start("coarse_apply", 1)
-    step(ctx)
-    dm_ms, dm_n, dm_bytes = ctx.timer_stop()
-    avg_ms = dm_ms / max(dm_n, 1)
-    avg_bytes = dm_bytes / max(dm_n, 1)
-    achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
-    lvl1_shape, lvl1_S = ctx.level_info(1)
-    dominant = (f"k_coarse_apply + k_pipe_step (level 1, {'x'.join(map(str, lvl1_shape))}, {lvl1_S}-point "
-                "Galerkin stencil, c64)")
+    workload_key = args.workload
+    cache_note = None
+    if args.workload == "3d_129":
+        cache_note = ("cache-resident: the level-1 planes (178 MB) fit in the 256 MB Infinity Cache, so this is "
+                      "not an HBM figure; the HBM roofline is the 3D 257^3 one")
+    roof = level1_roofline(ctx, q, a, u, workload_key, cache_note)
+    vc = vcycle_figures(ctx, wl.shape, workload_key)
+    log(f"breakdown done; level-1 apply {roof['avg_launch_ms'] * 1e3:.1f} us/launch; V-cycle {vc['ms']:.3f} ms")
+    acc = accuracy(ctxs["fp64"], q, a, a64)
+    log(f"accuracy vs FP64 1e-10: mixed {acc['mixed_rel_l2']:.2e}, fp64 {acc['fp64_rel_l2']:.2e}")
 
-    # V-cycle alone: algorithmic bytes summed over its kernel classes, time by events.
-    r = torch.randn(wl.shape, dtype=torch.complex128, device=dev)
-    z = torch.empty_like(r)
-    vc_bytes = 0.0
-    for cls in classes[:5]:
-        ctx.timer_start(cls)
-        ctx.vcycle(r, out=z)
-        _, _, by = ctx.timer_stop()
-        vc_bytes += by
-    reps = 20
-    for _ in range(3):
-        ctx.vcycle(r, out=z)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(reps):
-        ctx.vcycle(r, out=z)
-    e1.record()
-    torch.cuda.synchronize()
-    vc_ms = e0.elapsed_time(e1) / reps
-
-    traffic = measured_traffic(args.workload)
     iters_m = st_mixed[-1]["outer_iters"]
     iters_d = st_fp64[-1]["outer_iters"]
     value = N / (ms_mixed * 1e-3) / 1e6
@@ -547,29 +688,33 @@ def main():
         "dtype": "c64 V-cycle / c128 FGMRES",
         "data": "synthetic",
         "config": {"workload": wl.name, "grid": list(wl.shape), "nodes": N, "omega": wl.omega,
-                   "tol": TOL, "restart": 5, "levels": ctx.num_levels, "precision": "mixed",
+                   "tol": TOL, "restart": 5, "levels": ctx.num_levels, "precision": "mixed", "cycle": args.cycle,
                    "coarse_splits": [ctx.level_split(l) for l in range(1, ctx.num_levels - 1)]},
         "fp64": {"value": fp64_value, "ms_per_step": ms_fp64, "outer_iters": iters_d},
         "mixed_over_fp64": value / fp64_value,
         "outer_iters": iters_m,
         "final_relres": st_mixed[-1]["relres"],
+        "accuracy": acc,
         "setup_ms": setup_ms,
-        "vcycle": {"ms": vc_ms, "algorithmic_bytes": vc_bytes, "GBps": vc_bytes / (vc_ms * 1e-3) / 1e9,
-                   "frac": vc_bytes / (vc_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
-                   "traffic": traffic["vcycle"] if traffic else None},
-        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic["level1"] if traffic else None,
-                     "avg_launch_ms": avg_ms, "launches": dm_n, "algorithmic_bytes_per_launch": avg_bytes},
+        "vcycle": vc,
+        "roofline": roof,
         "breakdown_ms": {c: round(v["ms"], 4) for c, v in breakdown.items()},
         "breakdown_launches": {c: v["launches"] for c, v in breakdown.items()},
         "breakdown_truncated": [c for c, v in breakdown.items() if v["launches"] >= TIMER_LAUNCHES],
     }
-    log(f"breakdown done; level-1 apply {avg_ms * 1e3:.1f} us/launch; V-cycle {vc_ms:.3f} ms")
+    for c in ctxs.values():
+        c.close()
+    if args.workload == "3d_129" and not args.no_257:
+        # The HBM roofline claim: the same kernels where the working set exceeds the cache.
+        leg = hbm_leg(args)
+        out["roofline_3d_129"] = out["roofline"]
+        out["vcycle_3d_129"] = out["vcycle"]
+        out["roofline"] = leg.pop("roofline")
+        out["vcycle"] = leg.pop("vcycle")
+        out["hbm_3d_257"] = leg
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, one thread) ...")
         out["cpu_baseline"] = cpu_baseline(args, N, iters_d)
-    for c in ctxs.values():
-        c.close()
     print(json.dumps(out))
 
 
