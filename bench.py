@@ -575,6 +575,19 @@ def hbm_leg(args):
         kc = {"value": wl.nodes / (ms_k * 1e-3) / 1e6, "ms_per_step": ms_k, "outer_iters": st_k[-1]["outer_iters"],
               "final_relres": st_k[-1]["relres"]}
         log(f"3d_257 mixed Krylov cycle: {ms_k:.1f} ms/solve, {st_k[-1]['outer_iters']} iterations")
+    # The travel time itself on the GPU (factored-eikonal sweeps) against the CPU fast
+    # marching that produced the workload's tau.
+    from paper_1712_06091_amd import adr
+    torch.cuda.synchronize()
+    e0 = time.perf_counter()
+    tau_gpu, sweeps = adr.eikonal(tens[0], wl.h, wl.src)
+    torch.cuda.synchronize()
+    eik = {"gpu_ms": (time.perf_counter() - e0) * 1e3, "sweeps": sweeps, "cpu_fast_marching_s": wl.extra.get("fm_s"),
+           "max_abs_diff_vs_fast_marching": torch.max(torch.abs(tau_gpu - tens[1])).item(),
+           "median_abs_diff_vs_fast_marching": torch.median(torch.abs(tau_gpu - tens[1])).item(),
+           "max_tau": torch.max(tens[1]).item()}
+    del tau_gpu
+    log(f"3d_257 GPU eikonal: {eik['gpu_ms']:.1f} ms, {sweeps} sweeps (CPU fast marching {eik['cpu_fast_marching_s']} s)")
     c64 = make_ctx(wl, tens, "fp64", args)
     ms_d, st_d = timed_solves(c64, q, a64, u, 1, 0)
     log(f"3d_257 fp64: {ms_d:.1f} ms/solve, {st_d[-1]['outer_iters']} iterations")
@@ -587,7 +600,7 @@ def hbm_leg(args):
             "final_relres": st_m[-1]["relres"],
             "fp64": {"value": N / (ms_d * 1e-3) / 1e6, "ms_per_step": ms_d, "outer_iters": st_d[-1]["outer_iters"]},
             "mixed_over_fp64": ms_d / ms_m, "accuracy": acc, "setup_ms": setup_ms, "vcycle": vc,
-            "roofline": roof, "kcycle_mixed": kc}
+            "roofline": roof, "kcycle_mixed": kc, "eikonal": eik}
 
 
 def main():

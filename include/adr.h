@@ -302,6 +302,25 @@ int adr_batch_size(const adr_batch *b);
 adr_ctx *adr_batch_context(adr_batch *b, int i);   /* borrowed; owned by the batch */
 void adr_destroy_batch(adr_batch *b);               /* NULL is a no-op */
 
+/* First-arrival travel time for the ADR coefficients, on the GPU: the factored eikonal
+ * equation |tau0 grad tau1 + tau1 grad tau0|^2 = kappa^2, tau = tau0 tau1, tau0 = |x - x0|
+ * (Sec. 1, eq. factoredEikonal), discretized with first-order one-sided differences of
+ * tau1 towards the upwind neighbour of each axis and solved by fixed-point sweeps (the
+ * parallel counterpart of the paper's factored fast marching): every sweep recomputes all
+ * nodes from the previous sweep's values and keeps the smaller value, until a sweep
+ * changes nothing.  Each node's candidate uses the largest set of axes with a causal
+ * root, is held to tau_i <= tau_j + 1.1 h max(kappa_i, kappa_j) over its neighbours, and
+ * falls back to the unfactored first-order Godunov update where that fails.
+ * n[k], src[k]: HOST int arrays, axis 0 = x (as in adr_problem); kappa2: DEVICE, N
+ * doubles (N = product of n); tau: DEVICE output, N doubles (tau(src) = 0); work: DEVICE
+ * scratch of N + 1 doubles owned by the caller; max_sweeps >= 1; *sweeps (host, may be
+ * NULL) = the number of sweeps that changed a value.  Enqueued on `stream` (hipStream_t,
+ * NULL = default); synchronizes it every 32 sweeps.  ADR_ENOCONV if max_sweeps sweeps
+ * all changed something (tau holds the last iterate); ADR_EINVAL for bad sizes or a
+ * source outside the grid (message in adr_last_error(NULL)). */
+adr_status adr_eikonal(int ndim, const int *n, double h, const double *kappa2, const int *src, double *tau,
+                       double *work, int max_sweeps, int *sweeps, void *stream);
+
 /* Kernel classes that adr_timer_start can time. */
 typedef enum {
   ADR_TIMER_FINE_JACOBI = 0,    /* damped Jacobi sweep on the matrix-free finest level    */

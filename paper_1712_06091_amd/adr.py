@@ -116,6 +116,8 @@ def load_library(path=LIB_PATH):
         "adr_receiver_residual": (I, [P, P, P, P, I, P, ctypes.POINTER(ctypes.c_double)]),
         "adr_receiver_residual_noalloc": (I, [P, P, P, I, P, ctypes.POINTER(ctypes.c_double), P]),
         "adr_adjoint_source": (I, [P, P, P, I, P]),
+        "adr_eikonal": (I, [I, ctypes.POINTER(ctypes.c_int), D, P, ctypes.POINTER(ctypes.c_int), P, P, I,
+                            ctypes.POINTER(ctypes.c_int), P]),
         "adr_setup_batch": (I, [I, ctypes.POINTER(AdrProblem), ctypes.POINTER(AdrOptions), I, ctypes.POINTER(P)]),
         "adr_solve_batch": (I, [P, ctypes.POINTER(P), ctypes.POINTER(P), D, I, ctypes.POINTER(AdrStats)]),
         "adr_batch_size": (I, [P]),
@@ -190,6 +192,23 @@ def receiver_residual_noalloc(u, idx, d, out, stream=None):
                                              _dev(d, torch.complex128), int(idx.numel()),
                                              _dev(out, torch.complex128), ctypes.byref(J), _stream_ptr(stream)))
     return out, J.value
+
+
+def eikonal(kappa2, h, src, max_sweeps=100000, stream=None):
+    """adr_eikonal: first-arrival travel time (float64 tensor of kappa2's shape) from the
+    source node ``src`` (NumPy axis order) by factored-eikonal sweeps on the GPU; returns
+    (tau, sweeps that changed a value)."""
+    import torch
+    lib = load_library()
+    d = kappa2.dim()
+    n = (ctypes.c_int * 3)(*[kappa2.shape[d - 1 - k] if k < d else 1 for k in range(3)])
+    s = (ctypes.c_int * 3)(*[int(src[d - 1 - k]) if k < d else 0 for k in range(3)])
+    tau = torch.empty_like(kappa2)
+    work = torch.empty(kappa2.numel() + 1, dtype=torch.float64, device=kappa2.device)
+    sweeps = ctypes.c_int()
+    _check(lib.adr_eikonal(d, n, float(h), _dev(kappa2, torch.float64), s, _dev(tau, torch.float64),
+                           _dev(work, torch.float64), int(max_sweeps), ctypes.byref(sweeps), _stream_ptr(stream)))
+    return tau, sweeps.value
 
 
 def _check(status, ctx_ptr=None):

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libadr.so")
 FM_LIB = os.path.join(HERE, "libfm.so")
-SOURCES = ["adr_kernels.hip", "adr_api.hip"]
+SOURCES = ["adr_kernels.hip", "adr_api.hip", "adr_eikonal.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

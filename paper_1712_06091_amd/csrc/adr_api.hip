@@ -2324,3 +2324,7 @@ const char *adr_strerror(adr_status s) {
 const char *adr_last_error(const adr_ctx *ctx) { return ctx ? ctx->err.c_str() : g_setup_error.c_str(); }
 
 }  // extern "C"
+
+namespace adrk {
+void set_global_error(const std::string &e) { g_setup_error = e; }
+}  // namespace adrk

@@ -13,6 +13,7 @@ Arrays are C-ordered with the last axis = x (fastest); axis 0 is depth (y in 2D,
 """
 import ctypes
 import os
+import time
 from dataclasses import dataclass, field
 from typing import Optional, Tuple
 
@@ -203,10 +204,12 @@ def random_medium(n, ndim, seed, src_frac=None, ppw=10.0, absorb=True, name="ran
     src = tuple(int(round(f / h)) for f in reversed(src_frac))
     v = smooth_random_velocity(shape, h, seed)
     kappa2 = 1.0 / v ** 2
+    t0 = time.perf_counter()
     tau = factored_traveltime(kappa2, h, src, order=order)
+    fm_s = time.perf_counter() - t0
     omega = omega_for_ppw(float(v.min()), h, ppw)
     gamma = absorbing_layer(shape, h, omega, 10 * h) if absorb else None
-    return Workload(name, shape, h, omega, src, kappa2, tau, gamma, extra={"seed": seed})
+    return Workload(name, shape, h, omega, src, kappa2, tau, gamma, extra={"seed": seed, "fm_s": fm_s})
 
 
 def config_3d_257():
