@@ -125,9 +125,11 @@ typedef struct {
                         /* residual is <= this times the initial one; default 0.1       */
                         /* (Sec. 4.2.2); 0 always takes both steps                       */
   int coarse_split;     /* Galerkin-stencil apply on coarse levels: 1 = one lane per     */
-                        /* node, 4 = four wavefronts per 64 nodes, 0 (default) = the     */
-                        /* faster of the two per level, timed at setup and cached per    */
-                        /* grid shape and precision for the process                      */
+                        /* node, 4 = four wavefronts per 64 nodes, 8 = LDS z-marching    */
+                        /* tiles (3D complex-FP32 levels with rows of <= 129 nodes and   */
+                        /* >= 8 planes per slab; one lane elsewhere), 0 (default) = the  */
+                        /* fastest per level, timed at setup and cached per grid shape   */
+                        /* and precision for the process                                 */
   int tail_max_nodes;   /* V-cycle: coarse levels from the first one with at most this   */
                         /* many nodes down to the coarsest in one single-workgroup       */
                         /* kernel.  Disabled: must be 0 (the default); any other value   */
@@ -266,7 +268,7 @@ adr_status adr_get_coefficients(adr_ctx *ctx, double *g, double *L, void *c_c128
 adr_status adr_level_info(adr_ctx *ctx, int level, int *nodes, int *stencil_points);
 
 /* Galerkin-apply variant in use on coarse level `level`, 1 <= level <= levels - 2 (host
- * out-param): 1 = one lane per node, 4 = four wavefronts per 64 nodes
+ * out-param): 1 = one lane per node, 4 = four wavefronts per 64 nodes, 8 = LDS tiles
  * (adr_options.coarse_split, or the setup-time timing when that is 0).  ADR_EINVAL for
  * the fine level, the coarsest level (solved by its dense inverse), a level out of range
  * or a NULL pointer. */

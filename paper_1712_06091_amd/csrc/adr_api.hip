@@ -828,8 +828,8 @@ adr_status validate(const adr_problem *p, const adr_options *o, std::string &err
     err = "the single-workgroup coarse tail is disabled (tail_max_nodes must be 0)";
     return ADR_ENOTSUP;
   }
-  if (o->coarse_split != 0 && o->coarse_split != 1 && o->coarse_split != 4) {
-    err = "coarse_split must be 0, 1 or 4";
+  if (o->coarse_split != 0 && o->coarse_split != 1 && o->coarse_split != 4 && o->coarse_split != 8) {
+    err = "coarse_split must be 0, 1, 4 or 8";
     return ADR_EINVAL;
   }
   if (!(o->kcycle_threshold >= 0.0)) { err = "kcycle_threshold must be >= 0"; return ADR_EINVAL; }
@@ -867,17 +867,20 @@ int auto_levels(int D, const int n[3], int coarsest_max) {
   return levels;
 }
 
-// Galerkin-apply variant per coarse level (one lane per node, or four wavefronts per
-// 64 nodes): adr_options.coarse_split if set, else a short timing on this level (mode 0
-// with one fused dot, as in the GMRES relaxation) in which the four-wavefront variant
-// has to beat the one-lane variant by 10%, so that near ties do not flip from run to run.
+// Galerkin-apply variant per coarse level (one lane per node, four wavefronts per 64
+// nodes, or -- 3D FP32 levels with rows of at most 129 nodes -- LDS z-marching tiles):
+// adr_options.coarse_split if set (8 falls back to one lane where the tiles do not
+// apply), else a short timing on this level (mode 0 with one fused dot, as in the GMRES
+// relaxation) in which a variant has to beat the best one before it by 10%, so that near
+// ties do not flip from run to run.
 // The choice is cached per grid shape and precision for the life of the process, so
 // every context on a given shape launches the same kernels and sums in the same order.
 template <typename T>
 adr_status tune_split(adr_ctx *ctx, int l) {
   LevelT<T> &L = levels_of<T>(ctx)[l];
-  if (ctx->opt.coarse_split == 1 || ctx->opt.coarse_split == 4) {
-    L.split = ctx->opt.coarse_split;
+  const bool lds_ok = sizeof(T) == 4 && adrk::lds_blocks(L.G, ctx->D) > 0;
+  if (ctx->opt.coarse_split == 1 || ctx->opt.coarse_split == 4 || ctx->opt.coarse_split == 8) {
+    L.split = (ctx->opt.coarse_split == 8 && !lds_ok) ? 1 : ctx->opt.coarse_split;
     return ADR_OK;
   }
   static std::mutex mu;
@@ -901,7 +904,8 @@ adr_status tune_split(adr_ctx *ctx, int l) {
   VecSet<T> V1 = vecset<T>({L.r});
   float best_ms = 0.f;
   int best = 1;
-  for (int split : {1, 4}) {
+  for (int split : {1, 4, 8}) {
+    if (split == 8 && !lds_ok) continue;
     CoarseArgs<T> a{};
     a.split = split;
     a.G = L.G;
@@ -1197,7 +1201,7 @@ adr_status setup_impl(adr_ctx *ctx, const adr_problem *p) {
   }
   ADR_HIP(hipGetLastError());
   // Reduction scratch and scalars.
-  for (int i = 0; i < 2; ++i) ADR_TRY(dalloc(ctx, &ctx->part[i], (size_t)ADR_MAX_RED_BLOCKS * ADR_MAX_RED));
+  for (int i = 0; i < 2; ++i) ADR_TRY(dalloc(ctx, &ctx->part[i], (size_t)ADR_PART_BLOCKS * ADR_MAX_RED));
   ADR_TRY(dalloc(ctx, &ctx->scal, (size_t)kMaxLevels * kScalPerLevel));
   ADR_HIP(hipMemsetAsync(ctx->scal, 0, sizeof(double) * kMaxLevels * kScalPerLevel, s));
   ADR_TRY(dalloc(ctx, &ctx->osc, 64));

@@ -129,6 +129,9 @@ __device__ __forceinline__ void chunk_range(int N, int &beg, int &end) {
 // own.  (Device-scope fences and atomics would serialize through memory across the 8
 // XCDs; a separate one-block finish kernel costs a launch per reduction.)
 // ------------------------------------------------------------------------------------
+// Reduction partial buffers hold ADR_PART_BLOCKS blocks; most reducing kernels launch at
+// most ADR_MAX_RED_BLOCKS, the LDS-tiled Galerkin apply up to ADR_PART_BLOCKS.
+#define ADR_PART_BLOCKS 1024
 #ifndef ADR_MAX_RED_BLOCKS
 #define ADR_MAX_RED_BLOCKS 512
 #endif

@@ -44,7 +44,8 @@ struct CoarseArgs {
   cx<T> *zout;
   int mode;
   double *pout;          // partials (when reducing)
-  int split;             // 4: four wavefronts share each node's stencil sum; else one lane
+  int split;             // 4: four wavefronts share each node's stencil sum; 8: LDS z-marching
+                         // tiles (3D FP32, see lds_blocks); else one lane
 };
 
 // Coarse tail (one workgroup): per-level data and the level range.
@@ -161,6 +162,8 @@ void copy(hipStream_t s, long long n, const cx<double> *in, cx<double> *out);
 // count.
 template <typename T>
 int coarse_apply(hipStream_t s, int D, const CoarseArgs<T> &a, const VecSet<T> *dots, bool want_norm);
+// Blocks of the LDS z-marching Galerkin apply (split 8) on grid G, 0 where it does not apply.
+int lds_blocks(const Grid &G, int D);
 // The coarse_apply contract on the matrix-free finest level (a.planes and a.split unused):
 // GMRES relaxation there.  Pd: per-problem fine parameters of a shot group.
 template <typename T>

@@ -61,14 +61,18 @@ def test_cycle_fp64_random_129(split, cycle):
     assert err <= 1e-10
 
 
+@pytest.mark.parametrize("split", [0, 8])
 @pytest.mark.parametrize("cycle", ["v", "k"])
-def test_cycle_mixed_random_129(cycle):
-    """The complex-FP32 cycle (auto-tuned variant per level) within 1e-5 of the oracle."""
+def test_cycle_mixed_random_129(cycle, split):
+    """The complex-FP32 cycle within 1e-5 of the oracle: the auto-tuned variant per level,
+    and the LDS z-marching tiles forced on every coarse level (down to 9^3, one block)."""
     wl, p, hier = _case()
-    print(f"[rand3d-mixed] 129^3 seed 24 levels {LEVELS} cycle={cycle}", flush=True)
-    ctx = _ctx(wl, "mixed", cycle=cycle)
+    print(f"[rand3d-mixed] 129^3 seed 24 levels {LEVELS} cycle={cycle} split={split}", flush=True)
+    ctx = _ctx(wl, "mixed", cycle=cycle, coarse_split=split)
     splits = [ctx.level_split(l) for l in range(1, LEVELS - 1)]
-    assert all(s in (1, 4) for s in splits)
+    assert all(s in (1, 4, 8) for s in splits)
+    if split == 8:
+        assert splits == [8] * (LEVELS - 2)
     r = W.random_vector(wl.shape, 52)
     z = ctx.vcycle(_t(r)).cpu().numpy()
     ctx.close()
