@@ -541,6 +541,18 @@ def accuracy(ctx64, q, a_mixed, a_fp64):
             "fp64_rel_l2": torch.linalg.vector_norm(a_fp64 - ref).item() / nr}
 
 
+def tuning_table():
+    """The autotuner's choices so far (written by the library, read back)."""
+    import tempfile
+
+    from paper_1712_06091_amd import adr
+    with tempfile.NamedTemporaryFile("r", suffix=".txt") as fh:
+        adr.tuning_table_write(fh.name)
+        rows = [l.split() for l in fh.read().splitlines() if l and not l.startswith("#")]
+    return [{"ndim": int(r[0]), "shape": [int(r[1]), int(r[2]), int(r[3])], "real_bytes": int(r[4]),
+             "variant": int(r[5]), "slabs": int(r[6]), "ms_per_8": float(r[7])} for r in rows]
+
+
 def hbm_leg(args):
     """3D 257^3 random medium (fast-marching tau): where the working set exceeds the
     256 MB Infinity Cache, so the level-1 apply and the V-cycle are HBM-bound.  A few whole
@@ -725,6 +737,7 @@ def main():
         out["roofline"] = leg.pop("roofline")
         out["vcycle"] = leg.pop("vcycle")
         out["hbm_3d_257"] = leg
+    out["tuning_table"] = tuning_table()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, one thread) ...")
         out["cpu_baseline"] = cpu_baseline(args, N, iters_d)

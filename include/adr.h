@@ -275,6 +275,18 @@ adr_status adr_level_info(adr_ctx *ctx, int level, int *nodes, int *stencil_poin
 adr_status adr_level_split(adr_ctx *ctx, int level, int *split);
 int adr_num_levels(const adr_ctx *ctx);
 
+/* The setup-time autotuner's table (process-wide): for every coarse-level shape and
+ * precision timed so far, the Galerkin-apply variant (1, 4, 8) and, for the LDS tiles,
+ * the z-slab count of the launch, with the measured time of 8 launches.
+ * adr_tuning_table_write writes it as text to `path` (host string; one line per entry:
+ * ndim nx ny nz real_bytes variant slabs ms) and returns the number of entries, -1 if
+ * the file cannot be written.  adr_tuning_table_read loads such a file into the table
+ * (later setups on those shapes take the entries instead of timing) and returns the
+ * number of entries read, -1 if the file cannot be opened or holds a malformed entry.
+ * Not thread-safe against concurrent adr_setup calls. */
+int adr_tuning_table_write(const char *path);
+int adr_tuning_table_read(const char *path);
+
 /* Copy a Galerkin level's stencil (level >= 1) out as c128: stencil_points planes of
  * that level's node count, plane p holding the coefficient of neighbour offset
  * offsets[3p..3p+2] = (dx, dy, dz); offsets is a HOST int array of 3*stencil_points

@@ -109,6 +109,8 @@ def load_library(path=LIB_PATH):
         "adr_level_info": (I, [P, I, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
         "adr_level_split": (I, [P, I, ctypes.POINTER(ctypes.c_int)]),
         "adr_num_levels": (I, [P]),
+        "adr_tuning_table_write": (I, [ctypes.c_char_p]),
+        "adr_tuning_table_read": (I, [ctypes.c_char_p]),
         "adr_get_level_stencil": (I, [P, I, P, ctypes.POINTER(ctypes.c_int)]),
         "adr_solve_adjoint": (I, [P, P, P, D, I, I, ctypes.POINTER(AdrStats)]),
         "adr_apply_adjoint": (I, [P, P, P]),
@@ -209,6 +211,22 @@ def eikonal(kappa2, h, src, max_sweeps=100000, stream=None):
     _check(lib.adr_eikonal(d, n, float(h), _dev(kappa2, torch.float64), s, _dev(tau, torch.float64),
                            _dev(work, torch.float64), int(max_sweeps), ctypes.byref(sweeps), _stream_ptr(stream)))
     return tau, sweeps.value
+
+
+def tuning_table_write(path):
+    """Write the autotuner's table (adr_tuning_table_write); returns the entry count."""
+    n = load_library().adr_tuning_table_write(os.fsencode(path))
+    if n < 0:
+        raise OSError(f"cannot write the tuning table to {path}")
+    return n
+
+
+def tuning_table_read(path):
+    """Load a table written by tuning_table_write; returns the entry count."""
+    n = load_library().adr_tuning_table_read(os.fsencode(path))
+    if n < 0:
+        raise OSError(f"cannot read the tuning table {path}")
+    return n
 
 
 def _check(status, ctx_ptr=None):

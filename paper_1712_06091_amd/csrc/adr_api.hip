@@ -60,7 +60,8 @@ struct LevelT {
   cx<T> *Z = nullptr;        // (kMaxNu+1) x N, Z_j = D^{-1} V_j
   cx<T> *ku = nullptr;       // Krylov cycle: second coarse basis vector u_1
   cx<T> *kz = nullptr;       // Krylov cycle: first preconditioned direction K(u_0)
-  int split = 1;             // Galerkin-apply variant (wavefronts per node), tuned at setup
+  int split = 1;             // Galerkin-apply variant (1, 4 or 8 = LDS tiles), tuned at setup
+  int slabs = 0;             // split 8: z-slabs of the launch (tuned; 0 = the most)
   cx<T> *Gs = nullptr;       // pipelined relaxation: kMaxNu x N stored A D^{-1} u_i (see k_pipe_step)
   cx<T> *Yp = nullptr;       // pipelined relaxation: 2 x N, D^{-1} Gs_{k-1} (ping-pong)
   cx<T> *planes_adj = nullptr;   // conjugate-transposed stencil (adjoint solves)
@@ -505,6 +506,8 @@ void gmres_relax(adr_ctx *ctx, int l, const cx<T> *x0, const cx<T> *b, cx<T> *x_
     // V0 = b - A x0, Z0 = D^{-1} V0, with the norm partials.
     CoarseArgs<T> a{};
     a.split = L.split;
+  a.slabs = L.slabs;
+    a.slabs = L.slabs;
     a.G = L.G;
     a.planes = planes;
     a.x = x0;
@@ -529,6 +532,9 @@ void gmres_relax(adr_ctx *ctx, int l, const cx<T> *x0, const cx<T> *b, cx<T> *x_
       V0.v[0] = Vp[0];
       CoarseArgs<T> a{};
       a.split = L.split;
+  a.slabs = L.slabs;
+      a.slabs = L.slabs;
+    a.slabs = L.slabs;
       a.G = L.G;
       a.planes = planes;
       a.x = Zp[0];
@@ -560,7 +566,7 @@ void gmres_relax(adr_ctx *ctx, int l, const cx<T> *x0, const cx<T> *b, cx<T> *x_
       const ProIn pin{ctx->part[cur], nb, 2 * k + (k >= 2 ? 1 : 0)};
       if (k < nu) {
         int t0 = tbegin(ctx, ADR_TIMER_COARSE_APPLY, l);
-        nb = adrk::pipe_step<T>(s, D, L.split, L.G, planes, Yb[(k - 1) & 1], pin, sc + kS, hcol, hsub, sout, U, Gv,
+        nb = adrk::pipe_step<T>(s, D, L.split, L.slabs, L.G, planes, Yb[(k - 1) & 1], pin, sc + kS, hcol, hsub, sout, U, Gv,
                                 dinv, L.V + (size_t)k * N, Zp[k], Gp[k], Yb[k & 1], ctx->part[cur ^ 1]);
         // planes, the gathered D^{-1} Gs_{k-1}, U and Gs (k each), dinv; u, z, G, D^{-1} G written
         tend(ctx, t0, (double)N * cb * (L.S + 6 + 2 * k));
@@ -581,6 +587,8 @@ void gmres_relax(adr_ctx *ctx, int l, const cx<T> *x0, const cx<T> *b, cx<T> *x_
     // w = A Z_j s_j, with s_j = 1/||V_j|| from the previous kernel's partials.
     CoarseArgs<T> a{};
     a.split = L.split;
+  a.slabs = L.slabs;
+    a.slabs = L.slabs;
     a.G = L.G;
     a.planes = planes;
     a.x = Zp[j];
@@ -741,6 +749,7 @@ cx<T> *coarse_fgmres2(adr_ctx *ctx, int k, ProIn bpin) {
   VecSet<T> V1 = vecset<T>({L.b});
   CoarseArgs<T> a{};
   a.split = L.split;
+  a.slabs = L.slabs;
   a.G = L.G;
   a.planes = planes;
   a.x = L.kz;
@@ -875,22 +884,32 @@ int auto_levels(int D, const int n[3], int coarsest_max) {
 // ties do not flip from run to run.
 // The choice is cached per grid shape and precision for the life of the process, so
 // every context on a given shape launches the same kernels and sums in the same order.
+// The tuner's table: per (ndim, nx, ny, nz, bytes per real) the variant and slab count
+// chosen, and the timed milliseconds of the 8 launches.  Shared by every context of the
+// process; adr_tuning_table_write/_read save it to and restore it from a text file.
+struct TuneEntry {
+  int split, slabs;
+  float ms;
+};
+std::mutex g_tune_mu;
+std::map<std::array<int, 5>, TuneEntry> g_tune;
+
 template <typename T>
 adr_status tune_split(adr_ctx *ctx, int l) {
   LevelT<T> &L = levels_of<T>(ctx)[l];
-  const bool lds_ok = sizeof(T) == 4 && adrk::lds_blocks(L.G, ctx->D) > 0;
+  const int max_slabs = sizeof(T) == 4 ? adrk::lds_max_slabs(L.G, ctx->D) : 0;
   if (ctx->opt.coarse_split == 1 || ctx->opt.coarse_split == 4 || ctx->opt.coarse_split == 8) {
-    L.split = (ctx->opt.coarse_split == 8 && !lds_ok) ? 1 : ctx->opt.coarse_split;
+    L.split = (ctx->opt.coarse_split == 8 && max_slabs == 0) ? 1 : ctx->opt.coarse_split;
+    L.slabs = 0;
     return ADR_OK;
   }
-  static std::mutex mu;
-  static std::map<std::array<int, 5>, int> cache;
   const std::array<int, 5> key = {ctx->D, L.G.n[0], L.G.n[1], L.G.n[2], (int)sizeof(T)};
   {
-    std::lock_guard<std::mutex> g(mu);
-    auto it = cache.find(key);
-    if (it != cache.end()) {
-      L.split = it->second;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      L.split = it->second.split;
+      L.slabs = it->second.slabs;
       return ADR_OK;
     }
   }
@@ -902,12 +921,20 @@ adr_status tune_split(adr_ctx *ctx, int l) {
   ADR_HIP(hipEventCreate(&e0));
   ADR_HIP(hipEventCreate(&e1));
   VecSet<T> V1 = vecset<T>({L.r});
-  float best_ms = 0.f;
-  int best = 1;
-  for (int split : {1, 4, 8}) {
-    if (split == 8 && !lds_ok) continue;
+  // Candidates: one lane, four wavefronts, and the LDS tiles at three slab counts.
+  std::vector<std::pair<int, int>> cand = {{1, 0}, {4, 0}};
+  if (max_slabs > 0) {
+    for (int sl : {max_slabs, (3 * max_slabs + 3) / 4, (max_slabs + 1) / 2}) {
+      bool dup = false;
+      for (auto &c : cand) dup |= c.first == 8 && c.second == sl;
+      if (!dup && sl >= 1) cand.push_back({8, sl});
+    }
+  }
+  TuneEntry best{1, 0, 0.f};
+  for (auto [split, slabs] : cand) {
     CoarseArgs<T> a{};
     a.split = split;
+    a.slabs = slabs;
     a.G = L.G;
     a.planes = L.planes;
     a.x = L.x;
@@ -928,16 +955,14 @@ adr_status tune_split(adr_ctx *ctx, int l) {
       ctx->err = std::string("split tuning: ") + hipGetErrorString(e);
       return ADR_EHIP;
     }
-    if (split == 1 || ms < 0.90f * best_ms) {
-      best_ms = ms;
-      best = split;
-    }
+    if (split == 1 || ms < 0.90f * best.ms) best = TuneEntry{split, split == 8 ? slabs : 0, ms};
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
-  std::lock_guard<std::mutex> g(mu);
-  auto ins = cache.emplace(key, best);
-  L.split = ins.first->second;
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  auto ins = g_tune.emplace(key, best);
+  L.split = ins.first->second.split;
+  L.slabs = ins.first->second.slabs;
   return ADR_OK;
 }
 
@@ -1464,6 +1489,46 @@ adr_status adr_level_info(adr_ctx *ctx, int level, int *nodes, int *stencil_poin
     for (int k = 0; k < 3; ++k) nodes[k] = G.n[k];
   if (stencil_points) *stencil_points = level == 0 ? 0 : ctx->S_coarse;
   return ADR_OK;
+}
+
+int adr_tuning_table_write(const char *path) {
+  if (!path) return -1;
+  FILE *f = std::fopen(path, "w");
+  if (!f) return -1;
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  std::fprintf(f, "# ndim nx ny nz real_bytes variant slabs ms_per_8_launches\n");
+  int n = 0;
+  for (auto &kv : g_tune) {
+    const auto &k = kv.first;
+    std::fprintf(f, "%d %d %d %d %d %d %d %.6f\n", k[0], k[1], k[2], k[3], k[4], kv.second.split, kv.second.slabs,
+                 (double)kv.second.ms);
+    ++n;
+  }
+  std::fclose(f);
+  return n;
+}
+
+int adr_tuning_table_read(const char *path) {
+  if (!path) return -1;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return -1;
+  char line[256];
+  int n = 0;
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  while (std::fgets(line, sizeof(line), f)) {
+    if (line[0] == '#') continue;
+    int d, nx, ny, nz, rb, split, slabs;
+    double ms;
+    if (std::sscanf(line, "%d %d %d %d %d %d %d %lf", &d, &nx, &ny, &nz, &rb, &split, &slabs, &ms) != 8) continue;
+    if ((d != 2 && d != 3) || (rb != 4 && rb != 8) || (split != 1 && split != 4 && split != 8) || slabs < 0) {
+      std::fclose(f);
+      return -1;
+    }
+    g_tune[{d, nx, ny, nz, rb}] = TuneEntry{split, slabs, (float)ms};
+    ++n;
+  }
+  std::fclose(f);
+  return n;
 }
 
 adr_status adr_level_split(adr_ctx *ctx, int level, int *split) {

@@ -1050,15 +1050,22 @@ __device__ __forceinline__ void lds_march3(const Grid &G, const cx<T> *__restric
   }
 }
 
-// Blocks of the LDS variant on grid G (segments x slabs, at most ADR_PART_BLOCKS so the
-// partials fit), or 0 where it does not apply (2D, rows longer than kLdsMaxN0, or slabs
-// thinner than kLdsMinPlanes planes).
-int lds_blocks(const Grid &G, int D) {
+// The LDS variant's launch on grid G: segments x slabs blocks, at most ADR_PART_BLOCKS so
+// the partials fit and slabs of at least kLdsMinPlanes planes.  lds_max_slabs is 0 where
+// it does not apply (2D, rows longer than kLdsMaxN0); lds_blocks takes `slabs` (the tuned
+// tile depth; 0 or out of range = the most slabs) and returns the block count.
+int lds_max_slabs(const Grid &G, int D) {
   if (D != 3 || G.n[0] > kLdsMaxN0) return 0;
   const int nseg = (G.n[0] * G.n[1] + kLdsSeg - 1) / kLdsSeg;
   int nslab = ADR_PART_BLOCKS / nseg;
   if (nslab > G.n[2] / kLdsMinPlanes) nslab = G.n[2] / kLdsMinPlanes;
-  return nslab >= 1 ? nseg * nslab : 0;
+  return nslab >= 1 ? nslab : 0;
+}
+int lds_blocks(const Grid &G, int D, int slabs) {
+  const int mx = lds_max_slabs(G, D);
+  if (mx == 0) return 0;
+  const int nslab = (slabs >= 1 && slabs < mx) ? slabs : mx;
+  return ((G.n[0] * G.n[1] + kLdsSeg - 1) / kLdsSeg) * nslab;
 }
 
 // mode 0: y = s * (A x), where s = 1/||.|| of the predecessor's partials (prologue
@@ -1371,10 +1378,10 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_pipe_final(int N, ProIn pin, cons
 }
 
 template <typename T>
-int pipe_step(hipStream_t s, int D, int split, const Grid &G, const cx<T> *planes, const cx<T> *yin, ProIn pin,
-              const double *scales, double *hcol, double *hsub, double *sout, const VecSet<T> &U,
+int pipe_step(hipStream_t s, int D, int split, int slabs, const Grid &G, const cx<T> *planes, const cx<T> *yin,
+              ProIn pin, const double *scales, double *hcol, double *hsub, double *sout, const VecSet<T> &U,
               const VecSet<T> &Gs, const cx<T> *dinv, cx<T> *uo, cx<T> *zo, cx<T> *go, cx<T> *yo, double *pout) {
-  const int nlds = (split == 8 && sizeof(T) == 4) ? lds_blocks(G, D) : 0;
+  const int nlds = (split == 8 && sizeof(T) == 4) ? lds_blocks(G, D, slabs) : 0;
   if (split == 8 && nlds == 0) split = 1;
   const int nb = split == 8 ? nlds : (split == 4 ? launch_blocks_red(4LL * G.N) : launch_blocks_red(G.N));
 #define ADR_PIPE_CASE(n)                                                                                        \
@@ -1421,11 +1428,11 @@ int pipe_final(hipStream_t s, int N, ProIn pin, const double *scales, double *hc
   }
   return nb;
 }
-template int pipe_step<float>(hipStream_t, int, int, const Grid &, const cx<float> *, const cx<float> *, ProIn,
+template int pipe_step<float>(hipStream_t, int, int, int, const Grid &, const cx<float> *, const cx<float> *, ProIn,
                               const double *, double *, double *, double *, const VecSet<float> &,
                               const VecSet<float> &, const cx<float> *, cx<float> *, cx<float> *, cx<float> *,
                               cx<float> *, double *);
-template int pipe_step<double>(hipStream_t, int, int, const Grid &, const cx<double> *, const cx<double> *, ProIn,
+template int pipe_step<double>(hipStream_t, int, int, int, const Grid &, const cx<double> *, const cx<double> *, ProIn,
                                const double *, double *, double *, double *, const VecSet<double> &,
                                const VecSet<double> &, const cx<double> *, cx<double> *, cx<double> *,
                                cx<double> *, cx<double> *, double *);
@@ -1489,7 +1496,7 @@ int coarse_apply(hipStream_t s, int D, const CoarseArgs<T> &a, const VecSet<T> *
   if (dots) V = *dots;
   const bool red = want_norm || V.count > 0;
   if (a.split == 8) {
-    const int nb = sizeof(T) == 4 ? lds_blocks(a.G, D) : 0;
+    const int nb = sizeof(T) == 4 ? lds_blocks(a.G, D, a.slabs) : 0;
     if (nb > 0) {
       if (want_norm) dispatch_coarse_split<T, 3, true>(s, nb, a, V);
       else dispatch_coarse_split<T, 3, false>(s, nb, a, V);

@@ -46,6 +46,7 @@ struct CoarseArgs {
   double *pout;          // partials (when reducing)
   int split;             // 4: four wavefronts share each node's stencil sum; 8: LDS z-marching
                          // tiles (3D FP32, see lds_blocks); else one lane
+  int slabs;             // split 8: z-slabs per launch (0 = the most)
 };
 
 // Coarse tail (one workgroup): per-level data and the level range.
@@ -113,7 +114,7 @@ void fine_jacobi(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, cons
 // Pipelined GMRES relaxation steps (see k_pipe_step): one fused orthogonalization and
 // apply, and the last orthogonalization; return the block count of their partials.
 template <typename T>
-int pipe_step(hipStream_t s, int D, int split, const Grid &G, const cx<T> *planes, const cx<T> *yin, ProIn pin,
+int pipe_step(hipStream_t s, int D, int split, int slabs, const Grid &G, const cx<T> *planes, const cx<T> *yin, ProIn pin,
               const double *scales, double *hcol, double *hsub, double *sout, const VecSet<T> &U,
               const VecSet<T> &Gs, const cx<T> *dinv, cx<T> *uo, cx<T> *zo, cx<T> *go, cx<T> *yo, double *pout);
 template <typename T>
@@ -162,8 +163,10 @@ void copy(hipStream_t s, long long n, const cx<double> *in, cx<double> *out);
 // count.
 template <typename T>
 int coarse_apply(hipStream_t s, int D, const CoarseArgs<T> &a, const VecSet<T> *dots, bool want_norm);
-// Blocks of the LDS z-marching Galerkin apply (split 8) on grid G, 0 where it does not apply.
-int lds_blocks(const Grid &G, int D);
+// LDS z-marching Galerkin apply (split 8) on grid G: the most z-slabs (0 where it does not
+// apply) and the block count for a slab count (0 = the most).
+int lds_max_slabs(const Grid &G, int D);
+int lds_blocks(const Grid &G, int D, int slabs);
 // The coarse_apply contract on the matrix-free finest level (a.planes and a.split unused):
 // GMRES relaxation there.  Pd: per-problem fine parameters of a shot group.
 template <typename T>

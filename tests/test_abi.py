@@ -116,3 +116,23 @@ def test_setup_rejects_coarse_tail(lib):
     out = ctypes.c_void_p()
     assert lib.adr_setup(ctypes.byref(p), ctypes.byref(o), None, ctypes.byref(out)) == adr.ADR_ENOTSUP
     assert out.value is None
+
+
+def test_tuning_table_read_write(tmp_path):
+    """The autotuner's table file (host code only): a written table reads back entry for
+    entry; a malformed entry is refused."""
+    from paper_1712_06091_amd import adr
+    good = tmp_path / "table.txt"
+    good.write_text("# ndim nx ny nz real_bytes variant slabs ms\n3 129 129 129 4 8 11 2.5\n3 33 33 33 4 1 0 0.3\n")
+    assert adr.tuning_table_read(good) == 2
+    out = tmp_path / "out.txt"
+    n = adr.tuning_table_write(out)
+    rows = {tuple(l.split()[:7]) for l in out.read_text().splitlines() if not l.startswith("#")}
+    assert n == len(rows) >= 2
+    assert ("3", "129", "129", "129", "4", "8", "11") in rows and ("3", "33", "33", "33", "4", "1", "0") in rows
+    bad = tmp_path / "bad.txt"
+    bad.write_text("3 17 17 17 4 5 0 1.0\n")
+    with pytest.raises(OSError):
+        adr.tuning_table_read(bad)
+    with pytest.raises(OSError):
+        adr.tuning_table_read(tmp_path / "missing.txt")

@@ -325,3 +325,32 @@ def test_vcycle_coarse_tail_mixed_and_solves(name):
     refl = osolve.direct_solve(p.H2up.conj().T.tocsr(), osolve.rhs_hat(g, wl.tau, wl.omega)).reshape(wl.shape)
     lam, st = ctx.solve_adjoint(_t(g), tol=1e-10, maxit=300)
     assert st["relres"] <= 1e-10 and _rel(lam.cpu().numpy(), refl) <= 1e-6
+
+
+def test_tuning_table_entries_steer_setup(tmp_path):
+    """The autotuner writes its choice per coarse-level shape; an entry read from a table
+    file replaces the timing for that shape (the previous table is restored afterwards)."""
+    from paper_1712_06091_amd import adr
+    wl = W.linear_gradient(65, 3)
+    print("[tuning-table] 3d 65 mixed", flush=True)
+    ctx = _ctx(wl, prec="mixed")
+    saved = tmp_path / "saved.txt"
+    adr.tuning_table_write(saved)
+    rows = [l.split() for l in saved.read_text().splitlines() if not l.startswith("#")]
+    shapes = {(int(r[1]), int(r[2]), int(r[3]), int(r[4])): (int(r[5]), int(r[6])) for r in rows}
+    for l in range(1, ctx.num_levels - 1):
+        shape, _ = ctx.level_info(l)
+        assert (shape[2], shape[1], shape[0], 4) in shapes
+        assert shapes[(shape[2], shape[1], shape[0], 4)][0] == ctx.level_split(l)
+    ctx.close()
+    forced = tmp_path / "forced.txt"
+    forced.write_text("3 33 33 33 4 4 0 1.0\n")
+    try:
+        assert adr.tuning_table_read(forced) == 1
+        c2 = _ctx(wl, prec="mixed")
+        assert c2.level_split(1) == 4
+        a, st = c2.solve(_t(wl.rhs()), tol=1e-10, maxit=300)
+        assert st["relres"] <= 1e-10
+        c2.close()
+    finally:
+        adr.tuning_table_read(saved)
