@@ -159,6 +159,10 @@ typedef struct {
                         /* result up to rounding.  Default 2^31 - 1 (every coarse        */
                         /* level); 0 = the two-launch steps everywhere                   */
   adr_reaction reaction; /* default ADR_REACTION_NUMERICAL                                */
+  int kcycle_levels;    /* Krylov cycle: the flexible-GMRES coarse solve on coarse levels */
+                        /* 1..kcycle_levels only, the plain recursion of the V-cycle     */
+                        /* below (a Krylov acceleration of the top of the hierarchy);    */
+                        /* default 0 = every level                                        */
 } adr_options;
 
 typedef struct {

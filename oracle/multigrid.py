@@ -125,9 +125,11 @@ class Hierarchy:
             return self.gmres_relax(l, x, b, self.nu[l])
         raise ValueError(self.smoothers[l])
 
-    def kcycle(self, b, l=0, threshold=0.1):
+    def kcycle(self, b, l=0, threshold=0.1, kmax=0):
         """One Krylov cycle from a zero initial guess on level l: x ~ A_l^{-1} b.
-        ``self.kcalls[l]`` counts the cycles entered on level l."""
+        ``self.kcalls[l]`` counts the cycles entered on level l.  ``kmax`` > 0 keeps the
+        flexible-GMRES coarse solve for coarse levels 1..kmax only; deeper coarse problems
+        are solved by the same cycle directly, as in the V-cycle."""
         if not hasattr(self, "kcalls"):
             self.kcalls = [0] * self.levels
         self.kcalls[l] += 1
@@ -139,13 +141,15 @@ class Hierarchy:
         rc = self.P[l].T @ r
         if l + 1 == self.levels - 1:
             ec = sla.lu_solve(self.coarse_lu, rc)
+        elif kmax <= 0 or l + 1 <= kmax:
+            ec = self.coarse_fgmres(l + 1, rc, threshold, kmax)
         else:
-            ec = self.coarse_fgmres(l + 1, rc, threshold)
+            ec = self.kcycle(rc, l + 1, threshold, kmax)
         x = x + self.P[l] @ ec
         x = self.relax(l, x, b)
         return x
 
-    def coarse_fgmres(self, l, r, threshold):
+    def coarse_fgmres(self, l, r, threshold, kmax=0):
         """Flexible GMRES(2) on A_l e = r from e = 0, preconditioned by the Krylov cycle
         on level l; one step only if its residual is <= threshold * ||r||."""
         A = self.A[l]
@@ -157,7 +161,7 @@ class Hierarchy:
         H = np.zeros((3, 2), dtype=np.complex128)
         k = 0
         for j in range(2):
-            Z.append(self.kcycle(V[j], l, threshold))
+            Z.append(self.kcycle(V[j], l, threshold, kmax) if kmax > 0 else self.kcycle(V[j], l, threshold))
             w = A @ Z[j]
             for i in range(j + 1):
                 H[i, j] = np.vdot(V[i], w)

@@ -76,14 +76,14 @@ def direct_solve(A, b):
 
 
 def iterative_solve(prob, qhat, levels=None, tol=1e-10, maxit=500, restart=5, nu=None,
-                    jacobi_weight=0.8, smoothers=None, cycle="v", threshold=0.1):
+                    jacobi_weight=0.8, smoothers=None, cycle="v", threshold=0.1, kmax=0):
     """FGMRES(restart) on H_2up preconditioned by one V-cycle (cycle="v") or one Krylov
     cycle (cycle="k") on A_beta per step."""
     hier = prob.hierarchy(levels, nu=nu, jacobi_weight=jacobi_weight, smoothers=smoothers)
     if cycle == "v":
         precond = hier.vcycle
     elif cycle == "k":
-        precond = lambda v: hier.kcycle(v, threshold=threshold)
+        precond = lambda v: hier.kcycle(v, threshold=threshold, kmax=kmax)
     else:
         raise ValueError(cycle)
     x, info = krylov.fgmres(lambda v: prob.H2up @ v, qhat.ravel(), precond=precond,

@@ -60,6 +60,7 @@ class AdrOptions(ctypes.Structure):
         ("rescaled", ctypes.c_int),
         ("pipeline_max_nodes", ctypes.c_int),
         ("reaction", ctypes.c_int),
+        ("kcycle_levels", ctypes.c_int),
     ]
 
 

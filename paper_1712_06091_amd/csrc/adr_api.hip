@@ -709,7 +709,9 @@ cx<T> *vcycle(adr_ctx *ctx, int l, const cx<T> *b, cx<T> *out0, ProIn bpin = Pro
                                    coarse_relaxes ? C.Z : nullptr, coarse_relaxes ? ctx->part[0] : nullptr);
   tend(ctx, t1, cb * ((double)L.G.N + C.G.N * (coarse_relaxes ? 3.0 : 1.0)));
   const ProIn cpin = coarse_relaxes ? ProIn{ctx->part[0], rnb, 1} : ProIn{};
-  cx<T> *ec = (ctx->opt.cycle == ADR_CYCLE_K && coarse_relaxes) ? coarse_fgmres2<T>(ctx, l + 1, cpin)
+  const bool krylov = ctx->opt.cycle == ADR_CYCLE_K && coarse_relaxes &&
+                      (ctx->opt.kcycle_levels <= 0 || l + 1 <= ctx->opt.kcycle_levels);
+  cx<T> *ec = krylov ? coarse_fgmres2<T>(ctx, l + 1, cpin)
                                                                 : vcycle<T>(ctx, l + 1, C.b, nullptr, cpin);
   int t2 = tbegin(ctx, ADR_TIMER_TRANSFER, l);
   adrk::prolong_add<T>(s, L.G, C.G, D, ec, x);
@@ -842,6 +844,7 @@ adr_status validate(const adr_problem *p, const adr_options *o, std::string &err
     return ADR_EINVAL;
   }
   if (!(o->kcycle_threshold >= 0.0)) { err = "kcycle_threshold must be >= 0"; return ADR_EINVAL; }
+  if (o->kcycle_levels < 0) { err = "kcycle_levels must be >= 0"; return ADR_EINVAL; }
   if (o->pipeline_max_nodes < 0) { err = "pipeline_max_nodes must be >= 0"; return ADR_EINVAL; }
   if (o->advection != ADR_ADV_UPWIND && o->advection != ADR_ADV_CENTRAL) { err = "bad advection"; return ADR_EINVAL; }
   if (!(o->outer_beta >= 0.0 && o->outer_beta <= 1.0)) { err = "outer_beta must be in [0, 1]"; return ADR_EINVAL; }

@@ -145,3 +145,28 @@ def test_kcycle_adjoint_solve():
     lam, st = ctx.solve_adjoint(_t(g), tol=1e-10, maxit=300)
     assert st["relres"] <= 1e-10
     assert _rel(lam.cpu().numpy(), ref) <= 1e-6
+
+
+LIMITED = {
+    "2d_129_rand_5lv": (lambda: W.random_medium(129, 2, seed=21), 5),
+    "3d_65_rand_4lv": (lambda: W.random_medium(65, 3, seed=9), 4),
+}
+
+
+@pytest.mark.parametrize("name", list(LIMITED))
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_kcycle_limited_levels(name, prec):
+    """The Krylov cycle with the flexible-GMRES coarse solve on level 1 only (V-cycle
+    recursion below) against the oracle's cycle with kmax = 1."""
+    make, levels = LIMITED[name]
+    wl = make()
+    print(f"[kcycle-limited] {name} shape={wl.shape} prec={prec}", flush=True)
+    ctx = _ctx(wl, prec=prec, levels=levels, kcycle_levels=1)
+    p = osolve.Problem(wl.kappa2, wl.tau, wl.gamma, wl.h, wl.omega, wl.src)
+    hier = p.hierarchy(levels)
+    r = W.random_vector(wl.shape, 81)
+    z = ctx.vcycle(_t(r)).cpu().numpy()
+    ref = hier.kcycle(r.ravel(), kmax=1).reshape(wl.shape)
+    assert _rel(z, ref) <= (1e-10 if prec == "fp64" else 1e-5)
+    a, st = ctx.solve(_t(wl.rhs()), tol=1e-8, maxit=500)
+    assert st["relres"] <= 1e-8

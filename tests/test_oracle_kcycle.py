@@ -134,3 +134,20 @@ def test_kcycle_fewer_iterations_than_vcycle():
     _, iv = solve.iterative_solve(p, qh, tol=1e-6, maxit=300, cycle="v")
     _, ik = solve.iterative_solve(p, qh, tol=1e-6, maxit=300, cycle="k")
     assert ik["iters"] < iv["iters"]
+
+
+def test_kcycle_krylov_levels_limit():
+    """kmax limits the flexible-GMRES coarse solves to coarse levels 1..kmax: the call
+    counts are the W pattern down to level kmax and single calls below it; below kmax the
+    cycle is exactly the V-cycle; kmax at or beyond the last relaxed level is the full
+    Krylov cycle."""
+    p, _ = _problem(n=65)
+    hier = p.hierarchy(levels=5)
+    b = _rhs(p.H2up.shape[0], 11)
+    hier.kcalls = [0] * 5
+    hier.kcycle(b, threshold=0.0, kmax=1)
+    assert hier.kcalls == [1, 2, 2, 2, 0]
+    rc = hier.P[1].T @ (hier.P[0].T @ b)
+    np.testing.assert_array_equal(hier.kcycle(rc, l=2, kmax=1), hier.vcycle(rc, l=2))
+    np.testing.assert_array_equal(hier.kcycle(b, kmax=3), hier.kcycle(b))
+    assert not np.array_equal(hier.kcycle(b, kmax=1), hier.kcycle(b))
