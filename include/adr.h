@@ -163,6 +163,11 @@ typedef struct {
                         /* 1..kcycle_levels only, the plain recursion of the V-cycle     */
                         /* below (a Krylov acceleration of the top of the hierarchy);    */
                         /* default 0 = every level                                        */
+  int fine_tiles;       /* 1 (default): on 3D complex-FP32 finest levels with rows of at  */
+                        /* most 257 nodes and at least 16 planes, the Jacobi sweeps and  */
+                        /* the residual stage the iterate in LDS z-marching tiles (the   */
+                        /* same arithmetic) if a setup-time timing finds them at least   */
+                        /* 1% faster; 2: wherever they apply; 0: one lane per node       */
 } adr_options;
 
 typedef struct {

@@ -61,6 +61,7 @@ class AdrOptions(ctypes.Structure):
         ("pipeline_max_nodes", ctypes.c_int),
         ("reaction", ctypes.c_int),
         ("kcycle_levels", ctypes.c_int),
+        ("fine_tiles", ctypes.c_int),
     ]
 
 

@@ -138,6 +138,7 @@ struct adr_ctx {
   // Coarse tail: levels tail_level.. run in one single-workgroup kernel (-1: none); device
   // copies of its level table for the forward [0] and adjoint [1] hierarchies.
   int tail_level = -1;
+  bool fine_tiles_on = false;  // finest-level LDS tiles chosen at setup (fine_tiles = 1 and faster)
   void *tail_args[2] = {nullptr, nullptr};
 
   // Captured V-cycles (Alg. TwoCycle applied recursively; no host synchronization
@@ -637,7 +638,9 @@ cx<T> *jacobi_sweeps(adr_ctx *ctx, int nu, const cx<T> *x_start, const cx<T> *b,
     if (ctx->adj) adrk::fine_jacobi_adj<T>(ctx->stream, G, ctx->D, C, P, in, b, out, ctx->opt.jacobi_weight);
     else if (ctx->ph64)
       adrk::fine_jacobi_ph<T>(ctx->stream, G, ctx->D, C, P, phase_of<T>(ctx), in, b, out, ctx->opt.jacobi_weight);
-    else adrk::fine_jacobi<T>(ctx->stream, G, ctx->D, C, P, in, b, out, ctx->opt.jacobi_weight, ctx->Pdev + 1);
+    else if (!(ctx->fine_tiles_on && in &&
+               adrk::fine_lds<T>(ctx->stream, G, ctx->D, C, P, in, b, out, 0, ctx->opt.jacobi_weight, ctx->Pdev + 1)))
+      adrk::fine_jacobi<T>(ctx->stream, G, ctx->D, C, P, in, b, out, ctx->opt.jacobi_weight, ctx->Pdev + 1);
     tend(ctx, t0, (double)G.N * (fine_coef_bytes<T>(ctx->D) + sizeof(cx<T>) * (in ? 3 : 2)));
     in = out;
   }
@@ -696,7 +699,8 @@ cx<T> *vcycle(adr_ctx *ctx, int l, const cx<T> *b, cx<T> *out0, ProIn bpin = Pro
     else if (ctx->ph64)
       adrk::fine_residual_ph<T>(s, L.G, D, prec_coef<T>(ctx), fine_params(ctx, ctx->opt.beta), phase_of<T>(ctx), x,
                                 b, L.r);
-    else
+    else if (!(ctx->fine_tiles_on && adrk::fine_lds<T>(s, L.G, D, prec_coef<T>(ctx), fine_params(ctx, ctx->opt.beta),
+                                                          x, b, L.r, 1, 0.0, ctx->Pdev + 1)))
       adrk::fine_apply<T, T, T>(s, L.G, D, prec_coef<T>(ctx), fine_params(ctx, ctx->opt.beta), x, b, L.r, 1,
                                 nullptr, false, nullptr, ctx->Pdev + 1);
     tend(ctx, t0, (double)L.G.N * (fine_coef_bytes<T>(D) + 3 * cb));
@@ -845,6 +849,7 @@ adr_status validate(const adr_problem *p, const adr_options *o, std::string &err
   }
   if (!(o->kcycle_threshold >= 0.0)) { err = "kcycle_threshold must be >= 0"; return ADR_EINVAL; }
   if (o->kcycle_levels < 0) { err = "kcycle_levels must be >= 0"; return ADR_EINVAL; }
+  if (o->fine_tiles < 0 || o->fine_tiles > 2) { err = "fine_tiles must be 0, 1 or 2"; return ADR_EINVAL; }
   if (o->pipeline_max_nodes < 0) { err = "pipeline_max_nodes must be >= 0"; return ADR_EINVAL; }
   if (o->advection != ADR_ADV_UPWIND && o->advection != ADR_ADV_CENTRAL) { err = "bad advection"; return ADR_EINVAL; }
   if (!(o->outer_beta >= 0.0 && o->outer_beta <= 1.0)) { err = "outer_beta must be in [0, 1]"; return ADR_EINVAL; }
@@ -966,6 +971,56 @@ adr_status tune_split(adr_ctx *ctx, int l) {
   auto ins = g_tune.emplace(key, best);
   L.split = ins.first->second.split;
   L.slabs = ins.first->second.slabs;
+  return ADR_OK;
+}
+
+// Finest-level LDS tiles (fine_tiles = 1): where they apply, time Jacobi sweeps both ways
+// (8 launches each) and keep the tiles if they are at least 1% faster.  Both variants do
+// the same arithmetic, so the choice only affects speed (measured: 257^3 212 -> 201 us
+// per sweep; 129^3 29 -> 35 us, slower).
+template <typename T>
+adr_status tune_fine_tiles(adr_ctx *ctx) {
+  ctx->fine_tiles_on = false;
+  LevelT<T> &L = levels_of<T>(ctx)[0];
+  if (!ctx->opt.fine_tiles || sizeof(T) != 4 || adrk::fine_lds_blocks(L.G, ctx->D) == 0) return ADR_OK;
+  if (ctx->opt.fine_tiles == 2) {
+    ctx->fine_tiles_on = true;
+    return ADR_OK;
+  }
+  hipStream_t s = ctx->stream;
+  const size_t N = L.G.N;
+  ADR_HIP(hipMemsetAsync(L.x, 0, N * sizeof(cx<T>), s));
+  ADR_HIP(hipMemsetAsync(L.b, 0, N * sizeof(cx<T>), s));
+  FineCoef<T> C = prec_coef<T>(ctx);
+  FineParams P = fine_params(ctx, ctx->opt.beta);
+  hipEvent_t e0, e1;
+  ADR_HIP(hipEventCreate(&e0));
+  ADR_HIP(hipEventCreate(&e1));
+  float ms[2] = {0.f, 0.f};
+  for (int v = 0; v < 2; ++v) {
+    // Sweeps alternate between two buffers, each reading the previous one's output, as in
+    // the cycle.
+    auto sweep = [&](int r) {
+      cx<T> *in = (r & 1) ? L.xt : L.x, *out = (r & 1) ? L.x : L.xt;
+      if (v == 1) adrk::fine_lds<T>(s, L.G, ctx->D, C, P, in, L.b, out, 0, ctx->opt.jacobi_weight, ctx->Pdev + 1);
+      else adrk::fine_jacobi<T>(s, L.G, ctx->D, C, P, in, L.b, out, ctx->opt.jacobi_weight, ctx->Pdev + 1);
+    };
+    for (int w = 0; w < 2; ++w) sweep(w);
+    hipEventRecord(e0, s);
+    for (int r = 0; r < 8; ++r) sweep(r);
+    hipEventRecord(e1, s);
+    hipError_t e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms[v], e0, e1);
+    if (e != hipSuccess) {
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      ctx->err = std::string("fine tile tuning: ") + hipGetErrorString(e);
+      return ADR_EHIP;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  ctx->fine_tiles_on = ms[1] < 0.99f * ms[0];
   return ADR_OK;
 }
 
@@ -1132,6 +1187,7 @@ adr_status build_hierarchy(adr_ctx *ctx) {
   ctx->h_inv.swap(inv);
   for (int l = 0; l < ctx->levels; ++l) ADR_TRY(alloc_level_vectors<T>(ctx, lv[l], l));
   for (int l = 1; l < ctx->levels - 1; ++l) ADR_TRY(tune_split<T>(ctx, l));
+  if (ctx->levels > 1) ADR_TRY(tune_fine_tiles<T>(ctx));
   // Coarse tail: from the first coarse level with at most tail_max_nodes nodes (V-cycle;
   // the Krylov cycle's coarse GMRES steps stay on the multi-kernel path).
   ctx->tail_level = -1;
@@ -1471,6 +1527,7 @@ void adr_default_options(adr_options *o) {
   o->outer_beta = 0.0;
   o->rescaled = 0;
   o->pipeline_max_nodes = 0x7fffffff;   // every coarse level
+  o->fine_tiles = 1;
 }
 
 adr_status adr_setup(const adr_problem *prob, const adr_options *opt, void *stream, adr_ctx **out) {

@@ -428,6 +428,156 @@ void fine_jacobi(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, cons
                (T)weight, Pd);
   }
 }
+// -------------------------------------------------------------------------------------
+// LDS z-marching on the matrix-free finest level (3D, FP32): Jacobi sweeps from a given
+// iterate and the V-cycle residual.  A block owns a segment of kFineSeg consecutive
+// in-plane nodes and a slab of z-planes.  The 13-point row reads x at the node, at +-1 and
+// +-2 along x and y (all inside the plane window: the segment and 2 rows either side) and
+// at +-1, +-2 along z (only the segment of those planes).  So LDS holds the plane window of
+// the current plane (double-buffered: the next plane's is loaded during this one) and a
+// ring of six plane segments (z-2..z+3).  One barrier per plane.  The row arithmetic is
+// fine_row's, in the same order as the one-lane kernels, so the results are the same.
+// -------------------------------------------------------------------------------------
+constexpr int kFineSeg = ADR_BLOCK;
+constexpr int kFineMaxN0 = 257;
+constexpr int kFineWin = kFineSeg + 4 * kFineMaxN0;
+constexpr int kFineMinPlanes = 16;
+
+int fine_lds_blocks(const Grid &G, int D) {
+  if (D != 3 || G.n[0] > kFineMaxN0 || G.n[2] < kFineMinPlanes) return 0;
+  const int nseg = (G.n[0] * G.n[1] + kFineSeg - 1) / kFineSeg;
+  int nslab = G.n[2] / kFineMinPlanes;
+  const int cap = 4096 / nseg;
+  if (nslab > cap) nslab = cap;
+  if (nslab < 1) nslab = 1;
+  return nseg * nslab;
+}
+
+// MODE 0: Jacobi sweep out = x + w D^{-1} (b - A x); MODE 1: residual out = b - A x.
+template <typename T, int MODE, bool GRP>
+__global__ __launch_bounds__(ADR_BLOCK) void k_fine_lds(Grid G, FineCoef<T> C, FineParams P,
+                                                        const cx<T> *__restrict__ xin, const cx<T> *__restrict__ b,
+                                                        cx<T> *__restrict__ out, T weight, const FineParams *Pd,
+                                                        Shot sh) {
+  ADR_SHOT_ENTER(sh);
+  if constexpr (GRP) shift_fine_coef(C, shot_off_);
+  if constexpr (GRP) {
+    if (Pd) P = *shot_ptr(Pd, shot_off_);
+  }
+  ADR_SHIFT(xin);
+  ADR_SHIFT(b);
+  ADR_SHIFT(out);
+  ADR_SHOT_LIVE(sh);
+  constexpr int D = 3;
+  __shared__ cx<T> ring[6][kFineSeg];
+  __shared__ cx<T> cwin[2][kFineWin];
+  const int n0 = G.n[0], nxy = G.n[0] * G.n[1], n2 = G.n[2];
+  const int nseg = (nxy + kFineSeg - 1) / kFineSeg;
+  const int nslab = gridDim.x / nseg;
+  const int lb = logical_block();
+  const int seg = lb % nseg, slab = lb / nseg;
+  const int z0 = (int)((long long)n2 * slab / nslab), z1 = (int)((long long)n2 * (slab + 1) / nslab);
+  const int s0 = seg * kFineSeg;
+  const int halo = 2 * n0;
+  const int W = kFineSeg + 2 * halo;
+  const int tid = threadIdx.x;
+  constexpr int RW = (kFineWin + ADR_BLOCK - 1) / ADR_BLOCK;
+  auto xval = [&](int zp, int q) -> cx<T> {
+    return (zp >= 0 && zp < n2 && q >= 0 && q < nxy) ? xin[(size_t)zp * nxy + q] : mk<T>(T(0), T(0));
+  };
+  auto load_win = [&](int zp, cx<T> (&reg)[RW]) {
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const int w = tid + r * ADR_BLOCK;
+      reg[r] = w < W ? xval(zp, s0 - halo + w) : mk<T>(T(0), T(0));
+    }
+  };
+  auto store_win = [&](int buf, const cx<T> (&reg)[RW]) {
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const int w = tid + r * ADR_BLOCK;
+      if (w < W) cwin[buf][w] = reg[r];
+    }
+  };
+  // Preload: segments of planes z0-2 .. z0+2 and the window of plane z0.
+  for (int zp = z0 - 2; zp <= z0 + 2; ++zp) ring[(zp + 6) % 6][tid] = xval(zp, s0 + tid);
+  {
+    cx<T> reg[RW];
+    load_win(z0, reg);
+    store_win(z0 & 1, reg);
+  }
+  __syncthreads();
+  const int ip = s0 + tid;
+  const bool act = ip < nxy;
+  const int base = tid + halo;
+  for (int z = z0; z < z1; ++z) {
+    // Next plane's window and the segment of plane z + 3, in flight during this plane.
+    cx<T> reg[RW];
+    load_win(z + 1, reg);
+    const cx<T> seg3 = xval(z + 3, s0 + tid);
+    if (act) {
+      const int i = z * nxy + ip;
+      T gk[3], L;
+      cx<T> c;
+      load_fine_coef<T, D>(C, i, gk, L, c);
+      const cx<T> bi = b[i];
+      int idx[3];
+      idx[0] = ip % n0;
+      idx[1] = ip / n0;
+      idx[2] = z;
+      // x at the 13 stencil nodes in fine_neighbours' order: centre, then per axis
+      // offsets -2, -1, +1, +2.
+      const cx<T> *cw = cwin[z & 1];
+      cx<T> xv[1 + 4 * D];
+      xv[0] = cw[base];
+      xv[1] = cw[base - 2];
+      xv[2] = cw[base - 1];
+      xv[3] = cw[base + 1];
+      xv[4] = cw[base + 2];
+      xv[5] = cw[base - 2 * n0];
+      xv[6] = cw[base - n0];
+      xv[7] = cw[base + n0];
+      xv[8] = cw[base + 2 * n0];
+      xv[9] = ring[(z - 2 + 6) % 6][tid];
+      xv[10] = ring[(z - 1 + 6) % 6][tid];
+      xv[11] = ring[(z + 1) % 6][tid];
+      xv[12] = ring[(z + 2) % 6][tid];
+      cx<T> e[1 + 4 * D];
+      fine_row<T, D>(G, P, idx, gk, L, c, e);
+      cx<T> acc = mk<T>(T(0), T(0));
+#pragma unroll
+      for (int p = 0; p < 1 + 4 * D; ++p) acc = cfma(e[p], xv[p], acc);
+      const cx<T> r = bi - acc;
+      if constexpr (MODE == 0) out[i] = cfma(weight * cinv(e[0]), r, xv[0]);
+      else out[i] = r;
+    }
+    store_win((z + 1) & 1, reg);
+    ring[(z + 3) % 6][tid] = seg3;
+    __syncthreads();
+  }
+}
+
+template <typename T>
+bool fine_lds(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P, const cx<T> *x,
+              const cx<T> *b, cx<T> *out, int mode, double weight, const FineParams *Pd) {
+  if constexpr (sizeof(T) != 4) {
+    return false;
+  } else {
+    const int nb = fine_lds_blocks(G, D);
+    if (nb == 0 || !x) return false;
+    if (mode == 0)
+      launch_g(k_fine_lds<T, 0, false>, k_fine_lds<T, 0, true>, nb, s, G, C, P, x, b, out, (T)weight, Pd);
+    else
+      launch_g(k_fine_lds<T, 1, false>, k_fine_lds<T, 1, true>, nb, s, G, C, P, x, b, out, (T)weight, Pd);
+    return true;
+  }
+}
+template bool fine_lds<float>(hipStream_t, const Grid &, int, const FineCoef<float> &, const FineParams &,
+                              const cx<float> *, const cx<float> *, cx<float> *, int, double, const FineParams *);
+template bool fine_lds<double>(hipStream_t, const Grid &, int, const FineCoef<double> &, const FineParams &,
+                               const cx<double> *, const cx<double> *, cx<double> *, int, double,
+                               const FineParams *);
+
 template void fine_jacobi<double>(hipStream_t, const Grid &, int, const FineCoef<double> &, const FineParams &,
                                   const cx<double> *, const cx<double> *, cx<double> *, double, const FineParams *);
 template void fine_jacobi<float>(hipStream_t, const Grid &, int, const FineCoef<float> &, const FineParams &,

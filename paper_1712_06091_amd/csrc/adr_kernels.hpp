@@ -167,6 +167,13 @@ int coarse_apply(hipStream_t s, int D, const CoarseArgs<T> &a, const VecSet<T> *
 // apply) and the block count for a slab count (0 = the most).
 int lds_max_slabs(const Grid &G, int D);
 int lds_blocks(const Grid &G, int D, int slabs);
+// LDS z-marching on the matrix-free finest level (3D FP32, rows of at most 257 nodes and
+// at least 16 planes): mode 0 = Jacobi sweep from x, mode 1 = residual b - A x.  Returns
+// false (nothing launched) where it does not apply.
+template <typename T>
+bool fine_lds(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P, const cx<T> *x,
+              const cx<T> *b, cx<T> *out, int mode, double weight, const FineParams *Pd);
+int fine_lds_blocks(const Grid &G, int D);
 // The coarse_apply contract on the matrix-free finest level (a.planes and a.split unused):
 // GMRES relaxation there.  Pd: per-problem fine parameters of a shot group.
 template <typename T>
