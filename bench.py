@@ -57,6 +57,11 @@ def parse():
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tuning-table", default=None, metavar="PATH",
+                    help="read the Galerkin-apply autotuner's table from PATH before any setup (fixes the "
+                         "variant choices, e.g. for counter runs of the same configuration)")
+    ap.add_argument("--tuning-table-out", default=None, metavar="PATH",
+                    help="write the autotuner's table to PATH at the end")
     ap.add_argument("--no-257", action="store_true",
                     help="default workload: skip the 3D 257^3 leg that carries the HBM roofline")
     ap.add_argument("--cpu-sample-iters", type=int, default=60,
@@ -653,6 +658,8 @@ def main():
 
     from paper_1712_06091_amd import adr
 
+    if args.tuning_table:
+        log(f"tuning table: {adr.tuning_table_read(args.tuning_table)} entries from {args.tuning_table}")
     wl = make_workload(args.workload)
     N = wl.nodes
     tens = gpu_tensors(wl)
@@ -674,7 +681,8 @@ def main():
     ms_mixed, st_mixed = timed_solves(ctxs["mixed"], q, a, u, args.steps, args.warmup)
     log(f"mixed: {ms_mixed:.2f} ms/solve, {st_mixed[-1]['outer_iters']} iterations")
     if args.profile_only and args.mixed_only:
-        print(json.dumps({"ms_mixed": ms_mixed}))
+        print(json.dumps({"ms_mixed": ms_mixed, "outer_iters": st_mixed[-1]["outer_iters"],
+                          "levels": ctxs["mixed"].num_levels}))
         return
     ms_fp64, st_fp64 = timed_solves(ctxs["fp64"], q, a64, u, max(1, min(args.steps, 3)), 1)
     log(f"fp64: {ms_fp64:.2f} ms/solve, {st_fp64[-1]['outer_iters']} iterations")
@@ -745,6 +753,8 @@ def main():
         out["vcycle"] = leg.pop("vcycle")
         out["hbm_3d_257"] = leg
     out["tuning_table"] = tuning_table()
+    if args.tuning_table_out:
+        adr.tuning_table_write(args.tuning_table_out)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, one thread) ...")
         out["cpu_baseline"] = cpu_baseline(args, N, iters_d)
