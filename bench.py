@@ -222,7 +222,7 @@ def run_adjoint(args):
         J = misfit.receiver_misfit(kp, gam, taus, wl.sources, wl.h, wl.omega, rec, d_obs, options=opts, tol=TOL,
                                    stats=stats)
         J.backward()
-        return float(J), kp.grad
+        return float(J.detach()), kp.grad
 
     for _ in range(args.warmup):
         step()
