@@ -168,6 +168,11 @@ typedef struct {
                         /* the residual stage the iterate in LDS z-marching tiles (the   */
                         /* same arithmetic) if a setup-time timing finds them at least   */
                         /* 1% faster; 2: wherever they apply; 0: one lane per node       */
+  int batch_merge;      /* adr_setup_batch: 1 = one group for problems of different grid  */
+                        /* shapes when they nest under the largest (no more levels, no    */
+                        /* more nodes on any level): every launch covers all problems,    */
+                        /* each on its own grid (LDS tiles off; see adr_setup_batch);     */
+                        /* 0 (default) = one group per grid shape                        */
 } adr_options;
 
 typedef struct {
@@ -312,7 +317,12 @@ adr_status adr_get_level_stencil(adr_ctx *ctx, int level, void *planes_c128, int
  * adr_options.full_cycles; the options' own value is ignored) so that the problems of a
  * group stay in lockstep; converged problems are masked off on the device, and groups
  * advance independently.  Per problem the result equals adr_solve with full_cycles = 1
- * bit for bit.  q[i], a[i]: per-problem c128 device arrays as in adr_solve (zero initial
+ * bit for bit.  With batch_merge = 1 (and nesting shapes) all problems form one group:
+ * the arena holds one slot per problem in a common layout sized for the largest, each
+ * launch covers every problem on its own grid of the launch's level (a problem whose
+ * hierarchy ends above that level is skipped; one whose coarsest level it is applies its
+ * coarsest inverse there), with the largest problem's variants and block counts; results
+ * then match adr_solve up to rounding (different reduction partitions), not bit for bit.  q[i], a[i]: per-problem c128 device arrays as in adr_solve (zero initial
  * guess; a[i] is written when problem i finishes).  stats: host array of count entries,
  * or NULL.  Returns ADR_OK if every problem converged, else the first
  * non-convergence/error status; every a[i] holds its best iterate. */
@@ -322,6 +332,7 @@ adr_status adr_setup_batch(int count, const adr_problem *probs, const adr_option
 adr_status adr_solve_batch(adr_batch *b, const void *const *q_c128, void *const *a_c128, double tol, int maxit,
                            adr_stats *stats);
 int adr_batch_size(const adr_batch *b);
+int adr_batch_groups(const adr_batch *b);          /* launch groups (1 when merged); 0 for NULL */
 adr_ctx *adr_batch_context(adr_batch *b, int i);   /* borrowed; owned by the batch */
 void adr_destroy_batch(adr_batch *b);               /* NULL is a no-op */
 

@@ -62,6 +62,7 @@ class AdrOptions(ctypes.Structure):
         ("reaction", ctypes.c_int),
         ("kcycle_levels", ctypes.c_int),
         ("fine_tiles", ctypes.c_int),
+        ("batch_merge", ctypes.c_int),
     ]
 
 
@@ -125,6 +126,7 @@ def load_library(path=LIB_PATH):
         "adr_setup_batch": (I, [I, ctypes.POINTER(AdrProblem), ctypes.POINTER(AdrOptions), I, ctypes.POINTER(P)]),
         "adr_solve_batch": (I, [P, ctypes.POINTER(P), ctypes.POINTER(P), D, I, ctypes.POINTER(AdrStats)]),
         "adr_batch_size": (I, [P]),
+        "adr_batch_groups": (I, [P]),
         "adr_batch_context": (P, [P, I]),
         "adr_destroy_batch": (None, [P]),
         "adr_timer_start": (I, [P, I, I]),
@@ -488,6 +490,10 @@ class Batch:
         if st not in (ADR_OK, ADR_ENOCONV):
             raise AdrError(st, "batch solve failed")
         return st, [s.as_dict() for s in stats]
+
+    def groups(self):
+        """Launch groups of the batch (one per grid shape, or one when merged)."""
+        return int(self._lib.adr_batch_groups(self._ptr))
 
     def close(self):
         if getattr(self, "_ptr", None):

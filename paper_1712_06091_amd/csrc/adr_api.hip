@@ -68,6 +68,36 @@ struct LevelT {
   cx<T> *dinv_adj = nullptr;
 };
 
+// Slot layout of a merged shot group (problems of different grid shapes sharing every
+// launch): each setup allocation is keyed by its source line and the number of
+// allocations that line made before it in the same setup, and every key gets one offset
+// in the slot, sized for the largest problem that makes it.  So buffer k of problem s sits
+// at the same offset in every slot, and the largest problem's pointers, shifted by whole
+// slots, reach every problem's buffers.
+using AllocKey = std::pair<int, int>;
+struct SlotLayout {
+  std::map<AllocKey, std::pair<size_t, size_t>> at;   // key -> (offset, bytes)
+  size_t stride = 0;
+};
+
+// Per-level grid tables of a merged group, in device memory: for launch kind k, level l
+// and slot s, problem s's grid on level l where the launch applies to it, else a grid
+// with N = 0 (the kernels return at once for it).  Relaxation kinds cover the problems
+// for which l is above their coarsest level (they relax on l and restrict from it),
+// coarsest kinds those whose coarsest level is l, full kinds every problem with a level l.
+enum { kRelaxGrids = 0, kFullGrids = 1, kCoarsestGrids = 2, kGridKinds = 3 };
+struct MergedGrids {
+  int levels = 0, cols = 0;       // cols = problems + the spare slot (N = 0 everywhere)
+  std::vector<int> slot_levels;   // levels of the problem in each slot
+  Grid *dev = nullptr;            // [kGridKinds][levels][cols]
+  const Grid *table(int kind, int l) const { return dev + ((size_t)kind * levels + l) * cols; }
+  bool coarsest_at(int l) const {
+    for (int L : slot_levels)
+      if (L - 1 == l) return true;
+    return false;
+  }
+};
+
 }  // namespace
 
 struct adr_ctx {
@@ -130,6 +160,11 @@ struct adr_ctx {
   size_t arena_off = 0, arena_cap = 0;
   const char *arena_lo = nullptr, *arena_hi = nullptr;
   size_t alloc_need = 0;
+  const SlotLayout *layout = nullptr;   // merged groups: keyed offsets instead of a fixed order
+  std::map<int, int> site_seen;          // allocations per source line so far (layout keys)
+  std::vector<std::pair<AllocKey, size_t>> alloc_log;   // key and bytes of every allocation
+  const MergedGrids *mg = nullptr;       // member of a merged group: the group's grid tables
+  int mg_slot = 0;                       // ... and this problem's slot
   bool group_member = false;
   FineParams *Pdev = nullptr;     // device copies of the fine-operator parameters: [0] beta = 0, [1] A_beta
   int *active = nullptr;          // shot-group flag: 1 while the problem is being solved
@@ -180,11 +215,22 @@ struct adr_ctx {
 namespace {
 
 template <typename T>
-adr_status dalloc(adr_ctx *ctx, T **p, size_t count) {
+adr_status dalloc(adr_ctx *ctx, T **p, size_t count, int site = __builtin_LINE()) {
   *p = nullptr;
+  const AllocKey key{site, ctx->site_seen[site]++};
   if (count == 0) return ADR_OK;
   const size_t aligned = (count * sizeof(T) + 255) & ~(size_t)255;
   ctx->alloc_need += aligned;
+  ctx->alloc_log.push_back({key, aligned});
+  if (ctx->arena && ctx->layout) {
+    auto it = ctx->layout->at.find(key);
+    if (it == ctx->layout->at.end() || aligned > it->second.second) {
+      ctx->err = "merged shot-group slot layout has no room for the allocation at line " + std::to_string(site);
+      return ADR_ENOMEM;
+    }
+    *p = (T *)(ctx->arena + it->second.first);
+    return ADR_OK;
+  }
   if (ctx->arena) {
     if (ctx->arena_off + aligned > ctx->arena_cap) {
       ctx->err = "shot-group arena slot exhausted";
@@ -424,6 +470,17 @@ bool pipelined_level(const adr_ctx *ctx, int l, size_t N) {
 // The finest level relaxes by GMRES (Sec. 4.2) instead of damped Jacobi.
 bool fine_gmres(const adr_ctx *ctx) { return ctx->levels > 1 && ctx->relax[0] == ADR_RELAX_GMRES; }
 
+// Merged shot group: the per-problem grids of the launches that follow (kind on level l;
+// `l2` >= 0 adds the full table of level l2 as the transfers' coarse grids).  No-op outside
+// a merged group's launches.
+// The launching problem's pointers are the base, so the tables are offset to its slot
+// (the launches' slot lists hold slots relative to it).
+void use_grids(adr_ctx *ctx, int kind, int l, int l2 = -1) {
+  if (!ctx->mg || adrk::g_shot.count <= 1) return;
+  adrk::g_shot.sh.grid = ctx->mg->table(kind, l) + ctx->mg_slot;
+  adrk::g_shot.sh.grid2 = l2 >= 0 ? ctx->mg->table(kFullGrids, l2) + ctx->mg_slot : nullptr;
+}
+
 template <typename T>
 adr_status alloc_level_vectors(adr_ctx *ctx, LevelT<T> &L, int l) {
   const size_t N = L.G.N;
@@ -482,6 +539,7 @@ void gmres_relax(adr_ctx *ctx, int l, const cx<T> *x0, const cx<T> *b, cx<T> *x_
   const int N = L.G.N, nu = ctx->nu[l], D = ctx->D;
   const double cb = sizeof(cx<T>);
   double *sc = lscal(ctx, l);
+  use_grids(ctx, kRelaxGrids, l);
   const cx<T> *Vp[kMaxNu + 1];
   cx<T> *Zp[kMaxNu + 1];
   for (int j = 0; j <= nu; ++j) {
@@ -507,7 +565,6 @@ void gmres_relax(adr_ctx *ctx, int l, const cx<T> *x0, const cx<T> *b, cx<T> *x_
     // V0 = b - A x0, Z0 = D^{-1} V0, with the norm partials.
     CoarseArgs<T> a{};
     a.split = L.split;
-  a.slabs = L.slabs;
     a.slabs = L.slabs;
     a.G = L.G;
     a.planes = planes;
@@ -533,9 +590,7 @@ void gmres_relax(adr_ctx *ctx, int l, const cx<T> *x0, const cx<T> *b, cx<T> *x_
       V0.v[0] = Vp[0];
       CoarseArgs<T> a{};
       a.split = L.split;
-  a.slabs = L.slabs;
       a.slabs = L.slabs;
-    a.slabs = L.slabs;
       a.G = L.G;
       a.planes = planes;
       a.x = Zp[0];
@@ -588,7 +643,6 @@ void gmres_relax(adr_ctx *ctx, int l, const cx<T> *x0, const cx<T> *b, cx<T> *x_
     // w = A Z_j s_j, with s_j = 1/||V_j|| from the previous kernel's partials.
     CoarseArgs<T> a{};
     a.split = L.split;
-  a.slabs = L.slabs;
     a.slabs = L.slabs;
     a.G = L.G;
     a.planes = planes;
@@ -665,6 +719,7 @@ cx<T> *vcycle(adr_ctx *ctx, int l, const cx<T> *b, cx<T> *out0, ProIn bpin = Pro
   const int D = ctx->D;
   if (l == ctx->levels - 1) {
     cx<T> *x = out0 ? out0 : L.x;
+    use_grids(ctx, kCoarsestGrids, l);
     adrk::dense_gemv<T>(s, L.G.N, ctx->adj ? ctx->Ainv_adj : ctx->Ainv, b, x);
     return x;
   }
@@ -684,6 +739,7 @@ cx<T> *vcycle(adr_ctx *ctx, int l, const cx<T> *b, cx<T> *out0, ProIn bpin = Pro
   // (check_levels enforces this split.)
   const bool jacobi = l == 0 && !fine_gmres(ctx);
   if (jacobi) {
+    use_grids(ctx, kRelaxGrids, 0);
     x = jacobi_sweeps<T>(ctx, ctx->nu[l], nullptr, b, L.xt, xa);
   } else {
     gmres_relax<T>(ctx, l, nullptr, b, xa, bpin, L.r);
@@ -708,6 +764,7 @@ cx<T> *vcycle(adr_ctx *ctx, int l, const cx<T> *b, cx<T> *out0, ProIn bpin = Pro
   // The coarse level (unless it is the coarsest) starts with a GMRES relaxation from
   // zero: the restriction also writes its D^{-1} b and the partials of ||b||^2.
   const bool coarse_relaxes = l + 1 < ctx->levels - 1 && l + 1 != ctx->tail_level;
+  use_grids(ctx, kRelaxGrids, l, l + 1);
   int t1 = tbegin(ctx, ADR_TIMER_TRANSFER, l);
   int rnb = adrk::restrict_full<T>(s, L.G, C.G, D, L.r, C.b, coarse_relaxes ? lvl_dinv(ctx, C) : nullptr,
                                    coarse_relaxes ? C.Z : nullptr, coarse_relaxes ? ctx->part[0] : nullptr);
@@ -717,11 +774,19 @@ cx<T> *vcycle(adr_ctx *ctx, int l, const cx<T> *b, cx<T> *out0, ProIn bpin = Pro
                       (ctx->opt.kcycle_levels <= 0 || l + 1 <= ctx->opt.kcycle_levels);
   cx<T> *ec = krylov ? coarse_fgmres2<T>(ctx, l + 1, cpin)
                                                                 : vcycle<T>(ctx, l + 1, C.b, nullptr, cpin);
+  if (ctx->mg && adrk::g_shot.count > 1 && l + 1 < ctx->levels - 1 && ctx->mg->coarsest_at(l + 1)) {
+    // Merged group: the problems whose coarsest level is l + 1 solve it here, into the
+    // buffer the prolongation reads (the launches on level l + 1 skipped them).
+    use_grids(ctx, kCoarsestGrids, l + 1);
+    adrk::dense_gemv<T>(s, C.G.N, ctx->adj ? ctx->Ainv_adj : ctx->Ainv, C.b, ec);
+  }
+  use_grids(ctx, kRelaxGrids, l, l + 1);
   int t2 = tbegin(ctx, ADR_TIMER_TRANSFER, l);
   adrk::prolong_add<T>(s, L.G, C.G, D, ec, x);
   tend(ctx, t2, cb * ((double)C.G.N + 2.0 * L.G.N));
   // post-relaxation
   if (jacobi) {
+    use_grids(ctx, kRelaxGrids, 0);
     cx<T> *other = (x == xa) ? L.xt : xa;
     return jacobi_sweeps<T>(ctx, ctx->nu[l], x, b, other, x);
   }
@@ -747,9 +812,11 @@ cx<T> *coarse_fgmres2(adr_ctx *ctx, int k, ProIn bpin) {
   const cx<T> *planes = lvl_planes(ctx, L);
   // beta = ||u_0||, s_0 (the restriction into u_0 left the partials in part[0] and
   // D^{-1} u_0 in Z, which the first cycle's relaxation consumes as well)
+  use_grids(ctx, kRelaxGrids, k);
   adrk::reduce_norm(s, bpin, KB, 0, KS + 0);
   // Z_0 = K(u_0)
   vcycle<T>(ctx, k, L.b, L.kz, bpin);
+  use_grids(ctx, kRelaxGrids, k);
   int nb;
   // w = s_0 A Z_0 with the dot against u_0; u_1 = w - H00 s_0 u_0 and its norm
   VecSet<T> V1 = vecset<T>({L.b});
@@ -773,6 +840,7 @@ cx<T> *coarse_fgmres2(adr_ctx *ctx, int k, ProIn bpin) {
   adrk::reduce_norm(s, ProIn{ctx->part[1], nb, 1}, KH + 2 * 1, 1, KS + 1);
   // Z_1 = K(u_1)
   cx<T> *z1 = vcycle<T>(ctx, k, L.ku, L.x);
+  use_grids(ctx, kRelaxGrids, k);
   // w = s_1 A Z_1 with dots against u_0, u_1; u_2 (into r) only for its norm H21
   VecSet<T> V2 = vecset<T>({L.b, L.ku});
   a.x = z1;
@@ -850,6 +918,7 @@ adr_status validate(const adr_problem *p, const adr_options *o, std::string &err
   if (!(o->kcycle_threshold >= 0.0)) { err = "kcycle_threshold must be >= 0"; return ADR_EINVAL; }
   if (o->kcycle_levels < 0) { err = "kcycle_levels must be >= 0"; return ADR_EINVAL; }
   if (o->fine_tiles < 0 || o->fine_tiles > 2) { err = "fine_tiles must be 0, 1 or 2"; return ADR_EINVAL; }
+  if (o->batch_merge < 0 || o->batch_merge > 1) { err = "batch_merge must be 0 or 1"; return ADR_EINVAL; }
   if (o->pipeline_max_nodes < 0) { err = "pipeline_max_nodes must be >= 0"; return ADR_EINVAL; }
   if (o->advection != ADR_ADV_UPWIND && o->advection != ADR_ADV_CENTRAL) { err = "bad advection"; return ADR_EINVAL; }
   if (!(o->outer_beta >= 0.0 && o->outer_beta <= 1.0)) { err = "outer_beta must be in [0, 1]"; return ADR_EINVAL; }
@@ -1377,9 +1446,11 @@ void enqueue_vcycle(adr_ctx *ctx, const cx<double> *v, void *z, bool z_is_c128) 
     return;
   }
   if (ctx->opt.prec == ADR_PREC_MIXED) {
+    use_grids(ctx, kFullGrids, 0);
     adrk::convert<float, double>(s, N, v, ctx->b32);
     if (z_is_c128) {
       vcycle<float>(ctx, 0, ctx->b32, ctx->z32);
+      use_grids(ctx, kFullGrids, 0);
       adrk::convert<double, float>(s, N, ctx->z32, (cx<double> *)z);
     } else {
       vcycle<float>(ctx, 0, ctx->b32, (cx<float> *)z);
@@ -1446,7 +1517,7 @@ namespace {
 // (adjoint preparation) use hipMalloc.  `group_member` adds the group's right-hand-side
 // and solution buffers.
 adr_status setup_ctx(const adr_problem *prob, const adr_options *opt, hipStream_t stream, char *slot,
-                     size_t slot_cap, bool group_member, adr_ctx **out) {
+                     size_t slot_cap, bool group_member, adr_ctx **out, const SlotLayout *layout = nullptr) {
   if (!out) {
     g_setup_error = "null output pointer";
     return ADR_EINVAL;
@@ -1471,6 +1542,7 @@ adr_status setup_ctx(const adr_problem *prob, const adr_options *opt, hipStream_
     ctx->arena_cap = slot_cap;
     ctx->arena_lo = slot;
     ctx->arena_hi = slot + slot_cap;
+    ctx->layout = layout;
   }
   ctx->D = prob->ndim;
   ctx->G0 = make_grid(ctx->D, prob->n);
@@ -1494,6 +1566,7 @@ adr_status setup_ctx(const adr_problem *prob, const adr_options *opt, hipStream_
   }
   ctx->setup_ms = now_ms() - t0;
   ctx->arena = nullptr;   // later allocations are ordinary ones
+  ctx->layout = nullptr;
   *out = ctx;
   return ADR_OK;
 }
@@ -1528,6 +1601,7 @@ void adr_default_options(adr_options *o) {
   o->rescaled = 0;
   o->pipeline_max_nodes = 0x7fffffff;   // every coarse level
   o->fine_tiles = 1;
+  o->batch_merge = 0;
 }
 
 adr_status adr_setup(const adr_problem *prob, const adr_options *opt, void *stream, adr_ctx **out) {
@@ -1767,6 +1841,7 @@ adr_status solver_device(const Solver &A, adr_ctx *ctx, const cx<double> *q, cx<
   const int N = ctx->G0.N, D = ctx->D;
   const bool mixed = ctx->opt.prec == ADR_PREC_MIXED;
   auto Vp = [&](int j) { return ctx->Vo + (size_t)j * N; };
+  use_grids(ctx, kFullGrids, 0);
   switch (A.next) {
     case Solver::START: {
       adrk::phase(s, N, q, ctx->tau, ctx->omega, +1, ctx->qh, &ctx->Pdev[0].omega);
@@ -1786,6 +1861,7 @@ adr_status solver_device(const Solver &A, adr_ctx *ctx, const cx<double> *q, cx<
       // V_0 = r / ||r||, the norm from the partials of the residual just computed.
       if (j == 0) adrk::normalize(s, N, ctx->ro, ProIn{ctx->part[0], A.nb, 1}, Vp(0));
       ADR_TRY(precondition(ctx, Vp(j), zslot(ctx, j), !mixed));
+      use_grids(ctx, kFullGrids, 0);
       VecSet<double> Vs{};
       Vs.count = j + 1;
       for (int i = 0; i <= j; ++i) Vs.v[i] = Vp(i);
@@ -2195,14 +2271,23 @@ adr_status adr_adjoint_source(adr_ctx *ctx, const int *idx, const void *r, int n
 
 struct adr_batch {
   struct Group {
-    std::vector<int> members;   // batch indices, slot order
+    std::vector<int> members;   // batch indices, slot order (a merged group's lead first)
     char *arena = nullptr;
     size_t stride = 0;
+    bool merged = false;        // problems of different grid shapes (keyed slot layout)
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
+    // Slots the launches cover: the unfinished problems, padded to a power of two (at most
+    // the group size) with the spare slot after the last problem, whose flag stays 0, so
+    // that a captured cycle serves every count in its bucket.
+    int *slots_dev = nullptr;   // device copy of the list
+    int *slots_pin = nullptr;   // pinned staging for its updates
+    std::vector<int> slots_cur; // the list on the device
   };
   std::vector<adr_ctx *> ctx;   // per problem (contexts live in their group's arena)
   std::vector<Group> groups;
+  SlotLayout layout;            // merged group: the common slot layout
+  MergedGrids mg;               // merged group: per-level grid tables
   std::vector<hipStream_t> streams;
   int *pin_flags = nullptr;     // pinned host ints {0, 1} for the device flags
   std::string err;
@@ -2215,10 +2300,150 @@ void free_batch(adr_batch *b) {
   for (auto &g : b->groups) {
     if (g.ev) hipEventDestroy(g.ev);
     if (g.arena) hipFree(g.arena);
+    if (g.slots_dev) hipFree(g.slots_dev);
+    if (g.slots_pin) hipHostFree(g.slots_pin);
   }
   for (hipStream_t s : b->streams) hipStreamDestroy(s);
   if (b->pin_flags) hipHostFree(b->pin_flags);
+  if (b->mg.dev) hipFree(b->mg.dev);
   delete b;
+}
+Grid level_grid(const adr_ctx *c, int l) { return c->opt.prec == ADR_PREC_FP64 ? c->lv64[l].G : c->lv32[l].G; }
+
+// A group's slot list buffers, and the spare slot's flag (after the last problem's slot,
+// at the same offset as slot 0's) set to 0.
+bool init_slots(adr_batch *b, adr_batch::Group &g) {
+  const size_t n = g.members.size();
+  if (hipMalloc((void **)&g.slots_dev, n * sizeof(int)) != hipSuccess) return false;
+  if (hipHostMalloc((void **)&g.slots_pin, n * sizeof(int), hipHostMallocDefault) != hipSuccess) return false;
+  const adr_ctx *lead = b->ctx[g.members[0]];
+  int *spare_flag = (int *)((char *)lead->active + n * g.stride);
+  return hipMemset(spare_flag, 0, sizeof(int)) == hipSuccess;
+}
+
+// One group for problems of different grid shapes (adr_options.batch_merge).  A
+// measuring setup of each shape records its allocations and level grids.  The shapes
+// must nest under one lead shape -- as many levels or more, and as many nodes or more on
+// every level -- else this returns false (st = ADR_OK) and the batch is grouped by shape.
+// Otherwise every problem gets a slot of the common keyed layout (the lead shape's first
+// problem in slot 0, whose pointers every launch passes), plus one spare slot at the end
+// of the arena, and the per-level grid tables are built.
+bool setup_merged(adr_batch *b, const adr_problem *probs, const adr_options *opt, adr_status &st) {
+  struct Shape {
+    std::vector<std::pair<AllocKey, size_t>> log;
+    std::vector<Grid> grids;
+    int D = 0;
+  };
+  std::vector<Shape> shapes;
+  hipStream_t s0 = b->streams[0];
+  for (auto &g : b->groups) {
+    adr_ctx *m = nullptr;
+    st = setup_ctx(&probs[g.members[0]], opt, s0, nullptr, 0, true, &m);
+    if (st != ADR_OK) {
+      g_setup_error = "shot " + std::to_string(g.members[0]) + ": " + g_setup_error;
+      return false;
+    }
+    Shape sh;
+    sh.log = m->alloc_log;
+    sh.D = m->D;
+    for (int l = 0; l < m->levels; ++l) sh.grids.push_back(level_grid(m, l));
+    adr_destroy(m);
+    shapes.push_back(std::move(sh));
+  }
+  size_t lead = 0;
+  for (size_t k = 1; k < shapes.size(); ++k) {
+    const Shape &a = shapes[k], &c = shapes[lead];
+    if (a.grids.size() > c.grids.size() || (a.grids.size() == c.grids.size() && a.grids[0].N > c.grids[0].N)) lead = k;
+  }
+  const Shape &ld = shapes[lead];
+  for (const Shape &sh : shapes) {
+    if (sh.D != ld.D || sh.grids.size() > ld.grids.size()) return false;
+    for (size_t l = 0; l < sh.grids.size(); ++l)
+      if (sh.grids[l].N > ld.grids[l].N) return false;
+  }
+  // Common layout: the lead shape's allocations in its order, then the keys only other
+  // shapes make; each key sized for the largest allocation made under it.
+  std::map<AllocKey, size_t> bytes;
+  std::vector<AllocKey> order;
+  auto add = [&](const Shape &sh) {
+    for (const auto &[key, n] : sh.log) {
+      auto it = bytes.find(key);
+      if (it == bytes.end()) {
+        bytes.emplace(key, n);
+        order.push_back(key);
+      } else if (n > it->second) {
+        it->second = n;
+      }
+    }
+  };
+  add(ld);
+  for (size_t k = 0; k < shapes.size(); ++k)
+    if (k != lead) add(shapes[k]);
+  size_t off = 0;
+  for (const AllocKey &key : order) {
+    b->layout.at[key] = {off, bytes[key]};
+    off += bytes[key];
+  }
+  b->layout.stride = (off + 65535) & ~(size_t)65535;
+  adr_batch::Group g;
+  g.merged = true;
+  g.stride = b->layout.stride;
+  g.stream = b->streams[0];
+  g.members = b->groups[lead].members;
+  for (size_t k = 0; k < b->groups.size(); ++k)
+    if (k != lead) g.members.insert(g.members.end(), b->groups[k].members.begin(), b->groups[k].members.end());
+  b->groups.assign(1, g);
+  adr_batch::Group &G = b->groups[0];
+  const size_t count = G.members.size();
+  auto hip_fail = [&](const char *what) {
+    g_setup_error = what;
+    st = ADR_EHIP;
+    return false;
+  };
+  if (hipEventCreateWithFlags(&G.ev, hipEventDisableTiming) != hipSuccess) return hip_fail("hipEventCreate failed");
+  if (hipMalloc((void **)&G.arena, G.stride * (count + 1)) != hipSuccess) {
+    g_setup_error = "merged shot-group arena of " + std::to_string(G.stride * (count + 1)) + " bytes";
+    st = ADR_ENOMEM;
+    return false;
+  }
+  for (size_t k = 0; k < count; ++k) {
+    const int i = G.members[k];
+    adr_ctx *c = nullptr;
+    st = setup_ctx(&probs[i], opt, G.stream, G.arena + k * G.stride, G.stride, true, &c, &b->layout);
+    if (st != ADR_OK) {
+      g_setup_error = "shot " + std::to_string(i) + ": " + g_setup_error;
+      return false;
+    }
+    b->ctx[i] = c;
+  }
+  // Grid tables (the spare slot's column stays N = 0).
+  const int Lmax = (int)ld.grids.size();
+  const size_t cols = count + 1;
+  std::vector<Grid> host((size_t)kGridKinds * Lmax * cols, Grid{});
+  b->mg.levels = Lmax;
+  b->mg.cols = (int)cols;
+  b->mg.slot_levels.assign(count, 0);
+  for (size_t k = 0; k < count; ++k) {
+    const adr_ctx *c = b->ctx[G.members[k]];
+    const int Lk = c->levels;
+    b->mg.slot_levels[k] = Lk;
+    for (int l = 0; l < Lk; ++l) {
+      const Grid gl = level_grid(c, l);
+      auto at = [&](int kind) -> Grid & { return host[((size_t)kind * Lmax + l) * cols + k]; };
+      at(kFullGrids) = gl;
+      if (l < Lk - 1) at(kRelaxGrids) = gl;
+      else at(kCoarsestGrids) = gl;
+    }
+  }
+  if (hipMalloc((void **)&b->mg.dev, host.size() * sizeof(Grid)) != hipSuccess) return hip_fail("hipMalloc of grid tables failed");
+  if (hipMemcpy(b->mg.dev, host.data(), host.size() * sizeof(Grid), hipMemcpyHostToDevice) != hipSuccess)
+    return hip_fail("grid table copy failed");
+  for (size_t k = 0; k < count; ++k) {
+    b->ctx[G.members[k]]->mg = &b->mg;
+    b->ctx[G.members[k]]->mg_slot = (int)k;
+  }
+  if (!init_slots(b, G)) return hip_fail("shot-group slot list allocation failed");
+  return true;
 }
 }  // namespace
 
@@ -2264,6 +2489,15 @@ adr_status adr_setup_batch(int count, const adr_problem *probs, const adr_option
     b->groups[it->second].members.push_back(i);
   }
   b->ctx.assign(count, nullptr);
+  if (opt && opt->batch_merge && b->groups.size() > 1) {
+    adr_status st = ADR_OK;
+    const bool merged = setup_merged(b, probs, opt, st);
+    if (st != ADR_OK) return fail(st, g_setup_error);
+    if (merged) {
+      *out = b;
+      return ADR_OK;
+    }
+  }
   for (size_t gi = 0; gi < b->groups.size(); ++gi) {
     auto &g = b->groups[gi];
     g.stream = b->streams[gi % b->streams.size()];
@@ -2275,8 +2509,9 @@ adr_status adr_setup_batch(int count, const adr_problem *probs, const adr_option
     const size_t need = m->alloc_need;
     adr_destroy(m);
     g.stride = (need + 65535) & ~(size_t)65535;
-    if (hipMalloc((void **)&g.arena, g.stride * g.members.size()) != hipSuccess)
-      return fail(ADR_ENOMEM, "shot-group arena of " + std::to_string(g.stride * g.members.size()) + " bytes");
+    const size_t arena_bytes = g.stride * (g.members.size() + 1);   // + the spare slot
+    if (hipMalloc((void **)&g.arena, arena_bytes) != hipSuccess)
+      return fail(ADR_ENOMEM, "shot-group arena of " + std::to_string(arena_bytes) + " bytes");
     for (size_t k = 0; k < g.members.size(); ++k) {
       const int i = g.members[k];
       adr_ctx *c = nullptr;
@@ -2286,12 +2521,15 @@ adr_status adr_setup_batch(int count, const adr_problem *probs, const adr_option
       if (c->arena_off != need)
         return fail(ADR_EINVAL, "shot " + std::to_string(i) + ": layout differs from its group's first problem");
     }
+    if (!init_slots(b, g)) return fail(ADR_EHIP, "shot-group slot list allocation failed");
   }
   *out = b;
   return ADR_OK;
 }
 
 int adr_batch_size(const adr_batch *b) { return b ? (int)b->ctx.size() : 0; }
+
+int adr_batch_groups(const adr_batch *b) { return b ? (int)b->groups.size() : 0; }
 
 adr_ctx *adr_batch_context(adr_batch *b, int i) {
   if (!b || i < 0 || i >= (int)b->ctx.size()) return nullptr;
@@ -2321,6 +2559,7 @@ adr_status adr_solve_batch(adr_batch *b, const void *const *q, void *const *a, d
       solver_init(S[i], c, c->qin, c->xg, tol, maxit, 0);
       S[i].full = true;
     }
+
   // Enqueue the next action of group g for its live problems; false when none is left.
   auto launch = [&](adr_batch::Group &g, adr_status &st) -> bool {
     std::vector<int> live;
@@ -2336,15 +2575,58 @@ adr_status adr_solve_batch(adr_batch *b, const void *const *q, void *const *a, d
       }
     for (int i : live)
       if ((st = solver_pre(S[i])) != ADR_OK) return false;
-    adr_ctx *lead = b->ctx[g.members[0]];
-    adrk::g_shot.count = (int)g.members.size();
-    adrk::g_shot.sh = Shot{(long long)g.stride, lead->active};
+    // The launching problem: slot 0, or in a merged group the largest unfinished problem
+    // (most levels, then most nodes), so that the launches shrink as large problems finish.
+    const int n = (int)g.members.size();
+    int k0 = 0;
+    if (g.merged) {
+      k0 = -1;
+      for (int k = 0; k < n; ++k) {
+        const adr_ctx *c = b->ctx[g.members[k]];
+        if (S[g.members[k]].next == Solver::DONE) continue;
+        if (k0 < 0) {
+          k0 = k;
+          continue;
+        }
+        const adr_ctx *c0 = b->ctx[g.members[k0]];
+        if (c->levels > c0->levels || (c->levels == c0->levels && c->G0.N > c0->G0.N)) k0 = k;
+      }
+    }
+    adr_ctx *lead = b->ctx[g.members[k0]];
+    // The launches cover the live problems' slots (relative to the launching one), padded
+    // with the spare slot.
+    // (At least 2 in a group of several: a launch for one problem takes the plain,
+    // unshifted kernels, which address slot 0.)
+    int bucket = n >= 2 ? 2 : 1;
+    while (bucket < (int)live.size()) bucket *= 2;
+    if (bucket > n) bucket = n;
+    std::vector<int> list;
+    for (int k = 0; k < n; ++k)
+      if (S[g.members[k]].next != Solver::DONE) list.push_back(k - k0);
+    list.resize(bucket, n - k0);
+    if (list != g.slots_cur) {
+      // The previous update's copy has completed: this group's last action, enqueued
+      // after it, has.
+      std::copy(list.begin(), list.end(), g.slots_pin);
+      hipError_t e = hipMemcpyAsync(g.slots_dev, g.slots_pin, bucket * sizeof(int), hipMemcpyHostToDevice, g.stream);
+      if (e != hipSuccess) {
+        st = hip_fail("slot list copy", e);
+        return false;
+      }
+      g.slots_cur = list;
+    }
+    adrk::g_shot.count = bucket;
+    adrk::g_shot.sh = Shot{(long long)g.stride, lead->active, nullptr, nullptr, g.slots_dev};
     st = solver_device(A, lead, lead->qin, lead->xg);
     adrk::g_shot = adrk::ShotLaunch{};
     if (st != ADR_OK) {
       b->err = lead->err;
       return false;
     }
+    // This action's fine-grid reductions came in the launching problem's block count:
+    // its read-backs, and the next action's first step, which sums the partials of this
+    // one's residual, take that count (the step above used the previous action's).
+    for (int i : live) S[i].nb = launch_blocks_red(lead->G0.N);
     for (int i : live)
       if ((st = solver_post(S[i])) != ADR_OK) return false;
     hipError_t e = hipEventRecord(g.ev, g.stream);

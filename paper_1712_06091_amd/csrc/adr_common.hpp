@@ -145,14 +145,19 @@ inline int launch_blocks_red(long long N) {
 
 // ------------------------------------------------------------------------------------
 // Shot groups.  One launch can serve `count` problems whose device data are laid out at a
-// constant byte stride (one arena slot per problem): blockIdx.y is the problem, every
-// pointer argument refers to problem 0 and is shifted by blockIdx.y * stride, and a
-// problem whose flag (an int at `active` + blockIdx.y * stride) is 0 exits at once.
+// constant byte stride (one arena slot per problem): blockIdx.y selects the problem's
+// slot (through `slots` when set), every pointer argument refers to slot 0 and is shifted
+// by slot * stride, and a problem whose flag (an int at `active` + slot * stride) is 0
+// exits at once.
 // stride = 0, active = NULL is an ordinary single-problem launch.
 // ------------------------------------------------------------------------------------
 struct Shot {
   long long stride;
   const int *active;
+  const Grid *grid;    // merged shapes: each problem's grid on the launch's level (else NULL)
+  const Grid *grid2;   // merged shapes, transfers: each problem's coarse grid
+  const int *slots;    // slot of blockIdx.y (the problems still being solved, padded with a
+                       // spare slot whose flag is 0); NULL: slot = blockIdx.y
 };
 template <typename P>
 __device__ __forceinline__ P *shot_ptr(P *p, long long off) {
@@ -162,12 +167,49 @@ __device__ __forceinline__ P *shot_ptr(P *p, long long off) {
 // launches) compiles to the plain kernel, the GRP = true instance (shot-group launches)
 // shifts its pointers and skips inactive problems.  ADR_SHOT_ENTER declares shot_off_;
 // ADR_SHOT_LIVE returns from an inactive problem (uniform per block).
-#define ADR_SHOT_ENTER(sh) const long long shot_off_ = GRP ? (long long)blockIdx.y * (sh).stride : 0LL
+#define ADR_SHOT_ENTER(sh)                                                                     \
+  [[maybe_unused]] const int shot_slot_ = GRP ? ((sh).slots ? (sh).slots[blockIdx.y] : (int)blockIdx.y) : 0; \
+  const long long shot_off_ = GRP ? (long long)shot_slot_ * (sh).stride : 0LL
 #define ADR_SHOT_LIVE(sh)                                                                    \
   do {                                                                                       \
     if constexpr (GRP) {                                                                     \
       if ((sh).active && !*(const int *)((const char *)(sh).active + shot_off_)) return;    \
     }                                                                                        \
+  } while (0)
+// Groups that merge problems of different grid shapes (one slot layout for all, sized
+// for the largest) take each problem's own grid (and coarse grid, for the transfers) from
+// the launch's per-problem table instead of the argument, which is the largest problem's;
+// a problem without that level (N = 0 in the table) exits.  Block counts stay those of
+// the largest problem, so a smaller problem's blocks own shorter chunks.
+#define ADR_SHOT_GRID(sh, G)                               \
+  do {                                                     \
+    if constexpr (GRP) {                                   \
+      if ((sh).grid) {                                     \
+        (G) = (sh).grid[shot_slot_];                       \
+        if ((G).N == 0) return;                            \
+      }                                                    \
+    }                                                      \
+  } while (0)
+#define ADR_SHOT_GRID2(sh, G)                              \
+  do {                                                     \
+    if constexpr (GRP) {                                   \
+      if ((sh).grid2) (G) = (sh).grid2[shot_slot_];        \
+    }                                                      \
+  } while (0)
+#define ADR_SHOT_N(sh, n)                                  \
+  do {                                                     \
+    if constexpr (GRP) {                                   \
+      if ((sh).grid) {                                     \
+        (n) = (sh).grid[shot_slot_].N;                     \
+        if ((n) == 0) return;                              \
+      }                                                    \
+    }                                                      \
+  } while (0)
+#define ADR_SHOT_SKIP(sh)                                  \
+  do {                                                     \
+    if constexpr (GRP) {                                   \
+      if ((sh).grid && (sh).grid[shot_slot_].N == 0) return; \
+    }                                                      \
   } while (0)
 #define ADR_SHIFT(p)                        \
   do {                                      \

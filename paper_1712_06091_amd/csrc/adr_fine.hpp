@@ -32,7 +32,7 @@ struct FineParams {
   int central;     // 1: central advection (eq. londDiff) off the faces of each axis
 };
 
-// Shift the coefficient planes to problem blockIdx.y of a shot group (see Shot).
+// Shift the coefficient planes to the launch's problem of a shot group (see Shot).
 template <typename T>
 __device__ __forceinline__ void shift_fine_coef(FineCoef<T> &C, long long off) {
 #pragma unroll

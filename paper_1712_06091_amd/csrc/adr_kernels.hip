@@ -225,6 +225,7 @@ template void stencil_diag_inv<float>(hipStream_t, int, const cx<float> *, cx<fl
 template <typename To, typename Ti, bool GRP>
 __global__ __launch_bounds__(ADR_BLOCK) void k_convert(long long n, const cx<Ti> *in, cx<To> *out, Shot sh) {
   ADR_SHOT_ENTER(sh);
+  ADR_SHOT_N(sh, n);
   ADR_SHIFT(in);
   ADR_SHIFT(out);
   ADR_SHOT_LIVE(sh);
@@ -260,6 +261,7 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_fine_apply(Grid G, FineCoef<T> C,
                                                           int mode, VecSet<To> V, double *pout,
                                                           const FineParams *Pd, Shot sh) {
   ADR_SHOT_ENTER(sh);
+  ADR_SHOT_GRID(sh, G);
   if constexpr (GRP) shift_fine_coef(C, shot_off_);
   if constexpr (GRP) {
     if (Pd) P = *shot_ptr(Pd, shot_off_);
@@ -369,6 +371,7 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_fine_jacobi(Grid G, FineCoef<T> C
                                                            const cx<T> *__restrict__ b, cx<T> *__restrict__ xout,
                                                            T weight, const FineParams *Pd, Shot sh) {
   ADR_SHOT_ENTER(sh);
+  ADR_SHOT_GRID(sh, G);
   if constexpr (GRP) shift_fine_coef(C, shot_off_);
   if constexpr (GRP) {
     if (Pd) P = *shot_ptr(Pd, shot_off_);
@@ -563,7 +566,8 @@ bool fine_lds(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const F
   if constexpr (sizeof(T) != 4) {
     return false;
   } else {
-    const int nb = fine_lds_blocks(G, D);
+    // The tiles' geometry follows the launch's own grid: not in merged-shape groups.
+    const int nb = g_shot.sh.grid ? 0 : fine_lds_blocks(G, D);
     if (nb == 0 || !x) return false;
     if (mode == 0)
       launch_g(k_fine_lds<T, 0, false>, k_fine_lds<T, 0, true>, nb, s, G, C, P, x, b, out, (T)weight, Pd);
@@ -836,6 +840,7 @@ void receiver_residual(hipStream_t s, int nrec, const int *idx, const cx<double>
 template <bool GRP>
 __global__ __launch_bounds__(ADR_BLOCK) void k_zero(long long n, cx<double> *x, Shot sh) {
   ADR_SHOT_ENTER(sh);
+  ADR_SHOT_N(sh, n);
   ADR_SHIFT(x);
   ADR_SHOT_LIVE(sh);
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
@@ -855,6 +860,7 @@ void zero(hipStream_t s, long long n, cx<double> *x) { launch_g(k_zero<false>, k
 template <bool GRP>
 __global__ __launch_bounds__(ADR_BLOCK) void k_copy(long long n, const cx<double> *in, cx<double> *out, Shot sh) {
   ADR_SHOT_ENTER(sh);
+  ADR_SHOT_N(sh, n);
   ADR_SHIFT(in);
   ADR_SHIFT(out);
   ADR_SHOT_LIVE(sh);
@@ -1234,6 +1240,7 @@ __device__ __forceinline__ void coarse_apply_body(Grid G, const cx<T> *__restric
                                                   const cx<T> *__restrict__ dinv, cx<T> *__restrict__ zout, int mode,
                                                   VecSet<T> V, double *pout, Shot sh) {
   ADR_SHOT_ENTER(sh);
+  ADR_SHOT_GRID(sh, G);
   ADR_SHIFT(planes);
   ADR_SHIFT(x);
   ADR_SHIFT(pin.partials);
@@ -1407,6 +1414,7 @@ __global__ __launch_bounds__(ADR_BLOCK) __attribute__((amdgpu_waves_per_eu(1, 4)
     cx<T> *__restrict__ uo, cx<T> *__restrict__ zo, cx<T> *__restrict__ go, cx<T> *__restrict__ yo, double *pout,
     Shot sh) {
   ADR_SHOT_ENTER(sh);
+  ADR_SHOT_GRID(sh, G);
   ADR_SHIFT(planes);
   ADR_SHIFT(yin);
   ADR_SHIFT(pin.partials);
@@ -1501,6 +1509,7 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_pipe_final(int N, ProIn pin, cons
                                                           double *hsub, double *sout, VecSet<T> U, VecSet<T> Gs,
                                                           cx<T> *__restrict__ uo, double *pout, Shot sh) {
   ADR_SHOT_ENTER(sh);
+  ADR_SHOT_N(sh, N);
   ADR_SHIFT(pin.partials);
   ADR_SHIFT(scales);
   ADR_SHIFT(hcol);
@@ -1531,7 +1540,7 @@ template <typename T>
 int pipe_step(hipStream_t s, int D, int split, int slabs, const Grid &G, const cx<T> *planes, const cx<T> *yin,
               ProIn pin, const double *scales, double *hcol, double *hsub, double *sout, const VecSet<T> &U,
               const VecSet<T> &Gs, const cx<T> *dinv, cx<T> *uo, cx<T> *zo, cx<T> *go, cx<T> *yo, double *pout) {
-  const int nlds = (split == 8 && sizeof(T) == 4) ? lds_blocks(G, D, slabs) : 0;
+  const int nlds = (split == 8 && sizeof(T) == 4 && !g_shot.sh.grid) ? lds_blocks(G, D, slabs) : 0;
   if (split == 8 && nlds == 0) split = 1;
   const int nb = split == 8 ? nlds : (split == 4 ? launch_blocks_red(4LL * G.N) : launch_blocks_red(G.N));
 #define ADR_PIPE_CASE(n)                                                                                        \
@@ -1646,7 +1655,7 @@ int coarse_apply(hipStream_t s, int D, const CoarseArgs<T> &a, const VecSet<T> *
   if (dots) V = *dots;
   const bool red = want_norm || V.count > 0;
   if (a.split == 8) {
-    const int nb = sizeof(T) == 4 ? lds_blocks(a.G, D, a.slabs) : 0;
+    const int nb = (sizeof(T) == 4 && !g_shot.sh.grid) ? lds_blocks(a.G, D, a.slabs) : 0;
     if (nb > 0) {
       if (want_norm) dispatch_coarse_split<T, 3, true>(s, nb, a, V);
       else dispatch_coarse_split<T, 3, false>(s, nb, a, V);
@@ -1679,6 +1688,7 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_fine_gapply(Grid G, FineCoef<T> C
                                                            int mode, VecSet<T> V, double *pout, const FineParams *Pd,
                                                            Shot sh) {
   ADR_SHOT_ENTER(sh);
+  ADR_SHOT_GRID(sh, G);
   if constexpr (GRP) shift_fine_coef(C, shot_off_);
   if constexpr (GRP) {
     if (Pd) P = *shot_ptr(Pd, shot_off_);
@@ -1866,6 +1876,8 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_restrict(Grid Gf, Grid Gc, const 
                                                         cx<T> *__restrict__ rc, const cx<T> *__restrict__ dinv_c,
                                                         cx<T> *__restrict__ z_c, double *pout, Shot sh) {
   ADR_SHOT_ENTER(sh);
+  ADR_SHOT_GRID(sh, Gf);
+  ADR_SHOT_GRID2(sh, Gc);
   ADR_SHIFT(rf);
   ADR_SHIFT(rc);
   ADR_SHIFT(dinv_c);
@@ -1943,6 +1955,8 @@ template <typename T, int D, bool GRP>
 __global__ __launch_bounds__(ADR_BLOCK) void k_prolong_add(Grid Gf, Grid Gc, const cx<T> *__restrict__ ec,
                                                            cx<T> *__restrict__ xf, Shot sh) {
   ADR_SHOT_ENTER(sh);
+  ADR_SHOT_GRID(sh, Gf);
+  ADR_SHOT_GRID2(sh, Gc);
   ADR_SHIFT(ec);
   ADR_SHIFT(xf);
   ADR_SHOT_LIVE(sh);
@@ -1972,6 +1986,7 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_orth_step(int N, const cx<T> *__r
                                                          const cx<T> *__restrict__ dinv, cx<T> *__restrict__ vnew,
                                                          cx<T> *__restrict__ znew, double *pout, Shot sh) {
   ADR_SHOT_ENTER(sh);
+  ADR_SHOT_N(sh, N);
   ADR_SHIFT(w);
   if constexpr (GRP) shift_set<NV>(V, shot_off_);
   ADR_SHIFT(pin.partials);
@@ -2033,6 +2048,7 @@ template <typename T, bool GRP>
 __global__ __launch_bounds__(ADR_BLOCK) void k_norm2(int N, const cx<T> *__restrict__ x, const cx<T> *__restrict__ dinv,
                                                      cx<T> *__restrict__ z, double *pout, Shot sh) {
   ADR_SHOT_ENTER(sh);
+  ADR_SHOT_N(sh, N);
   ADR_SHIFT(x);
   ADR_SHIFT(dinv);
   ADR_SHIFT(z);
@@ -2115,6 +2131,7 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_gmres_update(int N, const cx<T> *
                                                             const double *scales, cx<T> *__restrict__ xout,
                                                             VecSet<T> Vr, cx<T> *__restrict__ rout, Shot sh) {
   ADR_SHOT_ENTER(sh);
+  ADR_SHOT_N(sh, N);
   ADR_SHIFT(x0);
   if constexpr (GRP) shift_set<NV>(Z, shot_off_);
   ADR_SHIFT(pin.partials);
@@ -2215,6 +2232,7 @@ template <bool GRP>
 __global__ __launch_bounds__(ADR_BLOCK) void k_reduce_norm(ProIn pin, double *norm_out, int norm_cplx,
                                                            double *inv_out, Shot sh) {
   ADR_SHOT_ENTER(sh);
+  ADR_SHOT_SKIP(sh);
   ADR_SHIFT(pin.partials);
   ADR_SHIFT(norm_out);
   ADR_SHIFT(inv_out);
@@ -2241,6 +2259,7 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_fgmres2_update(int N, const cx<T>
                                                               const double *scales, double threshold,
                                                               cx<T> *__restrict__ e, Shot sh) {
   ADR_SHOT_ENTER(sh);
+  ADR_SHOT_N(sh, N);
   ADR_SHIFT(Z0);
   ADR_SHIFT(Z1);
   ADR_SHIFT(pin.partials);
@@ -2306,6 +2325,7 @@ template <int NV, bool GRP>
 __global__ __launch_bounds__(ADR_BLOCK) void k_outer_orth1(int N, cx<double> *__restrict__ w, VecSet<double> V,
                                                            ProIn pin, double *h_out, double *pout, Shot sh) {
   ADR_SHOT_ENTER(sh);
+  ADR_SHOT_N(sh, N);
   ADR_SHIFT(w);
   if constexpr (GRP) shift_set<NV>(V, shot_off_);
   ADR_SHIFT(pin.partials);
@@ -2369,6 +2389,7 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_outer_orth2(int N, const cx<doubl
                                                            ProIn pin, double *red_out, cx<double> *__restrict__ vnew,
                                                            Shot sh) {
   ADR_SHOT_ENTER(sh);
+  ADR_SHOT_N(sh, N);
   ADR_SHIFT(w);
   if constexpr (GRP) shift_set<NV>(V, shot_off_);
   ADR_SHIFT(pin.partials);
@@ -2414,6 +2435,7 @@ template <typename Tz, int NV, bool GRP>
 __global__ __launch_bounds__(ADR_BLOCK) void k_multi_axpy(int N, cx<double> *__restrict__ x, VecSet<Tz> Z,
                                                           const double *y, Shot sh) {
   ADR_SHOT_ENTER(sh);
+  ADR_SHOT_N(sh, N);
   ADR_SHIFT(x);
   if constexpr (GRP) shift_set<NV>(Z, shot_off_);
   ADR_SHIFT(y);
@@ -2451,6 +2473,7 @@ template <bool GRP>
 __global__ __launch_bounds__(ADR_BLOCK) void k_normalize(int N, const cx<double> *__restrict__ x, ProIn pin,
                                                          cx<double> *__restrict__ y, Shot sh) {
   ADR_SHOT_ENTER(sh);
+  ADR_SHOT_N(sh, N);
   ADR_SHIFT(x);
   ADR_SHIFT(pin.partials);
   ADR_SHIFT(y);
@@ -2470,6 +2493,7 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_phase(int N, const cx<double> *__
                                                      const double *__restrict__ tau, double omega, int sign,
                                                      cx<double> *out, const double *omega_dev, Shot sh) {
   ADR_SHOT_ENTER(sh);
+  ADR_SHOT_N(sh, N);
   ADR_SHIFT(in);
   ADR_SHIFT(tau);
   ADR_SHIFT(out);
@@ -2510,6 +2534,7 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_dense_gemv(int N, const cx<double
                                                           const cx<T> *__restrict__ b, cx<T> *__restrict__ x,
                                                           Shot sh) {
   ADR_SHOT_ENTER(sh);
+  ADR_SHOT_N(sh, N);
   ADR_SHIFT(Ainv);
   ADR_SHIFT(b);
   ADR_SHIFT(x);

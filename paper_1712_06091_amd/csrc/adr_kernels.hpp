@@ -20,7 +20,7 @@ struct ProIn {
   int nb, K;
 };
 
-// Shift the first NV pointers of a set to problem blockIdx.y of a shot group.
+// Shift the first NV pointers of a set to the launch's problem of a shot group.
 template <int NV, typename T>
 __device__ __forceinline__ void shift_set(VecSet<T> &V, long long off) {
 #pragma unroll
