@@ -47,6 +47,7 @@ def parse():
                     help="compare_3d_129: shifted-Laplacian alpha of the preconditioner")
     ap.add_argument("--batch-maxit", type=int, default=3000, help="FGMRES iteration cap per shot (batch)")
     ap.add_argument("--no-looped", action="store_true", help="batch: skip the one-shot-at-a-time comparison")
+    ap.add_argument("--no-batch", action="store_true", help="default line: skip the batched-shot leg")
     ap.add_argument("--batch-merge", type=int, default=2, choices=[0, 1, 2],
                     help="batch: 0 = one group per grid shape, 1 = one merged group, 2 = both")
     ap.add_argument("--mixed-only", action="store_true", help="with --profile-only: skip the FP64 solves")
@@ -309,20 +310,16 @@ def batched(shots, qs, outs, opts, args, maxit):
     return ms, stats, setup_s
 
 
-def run_batch(args):
-    """64 2D shots (sizes from {257^2, 513^2, 1025^2}, random media, fast-marching tau):
-    lockstep batched solves over several streams in mixed precision (the value) and in
-    FP64, against the same shots solved one after another in FP64 (adr_solve), all to the
-    same true relative residual 1e-6."""
+def batch_figures(wls, args, merges, steps, warmup, looped=True):
+    """Batched solves of the shots ``wls`` to 1e-6 (mixed and FP64; one group per grid
+    shape and/or one merged group, per ``merges``) and, with ``looped``, the same shots
+    solved one after another in FP64 (adr_solve).  Returns the legs' figures."""
     import numpy as np
     import torch
 
     from paper_1712_06091_amd import adr
-    from paper_1712_06091_amd import workloads as W
 
     dev = torch.device("cuda:0")
-    wls = W.batch_2d()
-    log(f"batch: {len(wls)} shots, {sum(w.nodes for w in wls) / 1e6:.1f} M nodes")
     t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
     shots = [{"kappa2": t(w.kappa2, torch.float64), "tau": t(w.tau, torch.float64),
               "gamma": t(w.gamma, torch.float64), "h": w.h, "omega": w.omega, "src": w.src} for w in wls]
@@ -330,17 +327,18 @@ def run_batch(args):
     outs = [torch.empty(w.shape, dtype=torch.complex128, device=dev) for w in wls]
     nodes = sum(w.nodes for w in wls)
     maxit = args.batch_maxit
+    bargs = argparse.Namespace(**vars(args))
+    bargs.steps, bargs.warmup = steps, warmup
     legs = {}
-    merges = {0: (0,), 1: (1,), 2: (0, 1)}[args.batch_merge]
     for merge in merges:
         for prec in ("mixed", "fp64"):
             opts = adr.default_options(prec=prec, cycle=args.cycle, batch_merge=merge, **pipe_opt(args))
-            ms, stats, setup_s = batched(shots, qs, outs, opts, args, maxit)
+            ms, stats, setup_s = batched(shots, qs, outs, opts, bargs, maxit)
             its = sorted(s["outer_iters"] for s in stats)
-            key = prec + ("_merged" if merge else "")
             by_size = {}
             for w, st_ in zip(wls, stats):
                 by_size[w.shape[0]] = max(by_size.get(w.shape[0], 0), st_["outer_iters"])
+            key = prec + ("_merged" if merge else "")
             legs[key] = {"value": nodes / (ms * 1e-3) / 1e6, "ms_per_step": ms, "setup_s": setup_s,
                          "outer_iters": sum(its),
                          "outer_iters_per_shot": {"min": its[0], "median": its[len(its) // 2], "max": its[-1]},
@@ -348,32 +346,50 @@ def run_batch(args):
                          "final_relres_max": max(s["relres"] for s in stats)}
             log(f"batched {key}: {ms:.1f} ms per batch; iterations min {its[0]} median {its[len(its) // 2]} "
                 f"max {its[-1]}")
-    looped = None
-    if not args.no_looped:
+    lp = None
+    if looped:
         opts = adr.default_options(prec="fp64", cycle=args.cycle, **pipe_opt(args))
         ms_loop, iters_loop, worst = looped_batch(shots, qs, outs, opts, maxit)
-        looped = {"precision": "fp64", "value": nodes / (ms_loop * 1e-3) / 1e6, "ms": ms_loop,
-                  "outer_iters": iters_loop, "final_relres_max": worst}
+        lp = {"precision": "fp64", "value": nodes / (ms_loop * 1e-3) / 1e6, "ms": ms_loop,
+              "outer_iters": iters_loop, "final_relres_max": worst}
         log(f"looped fp64: {ms_loop:.1f} ms")
-    # The value: the one-group-per-shape launches unless only the merged group ran.
     m = legs["mixed"] if "mixed" in legs else legs["mixed_merged"]
+    return {
+        "shots": len(wls), "nodes": nodes, "sizes": sorted({w.shape[0] for w in wls}), "tol": TOL,
+        "steps": steps, "warmup": warmup,
+        "batched_mixed": legs.get("mixed"), "batched_fp64": legs.get("fp64"),
+        "batched_mixed_merged": legs.get("mixed_merged"), "batched_fp64_merged": legs.get("fp64_merged"),
+        "looped_fp64": lp,
+        "batched_mixed_over_looped_fp64": None if lp is None else lp["ms"] / m["ms_per_step"],
+        "batched_fp64_over_looped_fp64": (None if lp is None or "fp64" not in legs
+                                          else lp["ms"] / legs["fp64"]["ms_per_step"]),
+    }
+
+
+def run_batch(args):
+    """64 2D shots (sizes from {257^2, 513^2, 1025^2}, random media, fast-marching tau):
+    lockstep batched solves over several streams in mixed precision (the value) and in
+    FP64, against the same shots solved one after another in FP64 (adr_solve), all to the
+    same true relative residual 1e-6."""
+    from paper_1712_06091_amd import workloads as W
+
+    wls = W.batch_2d(workers=8)
+    log(f"batch: {len(wls)} shots, {sum(w.nodes for w in wls) / 1e6:.1f} M nodes")
+    merges = {0: (0,), 1: (1,), 2: (0, 1)}[args.batch_merge]
+    fig = batch_figures(wls, args, merges, args.steps, args.warmup, looped=not args.no_looped)
+    m = fig["batched_mixed"] or fig["batched_mixed_merged"]
     out = {
         "metric": "ADR amplitude solves: Mpoints/s to 1e-6 residual (batched shots)",
         "value": m["value"], "unit": "Mpoints/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": m["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "c64 V-cycle / c128 FGMRES", "data": "synthetic",
-        "config": {"workload": "batch_2d_64_shots", "shots": len(wls), "nodes": nodes,
-                   "sizes": sorted({w.shape[0] for w in wls}), "streams": args.streams, "tol": TOL,
-                   "cycle": args.cycle, "maxit": maxit,
+        "config": {"workload": "batch_2d_64_shots", "shots": fig["shots"], "nodes": fig["nodes"],
+                   "sizes": fig["sizes"], "streams": args.streams, "tol": TOL,
+                   "cycle": args.cycle, "maxit": args.batch_maxit,
                    "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "0")) or None},
-        "batched_mixed": legs.get("mixed"), "batched_fp64": legs.get("fp64"),
-        "batched_mixed_merged": legs.get("mixed_merged"), "batched_fp64_merged": legs.get("fp64_merged"),
-        "looped_fp64": looped,
-        "batched_mixed_over_looped_fp64": None if looped is None else looped["ms"] / m["ms_per_step"],
-        "batched_fp64_over_looped_fp64": (None if looped is None or "fp64" not in legs
-                                          else looped["ms"] / legs["fp64"]["ms_per_step"]),
         "outer_iters": m["outer_iters"],
     }
+    out.update({k: v for k, v in fig.items() if k.startswith(("batched", "looped"))})
     print(json.dumps(out))
 
 
@@ -667,6 +683,14 @@ def main():
         run_compare(args)
         return
 
+    batch_wls = None
+    if args.workload == "3d_129" and not args.no_batch and not args.profile_only:
+        # The batched-shot leg's inputs, with the fast marching in forked processes before
+        # anything initializes the GPU.
+        from paper_1712_06091_amd import workloads as W
+        batch_wls = W.batch_2d(workers=8)
+        log(f"batch leg inputs: {len(batch_wls)} shots")
+
     import torch
 
     from paper_1712_06091_amd import adr
@@ -765,6 +789,10 @@ def main():
         out["roofline"] = leg.pop("roofline")
         out["vcycle"] = leg.pop("vcycle")
         out["hbm_3d_257"] = leg
+    if batch_wls is not None:
+        # Config 4: 64 2D shots, batched (one group per grid shape) in mixed precision and
+        # FP64 against the same shots solved one after another in FP64; one timed batch each.
+        out["batch_2d_64"] = batch_figures(batch_wls, args, (0,), 1, 0, looped=True)
     out["tuning_table"] = tuning_table()
     if args.tuning_table_out:
         adr.tuning_table_write(args.tuning_table_out)

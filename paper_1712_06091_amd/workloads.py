@@ -218,21 +218,30 @@ def config_3d_257():
     return random_medium(257, 3, seed=3, name="3d_257_random")
 
 
-def batch_2d(count=64, seed=4, sizes=(257, 513, 1025), margin=12, name="batch_2d"):
+def batch_2d(count=64, seed=4, sizes=(257, 513, 1025), margin=12, name="batch_2d", workers=1):
     """``count`` 2D shots on the unit square: grid sizes drawn uniformly from ``sizes``
     and source nodes uniformly at least ``margin`` nodes from the faces (both seeded by
     ``seed``), medium v = 2 (1 + 0.2 eta) with eta seeded by 1000*seed + i, tau by factored
-    fast marching, 10 points per wavelength per shot."""
+    fast marching, 10 points per wavelength per shot.  ``workers`` > 1 runs the fast
+    marching in a pool of forked processes (call it before the GPU is initialized)."""
     rng = np.random.default_rng(seed)
     ns = rng.choice(np.asarray(sizes), size=count)
-    shots = []
+    media = []
     for i, n in enumerate(ns):
         n = int(n)
         h = 1.0 / (n - 1)
         src = tuple(int(v) for v in rng.integers(margin, n - margin, size=2))
         v = smooth_random_velocity((n, n), h, 1000 * seed + i)
-        kappa2 = 1.0 / v ** 2
-        tau = factored_traveltime(kappa2, h, src)
+        media.append((n, h, src, v))
+    jobs = [(1.0 / v ** 2, h, src) for n, h, src, v in media]
+    if workers > 1 and count > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(min(workers, count)) as pool:
+            taus = pool.map(_fm_worker, jobs)
+    else:
+        taus = [_fm_worker(j) for j in jobs]
+    shots = []
+    for i, ((n, h, src, v), (kappa2, _, _), tau) in enumerate(zip(media, jobs, taus)):
         omega = omega_for_ppw(float(v.min()), h)
         gamma = absorbing_layer((n, n), h, omega, 10 * h)
         shots.append(Workload(f"{name}_{i}", (n, n), h, omega, src, kappa2, tau, gamma, extra={"seed": 1000 * seed + i}))
