@@ -253,7 +253,7 @@ void dfree(adr_ctx *ctx, void *p) {
   if (!p) return;
   const char *c = (const char *)p;
   if (ctx->arena_lo && c >= ctx->arena_lo && c < ctx->arena_hi) return;
-  hipFree(p);
+  (void)hipFree(p);
 }
 
 #define ADR_TRY(x)                   \
@@ -444,13 +444,14 @@ int tbegin(adr_ctx *ctx, int kind, int level) {
   auto &T = ctx->timer;
   if (T.kind != kind || (T.level >= 0 && T.level != level)) return -1;
   if (T.used + 2 > (int)T.ev.size()) return -1;   // pool exhausted: stop timing
-  hipEventRecord(T.ev[T.used], ctx->stream);
+  // A failed record surfaces in adr_timer_stop, which reads every event pair.
+  (void)hipEventRecord(T.ev[T.used], ctx->stream);
   return T.used;
 }
 void tend(adr_ctx *ctx, int slot, double bytes) {
   if (slot < 0) return;
   auto &T = ctx->timer;
-  hipEventRecord(T.ev[slot + 1], ctx->stream);
+  (void)hipEventRecord(T.ev[slot + 1], ctx->stream);
   T.used = slot + 2;
   T.launches += 1;
   T.bytes += bytes;
@@ -1019,23 +1020,23 @@ adr_status tune_split(adr_ctx *ctx, int l) {
     a.mode = 0;
     a.pout = ctx->part[0];
     for (int w = 0; w < 2; ++w) adrk::coarse_apply<T>(s, ctx->D, a, &V1, false);
-    hipEventRecord(e0, s);
+    hipError_t e = hipEventRecord(e0, s);
     constexpr int reps = 8;
     for (int r = 0; r < reps; ++r) adrk::coarse_apply<T>(s, ctx->D, a, &V1, false);
-    hipEventRecord(e1, s);
-    hipError_t e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.f;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
     if (e != hipSuccess) {
-      hipEventDestroy(e0);
-      hipEventDestroy(e1);
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
       ctx->err = std::string("split tuning: ") + hipGetErrorString(e);
       return ADR_EHIP;
     }
     if (split == 1 || ms < 0.90f * best.ms) best = TuneEntry{split, split == 8 ? slabs : 0, ms};
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   std::lock_guard<std::mutex> g(g_tune_mu);
   auto ins = g_tune.emplace(key, best);
   L.split = ins.first->second.split;
@@ -1075,20 +1076,20 @@ adr_status tune_fine_tiles(adr_ctx *ctx) {
       else adrk::fine_jacobi<T>(s, L.G, ctx->D, C, P, in, L.b, out, ctx->opt.jacobi_weight, ctx->Pdev + 1);
     };
     for (int w = 0; w < 2; ++w) sweep(w);
-    hipEventRecord(e0, s);
+    hipError_t e = hipEventRecord(e0, s);
     for (int r = 0; r < 8; ++r) sweep(r);
-    hipEventRecord(e1, s);
-    hipError_t e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
     if (e == hipSuccess) e = hipEventElapsedTime(&ms[v], e0, e1);
     if (e != hipSuccess) {
-      hipEventDestroy(e0);
-      hipEventDestroy(e1);
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
       ctx->err = std::string("fine tile tuning: ") + hipGetErrorString(e);
       return ADR_EHIP;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   ctx->fine_tiles_on = ms[1] < 0.99f * ms[0];
   return ADR_OK;
 }
@@ -1304,7 +1305,7 @@ void free_ctx(adr_ctx *ctx) {
   F(ctx->Ainv);
   F(ctx->scal);
   F(ctx->osc);
-  if (ctx->hpin) hipHostFree(ctx->hpin);
+  if (ctx->hpin) (void)hipHostFree(ctx->hpin);
   F(ctx->part[0]);
   F(ctx->part[1]);
   F(ctx->Vo);
@@ -1320,12 +1321,12 @@ void free_ctx(adr_ctx *ctx) {
   F(ctx->active);
   F(ctx->qin);
   F(ctx->xg);
-  for (auto &e : ctx->timer.ev) hipEventDestroy(e);
+  for (auto &e : ctx->timer.ev) (void)hipEventDestroy(e);
   for (auto &g : ctx->graphs) {
-    hipGraphExecDestroy(g.e);
-    hipGraphDestroy(g.g);
+    (void)hipGraphExecDestroy(g.e);
+    (void)hipGraphDestroy(g.g);
   }
-  if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   delete ctx;
 }
 
@@ -1477,8 +1478,8 @@ adr_status precondition(adr_ctx *ctx, const cx<double> *v, void *z, bool z_is_c1
                                  [](const adr_ctx::GraphEntry &x, const adr_ctx::GraphEntry &y) {
                                    return x.last_use < y.last_use;
                                  });
-      hipGraphExecDestroy(it->e);
-      hipGraphDestroy(it->g);
+      (void)hipGraphExecDestroy(it->e);
+      (void)hipGraphDestroy(it->g);
       ctx->graphs.erase(it);
     }
     adr_ctx::GraphEntry ge;
@@ -1610,7 +1611,7 @@ adr_status adr_setup(const adr_problem *prob, const adr_options *opt, void *stre
 
 void adr_destroy(adr_ctx *ctx) {
   if (!ctx) return;
-  hipStreamSynchronize(ctx->stream);
+  (void)hipStreamSynchronize(ctx->stream);
   free_ctx(ctx);
 }
 
@@ -2298,14 +2299,14 @@ void free_batch(adr_batch *b) {
   if (!b) return;
   for (adr_ctx *c : b->ctx) adr_destroy(c);
   for (auto &g : b->groups) {
-    if (g.ev) hipEventDestroy(g.ev);
-    if (g.arena) hipFree(g.arena);
-    if (g.slots_dev) hipFree(g.slots_dev);
-    if (g.slots_pin) hipHostFree(g.slots_pin);
+    if (g.ev) (void)hipEventDestroy(g.ev);
+    if (g.arena) (void)hipFree(g.arena);
+    if (g.slots_dev) (void)hipFree(g.slots_dev);
+    if (g.slots_pin) (void)hipHostFree(g.slots_pin);
   }
-  for (hipStream_t s : b->streams) hipStreamDestroy(s);
-  if (b->pin_flags) hipHostFree(b->pin_flags);
-  if (b->mg.dev) hipFree(b->mg.dev);
+  for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
+  if (b->pin_flags) (void)hipHostFree(b->pin_flags);
+  if (b->mg.dev) (void)hipFree(b->mg.dev);
   delete b;
 }
 Grid level_grid(const adr_ctx *c, int l) { return c->opt.prec == ADR_PREC_FP64 ? c->lv64[l].G : c->lv32[l].G; }
