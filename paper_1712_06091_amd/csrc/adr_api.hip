@@ -65,6 +65,8 @@ struct LevelT {
   cx<T> *Gs = nullptr;       // pipelined relaxation: kMaxNu x N stored A D^{-1} u_i (see k_pipe_step)
   cx<T> *Yp = nullptr;       // pipelined relaxation: 2 x N, D^{-1} Gs_{k-1} (ping-pong)
   cx<T> *planes_adj = nullptr;   // conjugate-transposed stencil (adjoint solves)
+  cx<T> *planes_t = nullptr;     // segment-tiled copy of planes for the LDS apply (split 8)
+  cx<T> *planes_adj_t = nullptr; // ... and of planes_adj
   cx<T> *dinv_adj = nullptr;
 };
 
@@ -436,6 +438,8 @@ double *lscal(adr_ctx *ctx, int l) { return ctx->scal + (size_t)l * kScalPerLeve
 template <typename T>
 const cx<T> *lvl_planes(const adr_ctx *ctx, const LevelT<T> &L) { return ctx->adj ? L.planes_adj : L.planes; }
 template <typename T>
+const cx<T> *lvl_planes_t(const adr_ctx *ctx, const LevelT<T> &L) { return ctx->adj ? L.planes_adj_t : L.planes_t; }
+template <typename T>
 const cx<T> *lvl_dinv(const adr_ctx *ctx, const LevelT<T> &L) { return ctx->adj ? L.dinv_adj : L.dinv; }
 
 // Timed-launch brackets: tbegin returns an event slot (or -1 when this launch is not the
@@ -569,6 +573,7 @@ void gmres_relax(adr_ctx *ctx, int l, const cx<T> *x0, const cx<T> *b, cx<T> *x_
     a.slabs = L.slabs;
     a.G = L.G;
     a.planes = planes;
+    a.planes_t = lvl_planes_t(ctx, L);
     a.x = x0;
     a.b = b;
     a.y = L.V;
@@ -594,6 +599,7 @@ void gmres_relax(adr_ctx *ctx, int l, const cx<T> *x0, const cx<T> *b, cx<T> *x_
       a.slabs = L.slabs;
       a.G = L.G;
       a.planes = planes;
+      a.planes_t = lvl_planes_t(ctx, L);
       a.x = Zp[0];
       a.pin = ProIn{ctx->part[cur], nb, 1};
       a.norm_out = sc + kBeta;
@@ -623,8 +629,9 @@ void gmres_relax(adr_ctx *ctx, int l, const cx<T> *x0, const cx<T> *b, cx<T> *x_
       const ProIn pin{ctx->part[cur], nb, 2 * k + (k >= 2 ? 1 : 0)};
       if (k < nu) {
         int t0 = tbegin(ctx, ADR_TIMER_COARSE_APPLY, l);
-        nb = adrk::pipe_step<T>(s, D, L.split, L.slabs, L.G, planes, Yb[(k - 1) & 1], pin, sc + kS, hcol, hsub, sout, U, Gv,
-                                dinv, L.V + (size_t)k * N, Zp[k], Gp[k], Yb[k & 1], ctx->part[cur ^ 1]);
+        nb = adrk::pipe_step<T>(s, D, L.split, L.slabs, L.G, planes, lvl_planes_t(ctx, L), Yb[(k - 1) & 1], pin,
+                                sc + kS, hcol, hsub, sout, U, Gv, dinv, L.V + (size_t)k * N, Zp[k], Gp[k],
+                                Yb[k & 1], ctx->part[cur ^ 1]);
         // planes, the gathered D^{-1} Gs_{k-1}, U and Gs (k each), dinv; u, z, G, D^{-1} G written
         tend(ctx, t0, (double)N * cb * (L.S + 6 + 2 * k));
       } else {
@@ -647,6 +654,7 @@ void gmres_relax(adr_ctx *ctx, int l, const cx<T> *x0, const cx<T> *b, cx<T> *x_
     a.slabs = L.slabs;
     a.G = L.G;
     a.planes = planes;
+    a.planes_t = lvl_planes_t(ctx, L);
     a.x = Zp[j];
     a.pin = ProIn{ctx->part[cur], nb, 1};
     a.norm_out = (j == 0) ? sc + kBeta : sc + kH + 2 * ((j - 1) * kLdH + j);
@@ -826,6 +834,7 @@ cx<T> *coarse_fgmres2(adr_ctx *ctx, int k, ProIn bpin) {
   a.slabs = L.slabs;
   a.G = L.G;
   a.planes = planes;
+  a.planes_t = lvl_planes_t(ctx, L);
   a.x = L.kz;
   a.sdev = KS + 0;
   a.y = L.w;
@@ -1015,6 +1024,7 @@ adr_status tune_split(adr_ctx *ctx, int l) {
     a.slabs = slabs;
     a.G = L.G;
     a.planes = L.planes;
+    a.planes_t = L.planes_t;
     a.x = L.x;
     a.y = L.w;
     a.mode = 0;
@@ -1196,6 +1206,16 @@ adr_status build_hierarchy(adr_ctx *ctx) {
     if (st != ADR_OK) break;
     const int centre = (Sc - 1) / 2;
     adrk::stencil_diag_inv<T>(s, lv[l].G.N, lv[l].planes + (size_t)centre * lv[l].G.N, lv[l].dinv);
+    // The LDS apply's segment-tiled copy of the planes, on the relaxed 3D FP32 levels where
+    // that variant applies (released after tuning unless it is chosen).
+    if (sizeof(T) == 4 && l < ctx->levels - 1) {
+      const long long nt = adrk::tiled_plane_count(lv[l].G, D, Sc);
+      if (nt > 0) {
+        st = dalloc(ctx, &lv[l].planes_t, (size_t)nt);
+        if (st != ADR_OK) break;
+        adrk::tile_planes<T>(s, lv[l].G, Sc, lv[l].planes, lv[l].planes_t);
+      }
+    }
   }
   for (int i = 0; i < 2; ++i) {
     dfree(ctx, tri_start[i]);
@@ -1256,7 +1276,13 @@ adr_status build_hierarchy(adr_ctx *ctx) {
   ADR_HIP(hipMemcpy(ctx->Ainv, inv.data(), inv.size() * sizeof(cx<double>), hipMemcpyHostToDevice));
   ctx->h_inv.swap(inv);
   for (int l = 0; l < ctx->levels; ++l) ADR_TRY(alloc_level_vectors<T>(ctx, lv[l], l));
-  for (int l = 1; l < ctx->levels - 1; ++l) ADR_TRY(tune_split<T>(ctx, l));
+  for (int l = 1; l < ctx->levels - 1; ++l) {
+    ADR_TRY(tune_split<T>(ctx, l));
+    if (lv[l].split != 8 && lv[l].planes_t) {
+      dfree(ctx, lv[l].planes_t);
+      lv[l].planes_t = nullptr;
+    }
+  }
   if (ctx->levels > 1) ADR_TRY(tune_fine_tiles<T>(ctx));
   // Coarse tail: from the first coarse level with at most tail_max_nodes nodes (V-cycle;
   // the Krylov cycle's coarse GMRES steps stay on the multi-kernel path).
@@ -1297,7 +1323,7 @@ void free_ctx(adr_ctx *ctx) {
                     (void *)b.Gs, (void *)b.Yp, (void *)a.planes_adj,
                     (void *)a.dinv_adj, (void *)b.planes, (void *)b.dinv, (void *)b.x, (void *)b.xt, (void *)b.b,
                     (void *)b.r, (void *)b.w, (void *)b.V, (void *)b.Z, (void *)b.ku, (void *)b.kz,
-                    (void *)b.planes_adj, (void *)b.dinv_adj})
+                    (void *)b.planes_adj, (void *)b.dinv_adj, (void *)b.planes_t, (void *)b.planes_adj_t})
       F(p);
   }
   F(ctx->off_coarse);
@@ -1746,6 +1772,10 @@ adr_status prepare_adjoint_levels(adr_ctx *ctx) {
     if (L.S == 0) continue;
     ADR_TRY(dalloc(ctx, &L.planes_adj, (size_t)L.S * L.G.N));
     adrk::adjoint_planes<T>(ctx->stream, L.G, ctx->D, L.planes, L.planes_adj);
+    if (L.planes_t) {
+      ADR_TRY(dalloc(ctx, &L.planes_adj_t, (size_t)adrk::tiled_plane_count(L.G, ctx->D, L.S)));
+      adrk::tile_planes<T>(ctx->stream, L.G, L.S, L.planes_adj, L.planes_adj_t);
+    }
     ADR_TRY(dalloc(ctx, &L.dinv_adj, L.G.N));
     adrk::stencil_diag_inv<T>(ctx->stream, L.G.N, L.planes_adj + (size_t)((L.S - 1) / 2) * L.G.N, L.dinv_adj);
   }

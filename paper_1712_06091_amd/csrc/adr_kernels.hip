@@ -1114,8 +1114,10 @@ __device__ __forceinline__ cx<T> stencil_part_of(int w, const cx<T> *__restrict_
 // of a plane (the segment and 2 rows + 2 nodes either side, so every in-plane offset
 // (dx, dy) of the stencil lands in it) sits in a ring of kLdsSlots plane windows in LDS;
 // while plane z is computed from windows z-2..z+2, the window of plane z+3 is loaded into
-// registers and stored afterwards, one barrier per plane.  The stencil planes themselves
-// stream from HBM as before (one coalesced load per entry).  Window entries outside the
+// registers and stored afterwards, one barrier per plane.  The stencil planes stream
+// from the segment-tiled copy (tile_planes): per block and z-plane one contiguous run of
+// 81 x kLdsSeg entries, where the SoA planes would be 81 separate streams (a plane-read
+// probe of 129^3 measured 200 us tiled against 385 us SoA).  Window entries outside the
 // grid are zero; in-plane offsets that wrap to the next row meet zero stencil entries.
 // The sums run in the order of stencil_part, so the result equals the one-lane variant.
 constexpr int kLdsSeg = ADR_BLOCK;
@@ -1139,7 +1141,7 @@ __device__ __forceinline__ void lds_march3(const Grid &G, const cx<T> *__restric
                                            const cx<T> *__restrict__ x, F &&finish) {
   __shared__ cx<T> win[kLdsSlots][kLdsWin];
   constexpr OffTable<3> OT = make_off_table<3>();
-  const int n0 = G.n[0], nxy = G.n[0] * G.n[1], n2 = G.n[2], N = G.N;
+  const int n0 = G.n[0], nxy = G.n[0] * G.n[1], n2 = G.n[2];
   const int nseg = (nxy + kLdsSeg - 1) / kLdsSeg;
   const int nslab = gridDim.x / nseg;
   const int lb = logical_block();
@@ -1184,7 +1186,8 @@ __device__ __forceinline__ void lds_march3(const Grid &G, const cx<T> *__restric
       int sl[5];
 #pragma unroll
       for (int d = -2; d <= 2; ++d) sl[d + 2] = (z + d + kLdsSlots) % kLdsSlots;
-      const cx<T> *pl = planes + i;
+      // This segment's 81 entries of plane z are one contiguous run (tiled layout).
+      const cx<T> *pl = planes + ((size_t)z * nseg + seg) * (81 * kLdsSeg) + tid;
       constexpr int CH = 27;
       cx<T> acc[2] = {mk<T>(T(0), T(0)), mk<T>(T(0), T(0))};
 #pragma unroll
@@ -1192,7 +1195,7 @@ __device__ __forceinline__ void lds_march3(const Grid &G, const cx<T> *__restric
         // A batch of plane loads in flight; the LDS operands are read as they are used.
         cx<T> pv[CH];
 #pragma unroll
-        for (int q = 0; q < CH; ++q) pv[q] = lds_plane_load(pl + (size_t)(c + q) * N);
+        for (int q = 0; q < CH; ++q) pv[q] = lds_plane_load(pl + (size_t)(c + q) * kLdsSeg);
 #pragma unroll
         for (int q = 0; q < CH; ++q) {
           const int p = c + q;
@@ -1217,6 +1220,39 @@ int lds_max_slabs(const Grid &G, int D) {
   if (nslab > G.n[2] / kLdsMinPlanes) nslab = G.n[2] / kLdsMinPlanes;
   return nslab >= 1 ? nslab : 0;
 }
+long long tiled_plane_count(const Grid &G, int D, int S) {
+  if (lds_max_slabs(G, D) == 0) return 0;
+  const long long nseg = (G.n[0] * G.n[1] + kLdsSeg - 1) / kLdsSeg;
+  return (long long)G.n[2] * nseg * S * kLdsSeg;
+}
+
+// tiled[((z nseg + seg) S + p) kLdsSeg + k] = planes[p N + z nxy + seg kLdsSeg + k], zero
+// past the end of a plane.
+template <typename T>
+__global__ __launch_bounds__(ADR_BLOCK) void k_tile_planes(Grid G, int S, const cx<T> *__restrict__ planes,
+                                                           cx<T> *__restrict__ tiled, long long total) {
+  const int nxy = G.n[0] * G.n[1];
+  const int nseg = (nxy + kLdsSeg - 1) / kLdsSeg;
+  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(t % kLdsSeg);
+    const long long r = t / kLdsSeg;
+    const int p = (int)(r % S);
+    const long long zs = r / S;
+    const int seg = (int)(zs % nseg), z = (int)(zs / nseg);
+    const int ip = seg * kLdsSeg + k;
+    tiled[t] = ip < nxy ? planes[(size_t)p * G.N + (size_t)z * nxy + ip] : mk<T>(T(0), T(0));
+  }
+}
+template <typename T>
+void tile_planes(hipStream_t s, const Grid &G, int S, const cx<T> *planes, cx<T> *tiled) {
+  const long long total = tiled_plane_count(G, 3, S);
+  if (total == 0) return;
+  ADR_LAUNCH(k_tile_planes<T>, launch_blocks(total), s, G, S, planes, tiled, total);
+}
+template void tile_planes<float>(hipStream_t, const Grid &, int, const cx<float> *, cx<float> *);
+template void tile_planes<double>(hipStream_t, const Grid &, int, const cx<double> *, cx<double> *);
+
 int lds_blocks(const Grid &G, int D, int slabs) {
   const int mx = lds_max_slabs(G, D);
   if (mx == 0) return 0;
@@ -1537,17 +1573,18 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_pipe_final(int N, ProIn pin, cons
 }
 
 template <typename T>
-int pipe_step(hipStream_t s, int D, int split, int slabs, const Grid &G, const cx<T> *planes, const cx<T> *yin,
-              ProIn pin, const double *scales, double *hcol, double *hsub, double *sout, const VecSet<T> &U,
-              const VecSet<T> &Gs, const cx<T> *dinv, cx<T> *uo, cx<T> *zo, cx<T> *go, cx<T> *yo, double *pout) {
-  const int nlds = (split == 8 && sizeof(T) == 4 && !g_shot.sh.grid) ? lds_blocks(G, D, slabs) : 0;
+int pipe_step(hipStream_t s, int D, int split, int slabs, const Grid &G, const cx<T> *planes, const cx<T> *planes_t,
+              const cx<T> *yin, ProIn pin, const double *scales, double *hcol, double *hsub, double *sout,
+              const VecSet<T> &U, const VecSet<T> &Gs, const cx<T> *dinv, cx<T> *uo, cx<T> *zo, cx<T> *go, cx<T> *yo,
+              double *pout) {
+  const int nlds = (split == 8 && sizeof(T) == 4 && planes_t && !g_shot.sh.grid) ? lds_blocks(G, D, slabs) : 0;
   if (split == 8 && nlds == 0) split = 1;
   const int nb = split == 8 ? nlds : (split == 4 ? launch_blocks_red(4LL * G.N) : launch_blocks_red(G.N));
 #define ADR_PIPE_CASE(n)                                                                                        \
   case n:                                                                                                       \
     if (split == 8) {                                                                                           \
       if constexpr (sizeof(T) == 4)                                                                             \
-        launch_g(k_pipe_step<T, 3, n, 8, false>, k_pipe_step<T, 3, n, 8, true>, nb, s, G, planes, yin, pin, scales, \
+        launch_g(k_pipe_step<T, 3, n, 8, false>, k_pipe_step<T, 3, n, 8, true>, nb, s, G, planes_t, yin, pin, scales, \
                  hcol, hsub, sout, U, Gs, dinv, uo, zo, go, yo, pout);                                           \
     } else if (D == 2) {                                                                                        \
       if (split == 4)                                                                                           \
@@ -1587,11 +1624,13 @@ int pipe_final(hipStream_t s, int N, ProIn pin, const double *scales, double *hc
   }
   return nb;
 }
-template int pipe_step<float>(hipStream_t, int, int, int, const Grid &, const cx<float> *, const cx<float> *, ProIn,
+template int pipe_step<float>(hipStream_t, int, int, int, const Grid &, const cx<float> *, const cx<float> *,
+                              const cx<float> *, ProIn,
                               const double *, double *, double *, double *, const VecSet<float> &,
                               const VecSet<float> &, const cx<float> *, cx<float> *, cx<float> *, cx<float> *,
                               cx<float> *, double *);
-template int pipe_step<double>(hipStream_t, int, int, int, const Grid &, const cx<double> *, const cx<double> *, ProIn,
+template int pipe_step<double>(hipStream_t, int, int, int, const Grid &, const cx<double> *, const cx<double> *,
+                              const cx<double> *, ProIn,
                                const double *, double *, double *, double *, const VecSet<double> &,
                                const VecSet<double> &, const cx<double> *, cx<double> *, cx<double> *,
                                cx<double> *, cx<double> *, double *);
@@ -1655,10 +1694,13 @@ int coarse_apply(hipStream_t s, int D, const CoarseArgs<T> &a, const VecSet<T> *
   if (dots) V = *dots;
   const bool red = want_norm || V.count > 0;
   if (a.split == 8) {
-    const int nb = (sizeof(T) == 4 && !g_shot.sh.grid) ? lds_blocks(a.G, D, a.slabs) : 0;
+    const int nb = (sizeof(T) == 4 && a.planes_t && !g_shot.sh.grid) ? lds_blocks(a.G, D, a.slabs) : 0;
     if (nb > 0) {
-      if (want_norm) dispatch_coarse_split<T, 3, true>(s, nb, a, V);
-      else dispatch_coarse_split<T, 3, false>(s, nb, a, V);
+      // The LDS variant streams the segment-tiled copy of the planes.
+      CoarseArgs<T> at = a;
+      at.planes = a.planes_t;
+      if (want_norm) dispatch_coarse_split<T, 3, true>(s, nb, at, V);
+      else dispatch_coarse_split<T, 3, false>(s, nb, at, V);
       return nb;
     }
     CoarseArgs<T> a1 = a;

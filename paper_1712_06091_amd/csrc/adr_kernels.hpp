@@ -47,6 +47,8 @@ struct CoarseArgs {
   int split;             // 4: four wavefronts share each node's stencil sum; 8: LDS z-marching
                          // tiles (3D FP32, see lds_blocks); else one lane
   int slabs;             // split 8: z-slabs per launch (0 = the most)
+  const cx<T> *planes_t; // split 8: the same planes tiled by segment (see tile_planes); the
+                         // apply falls back to one lane when NULL
 };
 
 // Coarse tail (one workgroup): per-level data and the level range.
@@ -114,7 +116,8 @@ void fine_jacobi(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, cons
 // Pipelined GMRES relaxation steps (see k_pipe_step): one fused orthogonalization and
 // apply, and the last orthogonalization; return the block count of their partials.
 template <typename T>
-int pipe_step(hipStream_t s, int D, int split, int slabs, const Grid &G, const cx<T> *planes, const cx<T> *yin, ProIn pin,
+int pipe_step(hipStream_t s, int D, int split, int slabs, const Grid &G, const cx<T> *planes, const cx<T> *planes_t,
+              const cx<T> *yin, ProIn pin,
               const double *scales, double *hcol, double *hsub, double *sout, const VecSet<T> &U,
               const VecSet<T> &Gs, const cx<T> *dinv, cx<T> *uo, cx<T> *zo, cx<T> *go, cx<T> *yo, double *pout);
 template <typename T>
@@ -167,6 +170,14 @@ int coarse_apply(hipStream_t s, int D, const CoarseArgs<T> &a, const VecSet<T> *
 // apply) and the block count for a slab count (0 = the most).
 int lds_max_slabs(const Grid &G, int D);
 int lds_blocks(const Grid &G, int D, int slabs);
+// The planes as the LDS apply streams them: for each z-plane and each xy-segment of
+// kLdsSeg nodes, the S planes' entries of that segment, contiguous ([z][segment][plane]
+// [node], the last segment of a plane zero-padded), so that one block reads one
+// contiguous run per z-plane.  tiled_plane_count is the entry count (0 where the LDS
+// apply does not apply); tile_planes fills it from the SoA planes.
+long long tiled_plane_count(const Grid &G, int D, int S);
+template <typename T>
+void tile_planes(hipStream_t s, const Grid &G, int S, const cx<T> *planes, cx<T> *tiled);
 // LDS z-marching on the matrix-free finest level (3D FP32, rows of at most 257 nodes and
 // at least 16 planes): mode 0 = Jacobi sweep from x, mode 1 = residual b - A x.  Returns
 // false (nothing launched) where it does not apply.

@@ -83,6 +83,21 @@ def test_adjoint_solve_matches_direct(name, prec):
     assert _rel(lam.cpu().numpy(), ref) <= 1e-6
 
 
+def test_adjoint_solve_lds_tiles():
+    """Mixed adjoint solve with the LDS tiles forced on the 3D coarse levels: the
+    conjugate-transposed planes get their own segment-tiled copy."""
+    wl = CASES["3d_33"]()
+    print("[adj-solve-tiles] 3d_33 mixed split 8", flush=True)
+    c = _ctx(wl, prec="mixed", coarse_split=8)
+    assert c.level_split(1) == 8
+    p = osolve.Problem(wl.kappa2, wl.tau, wl.gamma, wl.h, wl.omega, wl.src)
+    s = W.random_vector(wl.shape, 35)
+    ref = osolve.direct_solve(p.H2up.conj().T.tocsr(), osolve.rhs_hat(s, wl.tau, wl.omega)).reshape(wl.shape)
+    lam, st = c.solve_adjoint(_t(s), tol=1e-10, maxit=400)
+    assert st["relres"] <= 1e-10
+    assert _rel(lam.cpu().numpy(), ref) <= 1e-6
+
+
 def _receivers(shape):
     """Every third node of the top face (depth index 1), as linear indices."""
     d = len(shape)

@@ -146,9 +146,11 @@ def test_vcycle_fp64(name, split):
 
 
 @pytest.mark.parametrize("name", ["2d_65_const", "3d_33_lin"])
-@pytest.mark.parametrize("split", [1, 4])
+@pytest.mark.parametrize("split", [1, 4, 8])
 def test_vcycle_mixed_close(name, split):
-    """The complex-FP32 V-cycle stays within FP32 rounding of the FP64 one."""
+    """The complex-FP32 V-cycle stays within FP32 rounding of the FP64 one, with each
+    Galerkin-apply variant (8: the LDS tiles over the segment-tiled planes on the 3D
+    coarse levels, a partial last segment on 17^3; one lane in 2D)."""
     wl = CASES[name]()
     print(f"[vcycle-mixed] {name} shape={wl.shape} split={split}", flush=True)
     ctx = _ctx(wl, prec="mixed", coarse_split=split)
