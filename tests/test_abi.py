@@ -85,7 +85,8 @@ def test_setup_rejects_bad_problem(lib, bad):
 @pytest.mark.parametrize("bad", [dict(restart=0), dict(restart=9), dict(levels=9), dict(beta=1.5), dict(prec=7),
                                  dict(cycle=2), dict(kcycle_threshold=-0.5), dict(coarse_split=2),
                                  dict(shift_alpha=-0.1), dict(shift_alpha=float("nan")), dict(advection=2),
-                                 dict(outer_beta=1.5), dict(rescaled=2), dict(pipeline_max_nodes=-1)])
+                                 dict(outer_beta=1.5), dict(rescaled=2), dict(pipeline_max_nodes=-1),
+                                 dict(kcycle_levels=-1), dict(fine_tiles=3), dict(batch_merge=2)])
 def test_setup_rejects_bad_options(lib, bad):
     from paper_1712_06091_amd import adr
     p = _problem()
@@ -105,6 +106,8 @@ def test_null_context_calls(lib):
     assert lib.adr_level_split(None, 1, ctypes.byref(sp)) == adr.ADR_EINVAL
     assert lib.adr_solve_two_stage(None, None, None, None, 1e-2, 5, 1e-6, 10, None, None) == adr.ADR_EINVAL
     lib.adr_destroy(None)
+    assert lib.adr_batch_size(None) == 0 and lib.adr_batch_groups(None) == 0
+    lib.adr_destroy_batch(None)
     assert lib.adr_strerror(adr.ADR_ENOCONV) == b"not converged"
 
 

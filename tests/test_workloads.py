@@ -66,3 +66,14 @@ def test_fast_marching_random_medium_is_a_first_arrival(n, d, seed):
         t1 = np.take(tau, np.arange(1, n), axis=ax)
         k = np.maximum(np.take(kap, np.arange(n - 1), axis=ax), np.take(kap, np.arange(1, n), axis=ax))
         assert np.max(np.abs(t1 - t0) / (wl.h * k)) <= 1.1 * (1 + 1e-12)
+
+
+def test_batch_workload_parallel_fast_marching_is_identical():
+    """The batch recipe with its fast marching in forked workers gives the same shots
+    (sizes, sources, media, travel times) as the serial recipe."""
+    a = W.batch_2d(count=5, seed=9, sizes=(33, 65))
+    b = W.batch_2d(count=5, seed=9, sizes=(33, 65), workers=3)
+    for x, y in zip(a, b):
+        assert x.shape == y.shape and x.src == y.src and x.omega == y.omega
+        assert np.array_equal(x.kappa2, y.kappa2) and np.array_equal(x.tau, y.tau)
+        assert np.array_equal(x.gamma, y.gamma)
