@@ -1499,7 +1499,10 @@ adr_status precondition(adr_ctx *ctx, const cx<double> *v, void *z, bool z_is_c1
     if (g.in == v && g.out == z && g.adj == ctx->adj && g.group == adrk::g_shot.count) hit = &g;
   if (!hit) {
     if (!ctx->cap_stream) ADR_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
-    if (ctx->graphs.size() >= 16) {   // evict the least recently used capture
+    // Up to 64 captures: a shot group's lead holds one per Arnoldi step and slot-list
+    // bucket (5 steps x up to 7 buckets), which a smaller cache would evict and recapture
+    // on every batch solve.
+    if (ctx->graphs.size() >= 64) {   // evict the least recently used capture
       auto it = std::min_element(ctx->graphs.begin(), ctx->graphs.end(),
                                  [](const adr_ctx::GraphEntry &x, const adr_ctx::GraphEntry &y) {
                                    return x.last_use < y.last_use;
