@@ -286,7 +286,8 @@ TAIL_CASES = {
 
 
 TAIL_SKIP = ("single-workgroup coarse tail disabled: its first GPU run (2d_129_rand_5lv, tail on levels 1-3, "
-             "FP64) ended in a memory aperture violation with no cause found; adr_setup rejects it")
+             "FP64) ended in a memory aperture violation; its device code runs clean and correct on the CPU "
+             "(test_tail_host.py), the launch-side cause is not found; adr_setup rejects it")
 
 
 @pytest.mark.skip(reason=TAIL_SKIP)
