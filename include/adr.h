@@ -126,8 +126,8 @@ typedef struct {
                         /* (Sec. 4.2.2); 0 always takes both steps                       */
   int coarse_split;     /* Galerkin-stencil apply on coarse levels: 1 = one lane per     */
                         /* node, 4 = four wavefronts per 64 nodes, 8 = LDS z-marching    */
-                        /* tiles (3D complex-FP32 levels with rows of <= 129 nodes and   */
-                        /* >= 8 planes per slab; one lane elsewhere), 0 (default) = the  */
+                        /* tiles (3D levels with rows of <= 129 nodes and >= 8 planes    */
+                        /* per slab; one lane elsewhere), 0 (default) = the              */
                         /* fastest per level, timed at setup and cached per grid shape   */
                         /* and precision for the process                                 */
   int tail_max_nodes;   /* V-cycle: coarse levels from the first one with at most this   */

@@ -964,7 +964,7 @@ int auto_levels(int D, const int n[3], int coarsest_max) {
 }
 
 // Galerkin-apply variant per coarse level (one lane per node, four wavefronts per 64
-// nodes, or -- 3D FP32 levels with rows of at most 129 nodes -- LDS z-marching tiles):
+// nodes, or -- 3D levels with rows of at most 129 nodes -- LDS z-marching tiles):
 // adr_options.coarse_split if set (8 falls back to one lane where the tiles do not
 // apply), else a short timing on this level (mode 0 with one fused dot, as in the GMRES
 // relaxation) in which a variant has to beat the best one before it by 10%, so that near
@@ -984,7 +984,7 @@ std::map<std::array<int, 5>, TuneEntry> g_tune;
 template <typename T>
 adr_status tune_split(adr_ctx *ctx, int l) {
   LevelT<T> &L = levels_of<T>(ctx)[l];
-  const int max_slabs = sizeof(T) == 4 ? adrk::lds_max_slabs(L.G, ctx->D) : 0;
+  const int max_slabs = adrk::lds_max_slabs(L.G, ctx->D);
   if (ctx->opt.coarse_split == 1 || ctx->opt.coarse_split == 4 || ctx->opt.coarse_split == 8) {
     L.split = (ctx->opt.coarse_split == 8 && max_slabs == 0) ? 1 : ctx->opt.coarse_split;
     L.slabs = 0;
@@ -1206,9 +1206,9 @@ adr_status build_hierarchy(adr_ctx *ctx) {
     if (st != ADR_OK) break;
     const int centre = (Sc - 1) / 2;
     adrk::stencil_diag_inv<T>(s, lv[l].G.N, lv[l].planes + (size_t)centre * lv[l].G.N, lv[l].dinv);
-    // The LDS apply's segment-tiled copy of the planes, on the relaxed 3D FP32 levels where
+    // The LDS apply's segment-tiled copy of the planes, on the relaxed 3D levels where
     // that variant applies (released after tuning unless it is chosen).
-    if (sizeof(T) == 4 && l < ctx->levels - 1) {
+    if (l < ctx->levels - 1) {
       const long long nt = adrk::tiled_plane_count(lv[l].G, D, Sc);
       if (nt > 0) {
         st = dalloc(ctx, &lv[l].planes_t, (size_t)nt);

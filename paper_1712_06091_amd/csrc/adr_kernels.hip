@@ -1109,7 +1109,8 @@ __device__ __forceinline__ cx<T> stencil_part_of(int w, const cx<T> *__restrict_
   }
 }
 
-// LDS z-marching of the 81-point apply (3D, FP32; "split" 8).  A block owns a segment of
+// LDS z-marching of the 81-point apply (3D, complex float or double; "split" 8; the
+// complex-double window ring takes 74.5 KB of LDS, two blocks per CU).  A block owns a segment of
 // kLdsSeg consecutive in-plane nodes and a slab of z-planes.  The gathered vector's window
 // of a plane (the segment and 2 rows + 2 nodes either side, so every in-plane offset
 // (dx, dy) of the stencil lands in it) sits in a ring of kLdsSlots plane windows in LDS;
@@ -1577,15 +1578,14 @@ int pipe_step(hipStream_t s, int D, int split, int slabs, const Grid &G, const c
               const cx<T> *yin, ProIn pin, const double *scales, double *hcol, double *hsub, double *sout,
               const VecSet<T> &U, const VecSet<T> &Gs, const cx<T> *dinv, cx<T> *uo, cx<T> *zo, cx<T> *go, cx<T> *yo,
               double *pout) {
-  const int nlds = (split == 8 && sizeof(T) == 4 && planes_t && !g_shot.sh.grid) ? lds_blocks(G, D, slabs) : 0;
+  const int nlds = (split == 8 && planes_t && !g_shot.sh.grid) ? lds_blocks(G, D, slabs) : 0;
   if (split == 8 && nlds == 0) split = 1;
   const int nb = split == 8 ? nlds : (split == 4 ? launch_blocks_red(4LL * G.N) : launch_blocks_red(G.N));
 #define ADR_PIPE_CASE(n)                                                                                        \
   case n:                                                                                                       \
     if (split == 8) {                                                                                           \
-      if constexpr (sizeof(T) == 4)                                                                             \
-        launch_g(k_pipe_step<T, 3, n, 8, false>, k_pipe_step<T, 3, n, 8, true>, nb, s, G, planes_t, yin, pin, scales, \
-                 hcol, hsub, sout, U, Gs, dinv, uo, zo, go, yo, pout);                                           \
+      launch_g(k_pipe_step<T, 3, n, 8, false>, k_pipe_step<T, 3, n, 8, true>, nb, s, G, planes_t, yin, pin, scales,   \
+               hcol, hsub, sout, U, Gs, dinv, uo, zo, go, yo, pout);                                             \
     } else if (D == 2) {                                                                                        \
       if (split == 4)                                                                                           \
         launch_g(k_pipe_step<T, 2, n, 4, false>, k_pipe_step<T, 2, n, 4, true>, nb, s, G, planes, yin, pin, scales, \
@@ -1662,7 +1662,7 @@ static void dispatch_coarse_nv(hipStream_t s, int nb, const CoarseArgs<T> &a, co
 
 template <typename T, int D, bool NORM>
 static void dispatch_coarse_split(hipStream_t s, int nb, const CoarseArgs<T> &a, const VecSet<T> &V) {
-  if constexpr (D == 3 && sizeof(T) == 4) {
+  if constexpr (D == 3) {
     if (a.split == 8) {
       dispatch_coarse_nv<T, D, NORM, 8>(s, nb, a, V);
       return;
@@ -1694,7 +1694,7 @@ int coarse_apply(hipStream_t s, int D, const CoarseArgs<T> &a, const VecSet<T> *
   if (dots) V = *dots;
   const bool red = want_norm || V.count > 0;
   if (a.split == 8) {
-    const int nb = (sizeof(T) == 4 && a.planes_t && !g_shot.sh.grid) ? lds_blocks(a.G, D, a.slabs) : 0;
+    const int nb = (a.planes_t && !g_shot.sh.grid) ? lds_blocks(a.G, D, a.slabs) : 0;
     if (nb > 0) {
       // The LDS variant streams the segment-tiled copy of the planes.
       CoarseArgs<T> at = a;

@@ -45,7 +45,7 @@ struct CoarseArgs {
   int mode;
   double *pout;          // partials (when reducing)
   int split;             // 4: four wavefronts share each node's stencil sum; 8: LDS z-marching
-                         // tiles (3D FP32, see lds_blocks); else one lane
+                         // tiles (3D, see lds_blocks); else one lane
   int slabs;             // split 8: z-slabs per launch (0 = the most)
   const cx<T> *planes_t; // split 8: the same planes tiled by segment (see tile_planes); the
                          // apply falls back to one lane when NULL

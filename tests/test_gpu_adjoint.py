@@ -83,12 +83,13 @@ def test_adjoint_solve_matches_direct(name, prec):
     assert _rel(lam.cpu().numpy(), ref) <= 1e-6
 
 
-def test_adjoint_solve_lds_tiles():
-    """Mixed adjoint solve with the LDS tiles forced on the 3D coarse levels: the
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_adjoint_solve_lds_tiles(prec):
+    """Adjoint solve with the LDS tiles forced on the 3D coarse levels: the
     conjugate-transposed planes get their own segment-tiled copy."""
     wl = CASES["3d_33"]()
-    print("[adj-solve-tiles] 3d_33 mixed split 8", flush=True)
-    c = _ctx(wl, prec="mixed", coarse_split=8)
+    print(f"[adj-solve-tiles] 3d_33 {prec} split 8", flush=True)
+    c = _ctx(wl, prec=prec, coarse_split=8)
     assert c.level_split(1) == 8
     p = osolve.Problem(wl.kappa2, wl.tau, wl.gamma, wl.h, wl.omega, wl.src)
     s = W.random_vector(wl.shape, 35)

@@ -257,7 +257,7 @@ def test_full_size_3d_129_bench_configuration():
 def test_split_variants_agree_on_solve(prec):
     """The Galerkin-apply variants only reorder the stencil sums (the LDS tiles not even
     that): whole solves agree to rounding, and the autotuned default picks one of them.
-    The tiles apply to complex-FP32 levels only; FP64 falls back to one lane."""
+    The LDS tiles apply to the 3D coarse levels in both precisions."""
     wl = W.linear_gradient(65, 3)
     print(f"[split-solve] shape={wl.shape} prec={prec}", flush=True)
     out = {}
@@ -265,7 +265,7 @@ def test_split_variants_agree_on_solve(prec):
         ctx = _ctx(wl, prec=prec, coarse_split=split)
         used = [ctx.level_split(l) for l in range(1, ctx.num_levels - 1)]
         if split == 8:
-            assert all(u == (8 if prec == "mixed" else 1) for u in used), used
+            assert all(u == 8 for u in used), used
         else:
             assert all(u == split for u in used) if split else all(u in (1, 4, 8) for u in used)
         a, st = ctx.solve(_t(wl.rhs()), tol=1e-10, maxit=300)
