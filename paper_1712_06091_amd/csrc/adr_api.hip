@@ -1055,9 +1055,10 @@ adr_status tune_split(adr_ctx *ctx, int l) {
 }
 
 // Finest-level LDS tiles (fine_tiles = 1): where they apply, time Jacobi sweeps both ways
-// (8 launches each) and keep the tiles if they are at least 1% faster.  Both variants do
-// the same arithmetic, so the choice only affects speed (measured: 257^3 212 -> 201 us
-// per sweep; 129^3 29 -> 35 us, slower).
+// (8 launches each, three rounds alternating the variants, best round of each) and keep
+// the tiles if they are at least 1% faster.  Both variants do the same arithmetic, so the
+// choice only affects speed (measured: 257^3 212 -> 201 us per sweep; 129^3 29 -> 35 us,
+// slower).
 template <typename T>
 adr_status tune_fine_tiles(adr_ctx *ctx) {
   ctx->fine_tiles_on = false;
@@ -1076,8 +1077,9 @@ adr_status tune_fine_tiles(adr_ctx *ctx) {
   hipEvent_t e0, e1;
   ADR_HIP(hipEventCreate(&e0));
   ADR_HIP(hipEventCreate(&e1));
-  float ms[2] = {0.f, 0.f};
-  for (int v = 0; v < 2; ++v) {
+  float ms[2] = {1e30f, 1e30f};
+  for (int round = 0; round < 6; ++round) {
+    const int v = round & 1;
     // Sweeps alternate between two buffers, each reading the previous one's output, as in
     // the cycle.
     auto sweep = [&](int r) {
@@ -1090,7 +1092,9 @@ adr_status tune_fine_tiles(adr_ctx *ctx) {
     for (int r = 0; r < 8; ++r) sweep(r);
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms[v], e0, e1);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (e == hipSuccess && t < ms[v]) ms[v] = t;
     if (e != hipSuccess) {
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);

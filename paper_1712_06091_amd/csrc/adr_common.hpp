@@ -101,6 +101,18 @@ inline int launch_blocks(long long N) {
   return (int)b;
 }
 
+// Gather-heavy kernels without reductions or per-block prologues (the matrix-free fine
+// rows, prolongation): about one node per thread, up to ADR_MAX_WIDE_BLOCKS blocks.  A
+// thread that loops over a chunk waits on each node's gathers in turn; many resident waves
+// with one node each keep more of them in flight.
+#define ADR_MAX_WIDE_BLOCKS (1 << 17)
+inline int launch_blocks_wide(long long N) {
+  long long b = (N + ADR_BLOCK - 1) / ADR_BLOCK;
+  if (b > ADR_MAX_WIDE_BLOCKS) b = ADR_MAX_WIDE_BLOCKS;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
 __device__ __forceinline__ int logical_block() {
   int nb = gridDim.x, bid = blockIdx.x;
   int q = nb / ADR_NUM_XCD, r = nb % ADR_NUM_XCD;

@@ -339,7 +339,7 @@ int fine_apply(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const 
   VecSet<To> V{};
   if (dots) V = *dots;
   const bool red = want_norm || V.count > 0;
-  const int nb = red ? launch_blocks_red(G.N) : launch_blocks(G.N);
+  const int nb = red ? launch_blocks_red(G.N) : launch_blocks_wide(G.N);
   if (D == 2) {
     if (want_norm) dispatch_fine_apply_nv<T, Tin, To, 2, true>(s, nb, G, C, P, x, b, y, mode, V, pout, Pd);
     else dispatch_fine_apply_nv<T, Tin, To, 2, false>(s, nb, G, C, P, x, b, y, mode, V, pout, Pd);
@@ -414,7 +414,7 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_fine_jacobi(Grid G, FineCoef<T> C
 template <typename T>
 void fine_jacobi(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P, const cx<T> *x_in,
                  const cx<T> *b, cx<T> *x_out, double weight, const FineParams *Pd) {
-  int nb = launch_blocks(G.N);
+  int nb = launch_blocks_wide(G.N);
   if (x_in) {
     if (D == 2)
       launch_g(k_fine_jacobi<T, 2, true, false>, k_fine_jacobi<T, 2, true, true>, nb, s, G, C, P, x_in, b, x_out,
@@ -438,8 +438,9 @@ void fine_jacobi(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, cons
 // +-2 along x and y (all inside the plane window: the segment and 2 rows either side) and
 // at +-1, +-2 along z (only the segment of those planes).  So LDS holds the plane window of
 // the current plane (double-buffered: the next plane's is loaded during this one) and a
-// ring of six plane segments (z-2..z+3).  One barrier per plane.  The row arithmetic is
-// fine_row's, in the same order as the one-lane kernels, so the results are the same.
+// ring of six plane segments (z-2..z+3); the node's coefficients and right-hand side are
+// also loaded a plane ahead.  One barrier per plane.  The row arithmetic is fine_row's, in
+// the same order as the one-lane kernels, so the results are the same.
 // -------------------------------------------------------------------------------------
 constexpr int kFineSeg = ADR_BLOCK;
 constexpr int kFineMaxN0 = 257;
@@ -513,17 +514,29 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_fine_lds(Grid G, FineCoef<T> C, F
   const int ip = s0 + tid;
   const bool act = ip < nxy;
   const int base = tid + halo;
+  // The node's coefficients and right-hand side are loaded one plane ahead too, so that a
+  // plane's arithmetic waits on LDS only and every global load of the step overlaps it.
+  auto load_cb = [&](int zp, T (&g)[3], T &l, cx<T> &cc, cx<T> &bb) {
+    if (act && zp < z1) {
+      const int i = zp * nxy + ip;
+      load_fine_coef<T, D>(C, i, g, l, cc);
+      bb = b[i];
+    }
+  };
+  T gk[3] = {T(0), T(0), T(0)}, L = T(0);
+  cx<T> c = mk<T>(T(0), T(0)), bi = c;
+  load_cb(z0, gk, L, c, bi);
   for (int z = z0; z < z1; ++z) {
-    // Next plane's window and the segment of plane z + 3, in flight during this plane.
+    // Next plane's window, coefficients and right-hand side and the segment of plane
+    // z + 3, in flight during this plane.
     cx<T> reg[RW];
     load_win(z + 1, reg);
     const cx<T> seg3 = xval(z + 3, s0 + tid);
+    T gn[3] = {T(0), T(0), T(0)}, Ln = T(0);
+    cx<T> cn = mk<T>(T(0), T(0)), bn = cn;
+    load_cb(z + 1, gn, Ln, cn, bn);
     if (act) {
       const int i = z * nxy + ip;
-      T gk[3], L;
-      cx<T> c;
-      load_fine_coef<T, D>(C, i, gk, L, c);
-      const cx<T> bi = b[i];
       int idx[3];
       idx[0] = ip % n0;
       idx[1] = ip / n0;
@@ -556,6 +569,11 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_fine_lds(Grid G, FineCoef<T> C, F
     }
     store_win((z + 1) & 1, reg);
     ring[(z + 3) % 6][tid] = seg3;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gk[k] = gn[k];
+    L = Ln;
+    c = cn;
+    bi = bn;
     __syncthreads();
   }
 }
@@ -701,7 +719,7 @@ int fine_apply_adj(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, co
   VecSet<To> V{};
   if (dots) V = *dots;
   const bool red = want_norm || V.count > 0;
-  const int nb = red ? launch_blocks_red(G.N) : launch_blocks(G.N);
+  const int nb = red ? launch_blocks_red(G.N) : launch_blocks_wide(G.N);
   if (D == 2) {
     if (want_norm) dispatch_fine_adj_nv<T, Tin, To, 2, true>(s, nb, G, C, P, x, b, y, mode, V, pout);
     else dispatch_fine_adj_nv<T, Tin, To, 2, false>(s, nb, G, C, P, x, b, y, mode, V, pout);
@@ -751,7 +769,7 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_fine_jacobi_adj(Grid G, FineCoef<
 template <typename T>
 void fine_jacobi_adj(hipStream_t s, const Grid &G, int D, const FineCoef<T> &C, const FineParams &P,
                      const cx<T> *x_in, const cx<T> *b, cx<T> *x_out, double weight) {
-  int nb = launch_blocks(G.N);
+  int nb = launch_blocks_wide(G.N);
   if (D == 2) ADR_LAUNCH((k_fine_jacobi_adj<T, 2>), nb, s, G, C, P, x_in, b, x_out, (T)weight);
   else ADR_LAUNCH((k_fine_jacobi_adj<T, 3>), nb, s, G, C, P, x_in, b, x_out, (T)weight);
 }
@@ -2009,7 +2027,7 @@ __global__ __launch_bounds__(ADR_BLOCK) void k_prolong_add(Grid Gf, Grid Gc, con
 
 template <typename T>
 void prolong_add(hipStream_t s, const Grid &Gf, const Grid &Gc, int D, const cx<T> *ec, cx<T> *xf) {
-  int nb = launch_blocks(Gf.N);
+  int nb = launch_blocks_wide(Gf.N);
   if (D == 2) launch_g(k_prolong_add<T, 2, false>, k_prolong_add<T, 2, true>, nb, s, Gf, Gc, ec, xf);
   else launch_g(k_prolong_add<T, 3, false>, k_prolong_add<T, 3, true>, nb, s, Gf, Gc, ec, xf);
 }
