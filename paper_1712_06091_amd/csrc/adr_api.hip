@@ -1017,33 +1017,43 @@ adr_status tune_split(adr_ctx *ctx, int l) {
       if (!dup && sl >= 1) cand.push_back({8, sl});
     }
   }
-  TuneEntry best{1, 0, 0.f};
-  for (auto [split, slabs] : cand) {
-    CoarseArgs<T> a{};
-    a.split = split;
-    a.slabs = slabs;
-    a.G = L.G;
-    a.planes = L.planes;
-    a.planes_t = L.planes_t;
-    a.x = L.x;
-    a.y = L.w;
-    a.mode = 0;
-    a.pout = ctx->part[0];
-    for (int w = 0; w < 2; ++w) adrk::coarse_apply<T>(s, ctx->D, a, &V1, false);
-    hipError_t e = hipEventRecord(e0, s);
-    constexpr int reps = 8;
-    for (int r = 0; r < reps; ++r) adrk::coarse_apply<T>(s, ctx->D, a, &V1, false);
-    if (e == hipSuccess) e = hipEventRecord(e1, s);
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
-    float ms = 0.f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    if (e != hipSuccess) {
-      (void)hipEventDestroy(e0);
-      (void)hipEventDestroy(e1);
-      ctx->err = std::string("split tuning: ") + hipGetErrorString(e);
-      return ADR_EHIP;
+  // Two rounds over the candidates, best round of each.  Small levels time 32 launches a
+  // round: 8 launches of a few microseconds each are mostly timing noise.
+  const int reps = N < (1u << 17) ? 32 : 8;
+  std::vector<float> cand_ms(cand.size(), 1e30f);
+  for (int round = 0; round < 2; ++round) {
+    for (size_t ci = 0; ci < cand.size(); ++ci) {
+      const int split = cand[ci].first, slabs = cand[ci].second;
+      CoarseArgs<T> a{};
+      a.split = split;
+      a.slabs = slabs;
+      a.G = L.G;
+      a.planes = L.planes;
+      a.planes_t = L.planes_t;
+      a.x = L.x;
+      a.y = L.w;
+      a.mode = 0;
+      a.pout = ctx->part[0];
+      for (int w = 0; w < 2; ++w) adrk::coarse_apply<T>(s, ctx->D, a, &V1, false);
+      hipError_t e = hipEventRecord(e0, s);
+      for (int r = 0; r < reps; ++r) adrk::coarse_apply<T>(s, ctx->D, a, &V1, false);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        ctx->err = std::string("split tuning: ") + hipGetErrorString(e);
+        return ADR_EHIP;
+      }
+      cand_ms[ci] = std::min(cand_ms[ci], ms * 8.f / reps);   // the table keeps ms per 8 launches
     }
-    if (split == 1 || ms < 0.90f * best.ms) best = TuneEntry{split, split == 8 ? slabs : 0, ms};
+  }
+  TuneEntry best{1, 0, 0.f};
+  for (size_t ci = 0; ci < cand.size(); ++ci) {
+    const int split = cand[ci].first, slabs = cand[ci].second;
+    if (split == 1 || cand_ms[ci] < 0.90f * best.ms) best = TuneEntry{split, split == 8 ? slabs : 0, cand_ms[ci]};
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
